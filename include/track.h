@@ -1,0 +1,228 @@
+/*
+ * track.h -- C ABI of the MI355X tracking library (libtrack.so).
+ *
+ * The library runs the per-frame Gauss-Newton step of the joint skeleton and
+ * mesh tracker of Walsman, Wan, Schmidt and Fox, "Dynamic High Resolution
+ * Deformable Articulated Tracking" (3DV 2017): dual-quaternion blend
+ * skinning of a template mesh (Section 3), projective association of every
+ * depth pixel to its nearest skinned vertex, point-to-plane residuals, the
+ * pose normal equations and damped Cholesky step (Sections 4.1, 4.2) and the
+ * regularised per-vertex offset update (Section 4.3).
+ *
+ * Conventions for every call:
+ *   - Returns TRACK_OK (0) or a negative track_status; nothing is thrown or
+ *     aborted across the ABI.  track_last_error() gives a message for the
+ *     last failure on the calling thread.
+ *   - Input arrays are read during the call only and copied where kept; the
+ *     caller keeps ownership.  Output arrays are caller-allocated; a NULL
+ *     output pointer means "skip".
+ *   - Host pointers unless a flag says the pointer is device memory.
+ *   - A context is used from one host thread at a time; contexts are
+ *     independent.  Work is issued on the HIP stream given at init (NULL =
+ *     the default stream) and calls return when their work has finished.
+ *   - Camera frame: +z forward, +y down, metres; pixel centres at integer
+ *     (u, v); a point (x, y, z) projects to u = fx*x/z + cx, v = fy*y/z + cy.
+ *   - Dual quaternions are stored as 8 numbers (r.w r.x r.y r.z d.w d.x d.y
+ *     d.z) for H = r + eps d.
+ */
+#ifndef TRACK_H
+#define TRACK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct track_ctx track_ctx; /* opaque; owned by the library */
+
+typedef enum {
+    TRACK_OK = 0,
+    TRACK_E_INVALID = -1, /* bad argument or model; nothing changed            */
+    TRACK_E_NOMEM = -2,   /* device allocation failed                           */
+    TRACK_E_DEVICE = -3,  /* a HIP call failed                                  */
+    TRACK_E_NOT_PD = -4,  /* pose system not positive definite; state kept      */
+    TRACK_E_LOST = -5,    /* frame rejected by the health check; state restored */
+    TRACK_E_BUDGET = -6   /* would exceed the memory budget                     */
+} track_status;
+
+enum { TRACK_HINGE = 0, TRACK_PRISMATIC = 1 };
+/* Operand form of the J^T J / J^T r contraction on the matrix cores:
+   float32; bfloat16 hi/lo split (3 products); bfloat16 hi/mid/lo split (6). */
+enum { TRACK_GRAM_FP32 = 0, TRACK_GRAM_BF16X3 = 1, TRACK_GRAM_BF16X6 = 2 };
+
+/* Limits of this build. */
+#define TRACK_MAX_JOINTS 127
+#define TRACK_MAX_LINKS 255
+#define TRACK_MAX_INFL 4
+
+/*
+ * Template model (Section 3).  The skeleton is a tree of elementary 1-DoF
+ * joints, parents listed before children (Section 3.1); a multi-DoF joint is
+ * several hinges in succession.  Joint j's frame is
+ *     H_{0,j} = H_{0,P(j)} * O_j * H_j(theta_j)
+ * with O_j the fixed offset given below and H_j Eq. (1) (hinge) or Eq. (2)
+ * (prismatic).  Theta = 0 is the bind pose (Section 3.2).  Each link rides
+ * the frame of one joint.  The mesh is V template vertices and F triangles;
+ * each vertex has at most TRACK_MAX_INFL (link, weight) pairs whose weights
+ * sum to one (Section 3.2).  Neighbours are the four closest template
+ * vertices used by the offset regulariser (Section 4.3).
+ */
+typedef struct {
+    int32_t n_joints;            /* P, 1..TRACK_MAX_JOINTS                          */
+    const int32_t *joint_parent; /* [P] parent joint, -1 = camera frame; < own index */
+    const int32_t *joint_type;   /* [P] TRACK_HINGE or TRACK_PRISMATIC               */
+    const float *joint_axis;     /* [P*3] unit axis z in the joint frame             */
+    const float *joint_offset;   /* [P*7] O_j: rotation quaternion (w,x,y,z), then
+                                    translation (x,y,z); x -> R x + t               */
+    int32_t n_links;             /* L, 1..TRACK_MAX_LINKS                            */
+    const int32_t *link_joint;   /* [L] joint whose frame the link rides             */
+    int32_t n_verts;             /* V >= 1                                           */
+    const float *rest_xyz;       /* [V*3] template vertices at Theta = 0             */
+    int32_t n_faces;             /* F >= 0                                           */
+    const int32_t *faces;        /* [F*3] vertex indices, counter-clockwise seen
+                                    from outside (normals point outward)             */
+    int32_t max_infl;            /* K, 1..TRACK_MAX_INFL                             */
+    const int32_t *skin_link;    /* [V*K] link index or -1 for an unused slot        */
+    const float *skin_w;         /* [V*K] weights in [0,1]; sum per vertex within
+                                    1e-4 of 1; 0 in unused slots                     */
+    const int32_t *neighbors;    /* [V*4] template neighbours (-1 = none) or NULL:
+                                    the library takes the 4 nearest template
+                                    vertices (ties to the lower index)              */
+} track_model;
+
+/* Pinhole depth camera; depth frames are H x W float32 row-major, metres,
+   0 or non-finite = no measurement (Section 4.1). */
+typedef struct {
+    int32_t width, height; /* 1..4096 each                          */
+    float fx, fy, cx, cy;  /* focal lengths (> 0) and principal point */
+} track_camera;
+
+/*
+ * Tracker constants (Section 4).  One frame runs n_iters iterations; each
+ * associates the frame with the current surface and then, as flagged, takes
+ * a pose step and/or a per-vertex offset step reusing that association.
+ */
+typedef struct {
+    float tau;                /* association cutoff (m) > 0                          */
+    int32_t n_iters;          /* iterations per frame, 1..256                        */
+    const uint8_t *do_pose;   /* [n_iters] take the pose step on iteration t         */
+    const uint8_t *do_shape;  /* [n_iters] take the offset step on iteration t       */
+    float lambda_k;           /* Marquardt damping of the pose step                  */
+    float lambda_s;           /* default-pose prior weight (0 = off)                 */
+    float lambda_phi;         /* offset magnitude weight                             */
+    float lambda_nbr;         /* neighbour smoothness weight                         */
+    float lambda_t;           /* temporal weight toward the previous frame's offsets */
+    float lambda_w;           /* Marquardt damping of the per-vertex step            */
+    int32_t gram_mode;        /* TRACK_GRAM_FP32, _BF16X3 or _BF16X6                  */
+    int32_t pose_solve_fp64;  /* 1 = pose Cholesky in float64, 0 = float32           */
+    int32_t shape_solve_fp64; /* 1 = per-vertex 3x3 solves in float64                */
+    const uint8_t *active;    /* [P] 0 freezes a joint, or NULL = all active         */
+} track_params;
+
+typedef struct {
+    int32_t status;        /* track_status of the frame                          */
+    int32_t n_valid_px;    /* pixels with a measurement                          */
+    int32_t n_assoc_px;    /* pixels associated on the last iteration            */
+    int32_t n_obs_verts;   /* vertices with at least one pixel, last iteration   */
+    float energy_first;    /* sum of squared residuals at the first pose step    */
+    float energy_last;     /* the same at the last pose step                     */
+    float step_norm_last;  /* |x| of the last pose step                          */
+    float ms_total;        /* GPU time of the frame in milliseconds              */
+} track_frame_stats;
+
+/*
+ * Create a context: validates and copies the model, camera and constants,
+ * allocates device memory, and poses the template at theta0 (P doubles,
+ * "an initial estimate of the skeletal pose", Section 3) with offsets phi0
+ * ([V*3], or NULL for the default shape Phi = 0).  hip_stream is a
+ * hipStream_t or NULL.  On success *out holds the context.
+ */
+int track_init(const track_model *model, const track_camera *camera, const track_params *params,
+               const double *theta0, const float *phi0, void *hip_stream, track_ctx **out);
+
+/*
+ * Track one depth frame (H*W float32, metres).  depth_on_device != 0 means a
+ * device pointer.  On success the state holds the new Theta and Phi.  On
+ * TRACK_E_NOT_PD or TRACK_E_LOST the state is that of the previous frame.
+ */
+int track_frame(track_ctx *ctx, const float *depth, int32_t depth_on_device);
+
+/* Same, from an organised point cloud (H*W*3 float32, camera frame; a pixel
+   with z <= 0 or a non-finite coordinate has no measurement). */
+int track_frame_xyz(track_ctx *ctx, const float *xyz, int32_t on_device);
+
+/* Copy the state out: Theta [P] float64, Phi [V*3], skinned vertices [V*3]
+   at the current state, and the last frame's statistics.  Never changes the
+   state. */
+int track_state(const track_ctx *ctx, double *theta, float *phi, float *verts,
+                track_frame_stats *stats);
+
+/* Replace the state (checkpoint restore): Theta [P], Phi [V*3] (NULL = 0);
+   the previous-frame offsets become Phi as well. */
+int track_reset(track_ctx *ctx, const double *theta, const float *phi);
+
+/* Replace the per-frame constants (same model and camera). */
+int track_set_params(track_ctx *ctx, const track_params *params);
+
+void track_destroy(track_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *track_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Per-pass access, for checking each step against an independent
+ * implementation on identical inputs.  Buffers are exchanged in the host
+ * layouts below; a pass reads and writes the context's buffers.
+ * ---------------------------------------------------------------------- */
+enum {
+    TRACK_BUF_THETA = 0,   /* float64 [P]                                             */
+    TRACK_BUF_PHI = 1,     /* float32 [V*3]                                           */
+    TRACK_BUF_VERTS = 2,   /* float32 [V*3] skinned vertices of the current surface   */
+    TRACK_BUF_NORMALS = 3, /* float32 [V*3] unit vertex normals                       */
+    TRACK_BUF_DEPTH = 4,   /* float32 [H*W] (set only)                                */
+    TRACK_BUF_XYZ = 5,     /* float32 [H*W*3] (set only)                              */
+    TRACK_BUF_ASSOC = 6,   /* int32 [H*W] nearest vertex per pixel or -1 (get only)   */
+    TRACK_BUF_COUNT = 7,   /* int32 [V] pixels per vertex                             */
+    TRACK_BUF_DELTA = 8,   /* float32 [V*3] mean offset p~_i - v_i (zero if count 0)  */
+    TRACK_BUF_GRAM = 9,    /* float64 [(P+1)*(P+1)] [J r]^T [J r], prior excluded (get) */
+    TRACK_BUF_STEP = 10,   /* float64 [P] last pose step x (get only)                 */
+    TRACK_BUF_PHI_PREV = 11, /* float32 [V*3] previous frame's offsets                */
+    TRACK_BUF_VERTS_NEW = 12 /* float32 [V*3] vertices after the pose step (get)     */
+};
+enum {
+    TRACK_PASS_SKIN = 0,      /* FK at THETA, skin PHI -> VERTS, NORMALS                    */
+    TRACK_PASS_NORMALS = 1,   /* NORMALS from VERTS                                        */
+    TRACK_PASS_ASSOCIATE = 2, /* buckets of VERTS; ASSOC, COUNT, DELTA from the set frame  */
+    TRACK_PASS_NORMAL_EQ = 3, /* GRAM from THETA, PHI, VERTS, NORMALS, COUNT, DELTA        */
+    TRACK_PASS_POSE_STEP = 4, /* damped solve of GRAM; THETA -= x; STEP                    */
+    TRACK_PASS_SHAPE = 5      /* re-skin at THETA into VERTS_NEW and new normals, then one
+                                 offset step; PHI updated                                  */
+};
+int track_dbg_set(track_ctx *ctx, int32_t buf, const void *host, size_t bytes);
+int track_dbg_get(const track_ctx *ctx, int32_t buf, void *host, size_t bytes);
+int track_dbg_run(track_ctx *ctx, int32_t pass);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing: when enabled, every launch of the named kernel is bracketed
+ * by HIP events on the context's stream; track_kernel_time returns the
+ * number of timed launches and their summed duration since the last reset.
+ * ---------------------------------------------------------------------- */
+enum {
+    TRACK_K_SKIN = 0,
+    TRACK_K_NORMALS = 1,
+    TRACK_K_BUCKET = 2,
+    TRACK_K_ASSOC = 3,
+    TRACK_K_NORMAL_EQ = 4,
+    TRACK_K_SOLVE = 5,
+    TRACK_K_SHAPE = 6,
+    TRACK_K_COUNT_ = 7
+};
+int track_kernel_timing(track_ctx *ctx, int32_t kernel, int32_t enable);
+int track_kernel_time(track_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRACK_H */

@@ -70,7 +70,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             build(force=True)
         _lib = ctypes.CDLL(LIB_PATH)
-        for name in ("orc_fk", "orc_skin", "orc_skin_dual", "orc_transform",
+        for name in ("orc_fk", "orc_skin", "orc_normals", "orc_skin_dual", "orc_transform",
                      "orc_associate", "orc_average", "orc_pose_system",
                      "orc_prior_weights", "orc_lm_solve", "orc_shape_step",
                      "orc_track_frame", "orc_set_threads"):
@@ -148,6 +148,15 @@ def skin(model, theta, phi=None):
     n = np.zeros((m.V, 3))
     lib().orc_skin(ctypes.byref(m.c), _p(th), _p(ph), _p(v), _p(n))
     return v, n
+
+
+def normals(model, v):
+    """Unit vertex normals of the given vertex positions (float64)."""
+    m = _model(model)
+    vv = _c(v, np.float64)
+    n = np.zeros((m.V, 3))
+    lib().orc_normals(ctypes.byref(m.c), _p(vv), _p(n))
+    return n
 
 
 def skin_dual(model, theta, dtheta=None, phi=None, dphi=None):

@@ -103,6 +103,13 @@ int orc_skin(const orc_model_in* in, const double* theta, const double* phi, dou
     return 0;
 }
 
+// Vertex normals of a given vertex array (float64 [V*3]).
+int orc_normals(const orc_model_in* in, const double* v, double* n) {
+    orc::Model m = to_model(in);
+    orc::vertex_normals(m, v, n);
+    return 0;
+}
+
 // Forward-mode derivative of the skinned vertices along (dtheta, dphi).
 int orc_skin_dual(const orc_model_in* in, const double* theta, const double* dtheta, const double* phi,
                   const double* dphi, double* v, double* dv) {

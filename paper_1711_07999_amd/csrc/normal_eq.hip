@@ -1,0 +1,307 @@
+// Residuals, pose Jacobian rows and the normal equations (Eq. 6-8).
+//
+// For each observed vertex i (at least one associated pixel and a non-zero
+// normal) the residual is r_i = n_i . delta_i with delta_i the mean offset of
+// its points (Eq. 6).  Its Jacobian row follows the chain rule of Section 4.2;
+// with dH_{l,Delta}/dtheta_k = Xi_k H_{l,Delta} (see the FK kernel) and
+// dT/dH collapsed against the normal into one dual quaternion c = (c_r, c_d),
+//   c_d = (2/N) n r,   c_r = -(2/N) (n r x + n d + (n . v) r),   N = |r|^2
+// for the blend H = (r, d), template point x = v0 + phi and skinned point v,
+// every entry is a dot product of 6-vectors:
+//   J_ik = - sum over influences m whose link chain holds joint k of
+//          w_m [ vec(c_r H_m,r^* + c_d H_m,d^*) . Xi_k,r + vec(c_d H_m,r^*) . Xi_k,d ].
+// Rows are built in LDS as [J | r] (never written to HBM) and the Gram matrix
+// G = [J r]^T [J r] (which holds J^T J, J^T r and r^T r) is accumulated with
+// MFMA with float32 accumulation, from one of three operand forms:
+//   mode 0: float32 operands (v_mfma_f32_16x16x4_f32);
+//   mode 1: each entry split as hi + lo in bfloat16, G ~ hi.hi + hi.lo + lo.hi
+//           (3 bfloat16 products, about 2^-17 relative error per product);
+//   mode 2: hi + mid + lo, G ~ hi.hi + hi.mid + mid.hi + hi.lo + lo.hi + mid.mid
+//           (6 products, about 2^-24: float32 accuracy at bfloat16 rate).
+// Each workgroup writes one partial G; partials are summed in workgroup
+// order (deterministic) by a second kernel.
+#include "common.h"
+#include "dq.h"
+
+namespace trk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int kJTStride = kNeRows + 8;  // floats per LDS column of the row tile
+constexpr int kGStride = 25;            // floats per row of per-influence 6-vectors
+
+__device__ __forceinline__ void block_of(int idx, int nb, int& I, int& J) {
+    int q = idx;
+    for (I = 0; I < nb; ++I) {
+        int len = nb - I;
+        if (q < len) { J = I + q; return; }
+        q -= len;
+    }
+    I = J = 0;
+}
+
+// per-vertex 6-vectors of the Jacobian (one per influence) and the residual
+__device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq, int i, CVec3Buf v,
+                                             CVec3Buf n, CVec3Buf phi, const Accum& a, float* G,
+                                             float& r_out) {
+    float H[8], sg[4];
+    const float4 w = m.w[i];
+    const uint32_t lk = m.links[i];
+    dq_blend(sdq, w, lk, H, sg);
+    const float nx = n.x[i], ny = n.y[i], nz = n.z[i];
+    const float vx = v.x[i], vy = v.y[i], vz = v.z[i];
+    const float x[4] = {0.0f, m.rx[i] + phi.x[i], m.ry[i] + phi.y[i], m.rz[i] + phi.z[i]};
+    const float nq[4] = {0.0f, nx, ny, nz};
+    const float N = H[0] * H[0] + H[1] * H[1] + H[2] * H[2] + H[3] * H[3];
+    const float s2 = 2.0f / N;
+    float nr[4], nrx[4], nd[4];
+    qmul(nq, H, nr);
+    qmul(nr, x, nrx);
+    qmul(nq, H + 4, nd);
+    const float ndotv = nx * vx + ny * vy + nz * vz;
+    float cr[4], cd[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        cd[c] = s2 * nr[c];
+        cr[c] = -s2 * (nrx[c] + nd[c] + ndotv * H[c]);
+    }
+    const float ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int l = (lk >> (8 * k)) & 0xFF;
+        float* g = G + 6 * k;
+        if (l == 0xFF) {
+            g[0] = g[1] = g[2] = g[3] = g[4] = g[5] = 0.0f;
+            continue;
+        }
+        const float* D = sdq + 8 * l;
+        const float s = sg[k];
+        const float rc[4] = {s * D[0], -s * D[1], -s * D[2], -s * D[3]};
+        const float dc[4] = {s * D[4], -s * D[5], -s * D[6], -s * D[7]};
+        float t1[4], t2[4], t3[4];
+        qmul(cr, rc, t1);
+        qmul(cd, dc, t2);
+        qmul(cd, rc, t3);
+        const float ww = ws[k];
+        g[0] = ww * (t1[1] + t2[1]);
+        g[1] = ww * (t1[2] + t2[2]);
+        g[2] = ww * (t1[3] + t2[3]);
+        g[3] = ww * t3[1];
+        g[4] = ww * t3[2];
+        g[5] = ww * t3[3];
+    }
+    const float inv = 1.0f / ((float)a.cnt[i] * 4294967296.0f);
+    const float dx = (float)a.sx[i] * inv, dy = (float)a.sy[i] * inv, dz = (float)a.sz[i] * inv;
+    r_out = nx * dx + ny * dy + nz * dz;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_normal_eq(DevModel m, int PP, const float* __restrict__ dq,
+                                                   const float* __restrict__ xi,
+                                                   const uint32_t* __restrict__ anc, CVec3Buf v, CVec3Buf n,
+                                                   CVec3Buf phi, Accum a, float* __restrict__ partials,
+                                                   int nchunks) {
+    __shared__ float sdq[8 * (kMaxLinks + 1)];
+    __shared__ float sxi[6 * kPPMax];
+    __shared__ uint32_t sanc[4 * (kMaxLinks + 1)];
+    __shared__ float sG[kNeRows * kGStride];
+    __shared__ uint32_t slink[kNeRows];
+    __shared__ float sr[kNeRows];
+    __shared__ int scount[2];
+    // [col][row] tile: float32 (mode 0) or up to three bfloat16 planes
+    __shared__ __attribute__((aligned(16))) unsigned short sT[3 * kPPMax * kJTStride];
+    float* sJT = reinterpret_cast<float*>(sT);
+    __bf16* plane0 = reinterpret_cast<__bf16*>(sT);
+    __bf16* plane1 = plane0 + kPPMax * kJTStride;
+    __bf16* plane2 = plane1 + kPPMax * kJTStride;
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int P = m.P;
+    for (int q = tid; q < 8 * m.L; q += 256) sdq[q] = dq[q];
+    for (int q = tid; q < 6 * P; q += 256) sxi[q] = xi[8 * (q / 6) + (q % 6)];
+    for (int q = tid; q < 4 * m.L; q += 256) sanc[q] = anc[q];
+
+    const int nb = PP >> 4;
+    const int nbt = nb * (nb + 1) / 2;
+    f4 acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    __syncthreads();
+
+    for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+        __syncthreads();  // the previous chunk's tile and counts are consumed
+        // 1. compact the observed vertices of this chunk
+        bool obs = false;
+        int i = chunk * kNeRows + tid;
+        if (tid < kNeRows && i < m.V && a.cnt[i] > 0u) {
+            float nx = n.x[i], ny = n.y[i], nz = n.z[i];
+            obs = (nx * nx + ny * ny + nz * nz) > 0.0f;
+        }
+        unsigned long long bal = __ballot(obs);
+        if (lane == 0 && wid < 2) scount[wid] = __popcll(bal);
+        __syncthreads();
+        const int nrows = scount[0] + scount[1];
+        if (obs) {
+            int row = __popcll(bal & ((1ull << lane) - 1ull)) + (wid == 1 ? scount[0] : 0);
+            float r;
+            vertex_terms(m, sdq, i, v, n, phi, a, &sG[row * kGStride], r);
+            sr[row] = r;
+            slink[row] = m.links[i];
+        }
+        __syncthreads();
+        if (nrows == 0) continue;
+        const int kstep = MODE == 0 ? 16 : 32;
+        const int npad = (nrows + kstep - 1) / kstep * kstep;
+
+        // 2. rows of [J r] into the [col][row] tile
+        for (int e = tid; e < PP * npad; e += 256) {
+            const int col = e / npad, row = e - col * npad;
+            float val = 0.0f;
+            if (row < nrows) {
+                if (col < P) {
+                    const uint32_t lk = slink[row];
+                    const float* g = &sG[row * kGStride];
+                    const float* xk = &sxi[6 * col];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        int l = (lk >> (8 * k)) & 0xFF;
+                        if (l == 0xFF) continue;
+                        if (!((sanc[4 * l + (col >> 5)] >> (col & 31)) & 1u)) continue;
+                        const float* gk = g + 6 * k;
+                        val -= gk[0] * xk[0] + gk[1] * xk[1] + gk[2] * xk[2] + gk[3] * xk[3] + gk[4] * xk[4] +
+                               gk[5] * xk[5];
+                    }
+                } else if (col == P) {
+                    val = sr[row];
+                }
+            }
+            const int at = col * kJTStride + row;
+            if (MODE == 0) {
+                sJT[at] = val;
+            } else {
+                __bf16 h = (__bf16)val;
+                float rem = val - (float)h;
+                __bf16 m = (__bf16)rem;
+                plane0[at] = h;
+                plane1[at] = m;
+                if (MODE == 2) plane2[at] = (__bf16)(rem - (float)m);
+            }
+        }
+        __syncthreads();
+
+        // 3. Gram blocks (I <= J) owned by this wave
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int idx = wid + 4 * q;
+            if (idx < nbt) {
+                int I, J;
+                block_of(idx, nb, I, J);
+                const int ca = (I * 16 + (lane & 15)) * kJTStride;
+                const int cb = (J * 16 + (lane & 15)) * kJTStride;
+                if (MODE == 0) {
+                    for (int k0 = 0; k0 < npad; k0 += 16) {
+                        const int ro = k0 + 4 * (lane >> 4);
+                        f4 av = *reinterpret_cast<const f4*>(&sJT[ca + ro]);
+                        f4 bv = *reinterpret_cast<const f4*>(&sJT[cb + ro]);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.x, bv.x, acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.y, bv.y, acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.z, bv.z, acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.w, bv.w, acc[q], 0, 0, 0);
+                    }
+                } else {
+                    for (int k0 = 0; k0 < npad; k0 += 32) {
+                        const int ro = k0 + 8 * (lane >> 4);
+                        bf8 ah = *reinterpret_cast<const bf8*>(&plane0[ca + ro]);
+                        bf8 am = *reinterpret_cast<const bf8*>(&plane1[ca + ro]);
+                        bf8 bh = *reinterpret_cast<const bf8*>(&plane0[cb + ro]);
+                        bf8 bm = *reinterpret_cast<const bf8*>(&plane1[cb + ro]);
+                        // smallest products first
+                        if (MODE == 2) {
+                            bf8 al = *reinterpret_cast<const bf8*>(&plane2[ca + ro]);
+                            bf8 bl = *reinterpret_cast<const bf8*>(&plane2[cb + ro]);
+                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[q], 0, 0, 0);
+                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[q], 0, 0, 0);
+                            acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm, acc[q], 0, 0, 0);
+                        }
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm, acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[q], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+
+    // 4. this workgroup's partial Gram (upper blocks only)
+    float* out = partials + (size_t)blockIdx.x * PP * PP;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        const int idx = wid + 4 * q;
+        if (idx < nbt) {
+            int I, J;
+            block_of(idx, nb, I, J);
+            const int j = J * 16 + (lane & 15);
+            const int i0 = I * 16 + 4 * (lane >> 4);
+            out[(i0 + 0) * PP + j] = acc[q][0];
+            out[(i0 + 1) * PP + j] = acc[q][1];
+            out[(i0 + 2) * PP + j] = acc[q][2];
+            out[(i0 + 3) * PP + j] = acc[q][3];
+        }
+    }
+}
+
+int ne_grid(int V) {
+    int nchunks = (V + kNeRows - 1) / kNeRows;
+    return nchunks < 256 ? nchunks : 256;
+}
+
+void launch_normal_eq(hipStream_t s, const DevModel& m, int PP, int gram_mode, const float* dq,
+                      const float* xi, const uint32_t* anc_dev, CVec3Buf v, CVec3Buf n, CVec3Buf phi,
+                      const Accum& a, float* partials, int grid) {
+    int nchunks = (m.V + kNeRows - 1) / kNeRows;
+    if (gram_mode == 0)
+        hipLaunchKernelGGL(k_normal_eq<0>, dim3(grid), dim3(256), 0, s, m, PP, dq, xi, anc_dev, v, n, phi, a,
+                           partials, nchunks);
+    else if (gram_mode == 1)
+        hipLaunchKernelGGL(k_normal_eq<1>, dim3(grid), dim3(256), 0, s, m, PP, dq, xi, anc_dev, v, n, phi, a,
+                           partials, nchunks);
+    else
+        hipLaunchKernelGGL(k_normal_eq<2>, dim3(grid), dim3(256), 0, s, m, PP, dq, xi, anc_dev, v, n, phi, a,
+                           partials, nchunks);
+}
+
+// Sum of the partial Gram matrices in workgroup order, in float64; writes the
+// full symmetric matrix.  One thread per upper-triangle element.
+__global__ void __launch_bounds__(256) k_gram_reduce(int PP, int nparts, const float* __restrict__ partials,
+                                                     double* __restrict__ gram) {
+    const int nb = PP >> 4;
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    // element e of the upper blocks, in block order
+    int blk = e >> 8, w = e & 255;
+    int nbt = nb * (nb + 1) / 2;
+    if (blk >= nbt) return;
+    int I, J;
+    block_of(blk, nb, I, J);
+    int i = I * 16 + (w >> 4), j = J * 16 + (w & 15);
+    if (i > j) return;  // the upper triangle is summed and mirrored: exactly symmetric
+    double s = 0.0;
+    const float* p = partials + (size_t)i * PP + j;
+    const size_t stride = (size_t)PP * PP;
+    int q = 0;
+    for (; q + 4 <= nparts; q += 4) {
+        float a0 = p[(q + 0) * stride], a1 = p[(q + 1) * stride], a2 = p[(q + 2) * stride], a3 = p[(q + 3) * stride];
+        s += (double)a0; s += (double)a1; s += (double)a2; s += (double)a3;
+    }
+    for (; q < nparts; ++q) s += (double)p[q * stride];
+    gram[i * PP + j] = s;
+    gram[j * PP + i] = s;
+}
+
+void launch_gram_reduce(hipStream_t s, int PP, int nparts, const float* partials, double* gram) {
+    int nb = PP >> 4;
+    int n = nb * (nb + 1) / 2 * 256;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((n + 255) / 256), dim3(256), 0, s, PP, nparts, partials, gram);
+}
+
+}  // namespace trk
