@@ -2,11 +2,16 @@
 //
 // Vertices are projected into per-pixel buckets (a point-rasterised index
 // buffer kept as a counting sort) together with each bucket's z range (the
-// z-buffer).  Every valid pixel then searches rings of buckets around itself
-// for the nearest vertex closer than tau, stopping as soon as a lower bound on
-// the distance of anything in the next ring exceeds the best distance, so the
-// result equals the exhaustive nearest-vertex search.  The matched offsets are
-// summed per vertex in 64-bit fixed point (deterministic).
+// z-buffer).  Pixels are numbered tile by tile (8x8 tiles, row-major) and in
+// Morton order inside a tile, so the vertices of every 4x4-pixel quadrant
+// ("cell") are contiguous after the sort and each cell has one record
+// (offset, count, zmin, zmax).  Every valid pixel then finds the nearest
+// vertex closer than tau: cells are visited in rings around the pixel's tile
+// and skipped when a lower bound on the distance of anything inside them
+// (from the pixel distance to the cell, or from its z range) cannot beat the
+// best distance so far, so the result equals the exhaustive nearest-vertex
+// search.  The matched offsets are summed per vertex in 64-bit fixed point
+// (deterministic).
 //
 // Float32 decisions follow one operation order, compiled without contraction:
 //   point       x = ((u - cx) * d) / fx, y = ((v - cy) * d) / fy, z = d
@@ -19,8 +24,10 @@
 
 namespace trk {
 
+// pixel (u, v) -> its bucket: tile-major, Morton order inside the tile
 __device__ __forceinline__ int tile_pixel(const DevCam& c, int u, int v) {
-    return (((v >> 3) * c.tiles_x + (u >> 3)) << 6) + ((v & 7) << 3) + (u & 7);
+    const int m = (u & 1) | ((v & 1) << 1) | ((u & 2) << 1) | ((v & 2) << 2) | ((u & 4) << 2) | ((v & 4) << 3);
+    return (((v >> 3) * c.tiles_x + (u >> 3)) << 6) + m;
 }
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
@@ -51,10 +58,11 @@ void launch_clear(hipStream_t s, int npad, const Buckets& b, int V, const Accum&
 // bucket construction: count -> per-tile sums and z ranges -> tile prefix ->
 // per-pixel offsets -> scatter
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_bucket_count(DevCam c, int V, CVec3Buf v, Buckets b) {
+__global__ void __launch_bounds__(256) k_bucket_count(DevCam c, int V, const float4* __restrict__ v, Buckets b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= V) return;
-    float x = v.x[i], y = v.y[i], z = v.z[i];
+    const float4 p = v[i];
+    const float x = p.x, y = p.y, z = p.z;
     int pix = -1;
     if (z > kZNear) {
         float fu = floorf((c.fx * x) / z + c.cx + 0.5f);
@@ -120,7 +128,9 @@ __global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, Buckets b) {
     }
 }
 
-// per-pixel (offset, count, zmin, zmax); one wave per tile
+// per-pixel (offset, count, zmin, zmax), and per 4x4 cell (the 16
+// consecutive Morton positions of a tile quadrant) the same record; one wave
+// per tile
 __global__ void __launch_bounds__(256) k_pixel_offsets(int ntiles, Buckets b) {
     int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
@@ -132,19 +142,29 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(int ntiles, Buckets b) {
         uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
-    b.rec[p] = make_uint4(b.toff[tile] + incl - cnt, cnt, b.pzmin[p], b.pzmax[p]);
+    const uint32_t off = b.toff[tile] + incl - cnt;
+    const uint32_t zmn = b.pzmin[p], zmx = b.pzmax[p];
+    b.rec[p] = make_uint4(off, cnt, zmn, zmx);
+    uint32_t csum = cnt, cmn = zmn, cmx = zmx;
+    for (int o = 1; o < 16; o <<= 1) {
+        csum += __shfl_xor(csum, o);
+        cmn = min(cmn, (uint32_t)__shfl_xor((int)cmn, o));
+        cmx = max(cmx, (uint32_t)__shfl_xor((int)cmx, o));
+    }
+    if ((lane & 15) == 0) b.cellrec[(tile << 2) + (lane >> 4)] = make_uint4(off, csum, cmn, cmx);
 }
 
-__global__ void __launch_bounds__(256) k_bucket_scatter(int V, CVec3Buf v, Buckets b) {
+__global__ void __launch_bounds__(256) k_bucket_scatter(int V, const float4* __restrict__ v, Buckets b) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= V) return;
     int pix = b.vpix[i];
     if (pix < 0) return;
     uint32_t dst = b.rec[pix].x + b.vslot[i];
-    b.sorted[dst] = make_float4(v.x[i], v.y[i], v.z[i], __int_as_float(i));
+    const float4 p = v[i];
+    b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
 }
 
-void launch_bucket(hipStream_t s, const DevCam& c, int V, CVec3Buf v, const Buckets& b) {
+void launch_bucket(hipStream_t s, const DevCam& c, int V, const float4* v, const Buckets& b) {
     int ntiles = c.tiles_x * c.tiles_y;
     hipLaunchKernelGGL(k_bucket_count, dim3((V + 255) / 256), dim3(256), 0, s, c, V, v, b);
     hipLaunchKernelGGL(k_tile_reduce, dim3((ntiles + 3) / 4), dim3(256), 0, s, ntiles, b);
@@ -177,16 +197,24 @@ __device__ __forceinline__ bool z_pruned(float zmn, float zmx, float pz, float b
     return g2s > bound || (!found && g2s >= bound);
 }
 
+// One workgroup per 8x8 tile; its four waves hold the same 64 pixels (one per
+// lane) and split the 4x4 cells of each search ring between them.  A cell's
+// vertices are loaded coalesced (one per lane), broadcast through LDS and
+// compared against every lane's point; each lane keeps the key
+// (d2 bits << 32 | vertex id), whose minimum is the nearest vertex with ties
+// to the lower index.  The four waves' keys are combined with an LDS minimum.
 __global__ void __launch_bounds__(256) k_associate(DevCam c, float tau, const float* __restrict__ depth,
                                                    const float* __restrict__ xyz, Buckets b, Accum a,
-                                                   int32_t* __restrict__ assoc, DevStats* st) {
-    const int ntiles = c.tiles_x * c.tiles_y;
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
-    const int lane = wave_lane();
+                                                   const float4* __restrict__ verts, int32_t* __restrict__ assoc) {
+    __shared__ float4 scand[4][64];
+    __shared__ unsigned long long skey[64];
+    __shared__ int s_cnt[3];
+    const int lane = wave_lane(), wid = threadIdx.x >> 6;
+    const int tile = blockIdx.x;
     const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
     const int u = tx * 8 + (lane & 7), v = ty * 8 + (lane >> 3);
     const bool inimg = u < c.W && v < c.H;
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     bool valid = false;
     if (inimg) {
@@ -205,70 +233,119 @@ __global__ void __launch_bounds__(256) k_associate(DevCam c, float tau, const fl
         }
     }
     const float tau2 = tau * tau;
-    int best = -1;
-    float bd2 = tau2, bdx = 0.0f, bdy = 0.0f, bdz = 0.0f;
+    const uint32_t tau2_bits = __float_as_uint(tau2);
+    // key of the best candidate so far; an unmatched valid pixel holds
+    // (tau^2, 0), which no candidate at distance >= tau can undercut
+    unsigned long long key = valid ? ((unsigned long long)tau2_bits << 32) : ~0ull;
+    // pixel rings that can hold a vertex closer than tau (over-estimate is
+    // harmless), capped by the image; the wave's widest need sets the cells
+    int rmax = 0;
     if (valid) {
-        // rings that can hold a vertex closer than tau
-        int rmax = 0;
-        while (rmax < kRhoCap && ring_lb(c, pz, rmax + 1) < tau) ++rmax;
-        // whole-window test on the tile z ranges (cheap rejection of background)
-        int u0 = max(u - rmax, 0), u1 = min(u + rmax, c.W - 1);
-        int v0 = max(v - rmax, 0), v1 = min(v + rmax, c.H - 1);
-        bool any = false;
-        for (int ty2 = v0 >> 3; ty2 <= (v1 >> 3) && !any; ++ty2)
-            for (int tx2 = u0 >> 3; tx2 <= (u1 >> 3); ++tx2) {
-                float2 tz = b.tz[ty2 * c.tiles_x + tx2];
-                if (!z_pruned(tz.x, tz.y, pz, tau2, false)) { any = true; break; }
+        const int cap = max(c.W, c.H);
+        float mf = 0.501f + (tau / pz + 1e-6f) / c.lb_c1;
+        rmax = mf >= (float)cap ? cap : (int)mf + 1;
+    }
+    int rw = rmax;
+    for (int o = 32; o > 0; o >>= 1) rw = max(rw, __shfl_xor(rw, o));
+    const int Rc = (rw + 3) / 4 + 1;
+    bool done = !valid;
+    const int cells_x = 2 * c.tiles_x, cells_y = 2 * c.tiles_y;
+    // cheap rejection of background tiles: if no tile of the wave's window has
+    // a z range any lane could match within tau, nothing can be found
+    bool candidate_tiles = false;
+    if (__any(valid)) {
+        const int tr = (rw + 7) / 8;
+        for (int ty2 = max(ty - tr, 0); ty2 <= min(ty + tr, c.tiles_y - 1) && !candidate_tiles; ++ty2)
+            for (int tx2 = max(tx - tr, 0); tx2 <= min(tx + tr, c.tiles_x - 1); ++tx2) {
+                const int t2 = ty2 * c.tiles_x + tx2;
+                if (b.tsum[t2] == 0u) continue;
+                const float2 tz = b.tz[t2];
+                if (__any(valid && !z_pruned(tz.x, tz.y, pz, tau2, false))) { candidate_tiles = true; break; }
             }
-        if (any) {
-            for (int rho = 0; rho <= rmax; ++rho) {
-                const int nring = rho == 0 ? 1 : 8 * rho;
-                for (int q = 0; q < nring; ++q) {
-                    int uu, vv;
-                    if (rho == 0) { uu = u; vv = v; }
-                    else if (q < 2 * rho + 1) { uu = u - rho + q; vv = v - rho; }
-                    else if (q < 4 * rho + 2) { uu = u - rho + (q - 2 * rho - 1); vv = v + rho; }
-                    else if (q < 6 * rho + 1) { uu = u - rho; vv = v - rho + 1 + (q - 4 * rho - 2); }
-                    else { uu = u + rho; vv = v - rho + 1 + (q - 6 * rho - 1); }
-                    if (uu < 0 || vv < 0 || uu >= c.W || vv >= c.H) continue;
-                    uint4 r = b.rec[tile_pixel(c, uu, vv)];
-                    if (r.y == 0u) continue;
-                    if (z_pruned(__uint_as_float(r.z), __uint_as_float(r.w), pz, bd2, best >= 0)) continue;
-                    for (uint32_t e = r.x; e < r.x + r.y; ++e) {
-                        float4 s = b.sorted[e];
-                        float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
-                        float d2 = (dx * dx + dy * dy) + dz * dz;
-                        int id = __float_as_int(s.w);
-                        if (d2 < bd2 || (d2 == bd2 && best >= 0 && id < best)) {
-                            best = id; bd2 = d2; bdx = dx; bdy = dy; bdz = dz;
-                        }
-                    }
+    }
+    if (candidate_tiles) {
+        for (int R = 0; R <= Rc; ++R) {
+            // perimeter of the cell square [2tx - R, 2tx + 1 + R] x [2ty - R, 2ty + 1 + R]
+            const int side = 2 + 2 * R;
+            const int ncell = R == 0 ? 4 : 4 * side - 4;
+            const int x0 = 2 * tx - R, y0 = 2 * ty - R;
+            for (int q = wid; q < ncell; q += 4) {
+                int ccx, ccy;
+                if (R == 0) { ccx = x0 + (q & 1); ccy = y0 + (q >> 1); }
+                else if (q < side) { ccx = x0 + q; ccy = y0; }
+                else if (q < 2 * side) { ccx = x0 + (q - side); ccy = y0 + side - 1; }
+                else if (q < 3 * side - 2) { ccx = x0; ccy = y0 + 1 + (q - 2 * side); }
+                else { ccx = x0 + side - 1; ccy = y0 + 1 + (q - (3 * side - 2)); }
+                if (ccx < 0 || ccy < 0 || ccx >= cells_x || ccy >= cells_y) continue;
+                const uint4 cr = b.cellrec[(((ccy >> 1) * c.tiles_x + (ccx >> 1)) << 2) | ((ccy & 1) << 1) | (ccx & 1)];
+                if (cr.y == 0u) continue;
+                bool need = false;
+                if (!done) {
+                    const int X0 = ccx * 4, Y0 = ccy * 4;
+                    const int mx = max(max(X0 - u, u - (X0 + 3)), 0), my = max(max(Y0 - v, v - (Y0 + 3)), 0);
+                    const float bound = __uint_as_float((uint32_t)(key >> 32));
+                    const bool found = (uint32_t)(key >> 32) < tau2_bits;
+                    const float lb = ring_lb(c, pz, max(mx, my));
+                    need = !(lb * lb >= bound) &&
+                           !z_pruned(__uint_as_float(cr.z), __uint_as_float(cr.w), pz, bound, found);
                 }
-                float lb = ring_lb(c, pz, rho + 1);
-                if (lb * lb >= bd2) break;
+                if (!__any(need)) continue;
+                for (uint32_t base = 0; base < cr.y; base += 64) {
+                    const int n = min(64u, cr.y - base);
+                    if (lane < n) scand[wid][lane] = b.sorted[cr.x + base + lane];
+                    __builtin_amdgcn_wave_barrier();
+                    for (int k = 0; k < n; ++k) {
+                        const float4 s = scand[wid][k];
+                        const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+                        const float d2 = (dx * dx + dy * dy) + dz * dz;
+                        const unsigned long long kk =
+                            ((unsigned long long)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(s.w);
+                        if (need && kk < key) key = kk;
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                }
             }
+            // every cell outside the square is at least m_next pixels away
+            if (!done) {
+                const int X0b = (2 * tx - R) * 4, X1b = (2 * tx + 2 + R) * 4 - 1;
+                const int Y0b = (2 * ty - R) * 4, Y1b = (2 * ty + 2 + R) * 4 - 1;
+                const int m_next = min(min(u - X0b, X1b - u), min(v - Y0b, Y1b - v)) + 1;
+                const float lb = ring_lb(c, pz, m_next);
+                done = lb * lb >= __uint_as_float((uint32_t)(key >> 32));
+            }
+            if (__all(done)) break;
         }
-        if (best >= 0) {
-            uint32_t old = atomicAdd(&a.cnt[best], 1u);
-            atomicAdd((unsigned long long*)&a.sx[best], (unsigned long long)(long long)rintf(-bdx * 4294967296.0f));
-            atomicAdd((unsigned long long*)&a.sy[best], (unsigned long long)(long long)rintf(-bdy * 4294967296.0f));
-            atomicAdd((unsigned long long*)&a.sz[best], (unsigned long long)(long long)rintf(-bdz * 4294967296.0f));
-            if (old == 0u) atomicAdd(&st->n_obs_verts, 1);
-        }
+    }
+    // combine the four waves' keys
+    if (wid == 0) skey[lane] = key;
+    __syncthreads();
+    if (wid != 0 && valid) atomicMin(&skey[lane], key);
+    __syncthreads();
+    if (wid != 0) return;
+    key = skey[lane];
+    int best = -1;
+    bool first = false;
+    if (valid && (uint32_t)(key >> 32) < tau2_bits) {
+        best = (int)(uint32_t)key;
+        const float4 s = verts[best];
+        const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
+        uint32_t old = atomicAdd(&a.cnt[best], 1u);
+        atomicAdd((unsigned long long*)&a.sx[best], (unsigned long long)(long long)rintf(-dx * 4294967296.0f));
+        atomicAdd((unsigned long long*)&a.sy[best], (unsigned long long)(long long)rintf(-dy * 4294967296.0f));
+        atomicAdd((unsigned long long*)&a.sz[best], (unsigned long long)(long long)rintf(-dz * 4294967296.0f));
+        first = old == 0u;
     }
     if (inimg) assoc[v * c.W + u] = best;
-    unsigned long long vb = __ballot(valid), ab = __ballot(best >= 0);
-    if (lane == 0) {
-        if (vb) atomicAdd(&st->n_valid_px, __popcll(vb));
-        if (ab) atomicAdd(&st->n_assoc_px, __popcll(ab));
-    }
+    // per-workgroup counts go to this workgroup's own slot (no shared counter:
+    // device-wide atomics on one address serialise across the chip)
+    const unsigned long long vb = __ballot(valid), ab = __ballot(best >= 0), fb = __ballot(first);
+    if (lane == 0) b.bstat[blockIdx.x] = make_int4(__popcll(vb), __popcll(ab), __popcll(fb), 0);
 }
 
 void launch_associate(hipStream_t s, const DevCam& c, float tau, const float* depth, const float* xyz,
-                      const Buckets& b, const Accum& a, int32_t* assoc, DevStats* st) {
-    int ntiles = c.tiles_x * c.tiles_y;
-    hipLaunchKernelGGL(k_associate, dim3((ntiles + 3) / 4), dim3(256), 0, s, c, tau, depth, xyz, b, a,
-                       assoc, st);
+                      const Buckets& b, const Accum& a, const float4* verts, int32_t* assoc) {
+    hipLaunchKernelGGL(k_associate, dim3(c.tiles_x * c.tiles_y), dim3(256), 0, s, c, tau, depth, xyz, b, a, verts,
+                       assoc);
 }
 
 }  // namespace trk

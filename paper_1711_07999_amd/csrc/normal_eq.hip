@@ -42,7 +42,7 @@ __device__ __forceinline__ void block_of(int idx, int nb, int& I, int& J) {
 }
 
 // per-vertex 6-vectors of the Jacobian (one per influence) and the residual
-__device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq, int i, CVec3Buf v,
+__device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq, int i, const float4* v,
                                              CVec3Buf n, CVec3Buf phi, const Accum& a, float* G,
                                              float& r_out) {
     float H[8], sg[4];
@@ -50,7 +50,8 @@ __device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq
     const uint32_t lk = m.links[i];
     dq_blend(sdq, w, lk, H, sg);
     const float nx = n.x[i], ny = n.y[i], nz = n.z[i];
-    const float vx = v.x[i], vy = v.y[i], vz = v.z[i];
+    const float4 vi = v[i];
+    const float vx = vi.x, vy = vi.y, vz = vi.z;
     const float x[4] = {0.0f, m.rx[i] + phi.x[i], m.ry[i] + phi.y[i], m.rz[i] + phi.z[i]};
     const float nq[4] = {0.0f, nx, ny, nz};
     const float N = H[0] * H[0] + H[1] * H[1] + H[2] * H[2] + H[3] * H[3];
@@ -99,7 +100,7 @@ __device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq
 template <int MODE>
 __global__ void __launch_bounds__(256) k_normal_eq(DevModel m, int PP, const float* __restrict__ dq,
                                                    const float* __restrict__ xi,
-                                                   const uint32_t* __restrict__ anc, CVec3Buf v, CVec3Buf n,
+                                                   const uint32_t* __restrict__ anc, const float4* __restrict__ v, CVec3Buf n,
                                                    CVec3Buf phi, Accum a, float* __restrict__ partials,
                                                    int nchunks) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
@@ -257,7 +258,7 @@ int ne_grid(int V) {
 }
 
 void launch_normal_eq(hipStream_t s, const DevModel& m, int PP, int gram_mode, const float* dq,
-                      const float* xi, const uint32_t* anc_dev, CVec3Buf v, CVec3Buf n, CVec3Buf phi,
+                      const float* xi, const uint32_t* anc_dev, const float4* v, CVec3Buf n, CVec3Buf phi,
                       const Accum& a, float* partials, int grid) {
     int nchunks = (m.V + kNeRows - 1) / kNeRows;
     if (gram_mode == 0)
@@ -272,36 +273,48 @@ void launch_normal_eq(hipStream_t s, const DevModel& m, int PP, int gram_mode, c
 }
 
 // Sum of the partial Gram matrices in workgroup order, in float64; writes the
-// full symmetric matrix.  One thread per upper-triangle element.
+// full symmetric matrix (the upper triangle is summed and mirrored, so the
+// result is exactly symmetric).  A workgroup handles 32 elements of one
+// 16x16 block; each element's partials are split into 8 contiguous groups
+// summed by 8 threads, and the 8 group sums are added in group order.
 __global__ void __launch_bounds__(256) k_gram_reduce(int PP, int nparts, const float* __restrict__ partials,
                                                      double* __restrict__ gram) {
+    __shared__ double part[8][32];
     const int nb = PP >> 4;
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    // element e of the upper blocks, in block order
-    int blk = e >> 8, w = e & 255;
-    int nbt = nb * (nb + 1) / 2;
-    if (blk >= nbt) return;
+    const int blk = blockIdx.x >> 3;          // 8 workgroups per 16x16 block
+    const int el = (blockIdx.x & 7) * 32 + (threadIdx.x & 31);
+    const int grp = threadIdx.x >> 5;
     int I, J;
     block_of(blk, nb, I, J);
-    int i = I * 16 + (w >> 4), j = J * 16 + (w & 15);
-    if (i > j) return;  // the upper triangle is summed and mirrored: exactly symmetric
-    double s = 0.0;
-    const float* p = partials + (size_t)i * PP + j;
+    const int i = I * 16 + (el >> 4), j = J * 16 + (el & 15);
     const size_t stride = (size_t)PP * PP;
-    int q = 0;
-    for (; q + 4 <= nparts; q += 4) {
-        float a0 = p[(q + 0) * stride], a1 = p[(q + 1) * stride], a2 = p[(q + 2) * stride], a3 = p[(q + 3) * stride];
-        s += (double)a0; s += (double)a1; s += (double)a2; s += (double)a3;
+    const int per = (nparts + 7) / 8;
+    const int q0 = grp * per, q1 = min(nparts, q0 + per);
+    const float* p = partials + (size_t)i * PP + j;
+    double s = 0.0;
+    int q = q0;
+    for (; q + 8 <= q1; q += 8) {
+        float a[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) a[t] = p[(size_t)(q + t) * stride];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) s += (double)a[t];
     }
-    for (; q < nparts; ++q) s += (double)p[q * stride];
-    gram[i * PP + j] = s;
-    gram[j * PP + i] = s;
+    for (; q < q1; ++q) s += (double)p[(size_t)q * stride];
+    part[grp][threadIdx.x & 31] = s;
+    __syncthreads();
+    if (grp == 0 && i <= j) {
+        double tot = 0.0;
+        for (int g = 0; g < 8; ++g) tot += part[g][threadIdx.x & 31];
+        gram[i * PP + j] = tot;
+        gram[j * PP + i] = tot;
+    }
 }
 
 void launch_gram_reduce(hipStream_t s, int PP, int nparts, const float* partials, double* gram) {
     int nb = PP >> 4;
-    int n = nb * (nb + 1) / 2 * 256;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((n + 255) / 256), dim3(256), 0, s, PP, nparts, partials, gram);
+    int nblocks = nb * (nb + 1) / 2 * 8;
+    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks), dim3(256), 0, s, PP, nparts, partials, gram);
 }
 
 }  // namespace trk

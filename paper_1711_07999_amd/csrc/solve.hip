@@ -8,89 +8,193 @@ namespace trk {
 // ---------------------------------------------------------------------------
 // Damped least squares (Marquardt): (A + lambda_k diag(A)) x = b with
 // A = J^T J + (lambda_s S)^2 and b = J^T r + (lambda_s S)^2 Theta, solved by
-// Cholesky in one workgroup; Theta <- Theta - x.  Parameters with A_kk == 0
-// (no observed vertex moves them) or marked inactive are frozen (x_k = 0).
-// A failed factorisation leaves Theta unchanged and flags the frame.  The
-// same workgroup then runs forward kinematics at the new pose.
+// Cholesky; Theta <- Theta - x.  Parameters with A_kk == 0 (no observed vertex
+// moves them) or marked inactive are frozen (x_k = 0).  A failed
+// factorisation leaves Theta unchanged and flags the frame.
+//
+// Blocked right-looking Cholesky in one workgroup: the matrix (padded to a
+// multiple of 8 with identity rows) is split into 8x8 blocks, thread (i, j)
+// of a 16x16 grid holds block (i, j) in registers.  For each 8-column panel:
+// the diagonal block is factored by its thread, the blocks below are solved
+// against it, and the trailing blocks take the rank-8 update, with the panel
+// exchanged through LDS -- three barriers per panel.  The right-hand side is
+// carried along (forward substitution) and back substitution runs panel by
+// panel.  The same workgroup then runs forward kinematics at the new pose.
 // ---------------------------------------------------------------------------
+constexpr int kBS = 8;                    // block size
+constexpr int kNBMax = (kMaxJoints + 1) / kBS;  // 16 blocks per side
+constexpr int kPanelStride = kBS * kBS + 1;
+
 template <class T>
 __global__ void __launch_bounds__(256) k_pose_solve(const JointTable* __restrict__ jt, int PP,
                                                     const double* __restrict__ gram, float lambda_k,
                                                     double* __restrict__ theta, double* __restrict__ step,
                                                     DevStats* st, int iter, float* dq, float* xi) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    // L blocks of the current panel column; block stride kBS*kBS + 1 keeps the
+    // 16 column-block reads of a wave on distinct LDS banks
+    __shared__ T s_panel[kNBMax * kPanelStride];
+    __shared__ T s_y[kNBMax * kBS];           // right-hand side -> z -> x
+    __shared__ T s_inv[kNBMax * kBS];         // 1 / L_jj: one division per column
+    __shared__ int s_frozen[kNBMax * kBS];
+    __shared__ int s_fail;
+    __shared__ double s_nrm[256];
     const int P = jt->P;
-    T* M = reinterpret_cast<T*>(smem);       // [P][P] row-major, lower triangle used
-    T* y = M + P * P;                         // [P]
-    __shared__ int frozen[kMaxJoints + 1];
-    __shared__ int fail;
+    const int NB = (P + kBS - 1) / kBS;
     const int tid = threadIdx.x;
-    if (tid == 0) fail = 0;
-    for (int k = tid; k < P; k += 256) {
-        double akk = gram[k * PP + k] + jt->prior[k];
-        frozen[k] = (akk == 0.0) || !jt->active[k];
+    const int bi = tid >> 4, bj = tid & 15;
+    const bool mine = bi < NB && bj <= bi;
+    if (tid == 0) s_fail = 0;
+    for (int k = tid; k < NB * kBS; k += 256) {
+        int fz = 1;
+        T yk = T(0);
+        if (k < P) {
+            const double pr = jt->prior[k];
+            fz = (gram[k * PP + k] + pr == 0.0) || !jt->active[k];
+            yk = fz ? T(0) : T(gram[k * PP + P] + pr * theta[k]);
+        }
+        s_frozen[k] = fz;
+        s_y[k] = yk;
     }
     __syncthreads();
-    for (int e = tid; e < P * P; e += 256) {
-        int k = e / P, q = e - k * P;
-        double a = gram[k * PP + q] + (k == q ? jt->prior[k] : 0.0);
-        T val;
-        if (k == q) val = frozen[k] ? T(1) : T(a * (1.0 + (double)lambda_k));
-        else val = (frozen[k] || frozen[q]) ? T(0) : T(a);
-        M[e] = val;
-    }
-    for (int k = tid; k < P; k += 256)
-        y[k] = frozen[k] ? T(0) : T(gram[k * PP + P] + jt->prior[k] * theta[k]);
-    __syncthreads();
-    // right-looking Cholesky, M = L L^T in the lower triangle
-    for (int j = 0; j < P; ++j) {
-        if (tid == 0) {
-            T d = M[j * P + j];
-            if (!(d > T(0))) fail = 1;
-            else M[j * P + j] = sqrt(d);
+    // this thread's block of the damped, frozen and padded matrix
+    T a[kBS][kBS];
+#pragma unroll
+    for (int r = 0; r < kBS; ++r)
+#pragma unroll
+        for (int c = 0; c < kBS; ++c) {
+            const int i = bi * kBS + r, j = bj * kBS + c;
+            T val = T(0);
+            if (mine) {
+                if (i == j) {
+                    val = (i >= P || s_frozen[i]) ? T(1)
+                                                  : T((gram[i * PP + i] + jt->prior[i]) * (1.0 + (double)lambda_k));
+                } else if (i < P && j < P && !s_frozen[i] && !s_frozen[j]) {
+                    val = T(gram[i * PP + j]);
+                }
+            }
+            a[r][c] = val;
+        }
+    for (int p = 0; p < NB; ++p) {
+        // (1) factor the diagonal block; forward-solve its part of y
+        if (bi == p && bj == p) {
+            bool ok = true;
+#pragma unroll
+            for (int j = 0; j < kBS; ++j) {
+                const T d = a[j][j];
+                ok = ok && (d > T(0));
+                const T s = ok ? sqrt(d) : T(1);
+                const T inv = T(1) / s;
+                a[j][j] = s;
+                s_inv[p * kBS + j] = inv;
+#pragma unroll
+                for (int i = j + 1; i < kBS; ++i) a[i][j] *= inv;
+#pragma unroll
+                for (int i = j + 1; i < kBS; ++i)
+#pragma unroll
+                    for (int k = j + 1; k <= i; ++k) a[i][k] -= a[i][j] * a[k][j];
+            }
+            T z[kBS];
+#pragma unroll
+            for (int r = 0; r < kBS; ++r) z[r] = s_y[p * kBS + r];
+#pragma unroll
+            for (int j = 0; j < kBS; ++j) {
+                z[j] *= s_inv[p * kBS + j];
+#pragma unroll
+                for (int i = j + 1; i < kBS; ++i) z[i] -= a[i][j] * z[j];
+            }
+#pragma unroll
+            for (int r = 0; r < kBS; ++r) {
+                s_y[p * kBS + r] = z[r];
+#pragma unroll
+                for (int c = 0; c < kBS; ++c) s_panel[p * kPanelStride + r * kBS + c] = a[r][c];
+            }
+            if (!ok) s_fail = 1;
         }
         __syncthreads();
-        if (fail) break;
-        const T djj = M[j * P + j];
-        for (int i = j + 1 + tid; i < P; i += 256) M[i * P + j] /= djj;
+        if (s_fail) break;
+        // (2) blocks below the diagonal: X L_pp^T = A_ip; update y_i
+        if (bj == p && bi > p && bi < NB) {
+#pragma unroll
+            for (int r = 0; r < kBS; ++r) {
+#pragma unroll
+                for (int j = 0; j < kBS; ++j) {
+                    T t = a[r][j];
+#pragma unroll
+                    for (int k = 0; k < j; ++k) t -= a[r][k] * s_panel[p * kPanelStride + j * kBS + k];
+                    a[r][j] = t * s_inv[p * kBS + j];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kBS; ++r) {
+                T t = s_y[bi * kBS + r];
+#pragma unroll
+                for (int j = 0; j < kBS; ++j) {
+                    t -= a[r][j] * s_y[p * kBS + j];
+                    s_panel[bi * kPanelStride + r * kBS + j] = a[r][j];
+                }
+                s_y[bi * kBS + r] = t;
+            }
+        }
         __syncthreads();
-        const int nrem = P - j - 1;
-        for (int e = tid; e < nrem * nrem; e += 256) {
-            int ii = e / nrem, kk = e - ii * nrem;
-            if (kk <= ii) {
-                int i = j + 1 + ii, k = j + 1 + kk;
-                M[i * P + k] -= M[i * P + j] * M[k * P + j];
+        // (3) trailing update A_ij -= L_ip L_jp^T for p < j <= i
+        if (mine && bj > p) {
+#pragma unroll
+            for (int k = 0; k < kBS; ++k) {
+                T li[kBS], lj[kBS];
+#pragma unroll
+                for (int r = 0; r < kBS; ++r) {
+                    li[r] = s_panel[bi * kPanelStride + r * kBS + k];
+                    lj[r] = s_panel[bj * kPanelStride + r * kBS + k];
+                }
+#pragma unroll
+                for (int r = 0; r < kBS; ++r)
+#pragma unroll
+                    for (int c = 0; c < kBS; ++c) a[r][c] -= li[r] * lj[c];
             }
         }
         __syncthreads();
     }
+    const bool fail = s_fail != 0;
     if (!fail) {
-        // L z = b, then L^T x = z
-        for (int j = 0; j < P; ++j) {
-            if (tid == 0) y[j] /= M[j * P + j];
+        // back substitution L^T x = z, panel by panel from the last
+        for (int p = NB - 1; p >= 0; --p) {
+            if (bi == p && bj == p) {
+                T x[kBS];
+#pragma unroll
+                for (int r = 0; r < kBS; ++r) x[r] = s_y[p * kBS + r];
+#pragma unroll
+                for (int j = kBS - 1; j >= 0; --j) {
+                    x[j] *= s_inv[p * kBS + j];
+#pragma unroll
+                    for (int i = 0; i < j; ++i) x[i] -= a[j][i] * x[j];
+                }
+#pragma unroll
+                for (int r = 0; r < kBS; ++r) s_y[p * kBS + r] = x[r];
+            }
             __syncthreads();
-            for (int i = j + 1 + tid; i < P; i += 256) y[i] -= M[i * P + j] * y[j];
+            if (bi == p && bj < p) {
+#pragma unroll
+                for (int c = 0; c < kBS; ++c) {
+                    T t = s_y[bj * kBS + c];
+#pragma unroll
+                    for (int r = 0; r < kBS; ++r) t -= a[r][c] * s_y[p * kBS + r];
+                    s_y[bj * kBS + c] = t;
+                }
+            }
             __syncthreads();
         }
-        for (int j = P - 1; j >= 0; --j) {
-            if (tid == 0) y[j] /= M[j * P + j];
-            __syncthreads();
-            for (int i = tid; i < j; i += 256) y[i] -= M[j * P + i] * y[j];
-            __syncthreads();
-        }
-        __shared__ double nrm[256];
         double part = 0.0;
         for (int k = tid; k < P; k += 256) {
-            double x = frozen[k] ? 0.0 : (double)y[k];
+            const double x = s_frozen[k] ? 0.0 : (double)s_y[k];
             step[k] = x;
             theta[k] -= x;
             part += x * x;
         }
-        nrm[tid] = part;
+        s_nrm[tid] = part;
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
-            for (int q = 0; q < 256; ++q) s += nrm[q];
+            for (int q = 0; q < 256; ++q) s += s_nrm[q];
             st->step_norm[iter] = (float)sqrt(s);
             st->energy[iter] = (float)gram[P * PP + P];
         }
@@ -105,16 +209,12 @@ __global__ void __launch_bounds__(256) k_pose_solve(const JointTable* __restrict
 
 void launch_pose_solve(hipStream_t s, const JointTable* jt, int PP, const double* gram, float lambda_k,
                        int fp64, double* theta, double* step, DevStats* st, int iter, float* dq, float* xi) {
-    int P = PP;  // upper bound on P for the LDS size
-    if (fp64) {
-        size_t sh = (size_t)(P * P + P) * sizeof(double);
-        hipLaunchKernelGGL(k_pose_solve<double>, dim3(1), dim3(256), sh, s, jt, PP, gram, lambda_k, theta, step,
-                           st, iter, dq, xi);
-    } else {
-        size_t sh = (size_t)(P * P + P) * sizeof(float);
-        hipLaunchKernelGGL(k_pose_solve<float>, dim3(1), dim3(256), sh, s, jt, PP, gram, lambda_k, theta, step,
-                           st, iter, dq, xi);
-    }
+    if (fp64)
+        hipLaunchKernelGGL(k_pose_solve<double>, dim3(1), dim3(256), 0, s, jt, PP, gram, lambda_k, theta, step, st,
+                           iter, dq, xi);
+    else
+        hipLaunchKernelGGL(k_pose_solve<float>, dim3(1), dim3(256), 0, s, jt, PP, gram, lambda_k, theta, step, st,
+                           iter, dq, xi);
 }
 
 // ---------------------------------------------------------------------------
@@ -142,8 +242,8 @@ __device__ __forceinline__ void solve3(const T M[9], const T g[3], T x[3]) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_shape(DevModel m, const float* __restrict__ dq, CVec3Buf v_old,
-                                               CVec3Buf v_new, CVec3Buf n, Accum a, CVec3Buf phi,
+__global__ void __launch_bounds__(256) k_shape(DevModel m, const float* __restrict__ dq, const float4* __restrict__ v_old,
+                                               const float4* __restrict__ v_new, CVec3Buf n, Accum a, CVec3Buf phi,
                                                CVec3Buf phi_prev, Vec3Buf phi_out, float lphi, float lnbr,
                                                float lt, float lw) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
@@ -166,9 +266,10 @@ __global__ void __launch_bounds__(256) k_shape(DevModel m, const float* __restri
                   s * (x * z - w * y), s * (y * z + w * x), T(1) - s * (x * x + y * y)};
         for (int q = 0; q < 3; ++q) u[q] = -(R[q] * nx + R[3 + q] * ny + R[6 + q] * nz);
         const T inv = T(1) / ((T)c * T(4294967296.0));
-        T dx = (T)a.sx[i] * inv + ((T)v_old.x[i] - (T)v_new.x[i]);
-        T dy = (T)a.sy[i] * inv + ((T)v_old.y[i] - (T)v_new.y[i]);
-        T dz = (T)a.sz[i] * inv + ((T)v_old.z[i] - (T)v_new.z[i]);
+        const float4 vo = v_old[i], vn = v_new[i];
+        T dx = (T)a.sx[i] * inv + ((T)vo.x - (T)vn.x);
+        T dy = (T)a.sy[i] * inv + ((T)vo.y - (T)vn.y);
+        T dz = (T)a.sz[i] * inv + ((T)vo.z - (T)vn.z);
         r = (T)nx * dx + (T)ny * dy + (T)nz * dz;
     }
     T alpha = (T)lphi + (T)lt;
@@ -197,7 +298,7 @@ __global__ void __launch_bounds__(256) k_shape(DevModel m, const float* __restri
     phi_out.z[i] = (float)(pz - xs[2]);
 }
 
-void launch_shape(hipStream_t s, const DevModel& m, const float* dq, CVec3Buf v_old, CVec3Buf v_new,
+void launch_shape(hipStream_t s, const DevModel& m, const float* dq, const float4* v_old, const float4* v_new,
                   CVec3Buf n, const Accum& a, CVec3Buf phi, CVec3Buf phi_prev, Vec3Buf phi_out,
                   float lphi, float lnbr, float lt, float lw, int fp64) {
     int grid = (m.V + 255) / 256;

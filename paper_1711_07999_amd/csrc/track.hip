@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -45,6 +46,17 @@ void hdq_mul(const double* a, const double* b, double* o) {
     for (int c = 0; c < 4; ++c) { o[c] = r[c]; o[4 + c] = d1[c] + d2[c]; }
 }
 
+// A captured frame: the kernel sequence depends on which ping-pong buffers
+// are current when the frame starts, so graphs are cached per starting state.
+struct FrameGraph {
+    int v0, p0, s0, mode;       // key: vertex buffer, offset buffer, surface valid, input kind
+    unsigned tmask;             // key: kernels timed with events inside the graph
+    int v1, p1, s1;             // state after the frame
+    hipGraphExec_t exec;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> tev;  // (kernel, start/stop)
+    hipEvent_t pending[TRACK_K_COUNT_];
+};
+
 struct KernelTimer {
     bool on = false;
     std::vector<hipEvent_t> ev;  // pairs
@@ -78,7 +90,8 @@ struct track_ctx {
     double *theta = nullptr, *theta_backup = nullptr, *step = nullptr, *gram = nullptr;
     float *dq = nullptr, *xi = nullptr, *partials = nullptr, *depth_buf = nullptr, *xyz_buf = nullptr;
     uint32_t* anc = nullptr;
-    Vec3Buf phi[2]{}, phi_prev{}, verts[2]{}, normals{};
+    Vec3Buf phi[2]{}, phi_prev{}, normals{};
+    float4* verts[2]{};
     int phi_cur = 0, v_cur = 0;
     bool surface_valid = false;
     int input_mode = 0;  // 0 depth, 1 xyz (for the per-pass interface)
@@ -88,9 +101,15 @@ struct track_ctx {
     DevStats* dstats = nullptr;
     DevStats* hstats = nullptr;  // pinned
     double* htheta = nullptr;    // pinned
+    int4* hbstat = nullptr;      // pinned, per association workgroup
+    int nassoc = 0;              // association workgroups
     track_frame_stats last{};
     hipEvent_t f0 = nullptr, f1 = nullptr;
     KernelTimer timers[TRACK_K_COUNT_];
+    bool use_graphs = true;
+    std::vector<FrameGraph> graphs;
+    FrameGraph* capturing = nullptr;  // graph under construction
+    int last_graph = -1;              // graph launched by the last frame, -1 = none
 };
 
 namespace {
@@ -103,9 +122,17 @@ T* carve(track_ctx* c, size_t n) {
     return p;
 }
 
+void drop_graphs(track_ctx* c);
+
 void timed_begin(track_ctx* c, int k) {
     KernelTimer& t = c->timers[k];
     if (!t.on) return;
+    if (c->capturing) {  // events of a captured frame belong to its graph
+        hipEvent_t e;
+        if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess) c->capturing->pending[k] = e;
+        else c->capturing->pending[k] = nullptr;
+        return;
+    }
     if (t.used + 2 > t.ev.size()) {
         for (int q = 0; q < 64; ++q) {
             hipEvent_t e;
@@ -116,7 +143,15 @@ void timed_begin(track_ctx* c, int k) {
 }
 void timed_end(track_ctx* c, int k) {
     KernelTimer& t = c->timers[k];
-    if (!t.on || t.used + 2 > t.ev.size()) return;
+    if (!t.on) return;
+    if (c->capturing) {
+        hipEvent_t e;
+        hipEvent_t b = c->capturing->pending[k];
+        if (b && hipEventCreate(&e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess)
+            c->capturing->tev.push_back({k, {b, e}});
+        return;
+    }
+    if (t.used + 2 > t.ev.size()) return;
     (void)hipEventRecord(t.ev[t.used + 1], c->stream);
     t.used += 2;
 }
@@ -131,6 +166,16 @@ void timed_collect(track_ctx* c) {
             }
         }
         t.used = 0;
+    }
+    if (c->last_graph >= 0) {
+        for (auto& te : c->graphs[c->last_graph].tev) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, te.second.first, te.second.second) == hipSuccess) {
+                c->timers[te.first].total_ms += ms;
+                c->timers[te.first].launches += 1;
+            }
+        }
+        c->last_graph = -1;
     }
 }
 
@@ -197,6 +242,7 @@ int set_params(track_ctx* c, const track_params* p) {
     c->lambda_k = p->lambda_k; c->lambda_s = p->lambda_s; c->lambda_phi = p->lambda_phi;
     c->lambda_nbr = p->lambda_nbr; c->lambda_t = p->lambda_t; c->lambda_w = p->lambda_w;
     c->gram_mode = p->gram_mode;
+    drop_graphs(c);
     c->pose_fp64 = p->pose_solve_fp64 ? 1 : 0;
     c->shape_fp64 = p->shape_solve_fp64 ? 1 : 0;
     for (int k = 0; k < c->P; ++k) {
@@ -318,7 +364,7 @@ void ensure_surface(track_ctx* c) {
     launch_skin(c->stream, c->dm, c->dq, cview(c->phi[c->phi_cur]), c->verts[c->v_cur]);
     timed_end(c, TRACK_K_SKIN);
     timed_begin(c, TRACK_K_NORMALS);
-    launch_normals(c->stream, c->dm, cview(c->verts[c->v_cur]), c->normals);
+    launch_normals(c->stream, c->dm, c->verts[c->v_cur], c->normals);
     timed_end(c, TRACK_K_NORMALS);
     c->surface_valid = true;
 }
@@ -326,16 +372,16 @@ void ensure_surface(track_ctx* c) {
 void pass_associate(track_ctx* c, const float* depth, const float* xyz) {
     timed_begin(c, TRACK_K_BUCKET);
     launch_clear(c->stream, c->npad, c->bk, c->V, c->acc, c->dstats);
-    launch_bucket(c->stream, c->dc, c->V, cview(c->verts[c->v_cur]), c->bk);
+    launch_bucket(c->stream, c->dc, c->V, c->verts[c->v_cur], c->bk);
     timed_end(c, TRACK_K_BUCKET);
     timed_begin(c, TRACK_K_ASSOC);
-    launch_associate(c->stream, c->dc, c->tau, depth, xyz, c->bk, c->acc, c->assoc, c->dstats);
+    launch_associate(c->stream, c->dc, c->tau, depth, xyz, c->bk, c->acc, c->verts[c->v_cur], c->assoc);
     timed_end(c, TRACK_K_ASSOC);
 }
 
 void pass_normal_eq(track_ctx* c) {
     timed_begin(c, TRACK_K_NORMAL_EQ);
-    launch_normal_eq(c->stream, c->dm, c->PP, c->gram_mode, c->dq, c->xi, c->anc, cview(c->verts[c->v_cur]),
+    launch_normal_eq(c->stream, c->dm, c->PP, c->gram_mode, c->dq, c->xi, c->anc, c->verts[c->v_cur],
                      cview(c->normals), cview(c->phi[c->phi_cur]), c->acc, c->partials, c->negrid);
     timed_end(c, TRACK_K_NORMAL_EQ);
     launch_gram_reduce(c->stream, c->PP, c->negrid, c->partials, c->gram);
@@ -358,11 +404,11 @@ void pass_shape(track_ctx* c, bool reskin) {
         launch_skin(c->stream, c->dm, c->dq, cview(c->phi[c->phi_cur]), c->verts[vn]);
         timed_end(c, TRACK_K_SKIN);
         timed_begin(c, TRACK_K_NORMALS);
-        launch_normals(c->stream, c->dm, cview(c->verts[vn]), c->normals);
+        launch_normals(c->stream, c->dm, c->verts[vn], c->normals);
         timed_end(c, TRACK_K_NORMALS);
     }
     timed_begin(c, TRACK_K_SHAPE);
-    launch_shape(c->stream, c->dm, c->dq, cview(c->verts[vo]), cview(c->verts[vn]), cview(c->normals), c->acc,
+    launch_shape(c->stream, c->dm, c->dq, c->verts[vo], c->verts[vn], cview(c->normals), c->acc,
                  cview(c->phi[c->phi_cur]), cview(c->phi_prev), c->phi[c->phi_cur ^ 1], c->lambda_phi,
                  c->lambda_nbr, c->lambda_t, c->lambda_w, c->shape_fp64);
     timed_end(c, TRACK_K_SHAPE);
@@ -371,10 +417,25 @@ void pass_shape(track_ctx* c, bool reskin) {
     c->surface_valid = false;
 }
 
-int run_frame(track_ctx* c, const float* depth, const float* xyz) {
-    HIP_TRY(hipEventRecord(c->f0, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->theta_backup, c->theta, sizeof(double) * c->P, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemsetAsync(&c->dstats->status, 0, sizeof(int), c->stream));
+void drop_graphs(track_ctx* c) {
+    for (auto& g : c->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        for (auto& te : g.tev) { (void)hipEventDestroy(te.second.first); (void)hipEventDestroy(te.second.second); }
+    }
+    c->graphs.clear();
+    c->last_graph = -1;
+}
+
+unsigned timing_mask(const track_ctx* c) {
+    unsigned m = 0;
+    for (int k = 0; k < TRACK_K_COUNT_; ++k)
+        if (c->timers[k].on) m |= 1u << k;
+    return m;
+}
+
+// the kernels of one frame, issued on the context's stream
+void enqueue_frame(track_ctx* c, const float* depth, const float* xyz) {
+    launch_frame_begin(c->stream, c->P, c->theta, c->theta_backup, c->dstats);
     for (int t = 0; t < c->n_iters; ++t) {
         ensure_surface(c);
         pass_associate(c, depth, xyz);
@@ -391,14 +452,83 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
             ensure_surface(c);
         }
     }
+}
+
+// Issue one frame as a replay of a cached graph (the frame reads its input
+// from the context's own buffer); timing events, when enabled, are part of
+// the graph.  If capture is unavailable the kernels are launched directly.
+int launch_frame(track_ctx* c, const float* depth, const float* xyz) {
+    if (!c->use_graphs) {
+        enqueue_frame(c, depth, xyz);
+        return TRACK_OK;
+    }
+    const int mode = xyz ? 1 : 0;
+    const float* in = xyz ? xyz : depth;
+    float* buf = xyz ? c->xyz_buf : c->depth_buf;
+    const size_t bytes = sizeof(float) * (size_t)c->W * c->H * (xyz ? 3 : 1);
+    if (in != buf) HIP_TRY(hipMemcpyAsync(buf, in, bytes, hipMemcpyDeviceToDevice, c->stream));
+    const int s0 = c->surface_valid ? 1 : 0;
+    const unsigned tm = timing_mask(c);
+    for (size_t q = 0; q < c->graphs.size(); ++q) {
+        FrameGraph& g = c->graphs[q];
+        if (g.v0 == c->v_cur && g.p0 == c->phi_cur && g.s0 == s0 && g.mode == mode && g.tmask == tm) {
+            HIP_TRY(hipGraphLaunch(g.exec, c->stream));
+            c->v_cur = g.v1; c->phi_cur = g.p1; c->surface_valid = g.s1 != 0;
+            c->last_graph = (int)q;
+            return TRACK_OK;
+        }
+    }
+    FrameGraph g{c->v_cur, c->phi_cur, s0, mode, tm, 0, 0, 0, nullptr, {}, {}};
+    const int v0 = c->v_cur, p0 = c->phi_cur;
+    const bool sv0 = c->surface_valid;
+    hipGraph_t graph = nullptr;
+    c->capturing = &g;
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue_frame(c, xyz ? nullptr : c->depth_buf, xyz ? c->xyz_buf : nullptr);
+        e = hipStreamEndCapture(c->stream, &graph);
+    }
+    c->capturing = nullptr;
+    if (e == hipSuccess) {
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+    }
+    if (e != hipSuccess) {
+        // no graphs on this stream: restore the state and launch directly
+        (void)hipGetLastError();
+        for (auto& te : g.tev) { (void)hipEventDestroy(te.second.first); (void)hipEventDestroy(te.second.second); }
+        c->v_cur = v0; c->phi_cur = p0; c->surface_valid = sv0;
+        c->use_graphs = false;
+        enqueue_frame(c, depth, xyz);
+        return TRACK_OK;
+    }
+    g.v1 = c->v_cur; g.p1 = c->phi_cur; g.s1 = c->surface_valid ? 1 : 0;
+    c->graphs.push_back(g);
+    c->last_graph = (int)c->graphs.size() - 1;
+    HIP_TRY(hipGraphLaunch(c->graphs.back().exec, c->stream));
+    return TRACK_OK;
+}
+
+int run_frame(track_ctx* c, const float* depth, const float* xyz) {
+    HIP_TRY(hipEventRecord(c->f0, c->stream));
+    int rc = launch_frame(c, depth, xyz);
+    if (rc) return rc;
     HIP_TRY(hipEventRecord(c->f1, c->stream));
     HIP_TRY(hipMemcpyAsync(c->hstats, c->dstats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->hbstat, c->bk.bstat, sizeof(int4) * c->nassoc, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(c->htheta, c->theta, sizeof(double) * c->P, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     timed_collect(c);
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, c->f0, c->f1);
-    const DevStats& s = *c->hstats;
+    DevStats& s = *c->hstats;
+    // counts of the last association, summed over its workgroups
+    s.n_valid_px = s.n_assoc_px = s.n_obs_verts = 0;
+    for (int q = 0; q < c->nassoc; ++q) {
+        s.n_valid_px += c->hbstat[q].x;
+        s.n_assoc_px += c->hbstat[q].y;
+        s.n_obs_verts += c->hbstat[q].z;
+    }
     track_frame_stats fs{};
     fs.n_valid_px = s.n_valid_px;
     fs.n_assoc_px = s.n_assoc_px;
@@ -456,8 +586,23 @@ int download_soa(const track_ctx* c, Vec3Buf src, float* aos) {
     return TRACK_OK;
 }
 
+int upload_v4(track_ctx* c, float4* dst, const float* aos) {
+    std::vector<float4> t(c->V);
+    for (int i = 0; i < c->V; ++i) t[i] = make_float4(aos[3 * i], aos[3 * i + 1], aos[3 * i + 2], 0.0f);
+    HIP_TRY(hipMemcpy(dst, t.data(), sizeof(float4) * c->V, hipMemcpyHostToDevice));
+    return TRACK_OK;
+}
+
+int download_v4(const track_ctx* c, const float4* src, float* aos) {
+    std::vector<float4> t(c->V);
+    HIP_TRY(hipMemcpy(t.data(), src, sizeof(float4) * c->V, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c->V; ++i) { aos[3 * i] = t[i].x; aos[3 * i + 1] = t[i].y; aos[3 * i + 2] = t[i].z; }
+    return TRACK_OK;
+}
+
 void free_ctx(track_ctx* c) {
     if (!c) return;
+    drop_graphs(c);
     for (auto& t : c->timers)
         for (auto e : t.ev) (void)hipEventDestroy(e);
     if (c->f0) (void)hipEventDestroy(c->f0);
@@ -466,6 +611,7 @@ void free_ctx(track_ctx* c) {
     if (c->djt) (void)hipFree(c->djt);
     if (c->hstats) (void)hipHostFree(c->hstats);
     if (c->htheta) (void)hipHostFree(c->htheta);
+    if (c->hbstat) (void)hipHostFree(c->hbstat);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -498,6 +644,10 @@ int track_init(const track_model* model, const track_camera* camera, const track
     c->ntiles = tx * ty;
     c->npad = c->ntiles * 64;
     c->negrid = ne_grid(c->V);
+    {
+        const char* env = std::getenv("TRACK_NO_GRAPH");
+        c->use_graphs = !(env && env[0] == '1');
+    }
     build_joint_table(c, model);
     if ((rc = set_params(c, params))) { free_ctx(c); return rc; }
     if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(TRACK_E_DEVICE, "no HIP device"); }
@@ -514,18 +664,23 @@ int track_init(const track_model* model, const track_camera* camera, const track
     add(8 * c->L, 4); add(8 * c->P, 4); add(4 * c->L, 4);                       // dq, xi, anc
     add((size_t)c->negrid * c->PP * c->PP, 4);                                  // partials
     add(N, 4); add(3 * N, 4);                                                   // depth, xyz
-    for (int q = 0; q < 3 * 9; ++q) add(V, 4);                                  // rest, phi x2, prev, verts x2, normals, 2 spare
+    for (int q = 0; q < 3 * 5; ++q) add(V, 4);                                  // rest, phi x2, prev, normals
+    add(V, 16); add(V, 16);                                                     // vertices x2
     add(V, 16); add(V, 4); add(V, 16); add(V + 1, 4); add(3 * (size_t)c->F, 8); // w, links, nbr, fan
     add(c->npad, 4); add(c->npad, 4); add(c->npad, 4); add(c->npad, 16);       // buckets
     add(c->ntiles, 4); add(c->ntiles, 4); add(c->ntiles, 8);
     add(V, 4); add(V, 4); add(V, 16);
+    c->nassoc = assoc_blocks(tx, ty);
+    add(c->nassoc, 16);
+    add(4 * (size_t)c->ntiles, 16);
     add(V, 4); add(V, 8); add(V, 8); add(V, 8);                                 // accumulators
     add(N, 4); add(1, sizeof(DevStats));
     c->arena_bytes = need;
     if (hipMalloc(&c->arena, need) != hipSuccess) { free_ctx(c); return fail(TRACK_E_NOMEM, "device allocation failed"); }
     if (hipMalloc(&c->djt, sizeof(JointTable)) != hipSuccess) { free_ctx(c); return fail(TRACK_E_NOMEM, "device allocation failed"); }
     if (hipHostMalloc(&c->hstats, sizeof(DevStats)) != hipSuccess ||
-        hipHostMalloc(&c->htheta, sizeof(double) * c->P) != hipSuccess) {
+        hipHostMalloc(&c->htheta, sizeof(double) * c->P) != hipSuccess ||
+        hipHostMalloc(&c->hbstat, sizeof(int4) * c->nassoc) != hipSuccess) {
         free_ctx(c);
         return fail(TRACK_E_NOMEM, "pinned allocation failed");
     }
@@ -542,8 +697,7 @@ int track_init(const track_model* model, const track_camera* camera, const track
     auto v3 = [&]() { Vec3Buf b; b.x = carve<float>(c, V); b.y = carve<float>(c, V); b.z = carve<float>(c, V); return b; };
     Vec3Buf rest = v3();
     c->phi[0] = v3(); c->phi[1] = v3(); c->phi_prev = v3();
-    c->verts[0] = v3(); c->verts[1] = v3(); c->normals = v3();
-    v3(); v3();
+    c->verts[0] = carve<float4>(c, V); c->verts[1] = carve<float4>(c, V); c->normals = v3();
     float4* w4 = carve<float4>(c, V);
     uint32_t* lk = carve<uint32_t>(c, V);
     int4* nb = carve<int4>(c, V);
@@ -559,6 +713,8 @@ int track_init(const track_model* model, const track_camera* camera, const track
     c->bk.vpix = carve<int>(c, V);
     c->bk.vslot = carve<uint32_t>(c, V);
     c->bk.sorted = carve<float4>(c, V);
+    c->bk.bstat = carve<int4>(c, c->nassoc);
+    c->bk.cellrec = carve<uint4>(c, 4 * (size_t)c->ntiles);
     c->acc.cnt = carve<uint32_t>(c, V);
     c->acc.sx = carve<long long>(c, V);
     c->acc.sy = carve<long long>(c, V);
@@ -666,7 +822,7 @@ int track_state(const track_ctx* cc, double* theta, float* phi, float* verts, tr
     if (verts) {
         ensure_surface(c);
         HIP_TRY(hipStreamSynchronize(c->stream));
-        if ((rc = download_soa(c, c->verts[c->v_cur], verts))) return rc;
+        if ((rc = download_v4(c, c->verts[c->v_cur], verts))) return rc;
     }
     if (stats) *stats = c->last;
     return TRACK_OK;
@@ -734,7 +890,7 @@ int track_dbg_set(track_ctx* c, int32_t buf, const void* host, size_t bytes) {
         case TRACK_BUF_VERTS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
             c->surface_valid = true;
-            return upload_soa(c, c->verts[c->v_cur], (const float*)host);
+            return upload_v4(c, c->verts[c->v_cur], (const float*)host);
         case TRACK_BUF_NORMALS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
             return upload_soa(c, c->normals, (const float*)host);
@@ -797,10 +953,10 @@ int track_dbg_get(const track_ctx* cc, int32_t buf, void* host, size_t bytes) {
             return download_soa(c, c->phi_prev, (float*)host);
         case TRACK_BUF_VERTS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_soa(c, c->verts[c->v_cur], (float*)host);
+            return download_v4(c, c->verts[c->v_cur], (float*)host);
         case TRACK_BUF_VERTS_NEW:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_soa(c, c->verts[c->v_cur], (float*)host);
+            return download_v4(c, c->verts[c->v_cur], (float*)host);
         case TRACK_BUF_NORMALS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
             return download_soa(c, c->normals, (float*)host);
@@ -854,7 +1010,7 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
             ensure_surface(c);
             break;
         case TRACK_PASS_NORMALS:
-            launch_normals(c->stream, c->dm, cview(c->verts[c->v_cur]), c->normals);
+            launch_normals(c->stream, c->dm, c->verts[c->v_cur], c->normals);
             break;
         case TRACK_PASS_ASSOCIATE:
             pass_associate(c, depth, xyz);
