@@ -214,8 +214,9 @@ def test_pose_step(T, human, fp64):
 def test_shape_step(T, tiny, human, case, fp64):
     """One offset step from identical inputs.  The GPU re-skins at theta in
     float32, so its normals carry ~ulp(v)/edge relative error (about 1e-4 on
-    the 5 mm edges of the human mesh); bound |dphi| <= 2e-4 |x| + 2e-8 m with
-    x the oracle's per-vertex step."""
+    the 5 mm edges of the human mesh) and its residuals ~8 ulp(v); bound
+    |dphi| <= 2e-4 |x| + 8 ulp(max|v|) / alpha_i with x the oracle's
+    per-vertex step and alpha_i the vertex's regulariser weight."""
     _say(f"[shape] {case} fp64={fp64}")
     if case == "tiny":
         m, cam, prm, th, depth = (tiny.body.model, tiny.body.camera, dict(tiny.params), 0.5 * tiny.theta_true[0],
@@ -245,8 +246,17 @@ def test_shape_step(T, tiny, human, case, fp64):
     d_new = np.where(cnt[:, None] > 0, delta.astype(np.float64) + (v32.astype(np.float64) - v_new), delta)
     phi_or = oracle.shape_step(m, th2, phi.astype(np.float64), prev.astype(np.float64), n_new, d_new, cnt,
                                prm["lambda_phi"], prm["lambda_nbr"], prm["lambda_t"], prm["lambda_w"])
-    x = np.abs(phi_or - phi)
-    assert (np.abs(phi_gpu - phi_or) <= 2e-4 * x.max(axis=1, keepdims=True) + 2e-8).all()
+    x = np.abs(phi_or - phi).max(axis=1, keepdims=True)
+    err = np.abs(phi_gpu - phi_or)
+    # rounding floor: the residual carries ~8 ulp of the float32 vertex
+    # coordinates and enters the step divided by the regulariser weight
+    nb = np.asarray(m["neighbors"])
+    alpha = prm["lambda_phi"] + prm["lambda_t"] + prm["lambda_nbr"] * (nb >= 0).sum(axis=1)
+    floor = 8 * float(np.spacing(np.float32(np.abs(v32).max()))) / alpha[:, None]
+    bad = np.flatnonzero((err > 2e-4 * x + floor).any(axis=1))
+    worst = int(np.argmax(err.max(axis=1) / (x[:, 0] + 1e-12)))
+    assert bad.size == 0, (f"{bad.size} vertices, worst {worst}: err {err[worst].max():.3e} step {x[worst, 0]:.3e} "
+                           f"count {cnt[worst]} |n| {np.linalg.norm(n_new[worst]):.3f}")
 
 
 def _near_tie_certified(m, cam, tau, v, depth, a_gpu, a_or):
@@ -264,44 +274,68 @@ def _near_tie_certified(m, cam, tau, v, depth, a_gpu, a_or):
     return True, len(bad), None
 
 
-# end-to-end bounds (joint angle rad, root translation and vertex m) per
+# end-to-end floors (joint angle rad, root translation and vertex m) per
 # (operand form of the Gram, float64 solves)
-E2E_BOUND = {(0, 0): (2e-3, 2e-3), (0, 1): (2e-3, 2e-3), (1, 1): (2e-2, 5e-3), (2, 1): (2e-3, 2e-3)}
+E2E_FLOOR = {(0, 0): (2e-3, 2e-3), (0, 1): (2e-3, 2e-3), (1, 1): (2e-2, 5e-3), (2, 1): (2e-3, 2e-3)}
+# perturbation of the starting pose that measures the oracle's own response,
+# and the multiple of that response allowed to the float32 path
+E2E_PERTURB, E2E_GAIN = 1e-6, 10.0
 
 
-@pytest.mark.parametrize("mode,fp64", list(E2E_BOUND))
+def _oracle_frame(m, cam, prm, th, phi, depth):
+    th, phi = th.copy(), phi.copy()
+    r = oracle.track_frame(m, cam, prm, th, phi, phi.copy(), depth=depth)
+    v, _ = oracle.skin(m, th, phi)
+    return th, phi, v, r
+
+
+@pytest.mark.parametrize("mode,fp64", list(E2E_FLOOR))
 def test_frame_end_to_end(T, human, mode, fp64):
     """Frames of the human workload against the float64 oracle, each frame
-    from the oracle's state at its start, so the comparison measures one
-    frame's arithmetic rather than the drift of weakly observed joints across
-    frames.  Prints the errors; bounds per configuration in E2E_BOUND."""
+    from the oracle's state at its start.  Five Gauss-Newton iterations of
+    a 75-DoF body can amplify rounding-level differences (weakly observed
+    distal joints and limb twists), so the bound is certified per frame by
+    the oracle itself: its own change when the starting pose moves by
+    E2E_PERTURB (random direction, two draws) is the frame's amplification;
+    the GPU may differ by E2E_GAIN times that change, and at least by the
+    floor of its configuration (E2E_FLOOR).  Prints both."""
     _say(f"[frame] gram mode={mode} fp64 solves={fp64}")
     m, cam = human.body.model, human.body.camera
     prm = dict(human.params, gram_mode=mode, pose_solve_fp64=fp64, shape_solve_fp64=fp64)
     V, P = m["rest_xyz"].shape[0], len(human.theta0)
+    ang = human.body.angular
     trk = T.Tracker(m, cam, prm, human.theta0)
     th_or, phi_or = human.theta0.copy(), np.zeros((V, 3))
-    worst = [0.0, 0.0, 0.0]
+    f_ang, f_lin = E2E_FLOOR[(mode, fp64)]
+    failures = []
     try:
         for f in range(3):
             trk.reset(th_or, phi_or.astype(np.float32))
             phi_or = phi_or.astype(np.float32).astype(np.float64)
-            pp = phi_or.copy()
             assert trk.frame(human.frames[f]) == 0, T.track_last_error()
-            r = oracle.track_frame(m, cam, prm, th_or, phi_or, pp, depth=human.frames[f])
+            th1, phi1, v1, r = _oracle_frame(m, cam, prm, th_or, phi_or, human.frames[f])
+            s_ang = s_lin = s_v = 0.0
+            for seed in (0, 1):
+                dth = E2E_PERTURB * np.random.default_rng(100 + 10 * f + seed).standard_normal(P)
+                th2, _, v2, _ = _oracle_frame(m, cam, prm, th_or + dth, phi_or, human.frames[f])
+                d = np.abs(th2 - th1)
+                s_ang, s_lin = max(s_ang, d[ang].max()), max(s_lin, d[~ang].max())
+                s_v = max(s_v, np.abs(v2 - v1).max())
             th_g, phi_g, v_g, st = trk.state()
-            ang = human.body.angular
-            dth = np.abs(th_g - th_or)
-            v_or_now, _ = oracle.skin(m, th_or, phi_or)
-            dv = np.abs(v_g - v_or_now).max()
-            _say(f"  frame {f}: max joint diff {dth[ang].max():.2e} rad, root {dth[~ang].max():.2e} m, "
-                 f"vertex {dv:.2e} m, assoc px {st['n_assoc_px']} vs {r['n_assoc_px']}")
-            worst = [max(worst[0], dth[ang].max()), max(worst[1], dth[~ang].max()), max(worst[2], dv)]
+            dth = np.abs(th_g - th1)
+            dv = np.abs(v_g - v1).max()
+            b_ang, b_lin, b_v = (max(f_ang, E2E_GAIN * s_ang), max(f_lin, E2E_GAIN * s_lin),
+                                 max(f_lin, E2E_GAIN * s_v))
+            _say(f"  frame {f}: joint {dth[ang].max():.2e} rad (bound {b_ang:.1e}), root {dth[~ang].max():.2e} m "
+                 f"(bound {b_lin:.1e}), vertex {dv:.2e} m (bound {b_v:.1e}), assoc px {st['n_assoc_px']} vs "
+                 f"{r['n_assoc_px']}")
+            if not (dth[ang].max() <= b_ang and dth[~ang].max() <= b_lin and dv <= b_v):
+                failures.append(f)
             assert abs(st["n_assoc_px"] - r["n_assoc_px"]) <= 0.001 * r["n_assoc_px"] + 5
+            th_or, phi_or = th1, phi1   # the oracle's state starts the next frame
     finally:
         trk.close()
-    b_ang, b_lin = E2E_BOUND[(mode, fp64)]
-    assert worst[0] <= b_ang and worst[1] <= b_lin and worst[2] <= b_lin, worst
+    assert not failures, failures
 
 
 def test_first_iteration_association_matches_up_to_near_ties(T, human):
