@@ -29,25 +29,23 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
 
-def algorithmic_bytes(kernel, V, F, N_px, V_obs, P, K=4):
-    """Minimum bytes one launch of each kernel must move (float32 SoA)."""
+def algorithmic_bytes(kernel, V, F, N_px, N_valid, K=4, temporal=False):
+    """Minimum HBM bytes of one launch of each timed pass (float32 SoA): the
+    method's own traffic, excluding the never-materialised dense J and any
+    exhaustive search."""
     return {
-        # template xyz + offsets + weights + links in, vertices out
-        "skin": V * (12 + 12 + 4 * K + 4 + 12),
-        # vertices in, faces in, normals out
-        "normals": 24 * V + 12 * F,
-        # vertices in; per-pixel counts, z range and records; sorted vertices out
-        "bucket": 12 * V + 16 * V + 28 * N_px,
-        # depth in, association out, per-pixel records and sorted vertices read
-        # once, fixed-point sums of the matched vertices
-        "assoc": 4 * N_px + 4 * N_px + 16 * N_px + 16 * V + 28 * V_obs,
-        # counts of all vertices; normals, vertices, offsets, template,
-        # weights, links and sums of the observed ones
-        "normal_eq": 4 * V + V_obs * (12 + 12 + 12 + 12 + 4 * K + 4 + 24),
-        "solve": 8 * (P + 1) * (P + 1),
-        # offsets, previous offsets, neighbours, counts, sums, normals, old and
-        # new vertices, weights, links in; offsets out
-        "shape": V * (12 + 12 + 16 + 4 + 24 + 12 + 12 + 12 + 4 * K + 4 + 12),
+        # template, offsets, weights, links in; vertices out
+        "skin": V * (36 + 5 * K),
+        # vertices, incident faces in; normals out
+        "normals": 12 * F + 24 * V,
+        # vertices in; per-pixel counts, z range and records; sorted vertices
+        "bucket": 36 * V + 24 * N_px,
+        # depth in, association out, the buckets read once, per-vertex sums
+        "assoc": 20 * N_px + 44 * V + 28 * N_valid,
+        # vertices, normals, offsets, template, weights, links, sums in
+        "normal_eq": V * (52 + 5 * K),
+        "solve": 0,
+        "shape": V * (92 + 5 * K + (12 if temporal else 0)),
     }[kernel]
 
 
@@ -73,20 +71,7 @@ def cpu_baseline(w, budget_s=15.0, max_frames=30):
                       f"{used} OpenMP threads (association loop), {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--gram", choices=["fp32", "bf16x3"], default="fp32")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "tracking streams shard across GPUs with no communication, see the design notes",
-              file=sys.stderr)
-        sys.exit(2)
-
+def single_stream(args):
     import torch
 
     from paper_1711_07999_amd import synth
@@ -120,10 +105,12 @@ def main():
             if lat is not None:
                 lat.append(t1 - t0)
 
-    # warmup with every kernel timed, to find the dominant kernel
+    # warmup: first with every kernel timed (to find the dominant kernel),
+    # then plain, so the frame graphs are captured before timing
     for k in range(len(T.KERNEL_NAMES)):
         T.track_kernel_timing(trk.ctx, k, True)
-    run(max(args.warmup, 1))
+    nw = max(args.warmup, 1)
+    run(nw)
     per_kernel = {}
     for k, name in enumerate(T.KERNEL_NAMES):
         n, ms = T.track_kernel_time(trk.ctx, k)
@@ -131,17 +118,23 @@ def main():
         T.track_kernel_timing(trk.ctx, k, False)
     dom = max(per_kernel, key=lambda k: per_kernel[k][1])
     dom_id = T.KERNEL_NAMES.index(dom)
+    run(nw)
     stats = trk.state(want_verts=False)[3]
-    V_obs = stats["n_obs_verts"]
+    V_obs, N_valid = stats["n_obs_verts"], stats["n_valid_px"]
 
-    # timed region: only the dominant kernel carries events
-    T.track_kernel_timing(trk.ctx, dom_id, True)
+    # timed region: whole frames replayed from their graphs
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
     run(args.steps, lat)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # roofline region: the same steps with HIP events around every launch of
+    # the dominant kernel (events need direct launches, not graph replays)
+    T.track_kernel_timing(trk.ctx, dom_id, True)
+    torch.cuda.synchronize()
+    run(args.steps)
+    torch.cuda.synchronize()
     n_launch, ms_total = T.track_kernel_time(trk.ctx, dom_id)
     T.track_kernel_timing(trk.ctx, dom_id, False)
     trk.close()
@@ -157,7 +150,7 @@ def main():
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": None}
     else:
-        b = algorithmic_bytes(dom, V, F, N_px, V_obs, P)
+        b = algorithmic_bytes(dom, V, F, N_px, N_valid, temporal=prm["lambda_t"] > 0)
         achieved = b / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
@@ -183,11 +176,216 @@ def main():
                    "gn_iters_per_frame": int(prm["n_iters"]), "sequence_frames": nseq,
                    "gram": args.gram},
         "roofline": roof,
-        "kernel_ms_per_frame": {k: (v[1] / max(args.warmup, 1)) for k, v in per_kernel.items()},
+        "kernel_ms_per_frame": {k: (v[1] / nw) for k, v in per_kernel.items()},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# serving: 64 streams of mixed sizes through one server
+# ---------------------------------------------------------------------------
+SERVE_COMBOS = [(V, W, H, f) for V in (10000, 50000, 200000)
+                for (W, H, f) in ((320, 240, 262.5), (640, 480, 525.0))]
+
+
+def _pingpong(k, n):
+    """Frame k of an endless forward-backward walk over n frames."""
+    q = k % (2 * n - 2)
+    return q if q < n else 2 * n - 2 - q
+
+
+def serve(args):
+    import torch
+
+    from paper_1711_07999_amd import synth
+    from paper_1711_07999_amd import track as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    log = lambda msg: print(f"[serve] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+    seqs = []
+    for ci, (V, W, H, f) in enumerate(SERVE_COMBOS):
+        w = synth.workload_human(seed=20 + ci, n_frames=args.seq_frames, n_verts=V, width=W, height=H, focal=f)
+        seqs.append((w, [torch.from_numpy(x).to(dev) for x in w.frames]))
+        log(f"workload {w.name} ready")
+    prm = dict(seqs[0][0].params, active=None)
+    streams = []
+    for s in range(args.streams):
+        rng = np.random.default_rng(5000 + s)
+        ci = int(rng.integers(len(SERVE_COMBOS)))
+        w = seqs[ci][0]
+        th0 = w.theta0 + np.where(w.body.angular, rng.uniform(-0.005, 0.005, len(w.theta0)), 0.0)
+        gaps = rng.exponential(1.0 / 30.0, args.frames)
+        streams.append(dict(ci=ci, th0=th0, arrive=np.cumsum(gaps)))
+
+    def open_all(sv):
+        return [T.track_server_open(sv, seqs[st["ci"]][0].body.model, seqs[st["ci"]][0].body.camera, st["th0"])
+                for st in streams]
+
+    def frame_of(s, k):
+        return seqs[streams[s]["ci"]][1][_pingpong(k, args.seq_frames)]
+
+    budget = int(args.budget_gb * (1 << 30))
+    # (i) configured load: Poisson arrivals at 30 frames/s per stream
+    sv = T.track_server_create(prm, budget, args.streams)
+    ids = open_all(sv)
+    for s in range(len(streams)):  # warm the graphs of the batch shapes with one frame each
+        T.track_server_submit(sv, ids[s], frame_of(s, 0), tag=-1)
+    while T.track_server_info(sv)["frames_pending"]:
+        T.track_server_step(sv)
+    T.track_server_poll(sv, 100000)
+    log("configured load")
+    nxt = [1] * len(streams)
+    total = len(streams) * args.frames
+    lat, done, steps = [], 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < total - len(streams):
+        now = time.perf_counter() - t0
+        for s, st in enumerate(streams):
+            while nxt[s] < args.frames and st["arrive"][nxt[s]] <= now:
+                T.track_server_submit(sv, ids[s], frame_of(s, nxt[s]), tag=s * 100000 + nxt[s])
+                nxt[s] += 1
+        info = T.track_server_info(sv)
+        if info["frames_pending"] == 0:
+            future = [st["arrive"][nxt[s]] for s, st in enumerate(streams) if nxt[s] < args.frames]
+            if future:
+                time.sleep(max(0.0, min(future) - (time.perf_counter() - t0)))
+            continue
+        T.track_server_step(sv)
+        steps += 1
+        t_now = time.perf_counter() - t0
+        for c in T.track_server_poll(sv, 100000):
+            s, k = divmod(c["tag"], 100000)
+            lat.append(t_now - streams[s]["arrive"][k])
+            done += 1
+    t_load = time.perf_counter() - t0
+    T.track_server_destroy(sv)
+    lat_ms = np.array(lat) * 1e3
+    log(f"configured load done: {done} frames in {t_load:.2f} s, {steps} steps")
+
+    # (ii) saturation: every stream always has frames waiting
+    sv = T.track_server_create(prm, budget, args.streams)
+    ids = open_all(sv)
+    nsat = args.sat_frames
+    for s in range(len(streams)):
+        T.track_server_submit(sv, ids[s], frame_of(s, 0), tag=-1)
+    while T.track_server_info(sv)["frames_pending"]:
+        T.track_server_step(sv)
+    T.track_server_poll(sv, 100000)
+    for s in range(len(streams)):
+        for k in range(1, nsat + 1):
+            T.track_server_submit(sv, ids[s], frame_of(s, k), tag=s * 100000 + k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_sat = 0
+    while n_sat < len(streams) * nsat:
+        n_sat += T.track_server_step(sv)
+    torch.cuda.synchronize()
+    t_sat = time.perf_counter() - t0
+    T.track_server_poll(sv, 1000000)
+    chosen = list(range(0, len(streams), max(1, len(streams) // 8)))[:8]
+    mix_state = {s: T.track_server_state(sv, ids[s], len(streams[s]["th0"]),
+                                         seqs[streams[s]["ci"]][0].body.model["rest_xyz"].shape[0])
+                 for s in chosen}
+    T.track_server_destroy(sv)
+    log(f"saturation: {n_sat} frames in {t_sat:.2f} s")
+
+    # (iv) eight streams rerun alone must end bit-identical
+    same = []
+    for s in chosen:
+        sv = T.track_server_create(prm, budget, 1)
+        sid = T.track_server_open(sv, seqs[streams[s]["ci"]][0].body.model, seqs[streams[s]["ci"]][0].body.camera,
+                                  streams[s]["th0"])
+        for k in range(0, nsat + 1):
+            T.track_server_submit(sv, sid, frame_of(s, k), tag=k)
+        while T.track_server_info(sv)["frames_pending"]:
+            T.track_server_step(sv)
+        th, phi = T.track_server_state(sv, sid, len(streams[s]["th0"]),
+                                       seqs[streams[s]["ci"]][0].body.model["rest_xyz"].shape[0])
+        T.track_server_destroy(sv)
+        same.append(bool(np.array_equal(th, mix_state[s][0]) and np.array_equal(phi, mix_state[s][1])))
+    log(f"alone vs mix: {same}")
+
+    # (iii) admission under a 1 GiB budget: streams queue instead of failing
+    sv = T.track_server_create(prm, 1 << 30, args.streams)
+    ids = open_all(sv)
+    info0 = T.track_server_info(sv)
+    for s in range(len(streams)):
+        for k in range(args.admit_frames):
+            T.track_server_submit(sv, ids[s], frame_of(s, k), tag=s * 100000 + k)
+    finished, max_res, n_adm, failed = set(), 0, 0, 0
+    t0 = time.perf_counter()
+    while len(finished) < len(streams):
+        T.track_server_step(sv)
+        for c in T.track_server_poll(sv, 100000):
+            n_adm += 1
+            failed += c["status"] != 0
+            s, k = divmod(c["tag"], 100000)
+            if k == args.admit_frames - 1:
+                finished.add(s)
+                T.track_server_close(sv, ids[s])
+        max_res = max(max_res, T.track_server_info(sv)["resident"])
+    t_adm = time.perf_counter() - t0
+    T.track_server_destroy(sv)
+    log(f"admission: {n_adm} frames, max resident {max_res}")
+
+    mix = {}
+    for st in streams:
+        name = seqs[st["ci"]][0].name
+        mix[name] = mix.get(name, 0) + 1
+    out = {
+        "metric": "aggregate tracked frames/s + p99 latency (64 streams, 10k-200k-vert bodies, 320x240/640x480)",
+        "value": n_sat / t_sat,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving-mix", "streams": len(streams), "mix": mix,
+                   "frames_per_stream_load": args.frames, "frames_per_stream_saturation": nsat,
+                   "arrivals": "Poisson, 30 frames/s per stream", "gn_iters_per_frame": int(prm["n_iters"]),
+                   "sequence": f"{args.seq_frames} rendered frames per size, walked forward and back"},
+        "configured_load": {"offered_fps": 30.0 * len(streams), "achieved_fps": done / t_load,
+                            "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                            "frames": done, "steps": steps},
+        "saturation": {"frames": n_sat, "seconds": t_sat, "fps": n_sat / t_sat},
+        "admission_1GiB": {"frames": n_adm, "failed_frames": failed, "max_resident": max_res,
+                           "waiting_at_open": info0["waiting"], "resident_at_open": info0["resident"],
+                           "seconds": t_adm},
+        "alone_vs_mix_bit_identical": {"streams": chosen, "identical": same},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--gram", choices=["fp32", "bf16x3"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving mix instead of the single-stream step")
+    ap.add_argument("--streams", type=int, default=64)
+    ap.add_argument("--frames", type=int, default=300, help="frames per stream at the configured load")
+    ap.add_argument("--sat-frames", type=int, default=30, help="frames per stream at saturation")
+    ap.add_argument("--admit-frames", type=int, default=10)
+    ap.add_argument("--seq-frames", type=int, default=30)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "tracking streams shard across GPUs with no communication, see the design notes",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.serve:
+        serve(args)
+    else:
+        single_stream(args)
 
 
 if __name__ == "__main__":

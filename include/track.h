@@ -172,6 +172,76 @@ void track_destroy(track_ctx *ctx);
 const char *track_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Serving: one server tracks many independent streams (each its own model,
+ * camera and state, as a context would) under one device-memory budget.
+ * Every step runs one Gauss-Newton iteration (Section 4) for every resident
+ * stream that has a frame in progress or waiting, in the same kernel
+ * launches, so a stream joins at the next iteration boundary after its frame
+ * arrives.  A stream's results do not depend on which other streams share
+ * its launches.  The server's constants (params) hold for every stream; the
+ * per-joint active mask must be NULL.
+ * ---------------------------------------------------------------------- */
+typedef struct track_server track_server; /* opaque; owned by the library */
+
+typedef struct {
+    int32_t stream;          /* id given by track_server_open                    */
+    int32_t status;          /* TRACK_OK, TRACK_E_NOT_PD or TRACK_E_LOST          */
+    int64_t tag;             /* the caller's tag from track_server_submit         */
+    track_frame_stats stats; /* ms_total is 0 (frames share launches)            */
+} track_completion;
+
+typedef struct {
+    int32_t resident;           /* streams holding device memory                  */
+    int32_t waiting;            /* streams queued for admission                   */
+    int32_t frames_in_progress; /* frames with iterations still to run            */
+    int32_t frames_pending;     /* submitted frames not yet completed             */
+    int64_t bytes_used;         /* device bytes of the resident streams           */
+    int64_t bytes_budget;
+} track_server_stats;
+
+/* Create a server.  hbm_budget_bytes bounds the device memory of resident
+   streams; max_streams bounds how many are resident at once (1..4096).
+   hip_stream is a hipStream_t or NULL. */
+int track_server_create(const track_params *params, int64_t hbm_budget_bytes, int32_t max_streams,
+                        void *hip_stream, track_server **out);
+
+/* Open a stream (model, camera and initial state as for track_init).  The
+   stream is admitted at once if it fits the budget and the resident count,
+   else it waits in arrival order and is admitted when closed streams free
+   room; frames may be submitted either way.  TRACK_E_BUDGET if the stream
+   alone exceeds the budget.  *stream_id receives its id. */
+int track_server_open(track_server *sv, const track_model *model, const track_camera *camera,
+                      const double *theta0, const float *phi0, int32_t *stream_id);
+
+/* Queue a depth frame (H*W float32, metres) for a stream; frames of a stream
+   are tracked in submission order.  A device frame (on_device != 0) must
+   stay valid until its completion is polled; a host frame is copied. */
+int track_server_submit(track_server *sv, int32_t stream_id, const float *depth, int32_t on_device,
+                        int64_t tag);
+
+/* Admit waiting streams where possible, then run one iteration for every
+   resident stream with work; returns when it has finished.  *n_completed
+   (may be NULL) receives the number of frames this step completed. */
+int track_server_step(track_server *sv, int32_t *n_completed);
+
+/* Move up to max_out completions, oldest first, into out; *n_out receives
+   the count. */
+int track_server_poll(track_server *sv, track_completion *out, int32_t max_out, int32_t *n_out);
+
+/* Copy a stream's Theta [P] float64 and Phi [V*3] (NULL = skip); not while
+   one of its frames is in progress.  A waiting stream reports its initial
+   state. */
+int track_server_state(track_server *sv, int32_t stream_id, double *theta, float *phi);
+
+/* Close a stream: its device memory returns to the budget and its pending
+   frames are dropped without completions. */
+int track_server_close(track_server *sv, int32_t stream_id);
+
+int track_server_info(track_server *sv, track_server_stats *out);
+
+void track_server_destroy(track_server *sv);
+
+/* ------------------------------------------------------------------------
  * Per-pass access, for checking each step against an independent
  * implementation on identical inputs.  Buffers are exchanged in the host
  * layouts below; a pass reads and writes the context's buffers.

@@ -35,8 +35,13 @@ __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 // ---------------------------------------------------------------------------
 // clear the bucket counters, z ranges, per-vertex accumulators and counters
 // ---------------------------------------------------------------------------
-__global__ void k_clear(int npad, Buckets b, int V, Accum a, DevStats* st) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_clear(Batch B) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_CLEAR, blockIdx.x, local)];
+    const Buckets& b = S.b;
+    const Accum& a = S.a;
+    const int npad = S.npad, V = S.m.V;
+    int i = local * blockDim.x + threadIdx.x;
     if (i < npad) {
         b.pcnt[i] = 0u;
         b.pzmin[i] = 0x7F800000u;  // +inf
@@ -46,21 +51,24 @@ __global__ void k_clear(int npad, Buckets b, int V, Accum a, DevStats* st) {
         a.cnt[i] = 0u;
         a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
     }
-    if (i == 0) { st->n_valid_px = 0; st->n_assoc_px = 0; st->n_obs_verts = 0; }
 }
 
-void launch_clear(hipStream_t s, int npad, const Buckets& b, int V, const Accum& a, DevStats* st) {
-    int n = npad > V ? npad : V;
-    hipLaunchKernelGGL(k_clear, dim3((n + 255) / 256), dim3(256), 0, s, npad, b, V, a, st);
+void launch_clear(const Launch& L) {
+    hipLaunchKernelGGL(k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.s, L.B);
 }
 
 // ---------------------------------------------------------------------------
 // bucket construction: count -> per-tile sums and z ranges -> tile prefix ->
 // per-pixel offsets -> scatter
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_bucket_count(DevCam c, int V, const float4* __restrict__ v, Buckets b) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V) return;
+__global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const DevCam& c = S.c;
+    const Buckets& b = S.b;
+    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
+    int i = local * blockDim.x + threadIdx.x;
+    if (i >= S.m.V) return;
     const float4 p = v[i];
     const float x = p.x, y = p.y, z = p.z;
     int pix = -1;
@@ -80,8 +88,12 @@ __global__ void __launch_bounds__(256) k_bucket_count(DevCam c, int V, const flo
 }
 
 // one wave per tile
-__global__ void __launch_bounds__(256) k_tile_reduce(int ntiles, Buckets b) {
-    int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ void __launch_bounds__(256) k_tile_reduce(Batch B) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_TILE4, blockIdx.x, local)];
+    const Buckets& b = S.b;
+    const int ntiles = S.c.tiles_x * S.c.tiles_y;
+    int tile = local * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     int p = (tile << 6) + wave_lane();
     uint32_t cnt = b.pcnt[p];
@@ -99,7 +111,11 @@ __global__ void __launch_bounds__(256) k_tile_reduce(int ntiles, Buckets b) {
 }
 
 // exclusive prefix over tiles, one workgroup of 1024 threads
-__global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, Buckets b) {
+__global__ void __launch_bounds__(1024) k_tile_scan(Batch B) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
+    const Buckets& b = S.b;
+    const int ntiles = S.c.tiles_x * S.c.tiles_y;
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t carry;
     if (threadIdx.x == 0) carry = 0;
@@ -131,8 +147,12 @@ __global__ void __launch_bounds__(1024) k_tile_scan(int ntiles, Buckets b) {
 // per-pixel (offset, count, zmin, zmax), and per 4x4 cell (the 16
 // consecutive Morton positions of a tile quadrant) the same record; one wave
 // per tile
-__global__ void __launch_bounds__(256) k_pixel_offsets(int ntiles, Buckets b) {
-    int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_TILE4, blockIdx.x, local)];
+    const Buckets& b = S.b;
+    const int ntiles = S.c.tiles_x * S.c.tiles_y;
+    int tile = local * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const int lane = wave_lane();
     int p = (tile << 6) + lane;
@@ -154,9 +174,13 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(int ntiles, Buckets b) {
     if ((lane & 15) == 0) b.cellrec[(tile << 2) + (lane >> 4)] = make_uint4(off, csum, cmn, cmx);
 }
 
-__global__ void __launch_bounds__(256) k_bucket_scatter(int V, const float4* __restrict__ v, Buckets b) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V) return;
+__global__ void __launch_bounds__(256) k_bucket_scatter(Batch B, int vsel) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const Buckets& b = S.b;
+    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
+    int i = local * blockDim.x + threadIdx.x;
+    if (i >= S.m.V) return;
     int pix = b.vpix[i];
     if (pix < 0) return;
     uint32_t dst = b.rec[pix].x + b.vslot[i];
@@ -164,13 +188,12 @@ __global__ void __launch_bounds__(256) k_bucket_scatter(int V, const float4* __r
     b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
 }
 
-void launch_bucket(hipStream_t s, const DevCam& c, int V, const float4* v, const Buckets& b) {
-    int ntiles = c.tiles_x * c.tiles_y;
-    hipLaunchKernelGGL(k_bucket_count, dim3((V + 255) / 256), dim3(256), 0, s, c, V, v, b);
-    hipLaunchKernelGGL(k_tile_reduce, dim3((ntiles + 3) / 4), dim3(256), 0, s, ntiles, b);
-    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, ntiles, b);
-    hipLaunchKernelGGL(k_pixel_offsets, dim3((ntiles + 3) / 4), dim3(256), 0, s, ntiles, b);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3((V + 255) / 256), dim3(256), 0, s, V, v, b);
+void launch_bucket(const Launch& L, int vsel) {
+    hipLaunchKernelGGL(k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel);
+    hipLaunchKernelGGL(k_tile_reduce, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.s, L.B);
+    hipLaunchKernelGGL(k_tile_scan, dim3(L.grid[KK_ONE]), dim3(1024), 0, L.s, L.B);
+    hipLaunchKernelGGL(k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.s, L.B);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,18 +226,24 @@ __device__ __forceinline__ bool z_pruned(float zmn, float zmx, float pz, float b
 // compared against every lane's point; each lane keeps the key
 // (d2 bits << 32 | vertex id), whose minimum is the nearest vertex with ties
 // to the lower index.  The four waves' keys are combined with an LDS minimum.
-__global__ void __launch_bounds__(256) k_associate(DevCam c, float tau, const float* __restrict__ depth,
-                                                   const float* __restrict__ xyz, Buckets b, Accum a,
-                                                   const float4* __restrict__ verts, int32_t* __restrict__ assoc) {
+__global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
     __shared__ float4 scand[4][64];
     __shared__ unsigned long long skey[64];
-    __shared__ int s_cnt[3];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_TILE, blockIdx.x, local)];
+    const DevCam& c = S.c;
+    const Buckets& b = S.b;
+    const Accum& a = S.a;
+    const float tau = S.tau;
+    const float* __restrict__ depth = S.depth;
+    const float* __restrict__ xyz = S.xyz;
+    const float4* __restrict__ verts = S.verts[S.v_cur ^ vsel];
+    int32_t* __restrict__ assoc = S.assoc;
     const int lane = wave_lane(), wid = threadIdx.x >> 6;
-    const int tile = blockIdx.x;
+    const int tile = local;
     const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
     const int u = tx * 8 + (lane & 7), v = ty * 8 + (lane >> 3);
     const bool inimg = u < c.W && v < c.H;
-    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     bool valid = false;
     if (inimg) {
@@ -339,13 +368,11 @@ __global__ void __launch_bounds__(256) k_associate(DevCam c, float tau, const fl
     // per-workgroup counts go to this workgroup's own slot (no shared counter:
     // device-wide atomics on one address serialise across the chip)
     const unsigned long long vb = __ballot(valid), ab = __ballot(best >= 0), fb = __ballot(first);
-    if (lane == 0) b.bstat[blockIdx.x] = make_int4(__popcll(vb), __popcll(ab), __popcll(fb), 0);
+    if (lane == 0) b.bstat[tile] = make_int4(__popcll(vb), __popcll(ab), __popcll(fb), 0);
 }
 
-void launch_associate(hipStream_t s, const DevCam& c, float tau, const float* depth, const float* xyz,
-                      const Buckets& b, const Accum& a, const float4* verts, int32_t* assoc) {
-    hipLaunchKernelGGL(k_associate, dim3(c.tiles_x * c.tiles_y), dim3(256), 0, s, c, tau, depth, xyz, b, a, verts,
-                       assoc);
+void launch_associate(const Launch& L, int vsel) {
+    hipLaunchKernelGGL(k_associate, dim3(L.grid[KK_TILE]), dim3(256), 0, L.s, L.B, vsel);
 }
 
 }  // namespace trk

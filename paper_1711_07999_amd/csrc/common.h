@@ -53,8 +53,6 @@ struct DevStats {
 // Offset and normal buffers: SoA x, y, z of V floats each (skinned vertices
 // are float4 (x, y, z, 0) so that neighbour gathers are single loads).
 struct Vec3Buf { float *x, *y, *z; };
-struct CVec3Buf { const float *x, *y, *z; };
-inline CVec3Buf cview(const Vec3Buf& b) { return {b.x, b.y, b.z}; }
 
 // Fixed-point per-vertex accumulators of the association.
 struct Accum {
@@ -79,28 +77,136 @@ struct Buckets {
     int4* bstat;       // [tiles] valid, matched, newly observed pixels per tile
 };
 
-// Association launch shape: one workgroup per 8x8 tile.
-inline int assoc_blocks(int tiles_x, int tiles_y) { return tiles_x * tiles_y; }
+// Summary of one frame, written by the frame-end kernel.
+struct DevSummary {
+    int status, n_valid_px, n_assoc_px, n_obs_verts;
+    float energy_first, energy_last, step_norm_last;
+    int reason;   // 0 ok, 1 not positive definite, 2 no valid pixel, 3 nothing matched, 4/5 diverged
+};
+
+// ---------------------------------------------------------------------------
+// Slot table.  Every kernel works on a batch of tracking streams ("slots"):
+// its grid is the concatenation of each slot's own grid, and a workgroup finds
+// its slot by a binary search of the per-kind workgroup prefix.  A single
+// tracker is a batch of one.  The table is rewritten by the host before each
+// frame; kernels address the double-buffered vertices and the triple-buffered
+// offsets relative to the frame-start indices held in the table, so one
+// captured frame serves every starting state.
+// ---------------------------------------------------------------------------
+constexpr int kSlotBeginFrame = 1;    // the launch starts a frame of this slot
+constexpr int kSlotEndFrame = 2;      // the launch ends a frame of this slot
+constexpr int kSlotRefreshPose = 4;   // redo forward kinematics at frame start
+
+struct Slot {
+    DevModel m;
+    DevCam c;
+    const JointTable* jt;
+    const uint32_t* anc;          // [L*4] joints on each link's chain
+    Buckets b;
+    Accum a;
+    float* dq;                    // [L*8] link offsets
+    float* xi;                    // [P*8] world joint generators
+    double *theta, *theta_backup, *step, *gram;
+    float* partials;              // [negrid][PP*PP]
+    float4* verts[2];
+    Vec3Buf normals;
+    Vec3Buf phi[3];
+    const float* depth;           // frame input: depth image ...
+    const float* xyz;             // ... or organised point cloud (the other is null)
+    int32_t* assoc;
+    DevStats* st;
+    DevSummary* summary;
+    int PP, npad, negrid, flags;
+    float tau, lambda_k, lphi, lnbr, lt, lw;
+    int v_cur;                    // current vertex buffer when the launch starts
+    int phi_cur, phi_prev;        // current and previous-frame offset buffers
+    int iter;                     // iteration of the frame the launch starts at
+};
+
+// Offset buffer written by the step after `src` (never the previous frame's
+// buffer, so a failed frame can return to it).
+__host__ __device__ __forceinline__ int phi_next(int src, int prev) {
+    int n = 0;
+    while (n == src || n == prev) ++n;
+    return n;
+}
+
+// offset buffer current after `n` offset steps of the frame
+__host__ __device__ __forceinline__ int phi_index(const Slot& S, int n) {
+    int q = S.phi_cur;
+    for (int k = 0; k < n; ++k) q = phi_next(q, S.phi_prev);
+    return q;
+}
+
+enum KernelKind {
+    KK_ONE = 0,     // one workgroup per slot (frame bookkeeping, FK, tile scan, solve)
+    KK_VERT,        // ceil(V / 256) workgroups
+    KK_VERT4,       // ceil(4 V / 256)
+    KK_CLEAR,       // ceil(max(Npad, V) / 256)
+    KK_TILE4,       // ceil(tiles / 4): one wave per tile
+    KK_TILE,        // tiles: one workgroup per tile
+    KK_NE,          // normal-equation workgroups
+    KK_REDUCE,      // Gram reduction workgroups
+    KK_COUNT_
+};
+
+struct Batch {
+    const Slot* slots;   // [n] device table
+    const int* pre;      // [KK_COUNT_][n + 1] exclusive prefix of workgroups per slot
+    int n;
+};
+
+// host-side launch description: the batch and its grid per kernel kind
+struct Launch {
+    Batch B;
+    int grid[KK_COUNT_];
+    hipStream_t s;
+};
+
+// slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
+__device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& local) {
+    const int* p = B.pre + kind * (B.n + 1);
+    int lo = 0, hi = B.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (p[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    local = blk - p[lo];
+    return lo;
+}
+
+int ne_grid(int V);
+
+// workgroups of each kind for one slot (host side)
+inline int slot_blocks(const Slot& s, int kind) {
+    const int V = s.m.V, ntiles = s.c.tiles_x * s.c.tiles_y;
+    switch (kind) {
+        case KK_ONE: return 1;
+        case KK_VERT: return (V + 255) / 256;
+        case KK_VERT4: return (4 * V + 255) / 256;
+        case KK_CLEAR: return ((s.npad > V ? s.npad : V) + 255) / 256;
+        case KK_TILE4: return (ntiles + 3) / 4;
+        case KK_TILE: return ntiles;
+        case KK_NE: return s.negrid;
+        case KK_REDUCE: { int nb = s.PP >> 4; return nb * (nb + 1) / 2 * 8; }
+    }
+    return 0;
+}
 
 // ---- launchers (each defined next to its kernels) -------------------------
-void launch_fk(hipStream_t s, const JointTable* jt, const double* theta, float* dq, float* xi);
-void launch_skin(hipStream_t s, const DevModel& m, const float* dq, CVec3Buf phi, float4* v);
-void launch_normals(hipStream_t s, const DevModel& m, const float4* v, Vec3Buf n);
-void launch_clear(hipStream_t s, int npad, const Buckets& b, int V, const Accum& a, DevStats* st);
-void launch_bucket(hipStream_t s, const DevCam& c, int V, const float4* v, const Buckets& b);
-void launch_associate(hipStream_t s, const DevCam& c, float tau, const float* depth, const float* xyz,
-                      const Buckets& b, const Accum& a, const float4* verts, int32_t* assoc);
-int ne_grid(int V);
-void launch_normal_eq(hipStream_t s, const DevModel& m, int PP, int gram_mode, const float* dq,
-                      const float* xi, const uint32_t* anc_dev, const float4* v, CVec3Buf n, CVec3Buf phi,
-                      const Accum& a, float* partials, int grid);
-void launch_gram_reduce(hipStream_t s, int PP, int nparts, const float* partials, double* gram);
-void launch_pose_solve(hipStream_t s, const JointTable* jt, int PP, const double* gram, float lambda_k,
-                       int fp64, double* theta, double* step, DevStats* st, int iter, float* dq, float* xi);
-void launch_shape(hipStream_t s, const DevModel& m, const float* dq, const float4* v_old, const float4* v_new,
-                  CVec3Buf n, const Accum& a, CVec3Buf phi, CVec3Buf phi_prev, Vec3Buf phi_out,
-                  float lphi, float lnbr, float lt, float lw, int fp64);
-void launch_copy3(hipStream_t s, int V, CVec3Buf src, Vec3Buf dst);
-void launch_frame_begin(hipStream_t s, int P, const double* theta, double* theta_backup, DevStats* st);
+// vsel: 0 = the slot's frame-start vertex buffer, 1 = the other one;
+// pn: number of offset steps taken so far in the frame (see phi_index).
+void launch_frame_begin(const Launch& L);
+void launch_frame_end(const Launch& L, int first_pose, int last_pose);  // iterations of the frame, -1 = none
+void launch_fk(const Launch& L);
+void launch_skin(const Launch& L, int vsel, int pn);
+void launch_normals(const Launch& L, int vsel);
+void launch_clear(const Launch& L);
+void launch_bucket(const Launch& L, int vsel);
+void launch_associate(const Launch& L, int vsel);
+void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
+void launch_gram_reduce(const Launch& L);
+void launch_pose_solve(const Launch& L, int fp64, int iter);
+void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn);
 
 }  // namespace trk

@@ -1,29 +1,54 @@
-// Forward kinematics, blend skinning and vertex normals (Sections 3.1, 3.2).
+// Forward kinematics, blend skinning and vertex normals (Sections 3.1, 3.2),
+// and the per-frame bookkeeping kernels, over a batch of slots.
 #include "common.h"
 #include "dq.h"
 #include "fk.h"
 
 namespace trk {
 
-__global__ void __launch_bounds__(128) k_fk(const JointTable* jt, const double* theta, float* dq, float* xi) {
-    fk_block(jt, theta, dq, xi);
+// ---------------------------------------------------------------------------
+// frame start: keep the pose for a rollback, clear the status flag and (when
+// the slot asks for it) redo forward kinematics at the current pose
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(128) k_frame_begin(Batch B) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
+    if (!(S.flags & kSlotBeginFrame)) return;
+    const int P = S.m.P;
+    for (int k = threadIdx.x; k < P; k += blockDim.x) S.theta_backup[k] = S.theta[k];
+    if (threadIdx.x == 0) S.st->status = 0;
+    if (S.flags & kSlotRefreshPose) fk_block(S.jt, S.theta, S.dq, S.xi);
 }
 
-void launch_fk(hipStream_t s, const JointTable* jt, const double* theta, float* dq, float* xi) {
-    hipLaunchKernelGGL(k_fk, dim3(1), dim3(128), 0, s, jt, theta, dq, xi);
+void launch_frame_begin(const Launch& L) {
+    hipLaunchKernelGGL(k_frame_begin, dim3(L.grid[KK_ONE]), dim3(128), 0, L.s, L.B);
+}
+
+__global__ void __launch_bounds__(128) k_fk(Batch B) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
+    fk_block(S.jt, S.theta, S.dq, S.xi);
+}
+
+void launch_fk(const Launch& L) {
+    hipLaunchKernelGGL(k_fk, dim3(L.grid[KK_ONE]), dim3(128), 0, L.s, L.B);
 }
 
 // ---------------------------------------------------------------------------
 // Skinning (Eq. 3 and 5): v_i = T(sum_j w_ij H_{j,Delta}, v0_i + phi_i), one
 // vertex per lane, link offsets staged in LDS, coalesced SoA streams.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_skin(DevModel m, const float* __restrict__ dq, CVec3Buf phi,
-                                              float4* __restrict__ v) {
+__global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
-    for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = dq[q];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const DevModel& m = S.m;
+    for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
     __syncthreads();
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = local * blockDim.x + threadIdx.x;
     if (i >= m.V) return;
+    const Vec3Buf phi = S.phi[phi_index(S, pn)];
+    float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
     float H[8];
     dq_blend(sdq, m.w[i], m.links[i], H);
     float x = m.rx[i] + phi.x[i], y = m.ry[i] + phi.y[i], z = m.rz[i] + phi.z[i];
@@ -32,9 +57,8 @@ __global__ void __launch_bounds__(256) k_skin(DevModel m, const float* __restric
     v[i] = make_float4(ox, oy, oz, 0.0f);
 }
 
-void launch_skin(hipStream_t s, const DevModel& m, const float* dq, CVec3Buf phi, float4* v) {
-    int grid = (m.V + 255) / 256;
-    hipLaunchKernelGGL(k_skin, dim3(grid), dim3(256), 0, s, m, dq, phi, v);
+void launch_skin(const Launch& L, int vsel, int pn) {
+    hipLaunchKernelGGL(k_skin, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel, pn);
 }
 
 // ---------------------------------------------------------------------------
@@ -45,8 +69,12 @@ void launch_skin(hipStream_t s, const DevModel& m, const float* dq, CVec3Buf phi
 // ---------------------------------------------------------------------------
 constexpr int kNormLanes = 4;
 
-__global__ void __launch_bounds__(256) k_normals(DevModel m, const float4* __restrict__ v, Vec3Buf n) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(256) k_normals(Batch B, int vsel) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_VERT4, blockIdx.x, local)];
+    const DevModel& m = S.m;
+    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
+    const int t = local * blockDim.x + threadIdx.x;
     const int i = t / kNormLanes, sub = t % kNormLanes;
     const bool live = i < m.V;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
@@ -72,33 +100,67 @@ __global__ void __launch_bounds__(256) k_normals(DevModel m, const float4* __res
     if (!live || sub != 0) return;
     float l = sqrtf(sx * sx + sy * sy + sz * sz);
     float inv = l > 0.0f ? 1.0f / l : 0.0f;
-    n.x[i] = sx * inv; n.y[i] = sy * inv; n.z[i] = sz * inv;
+    S.normals.x[i] = sx * inv; S.normals.y[i] = sy * inv; S.normals.z[i] = sz * inv;
 }
 
-void launch_normals(hipStream_t s, const DevModel& m, const float4* v, Vec3Buf n) {
-    int grid = (m.V * kNormLanes + 255) / 256;
-    hipLaunchKernelGGL(k_normals, dim3(grid), dim3(256), 0, s, m, v, n);
+void launch_normals(const Launch& L, int vsel) {
+    hipLaunchKernelGGL(k_normals, dim3(L.grid[KK_VERT4]), dim3(256), 0, L.s, L.B, vsel);
 }
 
-__global__ void k_copy3(int V, CVec3Buf src, Vec3Buf dst) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V) return;
-    dst.x[i] = src.x[i]; dst.y[i] = src.y[i]; dst.z[i] = src.z[i];
+// ---------------------------------------------------------------------------
+// frame end: the health check of the frame (solver failure, no valid pixel,
+// no matched pixel, non-finite pose or energy); on failure the pose is rolled
+// back to the frame's start (the offsets are rolled back by the host, which
+// keeps the frame-start offset buffer untouched).  The per-tile counts of the
+// last association are summed into the slot's summary.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int last_pose) {
+    __shared__ int s_sum[3][256];
+    __shared__ int s_bad;
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
+    if (!(S.flags & kSlotEndFrame)) return;
+    const int tid = threadIdx.x;
+    const int ntiles = S.c.tiles_x * S.c.tiles_y;
+    int nv = 0, na = 0, no = 0;
+    for (int t = tid; t < ntiles; t += 256) {
+        const int4 b = S.b.bstat[t];
+        nv += b.x; na += b.y; no += b.z;
+    }
+    s_sum[0][tid] = nv; s_sum[1][tid] = na; s_sum[2][tid] = no;
+    if (tid == 0) s_bad = 0;
+    __syncthreads();
+    for (int k = tid; k < S.m.P; k += 256)
+        if (!isfinite(S.theta[k])) s_bad = 1;
+    __syncthreads();
+    if (tid == 0) {
+        nv = na = no = 0;
+        for (int q = 0; q < 256; ++q) { nv += s_sum[0][q]; na += s_sum[1][q]; no += s_sum[2][q]; }
+        DevStats* st = S.st;
+        DevSummary& out = *S.summary;
+        out.n_valid_px = nv;
+        out.n_assoc_px = na;
+        out.n_obs_verts = no;
+        out.energy_first = first_pose >= 0 ? st->energy[first_pose] : 0.0f;
+        out.energy_last = last_pose >= 0 ? st->energy[last_pose] : 0.0f;
+        out.step_norm_last = last_pose >= 0 ? st->step_norm[last_pose] : 0.0f;
+        int status = 0, why = 0;
+        if (st->status == -4) { status = -4; why = 1; }
+        else if (nv == 0) { status = -5; why = 2; }
+        else if (na == 0) { status = -5; why = 3; }
+        else if (s_bad) { status = -5; why = 4; }
+        else if (!isfinite(out.energy_last)) { status = -5; why = 5; }
+        out.status = status;
+        out.reason = why;
+        s_bad = status != 0;
+    }
+    __syncthreads();
+    if (s_bad)
+        for (int k = tid; k < S.m.P; k += 256) S.theta[k] = S.theta_backup[k];
 }
 
-// frame start: keep the pose for a rollback, clear the status flag (a kernel,
-// not a memset, so that the frame can be captured in a graph)
-__global__ void k_frame_begin(int P, const double* theta, double* theta_backup, DevStats* st) {
-    for (int k = threadIdx.x; k < P; k += blockDim.x) theta_backup[k] = theta[k];
-    if (threadIdx.x == 0) st->status = 0;
-}
-
-void launch_frame_begin(hipStream_t s, int P, const double* theta, double* theta_backup, DevStats* st) {
-    hipLaunchKernelGGL(k_frame_begin, dim3(1), dim3(128), 0, s, P, theta, theta_backup, st);
-}
-
-void launch_copy3(hipStream_t s, int V, CVec3Buf src, Vec3Buf dst) {
-    hipLaunchKernelGGL(k_copy3, dim3((V + 255) / 256), dim3(256), 0, s, V, src, dst);
+void launch_frame_end(const Launch& L, int first_pose, int last_pose) {
+    hipLaunchKernelGGL(k_frame_end, dim3(L.grid[KK_ONE]), dim3(256), 0, L.s, L.B, first_pose, last_pose);
 }
 
 }  // namespace trk

@@ -43,7 +43,7 @@ __device__ __forceinline__ void block_of(int idx, int nb, int& I, int& J) {
 
 // per-vertex 6-vectors of the Jacobian (one per influence) and the residual
 __device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq, int i, const float4* v,
-                                             CVec3Buf n, CVec3Buf phi, const Accum& a, float* G,
+                                             const Vec3Buf& n, const Vec3Buf& phi, const Accum& a, float* G,
                                              float& r_out) {
     float H[8], sg[4];
     const float4 w = m.w[i];
@@ -98,11 +98,7 @@ __device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(256) k_normal_eq(DevModel m, int PP, const float* __restrict__ dq,
-                                                   const float* __restrict__ xi,
-                                                   const uint32_t* __restrict__ anc, const float4* __restrict__ v, CVec3Buf n,
-                                                   CVec3Buf phi, Accum a, float* __restrict__ partials,
-                                                   int nchunks) {
+__global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     __shared__ float sxi[6 * kPPMax];
     __shared__ uint32_t sanc[4 * (kMaxLinks + 1)];
@@ -117,6 +113,18 @@ __global__ void __launch_bounds__(256) k_normal_eq(DevModel m, int PP, const flo
     __bf16* plane1 = plane0 + kPPMax * kJTStride;
     __bf16* plane2 = plane1 + kPPMax * kJTStride;
 
+    int wg;
+    const Slot& S = B.slots[slot_of(B, KK_NE, blockIdx.x, wg)];
+    const DevModel& m = S.m;
+    const int PP = S.PP;
+    const float* __restrict__ dq = S.dq;
+    const float* __restrict__ xi = S.xi;
+    const uint32_t* __restrict__ anc = S.anc;
+    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
+    const Vec3Buf n = S.normals;
+    const Vec3Buf phi = S.phi[phi_index(S, pn)];
+    const Accum& a = S.a;
+    const int nchunks = (m.V + kNeRows - 1) / kNeRows;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int P = m.P;
     for (int q = tid; q < 8 * m.L; q += 256) sdq[q] = dq[q];
@@ -130,7 +138,7 @@ __global__ void __launch_bounds__(256) k_normal_eq(DevModel m, int PP, const flo
     for (int q = 0; q < 9; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     __syncthreads();
 
-    for (int chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    for (int chunk = wg; chunk < nchunks; chunk += S.negrid) {
         __syncthreads();  // the previous chunk's tile and counts are consumed
         // 1. compact the observed vertices of this chunk
         bool obs = false;
@@ -235,7 +243,7 @@ __global__ void __launch_bounds__(256) k_normal_eq(DevModel m, int PP, const flo
     }
 
     // 4. this workgroup's partial Gram (upper blocks only)
-    float* out = partials + (size_t)blockIdx.x * PP * PP;
+    float* out = S.partials + (size_t)wg * PP * PP;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int idx = wid + 4 * q;
@@ -257,19 +265,14 @@ int ne_grid(int V) {
     return nchunks < 256 ? nchunks : 256;
 }
 
-void launch_normal_eq(hipStream_t s, const DevModel& m, int PP, int gram_mode, const float* dq,
-                      const float* xi, const uint32_t* anc_dev, const float4* v, CVec3Buf n, CVec3Buf phi,
-                      const Accum& a, float* partials, int grid) {
-    int nchunks = (m.V + kNeRows - 1) / kNeRows;
+void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
+    const dim3 g(L.grid[KK_NE]);
     if (gram_mode == 0)
-        hipLaunchKernelGGL(k_normal_eq<0>, dim3(grid), dim3(256), 0, s, m, PP, dq, xi, anc_dev, v, n, phi, a,
-                           partials, nchunks);
+        hipLaunchKernelGGL(k_normal_eq<0>, g, dim3(256), 0, L.s, L.B, vsel, pn);
     else if (gram_mode == 1)
-        hipLaunchKernelGGL(k_normal_eq<1>, dim3(grid), dim3(256), 0, s, m, PP, dq, xi, anc_dev, v, n, phi, a,
-                           partials, nchunks);
+        hipLaunchKernelGGL(k_normal_eq<1>, g, dim3(256), 0, L.s, L.B, vsel, pn);
     else
-        hipLaunchKernelGGL(k_normal_eq<2>, dim3(grid), dim3(256), 0, s, m, PP, dq, xi, anc_dev, v, n, phi, a,
-                           partials, nchunks);
+        hipLaunchKernelGGL(k_normal_eq<2>, g, dim3(256), 0, L.s, L.B, vsel, pn);
 }
 
 // Sum of the partial Gram matrices in workgroup order, in float64; writes the
@@ -277,12 +280,16 @@ void launch_normal_eq(hipStream_t s, const DevModel& m, int PP, int gram_mode, c
 // result is exactly symmetric).  A workgroup handles 32 elements of one
 // 16x16 block; each element's partials are split into 8 contiguous groups
 // summed by 8 threads, and the 8 group sums are added in group order.
-__global__ void __launch_bounds__(256) k_gram_reduce(int PP, int nparts, const float* __restrict__ partials,
-                                                     double* __restrict__ gram) {
+__global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
     __shared__ double part[8][32];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_REDUCE, blockIdx.x, local)];
+    const int PP = S.PP, nparts = S.negrid;
+    const float* __restrict__ partials = S.partials;
+    double* __restrict__ gram = S.gram;
     const int nb = PP >> 4;
-    const int blk = blockIdx.x >> 3;          // 8 workgroups per 16x16 block
-    const int el = (blockIdx.x & 7) * 32 + (threadIdx.x & 31);
+    const int blk = local >> 3;               // 8 workgroups per 16x16 block
+    const int el = (local & 7) * 32 + (threadIdx.x & 31);
     const int grp = threadIdx.x >> 5;
     int I, J;
     block_of(blk, nb, I, J);
@@ -311,10 +318,8 @@ __global__ void __launch_bounds__(256) k_gram_reduce(int PP, int nparts, const f
     }
 }
 
-void launch_gram_reduce(hipStream_t s, int PP, int nparts, const float* partials, double* gram) {
-    int nb = PP >> 4;
-    int nblocks = nb * (nb + 1) / 2 * 8;
-    hipLaunchKernelGGL(k_gram_reduce, dim3(nblocks), dim3(256), 0, s, PP, nparts, partials, gram);
+void launch_gram_reduce(const Launch& L) {
+    hipLaunchKernelGGL(k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(256), 0, L.s, L.B);
 }
 
 }  // namespace trk

@@ -26,10 +26,7 @@ constexpr int kNBMax = (kMaxJoints + 1) / kBS;  // 16 blocks per side
 constexpr int kPanelStride = kBS * kBS + 1;
 
 template <class T>
-__global__ void __launch_bounds__(256) k_pose_solve(const JointTable* __restrict__ jt, int PP,
-                                                    const double* __restrict__ gram, float lambda_k,
-                                                    double* __restrict__ theta, double* __restrict__ step,
-                                                    DevStats* st, int iter, float* dq, float* xi) {
+__global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
     // L blocks of the current panel column; block stride kBS*kBS + 1 keeps the
     // 16 column-block reads of a wave on distinct LDS banks
     __shared__ T s_panel[kNBMax * kPanelStride];
@@ -38,6 +35,15 @@ __global__ void __launch_bounds__(256) k_pose_solve(const JointTable* __restrict
     __shared__ int s_frozen[kNBMax * kBS];
     __shared__ int s_fail;
     __shared__ double s_nrm[256];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
+    const JointTable* __restrict__ jt = S.jt;
+    const int PP = S.PP;
+    const double* __restrict__ gram = S.gram;
+    const float lambda_k = S.lambda_k;
+    double* __restrict__ theta = S.theta;
+    double* __restrict__ step = S.step;
+    DevStats* st = S.st;
     const int P = jt->P;
     const int NB = (P + kBS - 1) / kBS;
     const int tid = threadIdx.x;
@@ -195,26 +201,23 @@ __global__ void __launch_bounds__(256) k_pose_solve(const JointTable* __restrict
         if (tid == 0) {
             double s = 0.0;
             for (int q = 0; q < 256; ++q) s += s_nrm[q];
-            st->step_norm[iter] = (float)sqrt(s);
-            st->energy[iter] = (float)gram[P * PP + P];
+            st->step_norm[S.iter + iter] = (float)sqrt(s);
+            st->energy[S.iter + iter] = (float)gram[P * PP + P];
         }
     } else if (tid == 0) {
         st->status = -4;
-        st->energy[iter] = (float)gram[P * PP + P];
-        st->step_norm[iter] = 0.0f;
+        st->energy[S.iter + iter] = (float)gram[P * PP + P];
+        st->step_norm[S.iter + iter] = 0.0f;
     }
     __syncthreads();
-    fk_block(jt, theta, dq, xi);
+    fk_block(jt, theta, S.dq, S.xi);
 }
 
-void launch_pose_solve(hipStream_t s, const JointTable* jt, int PP, const double* gram, float lambda_k,
-                       int fp64, double* theta, double* step, DevStats* st, int iter, float* dq, float* xi) {
+void launch_pose_solve(const Launch& L, int fp64, int iter) {
     if (fp64)
-        hipLaunchKernelGGL(k_pose_solve<double>, dim3(1), dim3(256), 0, s, jt, PP, gram, lambda_k, theta, step, st,
-                           iter, dq, xi);
+        hipLaunchKernelGGL(k_pose_solve<double>, dim3(L.grid[KK_ONE]), dim3(256), 0, L.s, L.B, iter);
     else
-        hipLaunchKernelGGL(k_pose_solve<float>, dim3(1), dim3(256), 0, s, jt, PP, gram, lambda_k, theta, step, st,
-                           iter, dq, xi);
+        hipLaunchKernelGGL(k_pose_solve<float>, dim3(L.grid[KK_ONE]), dim3(256), 0, L.s, L.B, iter);
 }
 
 // ---------------------------------------------------------------------------
@@ -242,14 +245,23 @@ __device__ __forceinline__ void solve3(const T M[9], const T g[3], T x[3]) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_shape(DevModel m, const float* __restrict__ dq, const float4* __restrict__ v_old,
-                                               const float4* __restrict__ v_new, CVec3Buf n, Accum a, CVec3Buf phi,
-                                               CVec3Buf phi_prev, Vec3Buf phi_out, float lphi, float lnbr,
-                                               float lt, float lw) {
+__global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
-    for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = dq[q];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const DevModel& m = S.m;
+    const float4* __restrict__ v_old = S.verts[S.v_cur ^ vo_sel];
+    const float4* __restrict__ v_new = S.verts[S.v_cur ^ vn_sel];
+    const Vec3Buf n = S.normals;
+    const Accum& a = S.a;
+    const int src = phi_index(S, pn);
+    const Vec3Buf phi = S.phi[src];
+    const Vec3Buf phi_prev = S.phi[S.phi_prev];
+    const Vec3Buf phi_out = S.phi[phi_next(src, S.phi_prev)];
+    const float lphi = S.lphi, lnbr = S.lnbr, lt = S.lt, lw = S.lw;
+    for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
     __syncthreads();
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = local * blockDim.x + threadIdx.x;
     if (i >= m.V) return;
     const T px = phi.x[i], py = phi.y[i], pz = phi.z[i];
     T u[3] = {T(0), T(0), T(0)};
@@ -298,16 +310,12 @@ __global__ void __launch_bounds__(256) k_shape(DevModel m, const float* __restri
     phi_out.z[i] = (float)(pz - xs[2]);
 }
 
-void launch_shape(hipStream_t s, const DevModel& m, const float* dq, const float4* v_old, const float4* v_new,
-                  CVec3Buf n, const Accum& a, CVec3Buf phi, CVec3Buf phi_prev, Vec3Buf phi_out,
-                  float lphi, float lnbr, float lt, float lw, int fp64) {
-    int grid = (m.V + 255) / 256;
+void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn) {
+    const dim3 g(L.grid[KK_VERT]);
     if (fp64)
-        hipLaunchKernelGGL(k_shape<double>, dim3(grid), dim3(256), 0, s, m, dq, v_old, v_new, n, a, phi, phi_prev,
-                           phi_out, lphi, lnbr, lt, lw);
+        hipLaunchKernelGGL(k_shape<double>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn);
     else
-        hipLaunchKernelGGL(k_shape<float>, dim3(grid), dim3(256), 0, s, m, dq, v_old, v_new, n, a, phi, phi_prev,
-                           phi_out, lphi, lnbr, lt, lw);
+        hipLaunchKernelGGL(k_shape<float>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn);
 }
 
 }  // namespace trk

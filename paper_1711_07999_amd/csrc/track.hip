@@ -1,5 +1,13 @@
-// Host runtime and C ABI of libtrack: model preparation, device memory,
-// the per-frame iteration schedule (Section 4) and per-pass access.
+// Host runtime and C ABI of libtrack: model preparation, device memory, the
+// per-frame iteration schedule (Section 4), the batched serving loop and
+// per-pass access.
+//
+// Every kernel runs over a batch of tracking streams described by a device
+// slot table (common.h).  A context (track_ctx) is a batch of one whose
+// frames are captured once as HIP graphs and replayed; a server
+// (track_server) batches every resident stream into the same launches, one
+// Gauss-Newton iteration per step, so streams join and leave at iteration
+// boundaries.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -7,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -44,139 +53,6 @@ void hdq_mul(const double* a, const double* b, double* o) {
     hq_mul(a, b + 4, d1);
     hq_mul(a + 4, b, d2);
     for (int c = 0; c < 4; ++c) { o[c] = r[c]; o[4 + c] = d1[c] + d2[c]; }
-}
-
-// A captured frame: the kernel sequence depends on which ping-pong buffers
-// are current when the frame starts, so graphs are cached per starting state.
-struct FrameGraph {
-    int v0, p0, s0, mode;       // key: vertex buffer, offset buffer, surface valid, input kind
-    unsigned tmask;             // key: kernels timed with events inside the graph
-    int v1, p1, s1;             // state after the frame
-    hipGraphExec_t exec;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> tev;  // (kernel, start/stop)
-    hipEvent_t pending[TRACK_K_COUNT_];
-};
-
-struct KernelTimer {
-    bool on = false;
-    std::vector<hipEvent_t> ev;  // pairs
-    size_t used = 0;
-    int64_t launches = 0;
-    double total_ms = 0.0;
-};
-
-}  // namespace
-
-struct track_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int P = 0, L = 0, V = 0, F = 0, K = 0, PP = 0, W = 0, H = 0, npad = 0, ntiles = 0, negrid = 0;
-    // constants
-    float tau = 0.05f;
-    int n_iters = 1;
-    std::vector<uint8_t> do_pose, do_shape, active;
-    float lambda_k = 0, lambda_s = 0, lambda_phi = 0, lambda_nbr = 0, lambda_t = 0, lambda_w = 0;
-    int gram_mode = 0, pose_fp64 = 0, shape_fp64 = 0;
-    std::vector<double> prior_S;  // S_k (vertex share per joint)
-    // model tables
-    JointTable hjt{};
-    JointTable* djt = nullptr;
-    DevModel dm{};
-    DevCam dc{};
-    // device memory
-    void* arena = nullptr;
-    size_t arena_bytes = 0, arena_used = 0;
-    double *theta = nullptr, *theta_backup = nullptr, *step = nullptr, *gram = nullptr;
-    float *dq = nullptr, *xi = nullptr, *partials = nullptr, *depth_buf = nullptr, *xyz_buf = nullptr;
-    uint32_t* anc = nullptr;
-    Vec3Buf phi[2]{}, phi_prev{}, normals{};
-    float4* verts[2]{};
-    int phi_cur = 0, v_cur = 0;
-    bool surface_valid = false;
-    int input_mode = 0;  // 0 depth, 1 xyz (for the per-pass interface)
-    Buckets bk{};
-    Accum acc{};
-    int32_t* assoc = nullptr;
-    DevStats* dstats = nullptr;
-    DevStats* hstats = nullptr;  // pinned
-    double* htheta = nullptr;    // pinned
-    int4* hbstat = nullptr;      // pinned, per association workgroup
-    int nassoc = 0;              // association workgroups
-    track_frame_stats last{};
-    hipEvent_t f0 = nullptr, f1 = nullptr;
-    KernelTimer timers[TRACK_K_COUNT_];
-    bool use_graphs = true;
-    std::vector<FrameGraph> graphs;
-    FrameGraph* capturing = nullptr;  // graph under construction
-    int last_graph = -1;              // graph launched by the last frame, -1 = none
-};
-
-namespace {
-
-template <class T>
-T* carve(track_ctx* c, size_t n) {
-    size_t bytes = (n * sizeof(T) + 255) & ~size_t(255);
-    T* p = reinterpret_cast<T*>(static_cast<char*>(c->arena) + c->arena_used);
-    c->arena_used += bytes;
-    return p;
-}
-
-void drop_graphs(track_ctx* c);
-
-void timed_begin(track_ctx* c, int k) {
-    KernelTimer& t = c->timers[k];
-    if (!t.on) return;
-    if (c->capturing) {  // events of a captured frame belong to its graph
-        hipEvent_t e;
-        if (hipEventCreate(&e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess) c->capturing->pending[k] = e;
-        else c->capturing->pending[k] = nullptr;
-        return;
-    }
-    if (t.used + 2 > t.ev.size()) {
-        for (int q = 0; q < 64; ++q) {
-            hipEvent_t e;
-            if (hipEventCreate(&e) == hipSuccess) t.ev.push_back(e);
-        }
-    }
-    if (t.used + 2 <= t.ev.size()) (void)hipEventRecord(t.ev[t.used], c->stream);
-}
-void timed_end(track_ctx* c, int k) {
-    KernelTimer& t = c->timers[k];
-    if (!t.on) return;
-    if (c->capturing) {
-        hipEvent_t e;
-        hipEvent_t b = c->capturing->pending[k];
-        if (b && hipEventCreate(&e) == hipSuccess && hipEventRecord(e, c->stream) == hipSuccess)
-            c->capturing->tev.push_back({k, {b, e}});
-        return;
-    }
-    if (t.used + 2 > t.ev.size()) return;
-    (void)hipEventRecord(t.ev[t.used + 1], c->stream);
-    t.used += 2;
-}
-// called after a stream synchronisation: fold the recorded pairs into totals
-void timed_collect(track_ctx* c) {
-    for (auto& t : c->timers) {
-        for (size_t q = 0; q + 1 < t.used; q += 2) {
-            float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, t.ev[q], t.ev[q + 1]) == hipSuccess) {
-                t.total_ms += ms;
-                t.launches += 1;
-            }
-        }
-        t.used = 0;
-    }
-    if (c->last_graph >= 0) {
-        for (auto& te : c->graphs[c->last_graph].tev) {
-            float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, te.second.first, te.second.second) == hipSuccess) {
-                c->timers[te.first].total_ms += ms;
-                c->timers[te.first].launches += 1;
-            }
-        }
-        c->last_graph = -1;
-    }
 }
 
 // 4 nearest template vertices (ties: lower index) through a uniform grid
@@ -221,37 +97,6 @@ std::vector<int> nearest4(const float* xyz, int V) {
         for (int q = 0; q < 4 && q < (int)cand.size(); ++q) out[4 * (size_t)i + q] = cand[q].second;
     }
     return out;
-}
-
-int set_params(track_ctx* c, const track_params* p) {
-    if (!p) return fail(TRACK_E_INVALID, "params is NULL");
-    if (!(p->tau > 0.0f) || !std::isfinite(p->tau)) return fail(TRACK_E_INVALID, "tau must be > 0");
-    if (p->n_iters < 1 || p->n_iters > 256) return fail(TRACK_E_INVALID, "n_iters must be in 1..256");
-    if (!p->do_pose || !p->do_shape) return fail(TRACK_E_INVALID, "do_pose/do_shape are required");
-    if (p->gram_mode != TRACK_GRAM_FP32 && p->gram_mode != TRACK_GRAM_BF16X3 && p->gram_mode != TRACK_GRAM_BF16X6)
-        return fail(TRACK_E_INVALID, "unknown gram_mode");
-    const float lam[6] = {p->lambda_k, p->lambda_s, p->lambda_phi, p->lambda_nbr, p->lambda_t, p->lambda_w};
-    for (float l : lam)
-        if (!(l >= 0.0f) || !std::isfinite(l)) return fail(TRACK_E_INVALID, "weights must be finite and >= 0");
-    c->tau = p->tau;
-    c->n_iters = p->n_iters;
-    c->do_pose.assign(p->do_pose, p->do_pose + p->n_iters);
-    c->do_shape.assign(p->do_shape, p->do_shape + p->n_iters);
-    c->active.assign(c->P, 1);
-    if (p->active) c->active.assign(p->active, p->active + c->P);
-    c->lambda_k = p->lambda_k; c->lambda_s = p->lambda_s; c->lambda_phi = p->lambda_phi;
-    c->lambda_nbr = p->lambda_nbr; c->lambda_t = p->lambda_t; c->lambda_w = p->lambda_w;
-    c->gram_mode = p->gram_mode;
-    drop_graphs(c);
-    c->pose_fp64 = p->pose_solve_fp64 ? 1 : 0;
-    c->shape_fp64 = p->shape_solve_fp64 ? 1 : 0;
-    for (int k = 0; k < c->P; ++k) {
-        double w = (double)c->lambda_s * c->prior_S[k];
-        c->hjt.prior[k] = w * w;
-        c->hjt.active[k] = c->active[k] ? 1 : 0;
-    }
-    if (c->djt) HIP_TRY(hipMemcpy(c->djt, &c->hjt, sizeof(JointTable), hipMemcpyHostToDevice));
-    return TRACK_OK;
 }
 
 int validate_model(const track_model* m, const track_camera* cam) {
@@ -307,7 +152,69 @@ int validate_model(const track_model* m, const track_camera* cam) {
     return TRACK_OK;
 }
 
-void build_joint_table(track_ctx* c, const track_model* m) {
+int validate_params(const track_params* p, int P) {
+    if (!p) return fail(TRACK_E_INVALID, "params is NULL");
+    if (!(p->tau > 0.0f) || !std::isfinite(p->tau)) return fail(TRACK_E_INVALID, "tau must be > 0");
+    if (p->n_iters < 1 || p->n_iters > 256) return fail(TRACK_E_INVALID, "n_iters must be in 1..256");
+    if (!p->do_pose || !p->do_shape) return fail(TRACK_E_INVALID, "do_pose/do_shape are required");
+    if (p->gram_mode != TRACK_GRAM_FP32 && p->gram_mode != TRACK_GRAM_BF16X3 && p->gram_mode != TRACK_GRAM_BF16X6)
+        return fail(TRACK_E_INVALID, "unknown gram_mode");
+    const float lam[6] = {p->lambda_k, p->lambda_s, p->lambda_phi, p->lambda_nbr, p->lambda_t, p->lambda_w};
+    for (float l : lam)
+        if (!(l >= 0.0f) || !std::isfinite(l)) return fail(TRACK_E_INVALID, "weights must be finite and >= 0");
+    (void)P;
+    return TRACK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The iteration schedule shared by the streams of a batch.
+// ---------------------------------------------------------------------------
+struct Schedule {
+    int n_iters = 1;
+    std::vector<uint8_t> do_pose, do_shape;
+    int gram_mode = 0, pose_fp64 = 0, shape_fp64 = 0;
+    int first_pose = -1, last_pose = -1;
+
+    void set(const track_params* p) {
+        n_iters = p->n_iters;
+        do_pose.assign(p->do_pose, p->do_pose + n_iters);
+        do_shape.assign(p->do_shape, p->do_shape + n_iters);
+        gram_mode = p->gram_mode;
+        pose_fp64 = p->pose_solve_fp64 ? 1 : 0;
+        shape_fp64 = p->shape_solve_fp64 ? 1 : 0;
+        first_pose = last_pose = -1;
+        for (int t = 0; t < n_iters; ++t)
+            if (do_pose[t]) { if (first_pose < 0) first_pose = t; last_pose = t; }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One tracking stream's device state: model tables, per-frame buffers and
+// the host's record of which vertex and offset buffers are current.
+// ---------------------------------------------------------------------------
+struct Stream {
+    int P = 0, L = 0, V = 0, F = 0, K = 0, PP = 0, W = 0, H = 0, npad = 0, ntiles = 0, negrid = 0;
+    JointTable hjt{};
+    JointTable* djt = nullptr;
+    std::vector<double> prior_S;  // S_k: share of vertices each joint moves
+    void* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
+    Slot slot{};                   // device pointers and constants of this stream
+    float *depth_buf = nullptr, *xyz_buf = nullptr;
+    int v_cur = 0, phi_cur = 0, phi_prev = 0;
+    bool surface_valid = false, refresh_pose = true;
+    int input_mode = 0;            // per-pass interface: 0 depth, 1 xyz
+};
+
+template <class T>
+T* carve(Stream* s, size_t n) {
+    size_t bytes = (n * sizeof(T) + 255) & ~size_t(255);
+    T* p = s->arena ? reinterpret_cast<T*>(static_cast<char*>(s->arena) + s->arena_used) : nullptr;
+    s->arena_used += bytes;
+    return p;
+}
+
+void build_joint_table(Stream* c, const track_model* m) {
     JointTable& t = c->hjt;
     std::memset(&t, 0, sizeof(t));
     t.P = m->n_joints;
@@ -355,372 +262,158 @@ void build_joint_table(track_ctx* c, const track_model* m) {
     }
 }
 
-// --------------------------------------------------------------------------
-// the iteration schedule of one frame
-// --------------------------------------------------------------------------
-void ensure_surface(track_ctx* c) {
-    if (c->surface_valid) return;
-    timed_begin(c, TRACK_K_SKIN);
-    launch_skin(c->stream, c->dm, c->dq, cview(c->phi[c->phi_cur]), c->verts[c->v_cur]);
-    timed_end(c, TRACK_K_SKIN);
-    timed_begin(c, TRACK_K_NORMALS);
-    launch_normals(c->stream, c->dm, c->verts[c->v_cur], c->normals);
-    timed_end(c, TRACK_K_NORMALS);
-    c->surface_valid = true;
-}
-
-void pass_associate(track_ctx* c, const float* depth, const float* xyz) {
-    timed_begin(c, TRACK_K_BUCKET);
-    launch_clear(c->stream, c->npad, c->bk, c->V, c->acc, c->dstats);
-    launch_bucket(c->stream, c->dc, c->V, c->verts[c->v_cur], c->bk);
-    timed_end(c, TRACK_K_BUCKET);
-    timed_begin(c, TRACK_K_ASSOC);
-    launch_associate(c->stream, c->dc, c->tau, depth, xyz, c->bk, c->acc, c->verts[c->v_cur], c->assoc);
-    timed_end(c, TRACK_K_ASSOC);
-}
-
-void pass_normal_eq(track_ctx* c) {
-    timed_begin(c, TRACK_K_NORMAL_EQ);
-    launch_normal_eq(c->stream, c->dm, c->PP, c->gram_mode, c->dq, c->xi, c->anc, c->verts[c->v_cur],
-                     cview(c->normals), cview(c->phi[c->phi_cur]), c->acc, c->partials, c->negrid);
-    timed_end(c, TRACK_K_NORMAL_EQ);
-    launch_gram_reduce(c->stream, c->PP, c->negrid, c->partials, c->gram);
-}
-
-void pass_pose_step(track_ctx* c, int iter) {
-    timed_begin(c, TRACK_K_SOLVE);
-    launch_pose_solve(c->stream, c->djt, c->PP, c->gram, c->lambda_k, c->pose_fp64, c->theta, c->step,
-                      c->dstats, iter, c->dq, c->xi);
-    timed_end(c, TRACK_K_SOLVE);
-}
-
-// re-skin at the current pose into the other vertex buffer, then one offset
-// step; afterwards that buffer is the current surface
-void pass_shape(track_ctx* c, bool reskin) {
-    int vo = c->v_cur, vn = c->v_cur;
-    if (reskin) {
-        vn = c->v_cur ^ 1;
-        timed_begin(c, TRACK_K_SKIN);
-        launch_skin(c->stream, c->dm, c->dq, cview(c->phi[c->phi_cur]), c->verts[vn]);
-        timed_end(c, TRACK_K_SKIN);
-        timed_begin(c, TRACK_K_NORMALS);
-        launch_normals(c->stream, c->dm, c->verts[vn], c->normals);
-        timed_end(c, TRACK_K_NORMALS);
+// per-stream constants: association cutoff, weights, prior and active mask
+int stream_set_params(Stream* c, const track_params* p) {
+    Slot& S = c->slot;
+    S.tau = p->tau;
+    S.lambda_k = p->lambda_k;
+    S.lphi = p->lambda_phi;
+    S.lnbr = p->lambda_nbr;
+    S.lt = p->lambda_t;
+    S.lw = p->lambda_w;
+    for (int k = 0; k < c->P; ++k) {
+        double w = (double)p->lambda_s * c->prior_S[k];
+        c->hjt.prior[k] = w * w;
+        c->hjt.active[k] = p->active ? (p->active[k] ? 1 : 0) : 1;
     }
-    timed_begin(c, TRACK_K_SHAPE);
-    launch_shape(c->stream, c->dm, c->dq, c->verts[vo], c->verts[vn], cview(c->normals), c->acc,
-                 cview(c->phi[c->phi_cur]), cview(c->phi_prev), c->phi[c->phi_cur ^ 1], c->lambda_phi,
-                 c->lambda_nbr, c->lambda_t, c->lambda_w, c->shape_fp64);
-    timed_end(c, TRACK_K_SHAPE);
-    c->phi_cur ^= 1;
-    c->v_cur = vn;
-    c->surface_valid = false;
-}
-
-void drop_graphs(track_ctx* c) {
-    for (auto& g : c->graphs) {
-        (void)hipGraphExecDestroy(g.exec);
-        for (auto& te : g.tev) { (void)hipEventDestroy(te.second.first); (void)hipEventDestroy(te.second.second); }
-    }
-    c->graphs.clear();
-    c->last_graph = -1;
-}
-
-unsigned timing_mask(const track_ctx* c) {
-    unsigned m = 0;
-    for (int k = 0; k < TRACK_K_COUNT_; ++k)
-        if (c->timers[k].on) m |= 1u << k;
-    return m;
-}
-
-// the kernels of one frame, issued on the context's stream
-void enqueue_frame(track_ctx* c, const float* depth, const float* xyz) {
-    launch_frame_begin(c->stream, c->P, c->theta, c->theta_backup, c->dstats);
-    for (int t = 0; t < c->n_iters; ++t) {
-        ensure_surface(c);
-        pass_associate(c, depth, xyz);
-        if (c->do_pose[t]) {
-            pass_normal_eq(c);
-            pass_pose_step(c, t);
-        }
-        if (c->do_shape[t]) {
-            pass_shape(c, c->do_pose[t] != 0);
-        } else if (c->do_pose[t]) {
-            // re-skin at the new pose; the surface is current again
-            c->v_cur ^= 1;
-            c->surface_valid = false;
-            ensure_surface(c);
-        }
-    }
-}
-
-// Issue one frame as a replay of a cached graph (the frame reads its input
-// from the context's own buffer); timing events, when enabled, are part of
-// the graph.  If capture is unavailable the kernels are launched directly.
-int launch_frame(track_ctx* c, const float* depth, const float* xyz) {
-    if (!c->use_graphs) {
-        enqueue_frame(c, depth, xyz);
-        return TRACK_OK;
-    }
-    const int mode = xyz ? 1 : 0;
-    const float* in = xyz ? xyz : depth;
-    float* buf = xyz ? c->xyz_buf : c->depth_buf;
-    const size_t bytes = sizeof(float) * (size_t)c->W * c->H * (xyz ? 3 : 1);
-    if (in != buf) HIP_TRY(hipMemcpyAsync(buf, in, bytes, hipMemcpyDeviceToDevice, c->stream));
-    const int s0 = c->surface_valid ? 1 : 0;
-    const unsigned tm = timing_mask(c);
-    for (size_t q = 0; q < c->graphs.size(); ++q) {
-        FrameGraph& g = c->graphs[q];
-        if (g.v0 == c->v_cur && g.p0 == c->phi_cur && g.s0 == s0 && g.mode == mode && g.tmask == tm) {
-            HIP_TRY(hipGraphLaunch(g.exec, c->stream));
-            c->v_cur = g.v1; c->phi_cur = g.p1; c->surface_valid = g.s1 != 0;
-            c->last_graph = (int)q;
-            return TRACK_OK;
-        }
-    }
-    FrameGraph g{c->v_cur, c->phi_cur, s0, mode, tm, 0, 0, 0, nullptr, {}, {}};
-    const int v0 = c->v_cur, p0 = c->phi_cur;
-    const bool sv0 = c->surface_valid;
-    hipGraph_t graph = nullptr;
-    c->capturing = &g;
-    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        enqueue_frame(c, xyz ? nullptr : c->depth_buf, xyz ? c->xyz_buf : nullptr);
-        e = hipStreamEndCapture(c->stream, &graph);
-    }
-    c->capturing = nullptr;
-    if (e == hipSuccess) {
-        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-    }
-    if (e != hipSuccess) {
-        // no graphs on this stream: restore the state and launch directly
-        (void)hipGetLastError();
-        for (auto& te : g.tev) { (void)hipEventDestroy(te.second.first); (void)hipEventDestroy(te.second.second); }
-        c->v_cur = v0; c->phi_cur = p0; c->surface_valid = sv0;
-        c->use_graphs = false;
-        enqueue_frame(c, depth, xyz);
-        return TRACK_OK;
-    }
-    g.v1 = c->v_cur; g.p1 = c->phi_cur; g.s1 = c->surface_valid ? 1 : 0;
-    c->graphs.push_back(g);
-    c->last_graph = (int)c->graphs.size() - 1;
-    HIP_TRY(hipGraphLaunch(c->graphs.back().exec, c->stream));
+    if (c->djt) HIP_TRY(hipMemcpy(c->djt, &c->hjt, sizeof(JointTable), hipMemcpyHostToDevice));
     return TRACK_OK;
 }
 
-int run_frame(track_ctx* c, const float* depth, const float* xyz) {
-    HIP_TRY(hipEventRecord(c->f0, c->stream));
-    int rc = launch_frame(c, depth, xyz);
-    if (rc) return rc;
-    HIP_TRY(hipEventRecord(c->f1, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->hstats, c->dstats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->hbstat, c->bk.bstat, sizeof(int4) * c->nassoc, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->htheta, c->theta, sizeof(double) * c->P, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    timed_collect(c);
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, c->f0, c->f1);
-    DevStats& s = *c->hstats;
-    // counts of the last association, summed over its workgroups
-    s.n_valid_px = s.n_assoc_px = s.n_obs_verts = 0;
-    for (int q = 0; q < c->nassoc; ++q) {
-        s.n_valid_px += c->hbstat[q].x;
-        s.n_assoc_px += c->hbstat[q].y;
-        s.n_obs_verts += c->hbstat[q].z;
-    }
-    track_frame_stats fs{};
-    fs.n_valid_px = s.n_valid_px;
-    fs.n_assoc_px = s.n_assoc_px;
-    fs.n_obs_verts = s.n_obs_verts;
-    int first = -1, lastp = -1;
-    for (int t = 0; t < c->n_iters; ++t)
-        if (c->do_pose[t]) { if (first < 0) first = t; lastp = t; }
-    fs.energy_first = first >= 0 ? s.energy[first] : 0.0f;
-    fs.energy_last = lastp >= 0 ? s.energy[lastp] : 0.0f;
-    fs.step_norm_last = lastp >= 0 ? s.step_norm[lastp] : 0.0f;
-    fs.ms_total = ms;
-    // health check: solver failure, nothing measured, nothing matched, or a
-    // non-finite pose; the previous frame's state is restored
-    int status = TRACK_OK;
-    std::string why;
-    if (s.status == TRACK_E_NOT_PD) { status = TRACK_E_NOT_PD; why = "pose system not positive definite"; }
-    else if (s.n_valid_px == 0) { status = TRACK_E_LOST; why = "frame has no valid pixels"; }
-    else if (s.n_assoc_px == 0) { status = TRACK_E_LOST; why = "no pixel matched the surface"; }
-    else {
-        for (int k = 0; k < c->P; ++k)
-            if (!std::isfinite(c->htheta[k])) { status = TRACK_E_LOST; why = "pose diverged"; break; }
-        if (!std::isfinite(fs.energy_last)) { status = TRACK_E_LOST; why = "energy diverged"; }
-    }
-    fs.status = status;
-    c->last = fs;
-    if (status == TRACK_OK) {
-        launch_copy3(c->stream, c->V, cview(c->phi[c->phi_cur]), c->phi_prev);
-    } else {
-        HIP_TRY(hipMemcpyAsync(c->theta, c->theta_backup, sizeof(double) * c->P, hipMemcpyDeviceToDevice, c->stream));
-        launch_copy3(c->stream, c->V, cview(c->phi_prev), c->phi[c->phi_cur]);
-        launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
-        c->surface_valid = false;
-        ensure_surface(c);
-    }
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (status != TRACK_OK) return fail(status, why);
-    return TRACK_OK;
-}
-
-int upload_soa(track_ctx* c, Vec3Buf dst, const float* aos) {
-    std::vector<float> t(3 * (size_t)c->V);
-    for (int i = 0; i < c->V; ++i) { t[i] = aos[3 * i]; t[c->V + i] = aos[3 * i + 1]; t[2 * c->V + i] = aos[3 * i + 2]; }
-    HIP_TRY(hipMemcpy(dst.x, t.data(), sizeof(float) * c->V, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dst.y, t.data() + c->V, sizeof(float) * c->V, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(dst.z, t.data() + 2 * c->V, sizeof(float) * c->V, hipMemcpyHostToDevice));
-    return TRACK_OK;
-}
-
-int download_soa(const track_ctx* c, Vec3Buf src, float* aos) {
-    std::vector<float> t(3 * (size_t)c->V);
-    HIP_TRY(hipMemcpy(t.data(), src.x, sizeof(float) * c->V, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(t.data() + c->V, src.y, sizeof(float) * c->V, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(t.data() + 2 * c->V, src.z, sizeof(float) * c->V, hipMemcpyDeviceToHost));
-    for (int i = 0; i < c->V; ++i) { aos[3 * i] = t[i]; aos[3 * i + 1] = t[c->V + i]; aos[3 * i + 2] = t[2 * c->V + i]; }
-    return TRACK_OK;
-}
-
-int upload_v4(track_ctx* c, float4* dst, const float* aos) {
-    std::vector<float4> t(c->V);
-    for (int i = 0; i < c->V; ++i) t[i] = make_float4(aos[3 * i], aos[3 * i + 1], aos[3 * i + 2], 0.0f);
-    HIP_TRY(hipMemcpy(dst, t.data(), sizeof(float4) * c->V, hipMemcpyHostToDevice));
-    return TRACK_OK;
-}
-
-int download_v4(const track_ctx* c, const float4* src, float* aos) {
-    std::vector<float4> t(c->V);
-    HIP_TRY(hipMemcpy(t.data(), src, sizeof(float4) * c->V, hipMemcpyDeviceToHost));
-    for (int i = 0; i < c->V; ++i) { aos[3 * i] = t[i].x; aos[3 * i + 1] = t[i].y; aos[3 * i + 2] = t[i].z; }
-    return TRACK_OK;
-}
-
-void free_ctx(track_ctx* c) {
-    if (!c) return;
-    drop_graphs(c);
-    for (auto& t : c->timers)
-        for (auto e : t.ev) (void)hipEventDestroy(e);
-    if (c->f0) (void)hipEventDestroy(c->f0);
-    if (c->f1) (void)hipEventDestroy(c->f1);
-    if (c->arena) (void)hipFree(c->arena);
-    if (c->djt) (void)hipFree(c->djt);
-    if (c->hstats) (void)hipHostFree(c->hstats);
-    if (c->htheta) (void)hipHostFree(c->htheta);
-    if (c->hbstat) (void)hipHostFree(c->hbstat);
-    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
-    delete c;
-}
-
-}  // namespace
-
-// ==========================================================================
-// C ABI
-// ==========================================================================
-extern "C" {
-
-const char* track_last_error(void) { return g_err.c_str(); }
-
-int track_init(const track_model* model, const track_camera* camera, const track_params* params,
-               const double* theta0, const float* phi0, void* hip_stream, track_ctx** out) {
-    g_err.clear();
-    if (!out) return fail(TRACK_E_INVALID, "out is NULL");
-    *out = nullptr;
-    int rc = validate_model(model, camera);
-    if (rc) return rc;
-    if (!theta0) return fail(TRACK_E_INVALID, "theta0 is NULL");
-    for (int k = 0; k < model->n_joints; ++k)
-        if (!std::isfinite(theta0[k])) return fail(TRACK_E_INVALID, "theta0 not finite");
-    track_ctx* c = new track_ctx();
-    c->P = model->n_joints; c->L = model->n_links; c->V = model->n_verts; c->F = model->n_faces;
-    c->K = model->max_infl;
-    c->PP = ((c->P + 1) + 15) / 16 * 16;
-    c->W = camera->width; c->H = camera->height;
-    int tx = (c->W + 7) / 8, ty = (c->H + 7) / 8;
-    c->ntiles = tx * ty;
-    c->npad = c->ntiles * 64;
-    c->negrid = ne_grid(c->V);
-    {
-        const char* env = std::getenv("TRACK_NO_GRAPH");
-        c->use_graphs = !(env && env[0] == '1');
-    }
-    build_joint_table(c, model);
-    if ((rc = set_params(c, params))) { free_ctx(c); return rc; }
-    if (hipGetDevice(&c->device) != hipSuccess) { free_ctx(c); return fail(TRACK_E_DEVICE, "no HIP device"); }
-    if (hip_stream) c->stream = (hipStream_t)hip_stream;
-    else {
-        if (hipStreamCreate(&c->stream) != hipSuccess) { free_ctx(c); return fail(TRACK_E_DEVICE, "stream"); }
-        c->own_stream = true;
-    }
-    // ---- device memory (one arena) ----
+// Lay out the stream's device memory.  Without an arena only the size is
+// accumulated (admission control uses it).
+void stream_layout(Stream* c) {
     const size_t V = c->V, N = (size_t)c->W * c->H;
-    size_t need = 0;
-    auto add = [&](size_t n, size_t sz) { need += (n * sz + 255) & ~size_t(255); };
-    add(c->P, 8); add(c->P, 8); add(c->P, 8); add((size_t)c->PP * c->PP, 8);   // theta, backup, step, gram
-    add(8 * c->L, 4); add(8 * c->P, 4); add(4 * c->L, 4);                       // dq, xi, anc
-    add((size_t)c->negrid * c->PP * c->PP, 4);                                  // partials
-    add(N, 4); add(3 * N, 4);                                                   // depth, xyz
-    for (int q = 0; q < 3 * 5; ++q) add(V, 4);                                  // rest, phi x2, prev, normals
-    add(V, 16); add(V, 16);                                                     // vertices x2
-    add(V, 16); add(V, 4); add(V, 16); add(V + 1, 4); add(3 * (size_t)c->F, 8); // w, links, nbr, fan
-    add(c->npad, 4); add(c->npad, 4); add(c->npad, 4); add(c->npad, 16);       // buckets
-    add(c->ntiles, 4); add(c->ntiles, 4); add(c->ntiles, 8);
-    add(V, 4); add(V, 4); add(V, 16);
-    c->nassoc = assoc_blocks(tx, ty);
-    add(c->nassoc, 16);
-    add(4 * (size_t)c->ntiles, 16);
-    add(V, 4); add(V, 8); add(V, 8); add(V, 8);                                 // accumulators
-    add(N, 4); add(1, sizeof(DevStats));
-    c->arena_bytes = need;
-    if (hipMalloc(&c->arena, need) != hipSuccess) { free_ctx(c); return fail(TRACK_E_NOMEM, "device allocation failed"); }
-    if (hipMalloc(&c->djt, sizeof(JointTable)) != hipSuccess) { free_ctx(c); return fail(TRACK_E_NOMEM, "device allocation failed"); }
-    if (hipHostMalloc(&c->hstats, sizeof(DevStats)) != hipSuccess ||
-        hipHostMalloc(&c->htheta, sizeof(double) * c->P) != hipSuccess ||
-        hipHostMalloc(&c->hbstat, sizeof(int4) * c->nassoc) != hipSuccess) {
-        free_ctx(c);
-        return fail(TRACK_E_NOMEM, "pinned allocation failed");
-    }
-    c->theta = carve<double>(c, c->P);
-    c->theta_backup = carve<double>(c, c->P);
-    c->step = carve<double>(c, c->P);
-    c->gram = carve<double>(c, (size_t)c->PP * c->PP);
-    c->dq = carve<float>(c, 8 * c->L);
-    c->xi = carve<float>(c, 8 * c->P);
-    c->anc = carve<uint32_t>(c, 4 * c->L);
-    c->partials = carve<float>(c, (size_t)c->negrid * c->PP * c->PP);
+    c->arena_used = 0;
+    Slot& S = c->slot;
+    S.theta = carve<double>(c, c->P);
+    S.theta_backup = carve<double>(c, c->P);
+    S.step = carve<double>(c, c->P);
+    S.gram = carve<double>(c, (size_t)c->PP * c->PP);
+    S.dq = carve<float>(c, 8 * c->L);
+    S.xi = carve<float>(c, 8 * c->P);
+    uint32_t* anc = carve<uint32_t>(c, 4 * c->L);
+    S.anc = anc;
+    S.partials = carve<float>(c, (size_t)c->negrid * c->PP * c->PP);
     c->depth_buf = carve<float>(c, N);
     c->xyz_buf = carve<float>(c, 3 * N);
     auto v3 = [&]() { Vec3Buf b; b.x = carve<float>(c, V); b.y = carve<float>(c, V); b.z = carve<float>(c, V); return b; };
     Vec3Buf rest = v3();
-    c->phi[0] = v3(); c->phi[1] = v3(); c->phi_prev = v3();
-    c->verts[0] = carve<float4>(c, V); c->verts[1] = carve<float4>(c, V); c->normals = v3();
-    float4* w4 = carve<float4>(c, V);
-    uint32_t* lk = carve<uint32_t>(c, V);
-    int4* nb = carve<int4>(c, V);
-    uint32_t* fan_off = carve<uint32_t>(c, V + 1);
-    int2* fan = carve<int2>(c, 3 * (size_t)c->F);
-    c->bk.pcnt = carve<uint32_t>(c, c->npad);
-    c->bk.pzmin = carve<uint32_t>(c, c->npad);
-    c->bk.pzmax = carve<uint32_t>(c, c->npad);
-    c->bk.rec = carve<uint4>(c, c->npad);
-    c->bk.tsum = carve<uint32_t>(c, c->ntiles);
-    c->bk.toff = carve<uint32_t>(c, c->ntiles);
-    c->bk.tz = carve<float2>(c, c->ntiles);
-    c->bk.vpix = carve<int>(c, V);
-    c->bk.vslot = carve<uint32_t>(c, V);
-    c->bk.sorted = carve<float4>(c, V);
-    c->bk.bstat = carve<int4>(c, c->nassoc);
-    c->bk.cellrec = carve<uint4>(c, 4 * (size_t)c->ntiles);
-    c->acc.cnt = carve<uint32_t>(c, V);
-    c->acc.sx = carve<long long>(c, V);
-    c->acc.sy = carve<long long>(c, V);
-    c->acc.sz = carve<long long>(c, V);
-    c->assoc = carve<int32_t>(c, N);
-    c->dstats = carve<DevStats>(c, 1);
+    for (int q = 0; q < 3; ++q) S.phi[q] = v3();
+    S.verts[0] = carve<float4>(c, V);
+    S.verts[1] = carve<float4>(c, V);
+    S.normals = v3();
+    S.m.rx = rest.x; S.m.ry = rest.y; S.m.rz = rest.z;
+    S.m.w = carve<float4>(c, V);
+    S.m.links = carve<uint32_t>(c, V);
+    S.m.nbr = carve<int4>(c, V);
+    S.m.fan_off = carve<uint32_t>(c, V + 1);
+    S.m.fan = carve<int2>(c, 3 * (size_t)c->F);
+    Buckets& b = S.b;
+    b.pcnt = carve<uint32_t>(c, c->npad);
+    b.pzmin = carve<uint32_t>(c, c->npad);
+    b.pzmax = carve<uint32_t>(c, c->npad);
+    b.rec = carve<uint4>(c, c->npad);
+    b.tsum = carve<uint32_t>(c, c->ntiles);
+    b.toff = carve<uint32_t>(c, c->ntiles);
+    b.tz = carve<float2>(c, c->ntiles);
+    b.vpix = carve<int>(c, V);
+    b.vslot = carve<uint32_t>(c, V);
+    b.sorted = carve<float4>(c, V);
+    b.bstat = carve<int4>(c, c->ntiles);
+    b.cellrec = carve<uint4>(c, 4 * (size_t)c->ntiles);
+    S.a.cnt = carve<uint32_t>(c, V);
+    S.a.sx = carve<long long>(c, V);
+    S.a.sy = carve<long long>(c, V);
+    S.a.sz = carve<long long>(c, V);
+    S.assoc = carve<int32_t>(c, N);
+    S.st = carve<DevStats>(c, 1);
+}
+
+// device bytes of a stream (arena plus joint table)
+size_t stream_bytes(const track_model* m, const track_camera* cam) {
+    Stream s;
+    s.P = m->n_joints; s.L = m->n_links; s.V = m->n_verts; s.F = m->n_faces;
+    s.PP = ((s.P + 1) + 15) / 16 * 16;
+    s.W = cam->width; s.H = cam->height;
+    s.ntiles = ((s.W + 7) / 8) * ((s.H + 7) / 8);
+    s.npad = s.ntiles * 64;
+    s.negrid = ne_grid(s.V);
+    stream_layout(&s);
+    return s.arena_used + ((sizeof(JointTable) + 255) & ~size_t(255));
+}
+
+int upload_soa(int V, Vec3Buf dst, const float* aos) {
+    std::vector<float> t(3 * (size_t)V);
+    for (int i = 0; i < V; ++i) { t[i] = aos[3 * i]; t[V + i] = aos[3 * i + 1]; t[2 * (size_t)V + i] = aos[3 * i + 2]; }
+    HIP_TRY(hipMemcpy(dst.x, t.data(), sizeof(float) * V, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dst.y, t.data() + V, sizeof(float) * V, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(dst.z, t.data() + 2 * (size_t)V, sizeof(float) * V, hipMemcpyHostToDevice));
+    return TRACK_OK;
+}
+
+int download_soa(int V, Vec3Buf src, float* aos) {
+    std::vector<float> t(3 * (size_t)V);
+    HIP_TRY(hipMemcpy(t.data(), src.x, sizeof(float) * V, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t.data() + V, src.y, sizeof(float) * V, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t.data() + 2 * (size_t)V, src.z, sizeof(float) * V, hipMemcpyDeviceToHost));
+    for (int i = 0; i < V; ++i) { aos[3 * i] = t[i]; aos[3 * i + 1] = t[V + i]; aos[3 * i + 2] = t[2 * (size_t)V + i]; }
+    return TRACK_OK;
+}
+
+int upload_v4(int V, float4* dst, const float* aos) {
+    std::vector<float4> t(V);
+    for (int i = 0; i < V; ++i) t[i] = make_float4(aos[3 * i], aos[3 * i + 1], aos[3 * i + 2], 0.0f);
+    HIP_TRY(hipMemcpy(dst, t.data(), sizeof(float4) * V, hipMemcpyHostToDevice));
+    return TRACK_OK;
+}
+
+int download_v4(int V, const float4* src, float* aos) {
+    std::vector<float4> t(V);
+    HIP_TRY(hipMemcpy(t.data(), src, sizeof(float4) * V, hipMemcpyDeviceToHost));
+    for (int i = 0; i < V; ++i) { aos[3 * i] = t[i].x; aos[3 * i + 1] = t[i].y; aos[3 * i + 2] = t[i].z; }
+    return TRACK_OK;
+}
+
+void stream_free(Stream* c) {
+    if (!c) return;
+    if (c->arena) (void)hipFree(c->arena);
+    if (c->djt) (void)hipFree(c->djt);
+    c->arena = nullptr;
+    c->djt = nullptr;
+}
+
+// Allocate and fill a stream; on failure nothing stays allocated.
+int stream_create(Stream* c, const track_model* model, const track_camera* camera, const track_params* params,
+                  const double* theta0, const float* phi0) {
+    c->P = model->n_joints; c->L = model->n_links; c->V = model->n_verts; c->F = model->n_faces;
+    c->K = model->max_infl;
+    c->PP = ((c->P + 1) + 15) / 16 * 16;
+    c->W = camera->width; c->H = camera->height;
+    const int tx = (c->W + 7) / 8, ty = (c->H + 7) / 8;
+    c->ntiles = tx * ty;
+    c->npad = c->ntiles * 64;
+    c->negrid = ne_grid(c->V);
+    build_joint_table(c, model);
+    stream_layout(c);  // size only
+    c->arena_bytes = c->arena_used;
+    if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        c->arena = nullptr;
+        return fail(TRACK_E_NOMEM, "device allocation failed");
+    }
+    if (hipMalloc(&c->djt, sizeof(JointTable)) != hipSuccess) {
+        (void)hipGetLastError();
+        stream_free(c);
+        return fail(TRACK_E_NOMEM, "device allocation failed");
+    }
+    stream_layout(c);  // carve
+    Slot& S = c->slot;
+    S.jt = c->djt;
+    S.PP = c->PP;
+    S.npad = c->npad;
+    S.negrid = c->negrid;
+    const size_t V = c->V;
     // ---- host-side tables, uploaded once ----
     std::vector<float> h(3 * V);
     for (size_t i = 0; i < V; ++i) { h[i] = model->rest_xyz[3 * i]; h[V + i] = model->rest_xyz[3 * i + 1]; h[2 * V + i] = model->rest_xyz[3 * i + 2]; }
@@ -758,46 +451,618 @@ int track_init(const track_model* model, const track_camera* camera, const track
     std::vector<uint32_t> hanc(4 * (size_t)c->L);
     for (int l = 0; l < c->L; ++l)
         for (int q = 0; q < 4; ++q) hanc[4 * l + q] = c->hjt.anc[l][q];
-    auto up = [&](void* d, const void* s, size_t n) { return hipMemcpy(d, s, n, hipMemcpyHostToDevice) == hipSuccess; };
-    bool ok = up(rest.x, h.data(), 4 * V) && up(rest.y, h.data() + V, 4 * V) && up(rest.z, h.data() + 2 * V, 4 * V) &&
-              up(w4, hw.data(), 16 * V) && up(lk, hl.data(), 4 * V) && up(nb, hn.data(), 16 * V) &&
-              up(fan_off, hoff.data(), 4 * (V + 1)) && (c->F == 0 || up(fan, hfan.data(), 8 * 3 * (size_t)c->F)) &&
-              up(c->anc, hanc.data(), 4 * hanc.size()) && up(c->djt, &c->hjt, sizeof(JointTable)) &&
-              up(c->theta, theta0, 8 * (size_t)c->P);
-    if (!ok) { free_ctx(c); return fail(TRACK_E_DEVICE, "upload failed"); }
-    c->dm = DevModel{c->P, c->L, c->V, c->F, rest.x, rest.y, rest.z, w4, lk, nb, fan_off, fan};
-    float fmax = std::max(camera->fx, camera->fy);
-    double ex = std::max((double)camera->cx + 0.5, (double)camera->width - 0.5 - camera->cx) / camera->fx;
-    double ey = std::max((double)camera->cy + 0.5, (double)camera->height - 0.5 - camera->cy) / camera->fy;
-    double rmax = std::sqrt(1.0 + ex * ex + ey * ey);
-    c->dc = DevCam{c->W, c->H, tx, ty, camera->fx, camera->fy, camera->cx, camera->cy,
-                   (float)((1.0 - 1e-4) / (fmax * rmax))};
-    if (hipEventCreate(&c->f0) != hipSuccess || hipEventCreate(&c->f1) != hipSuccess) {
-        free_ctx(c);
-        return fail(TRACK_E_DEVICE, "event creation failed");
-    }
+    auto up = [&](const void* d, const void* s, size_t n) {
+        return hipMemcpy(const_cast<void*>(d), s, n, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    bool ok = up(S.m.rx, h.data(), 4 * V) && up(S.m.ry, h.data() + V, 4 * V) && up(S.m.rz, h.data() + 2 * V, 4 * V) &&
+              up(S.m.w, hw.data(), 16 * V) && up(S.m.links, hl.data(), 4 * V) && up(S.m.nbr, hn.data(), 16 * V) &&
+              up(S.m.fan_off, hoff.data(), 4 * (V + 1)) && (c->F == 0 || up(S.m.fan, hfan.data(), 8 * 3 * (size_t)c->F)) &&
+              up(S.anc, hanc.data(), 4 * hanc.size()) && up(S.theta, theta0, 8 * (size_t)c->P) &&
+              hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess;
+    if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
+    S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F;
+    const float fmax = std::max(camera->fx, camera->fy);
+    const double ex = std::max((double)camera->cx + 0.5, (double)camera->width - 0.5 - camera->cx) / camera->fx;
+    const double ey = std::max((double)camera->cy + 0.5, (double)camera->height - 0.5 - camera->cy) / camera->fy;
+    const double rmax = std::sqrt(1.0 + ex * ex + ey * ey);
+    S.c = DevCam{c->W, c->H, tx, ty, camera->fx, camera->fy, camera->cx, camera->cy,
+                 (float)((1.0 - 1e-4) / (fmax * rmax))};
+    int rc;
+    if ((rc = stream_set_params(c, params))) { stream_free(c); return rc; }
     std::vector<float> z3(3 * V, 0.0f);
-    const float* p0 = phi0 ? phi0 : z3.data();
-    if ((rc = upload_soa(c, c->phi[0], p0)) || (rc = upload_soa(c, c->phi_prev, p0))) { free_ctx(c); return rc; }
-    if (hipMemset(c->dstats, 0, sizeof(DevStats)) != hipSuccess) { free_ctx(c); return fail(TRACK_E_DEVICE, "memset"); }
-    launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
-    ensure_surface(c);
-    if (hipStreamSynchronize(c->stream) != hipSuccess) { free_ctx(c); return fail(TRACK_E_DEVICE, "init kernels failed"); }
+    if ((rc = upload_soa(c->V, S.phi[0], phi0 ? phi0 : z3.data()))) { stream_free(c); return rc; }
+    c->v_cur = c->phi_cur = c->phi_prev = 0;
+    c->surface_valid = false;
+    c->refresh_pose = true;
+    return TRACK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batch runner: the slot table, its launches, graphs and kernel timers.
+// ---------------------------------------------------------------------------
+struct KernelTimer {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // pairs
+    size_t used = 0;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+struct GraphKey {
+    int n, off, kind, skin_first;
+    int grid[KK_COUNT_];
+    bool operator==(const GraphKey& o) const {
+        if (n != o.n || off != o.off || kind != o.kind || skin_first != o.skin_first) return false;
+        for (int k = 0; k < KK_COUNT_; ++k)
+            if (grid[k] != o.grid[k]) return false;
+        return true;
+    }
+};
+
+struct CachedGraph {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+    int seen = 0;         // launches of this key without a graph
+    uint64_t last_use = 0;
+};
+
+constexpr size_t kMaxGraphs = 64;
+
+struct Runner {
+    hipStream_t s = nullptr;
+    bool own_stream = false;
+    int cap = 0;                       // table entries
+    Slot* dslots = nullptr;
+    int* dpre = nullptr;               // prefix rows of each table window
+    DevSummary* dsum = nullptr;
+    Slot* hslots = nullptr;            // pinned
+    int* hpre = nullptr;               // pinned
+    DevSummary* hsum = nullptr;        // pinned
+    KernelTimer timers[TRACK_K_COUNT_];
+    std::vector<CachedGraph> graphs;
+    bool use_graphs = true;
+    int capture_after = 0;             // plain launches of a key before it is captured
+    uint64_t clock = 0;
+    hipEvent_t f0 = nullptr, f1 = nullptr;
+};
+
+// prefix rows of the table window starting at entry `off`
+inline int pre_offset(int off) { return off * (KK_COUNT_ + 1) * 2; }
+
+int runner_init(Runner& R, int cap, void* hip_stream) {
+    R.cap = cap;
+    if (hip_stream) R.s = (hipStream_t)hip_stream;
+    else {
+        HIP_TRY(hipStreamCreate(&R.s));
+        R.own_stream = true;
+    }
+    const size_t npre = (size_t)pre_offset(cap) + (size_t)KK_COUNT_ * (cap + 1);
+    if (hipMalloc(&R.dslots, sizeof(Slot) * cap) != hipSuccess || hipMalloc(&R.dpre, sizeof(int) * npre) != hipSuccess ||
+        hipMalloc(&R.dsum, sizeof(DevSummary) * cap) != hipSuccess)
+        return fail(TRACK_E_NOMEM, "device allocation failed");
+    if (hipHostMalloc(&R.hslots, sizeof(Slot) * cap) != hipSuccess ||
+        hipHostMalloc(&R.hpre, sizeof(int) * npre) != hipSuccess ||
+        hipHostMalloc(&R.hsum, sizeof(DevSummary) * cap) != hipSuccess)
+        return fail(TRACK_E_NOMEM, "pinned allocation failed");
+    HIP_TRY(hipEventCreate(&R.f0));
+    HIP_TRY(hipEventCreate(&R.f1));
+    const char* env = std::getenv("TRACK_NO_GRAPH");
+    R.use_graphs = !(env && env[0] == '1');
+    return TRACK_OK;
+}
+
+void drop_graphs(Runner& R) {
+    if (R.s) (void)hipStreamSynchronize(R.s);
+    for (auto& g : R.graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    R.graphs.clear();
+}
+
+void runner_free(Runner& R) {
+    drop_graphs(R);
+    for (auto& t : R.timers)
+        for (auto e : t.ev) (void)hipEventDestroy(e);
+    if (R.f0) (void)hipEventDestroy(R.f0);
+    if (R.f1) (void)hipEventDestroy(R.f1);
+    if (R.dslots) (void)hipFree(R.dslots);
+    if (R.dpre) (void)hipFree(R.dpre);
+    if (R.dsum) (void)hipFree(R.dsum);
+    if (R.hslots) (void)hipHostFree(R.hslots);
+    if (R.hpre) (void)hipHostFree(R.hpre);
+    if (R.hsum) (void)hipHostFree(R.hsum);
+    if (R.own_stream && R.s) (void)hipStreamDestroy(R.s);
+    R = Runner();
+}
+
+bool timing_on(const Runner& R) {
+    for (const auto& t : R.timers)
+        if (t.on) return true;
+    return false;
+}
+
+// Kernel timing brackets launches with HIP events; launches are then issued
+// directly (never from a graph) so that every bracket is a recorded pair.
+void timed_begin(Runner& R, int k) {
+    KernelTimer& t = R.timers[k];
+    if (!t.on) return;
+    if (t.used + 2 > t.ev.size()) {
+        for (int q = 0; q < 64; ++q) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) == hipSuccess) t.ev.push_back(e);
+        }
+    }
+    if (t.used + 2 <= t.ev.size()) (void)hipEventRecord(t.ev[t.used], R.s);
+}
+
+void timed_end(Runner& R, int k) {
+    KernelTimer& t = R.timers[k];
+    if (!t.on || t.used + 2 > t.ev.size()) return;
+    (void)hipEventRecord(t.ev[t.used + 1], R.s);
+    t.used += 2;
+}
+
+// after a stream synchronisation: fold the recorded pairs into totals
+void timed_collect(Runner& R) {
+    for (auto& t : R.timers) {
+        for (size_t q = 0; q + 1 < t.used; q += 2) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, t.ev[q], t.ev[q + 1]) == hipSuccess) {
+                t.total_ms += ms;
+                t.launches += 1;
+            }
+        }
+        t.used = 0;
+    }
+}
+
+struct TableEntry {
+    Stream* s;
+    int flags, iter;
+    const float* depth;
+    const float* xyz;
+};
+
+// Write the table window [off, off + n) and its prefix rows, queue the
+// upload, and describe the launch.
+Launch stage_table(Runner& R, int off, const TableEntry* e, int n) {
+    Launch L;
+    L.s = R.s;
+    int* pre = R.hpre + pre_offset(off);
+    for (int k = 0; k < KK_COUNT_; ++k) pre[k * (n + 1)] = 0;
+    for (int i = 0; i < n; ++i) {
+        Slot S = e[i].s->slot;
+        S.v_cur = e[i].s->v_cur;
+        S.phi_cur = e[i].s->phi_cur;
+        S.phi_prev = e[i].s->phi_prev;
+        S.flags = e[i].flags;
+        S.iter = e[i].iter;
+        S.depth = e[i].depth;
+        S.xyz = e[i].xyz;
+        S.summary = R.dsum + off + i;
+        R.hslots[off + i] = S;
+        for (int k = 0; k < KK_COUNT_; ++k) pre[k * (n + 1) + i + 1] = pre[k * (n + 1) + i] + slot_blocks(S, k);
+    }
+    for (int k = 0; k < KK_COUNT_; ++k) L.grid[k] = pre[k * (n + 1) + n];
+    L.B.slots = R.dslots + off;
+    L.B.pre = R.dpre + pre_offset(off);
+    L.B.n = n;
+    (void)hipMemcpyAsync(R.dslots + off, R.hslots + off, sizeof(Slot) * n, hipMemcpyHostToDevice, R.s);
+    (void)hipMemcpyAsync(R.dpre + pre_offset(off), pre, sizeof(int) * KK_COUNT_ * (n + 1), hipMemcpyHostToDevice, R.s);
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// The schedule (Section 4): associate, then pose and/or offset steps.
+// ---------------------------------------------------------------------------
+struct SurfaceState {
+    int vsel = 0;      // vertex buffer relative to the launch's start
+    int pn = 0;        // offset steps taken since the launch's start
+    bool valid = false;
+};
+
+void enqueue_surface(Runner& R, const Launch& L, int vsel, int pn) {
+    timed_begin(R, TRACK_K_SKIN);
+    launch_skin(L, vsel, pn);
+    timed_end(R, TRACK_K_SKIN);
+    timed_begin(R, TRACK_K_NORMALS);
+    launch_normals(L, vsel);
+    timed_end(R, TRACK_K_NORMALS);
+}
+
+void enqueue_associate(Runner& R, const Launch& L, int vsel) {
+    timed_begin(R, TRACK_K_BUCKET);
+    launch_clear(L);
+    launch_bucket(L, vsel);
+    timed_end(R, TRACK_K_BUCKET);
+    timed_begin(R, TRACK_K_ASSOC);
+    launch_associate(L, vsel);
+    timed_end(R, TRACK_K_ASSOC);
+}
+
+void enqueue_normal_eq(Runner& R, const Launch& L, int gram_mode, int vsel, int pn) {
+    timed_begin(R, TRACK_K_NORMAL_EQ);
+    launch_normal_eq(L, gram_mode, vsel, pn);
+    timed_end(R, TRACK_K_NORMAL_EQ);
+    launch_gram_reduce(L);
+}
+
+void enqueue_pose_step(Runner& R, const Launch& L, int fp64, int iter) {
+    timed_begin(R, TRACK_K_SOLVE);
+    launch_pose_solve(L, fp64, iter);
+    timed_end(R, TRACK_K_SOLVE);
+}
+
+// One iteration; `iter` is added to each slot's own iteration index.  With
+// issue == false only the buffer bookkeeping runs (the state a captured
+// launch leaves behind).
+void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool shape, int iter, SurfaceState& st,
+               bool issue) {
+    if (!st.valid) {
+        if (issue) enqueue_surface(R, L, st.vsel, st.pn);
+        st.valid = true;
+    }
+    if (issue) enqueue_associate(R, L, st.vsel);
+    if (pose && issue) {
+        enqueue_normal_eq(R, L, sc.gram_mode, st.vsel, st.pn);
+        enqueue_pose_step(R, L, sc.pose_fp64, iter);
+    }
+    if (shape) {
+        // re-skin at the new pose into the other vertex buffer, then one
+        // offset step; afterwards the surface must be re-skinned
+        int vn = st.vsel;
+        if (pose) {
+            vn = st.vsel ^ 1;
+            if (issue) enqueue_surface(R, L, vn, st.pn);
+        }
+        if (issue) {
+            timed_begin(R, TRACK_K_SHAPE);
+            launch_shape(L, sc.shape_fp64, st.vsel, vn, st.pn);
+            timed_end(R, TRACK_K_SHAPE);
+        }
+        st.pn += 1;
+        st.vsel = vn;
+        st.valid = false;
+    } else if (pose) {
+        st.vsel ^= 1;
+        if (issue) enqueue_surface(R, L, st.vsel, st.pn);
+    }
+}
+
+// whole frame of a batch whose slots all start a frame
+SurfaceState frame(Runner& R, const Launch& L, const Schedule& sc, bool surface_valid, bool issue) {
+    SurfaceState st;
+    st.valid = surface_valid;
+    if (issue) launch_frame_begin(L);
+    for (int t = 0; t < sc.n_iters; ++t) iteration(R, L, sc, sc.do_pose[t] != 0, sc.do_shape[t] != 0, t, st, issue);
+    if (issue) launch_frame_end(L, sc.first_pose, sc.last_pose);
+    return st;
+}
+
+// Issue `body`: replay the cached graph of this key, or capture one (once
+// the key has been launched `capture_after` times without a graph), or launch
+// directly (graphs off, or kernel timing on).  `body` must issue the same
+// work for equal keys; what it reads from the slot table is uploaded before
+// every launch.
+template <class Body>
+int run_cached(Runner& R, const GraphKey& key, Body body) {
+    ++R.clock;
+    if (!R.use_graphs || timing_on(R)) {
+        body();
+        return TRACK_OK;
+    }
+    CachedGraph* g = nullptr;
+    for (auto& q : R.graphs)
+        if (q.key == key) { g = &q; break; }
+    if (g && g->exec) {
+        g->last_use = R.clock;
+        HIP_TRY(hipGraphLaunch(g->exec, R.s));
+        return TRACK_OK;
+    }
+    if (!g) {
+        if (R.graphs.size() >= kMaxGraphs) {
+            // forget the least recently used key (after its launches finished)
+            HIP_TRY(hipStreamSynchronize(R.s));
+            size_t lru = 0;
+            for (size_t q = 1; q < R.graphs.size(); ++q)
+                if (R.graphs[q].last_use < R.graphs[lru].last_use) lru = q;
+            if (R.graphs[lru].exec) (void)hipGraphExecDestroy(R.graphs[lru].exec);
+            R.graphs.erase(R.graphs.begin() + lru);
+        }
+        CachedGraph ng;
+        ng.key = key;
+        R.graphs.push_back(ng);
+        g = &R.graphs.back();
+    }
+    g->last_use = R.clock;
+    if (g->seen < R.capture_after) {
+        g->seen += 1;
+        body();
+        return TRACK_OK;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(R.s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        body();
+        e = hipStreamEndCapture(R.s, &graph);
+    }
+    if (e == hipSuccess) {
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+    }
+    if (e != hipSuccess) {
+        // no graphs on this stream: launch directly from now on
+        (void)hipGetLastError();
+        g->exec = nullptr;
+        R.use_graphs = false;
+        body();
+        return TRACK_OK;
+    }
+    HIP_TRY(hipGraphLaunch(g->exec, R.s));
+    return TRACK_OK;
+}
+
+const char* lost_reason(int why) {
+    switch (why) {
+        case 1: return "pose system not positive definite";
+        case 2: return "frame has no valid pixels";
+        case 3: return "no pixel matched the surface";
+        case 4: return "pose diverged";
+        case 5: return "energy diverged";
+    }
+    return "frame rejected";
+}
+
+// host record after a frame of stream s: advance or roll back the buffers
+void finish_frame(Stream* s, const SurfaceState& st, int status) {
+    if (status == TRACK_OK) {
+        s->v_cur ^= st.vsel;
+        int q = s->phi_cur;
+        for (int k = 0; k < st.pn; ++k) q = phi_next(q, s->phi_prev);
+        s->phi_cur = s->phi_prev = q;
+        s->surface_valid = st.valid;
+        s->refresh_pose = false;
+    } else {
+        // the pose was restored on the device; the frame-start offsets are
+        // untouched in the previous-frame buffer
+        s->phi_cur = s->phi_prev;
+        s->surface_valid = false;
+        s->refresh_pose = true;
+    }
+}
+
+track_frame_stats to_stats(const DevSummary& d, float ms) {
+    track_frame_stats fs{};
+    fs.status = d.status;
+    fs.n_valid_px = d.n_valid_px;
+    fs.n_assoc_px = d.n_assoc_px;
+    fs.n_obs_verts = d.n_obs_verts;
+    fs.energy_first = d.energy_first;
+    fs.energy_last = d.energy_last;
+    fs.step_norm_last = d.step_norm_last;
+    fs.ms_total = ms;
+    return fs;
+}
+
+}  // namespace
+
+// ==========================================================================
+// Single-stream context: a batch of one.
+// ==========================================================================
+struct track_ctx {
+    Stream st;
+    Runner run;
+    Schedule sched;
+    int gram_mode = 0;
+    track_frame_stats last{};
+};
+
+namespace {
+
+Launch stage_one(track_ctx* c, int flags, const float* depth, const float* xyz) {
+    TableEntry e{&c->st, flags, 0, depth, xyz};
+    return stage_table(c->run, 0, &e, 1);
+}
+
+// FK (if needed), skin and normals at the current state
+int refresh_surface(track_ctx* c) {
+    if (c->st.surface_valid) return TRACK_OK;
+    Launch L = stage_one(c, 0, nullptr, nullptr);
+    if (c->st.refresh_pose) launch_fk(L);
+    enqueue_surface(c->run, L, 0, 0);
+    c->st.surface_valid = true;
+    c->st.refresh_pose = false;
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    return TRACK_OK;
+}
+
+int run_frame(track_ctx* c, const float* depth, const float* xyz) {
+    Runner& R = c->run;
+    Stream& s = c->st;
+    const int flags = kSlotBeginFrame | kSlotEndFrame | (s.refresh_pose ? kSlotRefreshPose : 0);
+    Launch L = stage_one(c, flags, depth, xyz);
+    GraphKey key{};
+    key.n = 1; key.off = 0; key.kind = 0; key.skin_first = s.surface_valid ? 0 : 1;
+    for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
+    const bool valid0 = s.surface_valid;
+    const SurfaceState st = frame(R, L, c->sched, valid0, false);
+    HIP_TRY(hipEventRecord(R.f0, R.s));
+    int rc = run_cached(R, key, [&]() { frame(R, L, c->sched, valid0, true); });
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(R.f1, R.s));
+    HIP_TRY(hipMemcpyAsync(R.hsum, R.dsum, sizeof(DevSummary), hipMemcpyDeviceToHost, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    timed_collect(R);
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, R.f0, R.f1);
+    const DevSummary d = R.hsum[0];
+    c->last = to_stats(d, ms);
+    finish_frame(&s, st, d.status);
+    if (d.status != TRACK_OK) return fail(d.status, lost_reason(d.reason));
+    return TRACK_OK;
+}
+
+void free_ctx(track_ctx* c) {
+    if (!c) return;
+    runner_free(c->run);
+    stream_free(&c->st);
+    delete c;
+}
+
+}  // namespace
+
+// ==========================================================================
+// Serving: many streams, one launch sequence per Gauss-Newton iteration.
+// ==========================================================================
+namespace {
+
+// deep copy of a model, kept while a stream waits for admission
+struct HostModel {
+    track_model m{};
+    std::vector<int32_t> parent, type, link_joint, faces, skin_link, nbr;
+    std::vector<float> axis, offset, rest, skin_w;
+    void take(const track_model* s) {
+        m = *s;
+        parent.assign(s->joint_parent, s->joint_parent + s->n_joints);
+        type.assign(s->joint_type, s->joint_type + s->n_joints);
+        axis.assign(s->joint_axis, s->joint_axis + 3 * s->n_joints);
+        offset.assign(s->joint_offset, s->joint_offset + 7 * s->n_joints);
+        link_joint.assign(s->link_joint, s->link_joint + s->n_links);
+        rest.assign(s->rest_xyz, s->rest_xyz + 3 * (size_t)s->n_verts);
+        faces.assign(s->faces, s->faces + 3 * (size_t)s->n_faces);
+        skin_link.assign(s->skin_link, s->skin_link + (size_t)s->n_verts * s->max_infl);
+        skin_w.assign(s->skin_w, s->skin_w + (size_t)s->n_verts * s->max_infl);
+        if (s->neighbors) nbr.assign(s->neighbors, s->neighbors + 4 * (size_t)s->n_verts);
+        m.joint_parent = parent.data(); m.joint_type = type.data(); m.joint_axis = axis.data();
+        m.joint_offset = offset.data(); m.link_joint = link_joint.data(); m.rest_xyz = rest.data();
+        m.faces = faces.data(); m.skin_link = skin_link.data(); m.skin_w = skin_w.data();
+        m.neighbors = s->neighbors ? nbr.data() : nullptr;
+    }
+    void release() {
+        std::vector<int32_t>().swap(faces);
+        std::vector<int32_t>().swap(skin_link);
+        std::vector<int32_t>().swap(nbr);
+        std::vector<float>().swap(rest);
+        std::vector<float>().swap(skin_w);
+    }
+};
+
+struct PendingFrame {
+    const float* dev = nullptr;   // caller's device frame, or
+    std::vector<float> host;      // a copy of the caller's host frame
+    int64_t tag = 0;
+};
+
+struct ServerStream {
+    int id = -1;
+    bool open = false;
+    HostModel model;
+    track_camera cam{};
+    std::vector<double> theta0;
+    std::vector<float> phi0;
+    size_t bytes = 0;
+    Stream* dev = nullptr;        // resident when set
+    std::deque<PendingFrame> frames;
+    int iter = -1;                // iteration of the frame in progress, -1 = none
+};
+
+}  // namespace
+
+struct track_server {
+    Runner run;
+    Schedule sched;
+    track_params params{};
+    std::vector<uint8_t> do_pose, do_shape, active;
+    int64_t budget = 0, used = 0;
+    int max_streams = 0;
+    std::vector<ServerStream*> streams;
+    std::deque<int> waiting;        // admission queue (stream ids, FIFO)
+    std::vector<track_completion> done;
+};
+
+namespace {
+
+void server_release(track_server* sv, ServerStream* ss) {
+    if (ss->dev) {
+        stream_free(ss->dev);
+        delete ss->dev;
+        ss->dev = nullptr;
+        sv->used -= (int64_t)ss->bytes;
+    }
+}
+
+int server_resident(const track_server* sv) {
+    int n = 0;
+    for (auto* ss : sv->streams)
+        if (ss && ss->dev) ++n;
+    return n;
+}
+
+// admit waiting streams in arrival order while the budget allows
+int server_admit(track_server* sv) {
+    while (!sv->waiting.empty()) {
+        ServerStream* ss = sv->streams[sv->waiting.front()];
+        if (!ss || !ss->open) { sv->waiting.pop_front(); continue; }
+        if (sv->used + (int64_t)ss->bytes > sv->budget || server_resident(sv) >= sv->max_streams) break;
+        Stream* d = new Stream();
+        int rc = stream_create(d, &ss->model.m, &ss->cam, &sv->params, ss->theta0.data(),
+                               ss->phi0.empty() ? nullptr : ss->phi0.data());
+        if (rc == TRACK_E_NOMEM) { delete d; break; }  // the device is fuller than the budget says
+        if (rc) { delete d; return rc; }
+        ss->dev = d;
+        sv->used += (int64_t)ss->bytes;
+        ss->model.release();
+        sv->waiting.pop_front();
+    }
+    return TRACK_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char* track_last_error(void) { return g_err.c_str(); }
+
+int track_init(const track_model* model, const track_camera* camera, const track_params* params,
+               const double* theta0, const float* phi0, void* hip_stream, track_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(TRACK_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = validate_model(model, camera);
+    if (rc) return rc;
+    if ((rc = validate_params(params, model->n_joints))) return rc;
+    if (!theta0) return fail(TRACK_E_INVALID, "theta0 is NULL");
+    for (int k = 0; k < model->n_joints; ++k)
+        if (!std::isfinite(theta0[k])) return fail(TRACK_E_INVALID, "theta0 not finite");
+    track_ctx* c = new track_ctx();
+    if ((rc = runner_init(c->run, 1, hip_stream))) { free_ctx(c); return rc; }
+    if ((rc = stream_create(&c->st, model, camera, params, theta0, phi0))) { free_ctx(c); return rc; }
+    c->sched.set(params);
+    if ((rc = refresh_surface(c))) { free_ctx(c); return rc; }
     *out = c;
     return TRACK_OK;
 }
 
 int track_set_params(track_ctx* c, const track_params* p) {
     if (!c) return fail(TRACK_E_INVALID, "ctx is NULL");
-    return set_params(c, p);
+    int rc = validate_params(p, c->st.P);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    if ((rc = stream_set_params(&c->st, p))) return rc;
+    c->sched.set(p);
+    drop_graphs(c->run);
+    return TRACK_OK;
 }
 
 int track_frame(track_ctx* c, const float* depth, int32_t on_device) {
     if (!c || !depth) return fail(TRACK_E_INVALID, "ctx/depth is NULL");
     const float* d = depth;
     if (!on_device) {
-        HIP_TRY(hipMemcpyAsync(c->depth_buf, depth, sizeof(float) * c->W * c->H, hipMemcpyHostToDevice, c->stream));
-        d = c->depth_buf;
+        HIP_TRY(hipMemcpyAsync(c->st.depth_buf, depth, sizeof(float) * c->st.W * c->st.H, hipMemcpyHostToDevice,
+                               c->run.s));
+        d = c->st.depth_buf;
     }
     return run_frame(c, d, nullptr);
 }
@@ -806,8 +1071,9 @@ int track_frame_xyz(track_ctx* c, const float* xyz, int32_t on_device) {
     if (!c || !xyz) return fail(TRACK_E_INVALID, "ctx/xyz is NULL");
     const float* d = xyz;
     if (!on_device) {
-        HIP_TRY(hipMemcpyAsync(c->xyz_buf, xyz, sizeof(float) * 3 * c->W * c->H, hipMemcpyHostToDevice, c->stream));
-        d = c->xyz_buf;
+        HIP_TRY(hipMemcpyAsync(c->st.xyz_buf, xyz, sizeof(float) * 3 * c->st.W * c->st.H, hipMemcpyHostToDevice,
+                               c->run.s));
+        d = c->st.xyz_buf;
     }
     return run_frame(c, nullptr, d);
 }
@@ -815,14 +1081,14 @@ int track_frame_xyz(track_ctx* c, const float* xyz, int32_t on_device) {
 int track_state(const track_ctx* cc, double* theta, float* phi, float* verts, track_frame_stats* stats) {
     track_ctx* c = const_cast<track_ctx*>(cc);
     if (!c) return fail(TRACK_E_INVALID, "ctx is NULL");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (theta) HIP_TRY(hipMemcpy(theta, c->theta, sizeof(double) * c->P, hipMemcpyDeviceToHost));
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    const Slot& S = c->st.slot;
+    if (theta) HIP_TRY(hipMemcpy(theta, S.theta, sizeof(double) * c->st.P, hipMemcpyDeviceToHost));
     int rc;
-    if (phi && (rc = download_soa(c, c->phi[c->phi_cur], phi))) return rc;
+    if (phi && (rc = download_soa(c->st.V, S.phi[c->st.phi_cur], phi))) return rc;
     if (verts) {
-        ensure_surface(c);
-        HIP_TRY(hipStreamSynchronize(c->stream));
-        if ((rc = download_v4(c, c->verts[c->v_cur], verts))) return rc;
+        if ((rc = refresh_surface(c))) return rc;
+        if ((rc = download_v4(c->st.V, S.verts[c->st.v_cur], verts))) return rc;
     }
     if (stats) *stats = c->last;
     return TRACK_OK;
@@ -830,168 +1096,167 @@ int track_state(const track_ctx* cc, double* theta, float* phi, float* verts, tr
 
 int track_reset(track_ctx* c, const double* theta, const float* phi) {
     if (!c || !theta) return fail(TRACK_E_INVALID, "ctx/theta is NULL");
-    for (int k = 0; k < c->P; ++k)
+    for (int k = 0; k < c->st.P; ++k)
         if (!std::isfinite(theta[k])) return fail(TRACK_E_INVALID, "theta not finite");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipMemcpy(c->theta, theta, sizeof(double) * c->P, hipMemcpyHostToDevice));
-    std::vector<float> z3(3 * (size_t)c->V, 0.0f);
-    const float* p0 = phi ? phi : z3.data();
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    HIP_TRY(hipMemcpy(c->st.slot.theta, theta, sizeof(double) * c->st.P, hipMemcpyHostToDevice));
+    std::vector<float> z3(3 * (size_t)c->st.V, 0.0f);
     int rc;
-    if ((rc = upload_soa(c, c->phi[c->phi_cur], p0)) || (rc = upload_soa(c, c->phi_prev, p0))) return rc;
-    launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
-    c->surface_valid = false;
-    ensure_surface(c);
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return TRACK_OK;
+    if ((rc = upload_soa(c->st.V, c->st.slot.phi[0], phi ? phi : z3.data()))) return rc;
+    c->st.phi_cur = c->st.phi_prev = 0;
+    c->st.surface_valid = false;
+    c->st.refresh_pose = true;
+    return refresh_surface(c);
 }
 
-void track_destroy(track_ctx* c) {
-    if (!c) return;
-    (void)hipStreamSynchronize(c->stream);
-    free_ctx(c);
-}
+void track_destroy(track_ctx* c) { free_ctx(c); }
 
 int track_kernel_timing(track_ctx* c, int32_t k, int32_t enable) {
     if (!c || k < 0 || k >= TRACK_K_COUNT_) return fail(TRACK_E_INVALID, "bad kernel id");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    timed_collect(c);
-    c->timers[k].on = enable != 0;
-    c->timers[k].launches = 0;
-    c->timers[k].total_ms = 0.0;
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    timed_collect(c->run);
+    c->run.timers[k].on = enable != 0;
+    c->run.timers[k].launches = 0;
+    c->run.timers[k].total_ms = 0.0;
     return TRACK_OK;
 }
 
 int track_kernel_time(track_ctx* c, int32_t k, int64_t* launches, double* total_ms) {
     if (!c || k < 0 || k >= TRACK_K_COUNT_) return fail(TRACK_E_INVALID, "bad kernel id");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    timed_collect(c);
-    if (launches) *launches = c->timers[k].launches;
-    if (total_ms) *total_ms = c->timers[k].total_ms;
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    timed_collect(c->run);
+    if (launches) *launches = c->run.timers[k].launches;
+    if (total_ms) *total_ms = c->run.timers[k].total_ms;
     return TRACK_OK;
 }
 
 // ---- per-pass access -------------------------------------------------------
 int track_dbg_set(track_ctx* c, int32_t buf, const void* host, size_t bytes) {
     if (!c || !host) return fail(TRACK_E_INVALID, "ctx/host is NULL");
-    const size_t V = c->V, N = (size_t)c->W * c->H;
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    Stream& s = c->st;
+    Slot& S = s.slot;
+    const size_t V = s.V, N = (size_t)s.W * s.H;
+    HIP_TRY(hipStreamSynchronize(c->run.s));
     switch (buf) {
         case TRACK_BUF_THETA:
-            if (bytes != 8 * (size_t)c->P) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(c->theta, host, bytes, hipMemcpyHostToDevice));
-            launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
+            if (bytes != 8 * (size_t)s.P) return fail(TRACK_E_INVALID, "size");
+            HIP_TRY(hipMemcpy(S.theta, host, bytes, hipMemcpyHostToDevice));
+            launch_fk(stage_one(c, 0, nullptr, nullptr));
+            s.refresh_pose = false;
             break;
         case TRACK_BUF_PHI:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return upload_soa(c, c->phi[c->phi_cur], (const float*)host);
+            // keep the previous-frame offsets in their own buffer
+            if (s.phi_cur == s.phi_prev) s.phi_cur = phi_next(s.phi_cur, s.phi_prev);
+            return upload_soa(s.V, S.phi[s.phi_cur], (const float*)host);
         case TRACK_BUF_PHI_PREV:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return upload_soa(c, c->phi_prev, (const float*)host);
+            if (s.phi_cur == s.phi_prev) s.phi_prev = phi_next(s.phi_cur, s.phi_prev);
+            return upload_soa(s.V, S.phi[s.phi_prev], (const float*)host);
         case TRACK_BUF_VERTS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            c->surface_valid = true;
-            return upload_v4(c, c->verts[c->v_cur], (const float*)host);
+            s.surface_valid = true;
+            return upload_v4(s.V, S.verts[s.v_cur], (const float*)host);
         case TRACK_BUF_NORMALS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return upload_soa(c, c->normals, (const float*)host);
+            return upload_soa(s.V, S.normals, (const float*)host);
         case TRACK_BUF_DEPTH:
             if (bytes != 4 * N) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(c->depth_buf, host, bytes, hipMemcpyHostToDevice));
-            c->input_mode = 0;
+            HIP_TRY(hipMemcpy(s.depth_buf, host, bytes, hipMemcpyHostToDevice));
+            s.input_mode = 0;
             break;
         case TRACK_BUF_XYZ:
             if (bytes != 12 * N) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(c->xyz_buf, host, bytes, hipMemcpyHostToDevice));
-            c->input_mode = 1;
+            HIP_TRY(hipMemcpy(s.xyz_buf, host, bytes, hipMemcpyHostToDevice));
+            s.input_mode = 1;
             break;
-        case TRACK_BUF_COUNT: {
+        case TRACK_BUF_COUNT:
             if (bytes != 4 * V) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(c->acc.cnt, host, bytes, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(S.a.cnt, host, bytes, hipMemcpyHostToDevice));
             break;
-        }
         case TRACK_BUF_DELTA: {
             // stored as fixed-point sums: count * delta * 2^32 (set COUNT first)
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
             std::vector<uint32_t> cnt(V);
-            HIP_TRY(hipMemcpy(cnt.data(), c->acc.cnt, 4 * V, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(cnt.data(), S.a.cnt, 4 * V, hipMemcpyDeviceToHost));
             const float* d = (const float*)host;
-            std::vector<long long> s[3];
-            for (int q = 0; q < 3; ++q) s[q].resize(V);
+            std::vector<long long> sm[3];
+            for (int q = 0; q < 3; ++q) sm[q].resize(V);
             for (size_t i = 0; i < V; ++i)
-                for (int q = 0; q < 3; ++q) s[q][i] = std::llround((double)d[3 * i + q] * cnt[i] * kFix);
-            HIP_TRY(hipMemcpy(c->acc.sx, s[0].data(), 8 * V, hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(c->acc.sy, s[1].data(), 8 * V, hipMemcpyHostToDevice));
-            HIP_TRY(hipMemcpy(c->acc.sz, s[2].data(), 8 * V, hipMemcpyHostToDevice));
+                for (int q = 0; q < 3; ++q) sm[q][i] = std::llround((double)d[3 * i + q] * cnt[i] * kFix);
+            HIP_TRY(hipMemcpy(S.a.sx, sm[0].data(), 8 * V, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(S.a.sy, sm[1].data(), 8 * V, hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(S.a.sz, sm[2].data(), 8 * V, hipMemcpyHostToDevice));
             break;
         }
         default:
             return fail(TRACK_E_INVALID, "buffer cannot be set");
     }
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipStreamSynchronize(c->run.s));
     return TRACK_OK;
 }
 
 int track_dbg_get(const track_ctx* cc, int32_t buf, void* host, size_t bytes) {
     track_ctx* c = const_cast<track_ctx*>(cc);
     if (!c || !host) return fail(TRACK_E_INVALID, "ctx/host is NULL");
-    const size_t V = c->V, N = (size_t)c->W * c->H;
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    Stream& s = c->st;
+    const Slot& S = s.slot;
+    const size_t V = s.V, N = (size_t)s.W * s.H;
+    HIP_TRY(hipStreamSynchronize(c->run.s));
     switch (buf) {
         case TRACK_BUF_THETA:
-            if (bytes != 8 * (size_t)c->P) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(host, c->theta, bytes, hipMemcpyDeviceToHost));
+            if (bytes != 8 * (size_t)s.P) return fail(TRACK_E_INVALID, "size");
+            HIP_TRY(hipMemcpy(host, S.theta, bytes, hipMemcpyDeviceToHost));
             return TRACK_OK;
         case TRACK_BUF_STEP:
-            if (bytes != 8 * (size_t)c->P) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(host, c->step, bytes, hipMemcpyDeviceToHost));
+            if (bytes != 8 * (size_t)s.P) return fail(TRACK_E_INVALID, "size");
+            HIP_TRY(hipMemcpy(host, S.step, bytes, hipMemcpyDeviceToHost));
             return TRACK_OK;
         case TRACK_BUF_PHI:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_soa(c, c->phi[c->phi_cur], (float*)host);
+            return download_soa(s.V, S.phi[s.phi_cur], (float*)host);
         case TRACK_BUF_PHI_PREV:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_soa(c, c->phi_prev, (float*)host);
+            return download_soa(s.V, S.phi[s.phi_prev], (float*)host);
         case TRACK_BUF_VERTS:
-            if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_v4(c, c->verts[c->v_cur], (float*)host);
         case TRACK_BUF_VERTS_NEW:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_v4(c, c->verts[c->v_cur], (float*)host);
+            return download_v4(s.V, S.verts[s.v_cur], (float*)host);
         case TRACK_BUF_NORMALS:
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
-            return download_soa(c, c->normals, (float*)host);
+            return download_soa(s.V, S.normals, (float*)host);
         case TRACK_BUF_ASSOC:
             if (bytes != 4 * N) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(host, c->assoc, bytes, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(host, S.assoc, bytes, hipMemcpyDeviceToHost));
             return TRACK_OK;
         case TRACK_BUF_COUNT:
             if (bytes != 4 * V) return fail(TRACK_E_INVALID, "size");
-            HIP_TRY(hipMemcpy(host, c->acc.cnt, bytes, hipMemcpyDeviceToHost));
+            HIP_TRY(hipMemcpy(host, S.a.cnt, bytes, hipMemcpyDeviceToHost));
             return TRACK_OK;
         case TRACK_BUF_DELTA: {
             if (bytes != 12 * V) return fail(TRACK_E_INVALID, "size");
             std::vector<uint32_t> cnt(V);
-            std::vector<long long> s[3];
-            HIP_TRY(hipMemcpy(cnt.data(), c->acc.cnt, 4 * V, hipMemcpyDeviceToHost));
-            long long* src[3] = {c->acc.sx, c->acc.sy, c->acc.sz};
+            std::vector<long long> sm[3];
+            HIP_TRY(hipMemcpy(cnt.data(), S.a.cnt, 4 * V, hipMemcpyDeviceToHost));
+            long long* src[3] = {S.a.sx, S.a.sy, S.a.sz};
             for (int q = 0; q < 3; ++q) {
-                s[q].resize(V);
-                HIP_TRY(hipMemcpy(s[q].data(), src[q], 8 * V, hipMemcpyDeviceToHost));
+                sm[q].resize(V);
+                HIP_TRY(hipMemcpy(sm[q].data(), src[q], 8 * V, hipMemcpyDeviceToHost));
             }
             float* d = (float*)host;
             for (size_t i = 0; i < V; ++i)
                 for (int q = 0; q < 3; ++q)
-                    d[3 * i + q] = cnt[i] ? (float)((double)s[q][i] / ((double)cnt[i] * kFix)) : 0.0f;
+                    d[3 * i + q] = cnt[i] ? (float)((double)sm[q][i] / ((double)cnt[i] * kFix)) : 0.0f;
             return TRACK_OK;
         }
         case TRACK_BUF_GRAM: {
-            const size_t n1 = (size_t)c->P + 1;
+            const size_t n1 = (size_t)s.P + 1;
             if (bytes != 8 * n1 * n1) return fail(TRACK_E_INVALID, "size");
-            std::vector<double> g((size_t)c->PP * c->PP);
-            HIP_TRY(hipMemcpy(g.data(), c->gram, 8 * g.size(), hipMemcpyDeviceToHost));
+            std::vector<double> g((size_t)s.PP * s.PP);
+            HIP_TRY(hipMemcpy(g.data(), S.gram, 8 * g.size(), hipMemcpyDeviceToHost));
             double* d = (double*)host;
             for (size_t i = 0; i < n1; ++i)
-                for (size_t j = 0; j < n1; ++j) d[i * n1 + j] = g[i * c->PP + j];
+                for (size_t j = 0; j < n1; ++j) d[i * n1 + j] = g[i * s.PP + j];
             return TRACK_OK;
         }
         default:
@@ -1001,42 +1266,303 @@ int track_dbg_get(const track_ctx* cc, int32_t buf, void* host, size_t bytes) {
 
 int track_dbg_run(track_ctx* c, int32_t pass) {
     if (!c) return fail(TRACK_E_INVALID, "ctx is NULL");
-    const float* depth = c->input_mode == 0 ? c->depth_buf : nullptr;
-    const float* xyz = c->input_mode == 1 ? c->xyz_buf : nullptr;
+    Stream& s = c->st;
+    Runner& R = c->run;
+    const float* depth = s.input_mode == 0 ? s.depth_buf : nullptr;
+    const float* xyz = s.input_mode == 1 ? s.xyz_buf : nullptr;
+    HIP_TRY(hipStreamSynchronize(R.s));
     switch (pass) {
-        case TRACK_PASS_SKIN:
-            launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
-            c->surface_valid = false;
-            ensure_surface(c);
+        case TRACK_PASS_SKIN: {
+            Launch L = stage_one(c, 0, depth, xyz);
+            launch_fk(L);
+            enqueue_surface(R, L, 0, 0);
+            s.surface_valid = true;
+            s.refresh_pose = false;
             break;
+        }
         case TRACK_PASS_NORMALS:
-            launch_normals(c->stream, c->dm, c->verts[c->v_cur], c->normals);
+            launch_normals(stage_one(c, 0, depth, xyz), 0);
             break;
         case TRACK_PASS_ASSOCIATE:
-            pass_associate(c, depth, xyz);
+            enqueue_associate(R, stage_one(c, 0, depth, xyz), 0);
             break;
-        case TRACK_PASS_NORMAL_EQ:
-            launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
-            pass_normal_eq(c);
+        case TRACK_PASS_NORMAL_EQ: {
+            Launch L = stage_one(c, 0, depth, xyz);
+            launch_fk(L);
+            enqueue_normal_eq(R, L, c->sched.gram_mode, 0, 0);
             break;
-        case TRACK_PASS_POSE_STEP:
-            HIP_TRY(hipMemsetAsync(&c->dstats->status, 0, sizeof(int), c->stream));
-            pass_pose_step(c, 0);
+        }
+        case TRACK_PASS_POSE_STEP: {
+            Launch L = stage_one(c, kSlotBeginFrame, depth, xyz);
+            launch_frame_begin(L);  // clears the status flag
+            enqueue_pose_step(R, L, c->sched.pose_fp64, 0);
+            s.surface_valid = false;
             break;
-        case TRACK_PASS_SHAPE:
-            launch_fk(c->stream, c->djt, c->theta, c->dq, c->xi);
-            pass_shape(c, true);
+        }
+        case TRACK_PASS_SHAPE: {
+            Launch L = stage_one(c, 0, depth, xyz);
+            launch_fk(L);
+            enqueue_surface(R, L, 1, 0);
+            timed_begin(R, TRACK_K_SHAPE);
+            launch_shape(L, c->sched.shape_fp64, 0, 1, 0);
+            timed_end(R, TRACK_K_SHAPE);
+            s.v_cur ^= 1;
+            s.phi_cur = phi_next(s.phi_cur, s.phi_prev);
+            s.surface_valid = false;
+            s.refresh_pose = false;
             break;
+        }
         default:
             return fail(TRACK_E_INVALID, "unknown pass");
     }
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    timed_collect(R);
     if (pass == TRACK_PASS_POSE_STEP) {
         int st = 0;
-        HIP_TRY(hipMemcpy(&st, &c->dstats->status, sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(&st, &s.slot.st->status, sizeof(int), hipMemcpyDeviceToHost));
         if (st == TRACK_E_NOT_PD) return fail(TRACK_E_NOT_PD, "pose system not positive definite");
     }
     return TRACK_OK;
+}
+
+// ---- serving ---------------------------------------------------------------
+int track_server_create(const track_params* params, int64_t hbm_budget_bytes, int32_t max_streams, void* hip_stream,
+                        track_server** out) {
+    g_err.clear();
+    if (!out) return fail(TRACK_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (max_streams < 1 || max_streams > 4096) return fail(TRACK_E_INVALID, "max_streams must be in 1..4096");
+    if (hbm_budget_bytes <= 0) return fail(TRACK_E_INVALID, "budget must be > 0");
+    int rc = validate_params(params, 0);
+    if (rc) return rc;
+    if (params->active) return fail(TRACK_E_INVALID, "a server takes no per-joint active mask");
+    track_server* sv = new track_server();
+    sv->params = *params;
+    sv->do_pose.assign(params->do_pose, params->do_pose + params->n_iters);
+    sv->do_shape.assign(params->do_shape, params->do_shape + params->n_iters);
+    sv->params.do_pose = sv->do_pose.data();
+    sv->params.do_shape = sv->do_shape.data();
+    sv->sched.set(params);
+    sv->budget = hbm_budget_bytes;
+    sv->max_streams = max_streams;
+    // three iteration kinds (pose, offset, both) can share a step
+    if ((rc = runner_init(sv->run, 3 * max_streams, hip_stream))) {
+        runner_free(sv->run);
+        delete sv;
+        return rc;
+    }
+    sv->run.capture_after = 2;  // capture a batch shape once it repeats
+    *out = sv;
+    return TRACK_OK;
+}
+
+int track_server_open(track_server* sv, const track_model* model, const track_camera* camera, const double* theta0,
+                      const float* phi0, int32_t* stream_id) {
+    if (!sv || !stream_id) return fail(TRACK_E_INVALID, "server/stream_id is NULL");
+    int rc = validate_model(model, camera);
+    if (rc) return rc;
+    if (!theta0) return fail(TRACK_E_INVALID, "theta0 is NULL");
+    for (int k = 0; k < model->n_joints; ++k)
+        if (!std::isfinite(theta0[k])) return fail(TRACK_E_INVALID, "theta0 not finite");
+    const size_t bytes = stream_bytes(model, camera);
+    if ((int64_t)bytes > sv->budget) return fail(TRACK_E_BUDGET, "stream alone exceeds the memory budget");
+    ServerStream* ss = new ServerStream();
+    ss->id = (int)sv->streams.size();
+    ss->open = true;
+    ss->model.take(model);
+    ss->cam = *camera;
+    ss->theta0.assign(theta0, theta0 + model->n_joints);
+    if (phi0) ss->phi0.assign(phi0, phi0 + 3 * (size_t)model->n_verts);
+    ss->bytes = bytes;
+    sv->streams.push_back(ss);
+    sv->waiting.push_back(ss->id);
+    *stream_id = ss->id;
+    return server_admit(sv);
+}
+
+int track_server_submit(track_server* sv, int32_t id, const float* depth, int32_t on_device, int64_t tag) {
+    if (!sv || !depth) return fail(TRACK_E_INVALID, "server/depth is NULL");
+    if (id < 0 || id >= (int)sv->streams.size() || !sv->streams[id] || !sv->streams[id]->open)
+        return fail(TRACK_E_INVALID, "unknown stream");
+    ServerStream* ss = sv->streams[id];
+    PendingFrame f;
+    f.tag = tag;
+    if (on_device) f.dev = depth;
+    else f.host.assign(depth, depth + (size_t)ss->cam.width * ss->cam.height);
+    ss->frames.push_back(std::move(f));
+    return TRACK_OK;
+}
+
+int track_server_step(track_server* sv, int32_t* n_completed) {
+    if (!sv) return fail(TRACK_E_INVALID, "server is NULL");
+    if (n_completed) *n_completed = 0;
+    int rc = server_admit(sv);
+    if (rc) return rc;
+    Runner& R = sv->run;
+    const Schedule& sc = sv->sched;
+    // streams with work, grouped by the kind of their next iteration
+    std::vector<TableEntry> group[3];
+    std::vector<ServerStream*> who[3];
+    for (ServerStream* ss : sv->streams) {
+        if (!ss || !ss->dev) continue;
+        if (ss->iter < 0) {
+            if (ss->frames.empty()) continue;
+            ss->iter = 0;
+            PendingFrame& f = ss->frames.front();
+            if (f.dev == nullptr)
+                HIP_TRY(hipMemcpyAsync(ss->dev->depth_buf, f.host.data(), sizeof(float) * f.host.size(),
+                                       hipMemcpyHostToDevice, R.s));
+        }
+        const PendingFrame& f = ss->frames.front();
+        const int t = ss->iter;
+        int flags = 0;
+        if (t == 0) flags |= kSlotBeginFrame | (ss->dev->refresh_pose ? kSlotRefreshPose : 0);
+        if (t == sc.n_iters - 1) flags |= kSlotEndFrame;
+        const int kind = (sc.do_pose[t] ? 1 : 0) | (sc.do_shape[t] ? 2 : 0);
+        const int g = kind == 3 ? 0 : kind;  // 0: pose+offset (or neither), 1: pose, 2: offset
+        group[g].push_back(TableEntry{ss->dev, flags, t, f.dev ? f.dev : ss->dev->depth_buf, nullptr});
+        who[g].push_back(ss);
+    }
+    int off = 0;
+    int nentries = 0;
+    for (int g = 0; g < 3; ++g) {
+        const int n = (int)group[g].size();
+        if (n == 0) continue;
+        const bool pose = g == 1 || (g == 0 && sc.do_pose[who[g][0]->iter]);
+        const bool shape = g == 2 || (g == 0 && sc.do_shape[who[g][0]->iter]);
+        Launch L = stage_table(R, off, group[g].data(), n);
+        GraphKey key{};
+        key.n = n; key.off = off; key.kind = 1 + (pose ? 1 : 0) + (shape ? 2 : 0); key.skin_first = 1;
+        for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
+        rc = run_cached(R, key, [&]() {
+            SurfaceState st;
+            launch_frame_begin(L);
+            iteration(R, L, sc, pose, shape, 0, st, true);
+            launch_frame_end(L, sc.first_pose, sc.last_pose);
+        });
+        if (rc) return rc;
+        // the iteration's effect on each stream's buffers
+        SurfaceState it;
+        iteration(R, L, sc, pose, shape, 0, it, false);
+        for (ServerStream* ss : who[g]) {
+            Stream* d = ss->dev;
+            d->v_cur ^= it.vsel;
+            if (it.pn) d->phi_cur = phi_next(d->phi_cur, d->phi_prev);
+        }
+        off += n;
+        nentries = off;
+    }
+    if (nentries == 0) return TRACK_OK;
+    HIP_TRY(hipMemcpyAsync(R.hsum, R.dsum, sizeof(DevSummary) * nentries, hipMemcpyDeviceToHost, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    timed_collect(R);
+    int ndone = 0;
+    off = 0;
+    for (int g = 0; g < 3; ++g) {
+        for (size_t q = 0; q < who[g].size(); ++q) {
+            ServerStream* ss = who[g][q];
+            const int t = ss->iter;
+            if (t == sc.n_iters - 1) {
+                const DevSummary& d = R.hsum[off + q];
+                Stream* s = ss->dev;
+                // the buffers already advanced; on failure return to the
+                // frame-start offsets and redo the surface next frame
+                if (d.status == TRACK_OK) {
+                    s->phi_prev = s->phi_cur;
+                    s->refresh_pose = false;
+                } else {
+                    s->phi_cur = s->phi_prev;
+                    s->refresh_pose = true;
+                }
+                s->surface_valid = false;
+                track_completion cpl{};
+                cpl.stream = ss->id;
+                cpl.status = d.status;
+                cpl.tag = ss->frames.front().tag;
+                cpl.stats = to_stats(d, 0.0f);
+                sv->done.push_back(cpl);
+                ss->frames.pop_front();
+                ss->iter = -1;
+                ++ndone;
+            } else {
+                ss->iter = t + 1;
+            }
+        }
+        off += (int)who[g].size();
+    }
+    if (n_completed) *n_completed = ndone;
+    return TRACK_OK;
+}
+
+int track_server_poll(track_server* sv, track_completion* out, int32_t max_out, int32_t* n_out) {
+    if (!sv || !n_out || (max_out > 0 && !out)) return fail(TRACK_E_INVALID, "bad arguments");
+    const int n = std::min<int>(max_out, (int)sv->done.size());
+    for (int q = 0; q < n; ++q) out[q] = sv->done[q];
+    sv->done.erase(sv->done.begin(), sv->done.begin() + n);
+    *n_out = n;
+    return TRACK_OK;
+}
+
+int track_server_state(track_server* sv, int32_t id, double* theta, float* phi) {
+    if (!sv) return fail(TRACK_E_INVALID, "server is NULL");
+    if (id < 0 || id >= (int)sv->streams.size() || !sv->streams[id] || !sv->streams[id]->open)
+        return fail(TRACK_E_INVALID, "unknown stream");
+    ServerStream* ss = sv->streams[id];
+    if (!ss->dev) {
+        if (theta) std::memcpy(theta, ss->theta0.data(), sizeof(double) * ss->theta0.size());
+        if (phi) {
+            const size_t n = 3 * (size_t)ss->model.m.n_verts;
+            if (ss->phi0.empty()) std::fill(phi, phi + n, 0.0f);
+            else std::memcpy(phi, ss->phi0.data(), sizeof(float) * n);
+        }
+        return TRACK_OK;
+    }
+    if (ss->iter >= 0) return fail(TRACK_E_INVALID, "stream has a frame in progress");
+    HIP_TRY(hipStreamSynchronize(sv->run.s));
+    Stream* s = ss->dev;
+    if (theta) HIP_TRY(hipMemcpy(theta, s->slot.theta, sizeof(double) * s->P, hipMemcpyDeviceToHost));
+    if (phi) return download_soa(s->V, s->slot.phi[s->phi_cur], phi);
+    return TRACK_OK;
+}
+
+int track_server_close(track_server* sv, int32_t id) {
+    if (!sv) return fail(TRACK_E_INVALID, "server is NULL");
+    if (id < 0 || id >= (int)sv->streams.size() || !sv->streams[id] || !sv->streams[id]->open)
+        return fail(TRACK_E_INVALID, "unknown stream");
+    HIP_TRY(hipStreamSynchronize(sv->run.s));
+    ServerStream* ss = sv->streams[id];
+    server_release(sv, ss);
+    delete ss;
+    sv->streams[id] = nullptr;
+    return server_admit(sv);
+}
+
+int track_server_info(track_server* sv, track_server_stats* out) {
+    if (!sv || !out) return fail(TRACK_E_INVALID, "server/out is NULL");
+    track_server_stats s{};
+    for (auto* ss : sv->streams) {
+        if (!ss) continue;
+        if (ss->dev) ++s.resident;
+        else ++s.waiting;
+        if (ss->iter >= 0) ++s.frames_in_progress;
+        s.frames_pending += (int32_t)ss->frames.size();
+    }
+    s.bytes_used = sv->used;
+    s.bytes_budget = sv->budget;
+    *out = s;
+    return TRACK_OK;
+}
+
+void track_server_destroy(track_server* sv) {
+    if (!sv) return;
+    if (sv->run.s) (void)hipStreamSynchronize(sv->run.s);
+    for (auto* ss : sv->streams) {
+        if (!ss) continue;
+        server_release(sv, ss);
+        delete ss;
+    }
+    runner_free(sv->run);
+    delete sv;
 }
 
 }  // extern "C"

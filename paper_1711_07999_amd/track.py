@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtrack.so")
 
 TRACK_OK, TRACK_E_INVALID, TRACK_E_NOMEM, TRACK_E_DEVICE = 0, -1, -2, -3
 TRACK_E_NOT_PD, TRACK_E_LOST, TRACK_E_BUDGET = -4, -5, -6
-TRACK_GRAM_FP32, TRACK_GRAM_BF16X3 = 0, 1
+TRACK_GRAM_FP32, TRACK_GRAM_BF16X3, TRACK_GRAM_BF16X6 = 0, 1, 2
 
 (TRACK_BUF_THETA, TRACK_BUF_PHI, TRACK_BUF_VERTS, TRACK_BUF_NORMALS, TRACK_BUF_DEPTH,
  TRACK_BUF_XYZ, TRACK_BUF_ASSOC, TRACK_BUF_COUNT, TRACK_BUF_DELTA, TRACK_BUF_GRAM,
@@ -33,6 +33,9 @@ EXPORTED = [
     "track_init", "track_frame", "track_frame_xyz", "track_state", "track_reset",
     "track_set_params", "track_destroy", "track_last_error", "track_dbg_set",
     "track_dbg_get", "track_dbg_run", "track_kernel_timing", "track_kernel_time",
+    "track_server_create", "track_server_open", "track_server_submit", "track_server_step",
+    "track_server_poll", "track_server_state", "track_server_close", "track_server_info",
+    "track_server_destroy",
 ]
 
 
@@ -81,6 +84,20 @@ class track_frame_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class track_completion(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_int32), ("status", ctypes.c_int32), ("tag", ctypes.c_int64),
+                ("stats", track_frame_stats)]
+
+
+class track_server_stats(ctypes.Structure):
+    _fields_ = [("resident", ctypes.c_int32), ("waiting", ctypes.c_int32),
+                ("frames_in_progress", ctypes.c_int32), ("frames_pending", ctypes.c_int32),
+                ("bytes_used", ctypes.c_int64), ("bytes_budget", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -104,6 +121,14 @@ def lib():
             "track_dbg_run": [vp, i32],
             "track_kernel_timing": [vp, i32, i32],
             "track_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+            "track_server_create": [vp, ctypes.c_int64, i32, vp, ctypes.POINTER(vp)],
+            "track_server_open": [vp, vp, vp, vp, vp, ctypes.POINTER(i32)],
+            "track_server_submit": [vp, i32, vp, i32, ctypes.c_int64],
+            "track_server_step": [vp, ctypes.POINTER(i32)],
+            "track_server_poll": [vp, vp, i32, ctypes.POINTER(i32)],
+            "track_server_state": [vp, i32, vp, vp],
+            "track_server_close": [vp, i32],
+            "track_server_info": [vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -111,6 +136,8 @@ def lib():
             f.restype = ctypes.c_int
         L.track_destroy.argtypes = [vp]
         L.track_destroy.restype = None
+        L.track_server_destroy.argtypes = [vp]
+        L.track_server_destroy.restype = None
         L.track_last_error.argtypes = []
         L.track_last_error.restype = ctypes.c_char_p
         _lib = L
@@ -189,13 +216,22 @@ def make_params(prm: dict, keep: _Keep) -> track_params:
     return p
 
 
+def _check_active(params: dict, P: int):
+    act = params.get("active")
+    if act is not None and np.asarray(act).shape != (P,):
+        raise ValueError("params['active'] must hold one flag per joint")
+
+
 def track_init(model: dict, camera: dict, params: dict, theta0, phi0=None, stream=None):
     """Returns an opaque context handle (ctypes.c_void_p)."""
     keep = _Keep()
     m = make_model(model, keep)
     c = make_camera(camera)
+    _check_active(params, m.n_joints)
     p = make_params(params, keep)
     th = _c(theta0, np.float64)
+    if th.shape != (m.n_joints,):
+        raise ValueError("theta0 must hold one value per joint")
     ph = None if phi0 is None else _c(phi0, np.float32)
     ctx = ctypes.c_void_p()
     st = None if stream is None else ctypes.c_void_p(int(stream))
@@ -299,6 +335,7 @@ class Tracker:
         track_reset(self.ctx, theta, phi)
 
     def set_params(self, params):
+        _check_active(params, self.P)
         track_set_params(self.ctx, params)
 
     def close(self):
@@ -311,3 +348,68 @@ class Tracker:
             self.close()
         except Exception:
             pass
+
+
+# ---- serving -----------------------------------------------------------------
+def track_server_create(params: dict, hbm_budget_bytes: int, max_streams: int, stream=None):
+    keep = _Keep()
+    p = make_params(dict(params, active=None), keep)
+    sv = ctypes.c_void_p()
+    st = None if stream is None else ctypes.c_void_p(int(stream))
+    _check(lib().track_server_create(ctypes.byref(p), int(hbm_budget_bytes), int(max_streams), st,
+                                     ctypes.byref(sv)))
+    return sv
+
+
+def track_server_open(sv, model: dict, camera: dict, theta0, phi0=None) -> int:
+    keep = _Keep()
+    m = make_model(model, keep)
+    c = make_camera(camera)
+    th = _c(theta0, np.float64)
+    ph = None if phi0 is None else _c(phi0, np.float32)
+    sid = ctypes.c_int32(-1)
+    _check(lib().track_server_open(sv, ctypes.byref(m), ctypes.byref(c), _p(th), _p(ph), ctypes.byref(sid)))
+    return int(sid.value)
+
+
+def track_server_submit(sv, stream_id: int, depth, tag: int = 0):
+    """depth: numpy (copied) or a GPU torch tensor (kept alive by the caller
+    until its completion is polled)."""
+    ptr, dev, _k = _frame_ptr(depth, np.float32)
+    _check(lib().track_server_submit(sv, int(stream_id), ptr, dev, int(tag)))
+
+
+def track_server_step(sv) -> int:
+    n = ctypes.c_int32(0)
+    _check(lib().track_server_step(sv, ctypes.byref(n)))
+    return int(n.value)
+
+
+def track_server_poll(sv, max_out: int = 1024):
+    buf = (track_completion * max(1, max_out))()
+    n = ctypes.c_int32(0)
+    _check(lib().track_server_poll(sv, buf, int(max_out), ctypes.byref(n)))
+    return [dict(buf[q].stats.as_dict(), stream=buf[q].stream, status=buf[q].status, tag=buf[q].tag)
+            for q in range(n.value)]
+
+
+def track_server_state(sv, stream_id: int, P: int, V: int):
+    th = np.zeros(P, np.float64)
+    ph = np.zeros((V, 3), np.float32)
+    _check(lib().track_server_state(sv, int(stream_id), _p(th), _p(ph)))
+    return th, ph
+
+
+def track_server_close(sv, stream_id: int):
+    _check(lib().track_server_close(sv, int(stream_id)))
+
+
+def track_server_info(sv) -> dict:
+    s = track_server_stats()
+    _check(lib().track_server_info(sv, ctypes.byref(s)))
+    return s.as_dict()
+
+
+def track_server_destroy(sv):
+    if sv:
+        lib().track_server_destroy(sv)

@@ -1,0 +1,213 @@
+"""GPU serving path: many streams batched into the same launches.
+
+A stream's result must not depend on the streams it shares launches with:
+each stream tracked inside a mix of streams (different meshes, cameras and
+arrival times, so that their frames are at different iterations in the same
+launch) must end bit-identical to the same stream tracked by a single-stream
+context and by a server holding it alone.  Admission under a memory budget
+queues streams instead of failing them; a rejected frame keeps the stream's
+state.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1711_07999_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1711_07999_amd import track
+    track.lib()
+    return track
+
+
+def _frames(body, th, n, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for f in range(n):
+        t = th + np.where(body.angular, 0.01 * f, 0.002 * f)
+        out.append(synth.render_frame(body.model, body.camera, synth.pose_surface(body.model, t), rng, 0.2, 0.002))
+    return out
+
+
+@pytest.fixture(scope="module")
+def streams(tiny, small_body):
+    """(model, camera, theta0, frames, submit step) per stream."""
+    ragged_cam = dict(width=100, height=75, fx=90.0, fy=90.0, cx=49.5, cy=37.0)
+    ragged = synth.make_body(3001, ragged_cam, 2.6)
+    out = []
+    for k, (body, start) in enumerate(((tiny.body, 0), (small_body, 0), (ragged, 2), (tiny.body, 7))):
+        P = len(body.model["joint_parent"])
+        rng = np.random.default_rng(40 + k)
+        th = np.where(body.angular, rng.uniform(-0.05, 0.05, P), rng.uniform(-0.01, 0.01, P))
+        frames = _frames(body, th, 3 if k != 1 else 2, 50 + k)
+        th0 = th + np.where(body.angular, 0.02, 0.005)
+        out.append((body.model, body.camera, th0, frames, start))
+    return out
+
+
+def _params():
+    return dict(synth.default_params(1, 5, 0.05, lambda_k=0.1), active=None)
+
+
+def _run_server(T, streams, which, budget=1 << 36, close_done=False):
+    sv = T.track_server_create(_params(), budget, 64)
+    try:
+        ids, pending = {}, {}
+        step = 0
+        results = {}
+        done = {k: 0 for k in which}
+        order = []
+        while True:
+            for k in which:
+                m, cam, th0, frames, start = streams[k]
+                if step == start:
+                    ids[k] = T.track_server_open(sv, m, cam, th0)
+                    for f, d in enumerate(frames):
+                        T.track_server_submit(sv, ids[k], d, tag=100 * k + f)
+            if all(done[k] == len(streams[k][3]) for k in which) and step > max(streams[k][4] for k in which):
+                break
+            T.track_server_step(sv)
+            for c in T.track_server_poll(sv):
+                k = c["tag"] // 100
+                assert c["status"] == 0, c
+                assert c["stream"] == ids[k]
+                assert c["tag"] % 100 == done[k], "frames of a stream complete in order"
+                done[k] += 1
+                order.append(k)
+                if done[k] == len(streams[k][3]):
+                    P, V = len(streams[k][0]["joint_parent"]), streams[k][0]["rest_xyz"].shape[0]
+                    results[k] = T.track_server_state(sv, ids[k], P, V)
+                    if close_done:
+                        T.track_server_close(sv, ids[k])
+            step += 1
+            assert step < 500
+        return results, order
+    finally:
+        T.track_server_destroy(sv)
+
+
+def _run_alone(T, stream):
+    m, cam, th0, frames, _ = stream
+    trk = T.Tracker(m, cam, _params(), th0)
+    try:
+        for d in frames:
+            assert trk.frame(d) == 0, T.track_last_error()
+        th, phi, _, _ = trk.state(want_verts=False)
+        return th, phi
+    finally:
+        trk.close()
+
+
+def test_mix_equals_alone_bit_for_bit(T, streams):
+    _say("[server] mix of 4 streams vs single-stream contexts and servers holding one stream")
+    mix, order = _run_server(T, streams, [0, 1, 2, 3])
+    _say(f"  completion order {order}")
+    assert len(set(order[:3])) > 1, "streams interleave"
+    for k in range(4):
+        th_a, phi_a = _run_alone(T, streams[k])
+        th_s, phi_s = _run_server(T, streams, [k])[0][k]
+        th_m, phi_m = mix[k]
+        assert np.array_equal(th_m, th_a) and np.array_equal(phi_m, phi_a), k
+        assert np.array_equal(th_m, th_s) and np.array_equal(phi_m, phi_s), k
+
+
+def test_admission_queues_under_a_budget(T, streams):
+    _say("[server] admission under a budget of two streams")
+    probe = T.track_server_create(_params(), 1 << 36, 64)
+    try:
+        sizes = []
+        for k in (0, 1, 2):
+            m, cam, th0, _, _ = streams[k]
+            before = T.track_server_info(probe)["bytes_used"]
+            T.track_server_open(probe, m, cam, th0)
+            sizes.append(T.track_server_info(probe)["bytes_used"] - before)
+    finally:
+        T.track_server_destroy(probe)
+    budget = sizes[0] + sizes[1] + sizes[2] // 2
+    sv = T.track_server_create(_params(), budget, 64)
+    try:
+        ids = []
+        for k in (0, 1, 2):
+            m, cam, th0, frames, _ = streams[k]
+            ids.append(T.track_server_open(sv, m, cam, th0))
+            for f, d in enumerate(frames):
+                T.track_server_submit(sv, ids[-1], d, tag=100 * k + f)
+        info = T.track_server_info(sv)
+        _say(f"  sizes {sizes} budget {budget} -> {info}")
+        assert info["resident"] == 2 and info["waiting"] == 1 and info["bytes_used"] <= budget
+        done = {0: 0, 1: 0, 2: 0}
+        for _ in range(400):
+            if all(done[k] == len(streams[k][3]) for k in done):
+                break
+            T.track_server_step(sv)
+            for c in T.track_server_poll(sv):
+                k = c["tag"] // 100
+                assert c["status"] == 0
+                done[k] += 1
+                if done[k] == len(streams[k][3]) and k != 2:
+                    if k == 0:
+                        th_q, phi_q = T.track_server_state(sv, ids[0], len(streams[0][0]["joint_parent"]),
+                                                           streams[0][0]["rest_xyz"].shape[0])
+                    T.track_server_close(sv, ids[k])
+        assert all(done[k] == len(streams[k][3]) for k in done), done
+        P, V = len(streams[2][0]["joint_parent"]), streams[2][0]["rest_xyz"].shape[0]
+        th2, phi2 = T.track_server_state(sv, ids[2], P, V)
+    finally:
+        T.track_server_destroy(sv)
+    th_a, phi_a = _run_alone(T, streams[2])
+    assert np.array_equal(th2, th_a) and np.array_equal(phi2, phi_a)
+    th_a0, phi_a0 = _run_alone(T, streams[0])
+    assert np.array_equal(th_q, th_a0) and np.array_equal(phi_q, phi_a0)
+
+
+def test_a_stream_alone_exceeding_the_budget_is_refused(T, streams):
+    sv = T.track_server_create(_params(), 1 << 20, 4)
+    try:
+        m, cam, th0, _, _ = streams[1]
+        with pytest.raises(T.TrackError) as e:
+            T.track_server_open(sv, m, cam, th0)
+        assert e.value.code == T.TRACK_E_BUDGET
+    finally:
+        T.track_server_destroy(sv)
+
+
+def test_rejected_frame_keeps_the_stream_state(T, streams):
+    _say("[server] empty frame in the middle of a stream")
+    m, cam, th0, frames, _ = streams[1]
+    P, V = len(m["joint_parent"]), m["rest_xyz"].shape[0]
+    sv = T.track_server_create(_params(), 1 << 36, 8)
+    try:
+        sid = T.track_server_open(sv, m, cam, th0)
+        T.track_server_submit(sv, sid, frames[0], tag=0)
+        T.track_server_submit(sv, sid, np.zeros_like(frames[0]), tag=1)
+        T.track_server_submit(sv, sid, frames[1], tag=2)
+        got = []
+        for _ in range(100):
+            T.track_server_step(sv)
+            got += T.track_server_poll(sv)
+            if len(got) == 1 and "after0" not in locals():
+                after0 = T.track_server_state(sv, sid, P, V)
+            if len(got) == 2 and "after1" not in locals():
+                after1 = T.track_server_state(sv, sid, P, V)
+            if len(got) == 3:
+                break
+        assert [c["status"] for c in got] == [0, T.TRACK_E_LOST, 0]
+        assert np.array_equal(after0[0], after1[0]) and np.array_equal(after0[1], after1[1])
+        th_s, phi_s = T.track_server_state(sv, sid, P, V)
+    finally:
+        T.track_server_destroy(sv)
+    # the same frames without the empty one, tracked alone
+    th_a, phi_a = _run_alone(T, (m, cam, th0, [frames[0], frames[1]], 0))
+    assert np.array_equal(th_s, th_a) and np.array_equal(phi_s, phi_a)
