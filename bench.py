@@ -362,6 +362,22 @@ def serve(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_calibration(args):
+    """A plain device copy of known size, for scaling hardware byte counters
+    (FETCH_SIZE / WRITE_SIZE) to bytes: 64 MiB read and 64 MiB written per
+    launch, 10 launches."""
+    import torch
+
+    n = 16 << 20
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_kernel_bytes_read": 4 * n, "copy_kernel_bytes_written": 4 * n, "launches": 10}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -376,13 +392,17 @@ def main():
     ap.add_argument("--admit-frames", type=int, default=10)
     ap.add_argument("--seq-frames", type=int, default=30)
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only a plain copy of known size (for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
               "tracking streams shard across GPUs with no communication, see the design notes",
               file=sys.stderr)
         sys.exit(2)
-    if args.serve:
+    if args.copy_calibration:
+        copy_calibration(args)
+    elif args.serve:
         serve(args)
     else:
         single_stream(args)

@@ -19,21 +19,17 @@
 //   distance    (dx*dx + dy*dy) + dz*dz, accepted if < tau*tau,
 //               ties to the lower vertex index.
 #include "common.h"
+#include "surface.h"
 
 #pragma clang fp contract(off)
 
 namespace trk {
 
-// pixel (u, v) -> its bucket: tile-major, Morton order inside the tile
-__device__ __forceinline__ int tile_pixel(const DevCam& c, int u, int v) {
-    const int m = (u & 1) | ((v & 1) << 1) | ((u & 2) << 1) | ((v & 2) << 2) | ((u & 4) << 2) | ((v & 4) << 3);
-    return (((v >> 3) * c.tiles_x + (u >> 3)) << 6) + m;
-}
-
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
 // ---------------------------------------------------------------------------
-// clear the bucket counters, z ranges, per-vertex accumulators and counters
+// clear the bucket counters, z ranges, tile sums and per-vertex accumulators
+// (on the frame path they are cleared by their last reader instead)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_clear(Batch B) {
     int local;
@@ -41,12 +37,13 @@ __global__ void __launch_bounds__(256) k_clear(Batch B) {
     const Buckets& b = S.b;
     const Accum& a = S.a;
     const int npad = S.npad, V = S.m.V;
-    int i = local * blockDim.x + threadIdx.x;
+    const int i = local * blockDim.x + threadIdx.x;
     if (i < npad) {
         b.pcnt[i] = 0u;
         b.pzmin[i] = 0x7F800000u;  // +inf
         b.pzmax[i] = 0u;
     }
+    if (i < (npad >> 6)) b.tsum[i] = 0u;
     if (i < V) {
         a.cnt[i] = 0u;
         a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
@@ -57,60 +54,38 @@ void launch_clear(const Launch& L) {
     hipLaunchKernelGGL(k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.s, L.B);
 }
 
-// ---------------------------------------------------------------------------
-// bucket construction: count -> per-tile sums and z ranges -> tile prefix ->
-// per-pixel offsets -> scatter
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel) {
+__global__ void __launch_bounds__(256) k_clear_acc(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
-    const DevCam& c = S.c;
-    const Buckets& b = S.b;
-    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
-    int i = local * blockDim.x + threadIdx.x;
+    const int i = local * blockDim.x + threadIdx.x;
     if (i >= S.m.V) return;
-    const float4 p = v[i];
-    const float x = p.x, y = p.y, z = p.z;
-    int pix = -1;
-    if (z > kZNear) {
-        float fu = floorf((c.fx * x) / z + c.cx + 0.5f);
-        float fv = floorf((c.fy * y) / z + c.cy + 0.5f);
-        if (fu >= 0.0f && fu < (float)c.W && fv >= 0.0f && fv < (float)c.H)
-            pix = tile_pixel(c, (int)fu, (int)fv);
-    }
-    b.vpix[i] = pix;
-    if (pix >= 0) {
-        b.vslot[i] = atomicAdd(&b.pcnt[pix], 1u);
-        uint32_t zb = __float_as_uint(z);  // z > 0: integer order is float order
-        atomicMin(&b.pzmin[pix], zb);
-        atomicMax(&b.pzmax[pix], zb);
-    }
+    S.a.cnt[i] = 0u;
+    S.a.sx[i] = 0; S.a.sy[i] = 0; S.a.sz[i] = 0;
 }
 
-// one wave per tile
-__global__ void __launch_bounds__(256) k_tile_reduce(Batch B) {
+void launch_clear_acc(const Launch& L) {
+    hipLaunchKernelGGL(k_clear_acc, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B);
+}
+
+// ---------------------------------------------------------------------------
+// bucket construction: count (fused into skinning, or this kernel for a
+// given surface) -> tile prefix -> per-pixel records -> scatter
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int which) {
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_TILE4, blockIdx.x, local)];
-    const Buckets& b = S.b;
-    const int ntiles = S.c.tiles_x * S.c.tiles_y;
-    int tile = local * 4 + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
-    int p = (tile << 6) + wave_lane();
-    uint32_t cnt = b.pcnt[p];
-    float zmn = __uint_as_float(b.pzmin[p]);
-    float zmx = cnt ? __uint_as_float(b.pzmax[p]) : -INFINITY;
-    for (int o = 32; o > 0; o >>= 1) {
-        cnt += __shfl_xor(cnt, o);
-        zmn = fminf(zmn, __shfl_xor(zmn, o));
-        zmx = fmaxf(zmx, __shfl_xor(zmx, o));
-    }
-    if (wave_lane() == 0) {
-        b.tsum[tile] = cnt;
-        b.tz[tile] = make_float2(zmn, zmx);
-    }
+    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    if (!selected(S, which)) return;
+    const int i = local * blockDim.x + threadIdx.x;
+    if (i >= S.m.V) return;
+    count_vertex(S, i, S.verts[S.v_cur ^ vsel][i]);
 }
 
-// exclusive prefix over tiles, one workgroup of 1024 threads
+void launch_bucket_count(const Launch& L, int vsel, int which) {
+    hipLaunchKernelGGL(k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel, which);
+}
+
+// exclusive prefix over tiles, one workgroup of 1024 threads; the tile sums
+// are zeroed for the next count
 __global__ void __launch_bounds__(1024) k_tile_scan(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
@@ -123,7 +98,11 @@ __global__ void __launch_bounds__(1024) k_tile_scan(Batch B) {
     const int lane = wave_lane(), wid = threadIdx.x >> 6;
     for (int base = 0; base < ntiles; base += 1024) {
         int i = base + threadIdx.x;
-        uint32_t x = i < ntiles ? b.tsum[i] : 0u;
+        uint32_t x = 0u;
+        if (i < ntiles) {
+            x = b.tsum[i];
+            b.tsum[i] = 0u;
+        }
         uint32_t incl = x;
         for (int o = 1; o < 64; o <<= 1) {
             uint32_t y = __shfl_up(incl, o);
@@ -144,19 +123,19 @@ __global__ void __launch_bounds__(1024) k_tile_scan(Batch B) {
     }
 }
 
-// per-pixel (offset, count, zmin, zmax), and per 4x4 cell (the 16
-// consecutive Morton positions of a tile quadrant) the same record; one wave
-// per tile
+// Per-pixel (offset, count, zmin, zmax), the same record per 4x4 cell (the 16
+// consecutive Morton positions of a tile quadrant) and the tile's z range;
+// one wave per tile.  The pixel counters are reset for the next count.
 __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_TILE4, blockIdx.x, local)];
     const Buckets& b = S.b;
     const int ntiles = S.c.tiles_x * S.c.tiles_y;
-    int tile = local * 4 + (threadIdx.x >> 6);
+    const int tile = local * 4 + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const int lane = wave_lane();
-    int p = (tile << 6) + lane;
-    uint32_t cnt = b.pcnt[p];
+    const int p = (tile << 6) + lane;
+    const uint32_t cnt = b.pcnt[p];
     uint32_t incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
         uint32_t y = __shfl_up(incl, o);
@@ -165,6 +144,9 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
     const uint32_t off = b.toff[tile] + incl - cnt;
     const uint32_t zmn = b.pzmin[p], zmx = b.pzmax[p];
     b.rec[p] = make_uint4(off, cnt, zmn, zmx);
+    b.pcnt[p] = 0u;
+    b.pzmin[p] = 0x7F800000u;
+    b.pzmax[p] = 0u;
     uint32_t csum = cnt, cmn = zmn, cmx = zmx;
     for (int o = 1; o < 16; o <<= 1) {
         csum += __shfl_xor(csum, o);
@@ -172,28 +154,43 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
         cmx = max(cmx, (uint32_t)__shfl_xor((int)cmx, o));
     }
     if ((lane & 15) == 0) b.cellrec[(tile << 2) + (lane >> 4)] = make_uint4(off, csum, cmn, cmx);
+    // tile z range (an empty pixel holds +inf / 0, neutral for min / max of z > 0)
+    for (int o = 16; o < 64; o <<= 1) {
+        cmn = min(cmn, (uint32_t)__shfl_xor((int)cmn, o));
+        cmx = max(cmx, (uint32_t)__shfl_xor((int)cmx, o));
+    }
+    if (lane == 0) b.tz[tile] = make_float2(__uint_as_float(cmn), cmx ? __uint_as_float(cmx) : -INFINITY);
 }
 
-__global__ void __launch_bounds__(256) k_bucket_scatter(Batch B, int vsel) {
+// vertices grouped by bucket (first half of the grid) and vertex normals of
+// the same surface (second half)
+__global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
-    const Buckets& b = S.b;
+    const Slot& S = B.slots[slot_of(B, KK_VERT2, blockIdx.x, local)];
+    const int half = (S.m.V + 255) / 256;
     const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
-    int i = local * blockDim.x + threadIdx.x;
-    if (i >= S.m.V) return;
-    int pix = b.vpix[i];
-    if (pix < 0) return;
-    uint32_t dst = b.rec[pix].x + b.vslot[i];
-    const float4 p = v[i];
-    b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
+    if (local < half) {
+        const Buckets& b = S.b;
+        const int i = local * blockDim.x + threadIdx.x;
+        if (i >= S.m.V) return;
+        const int pix = b.vpix[i];
+        if (pix < 0) return;
+        const uint32_t dst = b.rec[pix].x + b.vslot[i];
+        const float4 p = v[i];
+        b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
+    } else {
+        const int i = (local - half) * blockDim.x + threadIdx.x;
+        if (i >= S.m.V) return;
+        float nx, ny, nz;
+        vertex_normal(S.m, v, i, nx, ny, nz);
+        S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz;
+    }
 }
 
 void launch_bucket(const Launch& L, int vsel) {
-    hipLaunchKernelGGL(k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel);
-    hipLaunchKernelGGL(k_tile_reduce, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.s, L.B);
     hipLaunchKernelGGL(k_tile_scan, dim3(L.grid[KK_ONE]), dim3(1024), 0, L.s, L.B);
     hipLaunchKernelGGL(k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.s, L.B);
-    hipLaunchKernelGGL(k_bucket_scatter, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel);
+    hipLaunchKernelGGL(k_scatter_normals, dim3(L.grid[KK_VERT2]), dim3(256), 0, L.s, L.B, vsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,17 +277,30 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
     bool done = !valid;
     const int cells_x = 2 * c.tiles_x, cells_y = 2 * c.tiles_y;
     // cheap rejection of background tiles: if no tile of the wave's window has
-    // a z range any lane could match within tau, nothing can be found
+    // a z range within tau of the z range of the wave's points, nothing can
+    // be found.  One tile of the window per lane, all loads in flight at once.
     bool candidate_tiles = false;
     if (__any(valid)) {
+        float pmin = valid ? pz : INFINITY, pmax = valid ? pz : -INFINITY;
+        for (int o = 32; o > 0; o >>= 1) {
+            pmin = fminf(pmin, __shfl_xor(pmin, o));
+            pmax = fmaxf(pmax, __shfl_xor(pmax, o));
+        }
+        const float tz_tol = tau * 1.0001f + 1e-6f;  // generous: this is only a filter
         const int tr = (rw + 7) / 8;
-        for (int ty2 = max(ty - tr, 0); ty2 <= min(ty + tr, c.tiles_y - 1) && !candidate_tiles; ++ty2)
-            for (int tx2 = max(tx - tr, 0); tx2 <= min(tx + tr, c.tiles_x - 1); ++tx2) {
-                const int t2 = ty2 * c.tiles_x + tx2;
-                if (b.tsum[t2] == 0u) continue;
-                const float2 tz = b.tz[t2];
-                if (__any(valid && !z_pruned(tz.x, tz.y, pz, tau2, false))) { candidate_tiles = true; break; }
+        const int wx0 = max(tx - tr, 0), wx1 = min(tx + tr, c.tiles_x - 1);
+        const int wy0 = max(ty - tr, 0), wy1 = min(ty + tr, c.tiles_y - 1);
+        const int nwx = wx1 - wx0 + 1, nwin = nwx * (wy1 - wy0 + 1);
+        for (int base = 0; base < nwin && !candidate_tiles; base += 64) {
+            const int q = base + lane;
+            bool cand = false;
+            if (q < nwin) {
+                const int wy = q / nwx;
+                const float2 tz = b.tz[(wy0 + wy) * c.tiles_x + wx0 + (q - wy * nwx)];
+                cand = tz.x <= tz.y && tz.x < pmax + tz_tol && tz.y > pmin - tz_tol;
             }
+            candidate_tiles = __any(cand);
+        }
     }
     if (candidate_tiles) {
         for (int R = 0; R <= Rc; ++R) {
@@ -298,40 +308,54 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
             const int side = 2 + 2 * R;
             const int ncell = R == 0 ? 4 : 4 * side - 4;
             const int x0 = 2 * tx - R, y0 = 2 * ty - R;
-            for (int q = wid; q < ncell; q += 4) {
-                int ccx, ccy;
-                if (R == 0) { ccx = x0 + (q & 1); ccy = y0 + (q >> 1); }
-                else if (q < side) { ccx = x0 + q; ccy = y0; }
-                else if (q < 2 * side) { ccx = x0 + (q - side); ccy = y0 + side - 1; }
-                else if (q < 3 * side - 2) { ccx = x0; ccy = y0 + 1 + (q - 2 * side); }
-                else { ccx = x0 + side - 1; ccy = y0 + 1 + (q - (3 * side - 2)); }
-                if (ccx < 0 || ccy < 0 || ccx >= cells_x || ccy >= cells_y) continue;
-                const uint4 cr = b.cellrec[(((ccy >> 1) * c.tiles_x + (ccx >> 1)) << 2) | ((ccy & 1) << 1) | (ccx & 1)];
-                if (cr.y == 0u) continue;
-                bool need = false;
-                if (!done) {
-                    const int X0 = ccx * 4, Y0 = ccy * 4;
-                    const int mx = max(max(X0 - u, u - (X0 + 3)), 0), my = max(max(Y0 - v, v - (Y0 + 3)), 0);
-                    const float bound = __uint_as_float((uint32_t)(key >> 32));
-                    const bool found = (uint32_t)(key >> 32) < tau2_bits;
-                    const float lb = ring_lb(c, pz, max(mx, my));
-                    need = !(lb * lb >= bound) &&
-                           !z_pruned(__uint_as_float(cr.z), __uint_as_float(cr.w), pz, bound, found);
+            // the wave's cells of this ring are q = wid + 4 k; lane k loads the
+            // record of its cell, so a ring costs one round trip per 64 cells
+            for (int cbase = 0; cbase < ncell; cbase += 256) {
+                const int qm = cbase + wid + 4 * lane;
+                uint4 myrec = make_uint4(0u, 0u, 0u, 0u);
+                int mycx = 0, mycy = 0;
+                if (qm < ncell) {
+                    if (R == 0) { mycx = x0 + (qm & 1); mycy = y0 + (qm >> 1); }
+                    else if (qm < side) { mycx = x0 + qm; mycy = y0; }
+                    else if (qm < 2 * side) { mycx = x0 + (qm - side); mycy = y0 + side - 1; }
+                    else if (qm < 3 * side - 2) { mycx = x0; mycy = y0 + 1 + (qm - 2 * side); }
+                    else { mycx = x0 + side - 1; mycy = y0 + 1 + (qm - (3 * side - 2)); }
+                    if (mycx >= 0 && mycy >= 0 && mycx < cells_x && mycy < cells_y)
+                        myrec = b.cellrec[(((mycy >> 1) * c.tiles_x + (mycx >> 1)) << 2) | ((mycy & 1) << 1) | (mycx & 1)];
                 }
-                if (!__any(need)) continue;
-                for (uint32_t base = 0; base < cr.y; base += 64) {
-                    const int n = min(64u, cr.y - base);
-                    if (lane < n) scand[wid][lane] = b.sorted[cr.x + base + lane];
-                    __builtin_amdgcn_wave_barrier();
-                    for (int k = 0; k < n; ++k) {
-                        const float4 s = scand[wid][k];
-                        const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
-                        const float d2 = (dx * dx + dy * dy) + dz * dz;
-                        const unsigned long long kk =
-                            ((unsigned long long)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(s.w);
-                        if (need && kk < key) key = kk;
+                unsigned long long pending = __ballot(myrec.y != 0u);
+                while (pending) {
+                    const int k = __builtin_ctzll(pending);
+                    pending &= pending - 1ull;
+                    const uint32_t c_off = (uint32_t)__builtin_amdgcn_readlane((int)myrec.x, k);
+                    const uint32_t c_cnt = (uint32_t)__builtin_amdgcn_readlane((int)myrec.y, k);
+                    const float c_zmn = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)myrec.z, k));
+                    const float c_zmx = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)myrec.w, k));
+                    const int ccx = __builtin_amdgcn_readlane(mycx, k), ccy = __builtin_amdgcn_readlane(mycy, k);
+                    bool need = false;
+                    if (!done) {
+                        const int X0 = ccx * 4, Y0 = ccy * 4;
+                        const int mx = max(max(X0 - u, u - (X0 + 3)), 0), my = max(max(Y0 - v, v - (Y0 + 3)), 0);
+                        const float bound = __uint_as_float((uint32_t)(key >> 32));
+                        const bool found = (uint32_t)(key >> 32) < tau2_bits;
+                        const float lb = ring_lb(c, pz, max(mx, my));
+                        need = !(lb * lb >= bound) && !z_pruned(c_zmn, c_zmx, pz, bound, found);
                     }
-                    __builtin_amdgcn_wave_barrier();
+                    if (!__any(need)) continue;
+                    for (uint32_t base = 0; base < c_cnt; base += 64) {
+                        const int n = min(64u, c_cnt - base);
+                        if (lane < n) scand[wid][lane] = b.sorted[c_off + base + lane];
+                        __builtin_amdgcn_wave_barrier();
+                        for (int kk2 = 0; kk2 < n; ++kk2) {
+                            const float4 sv = scand[wid][kk2];
+                            const float dx = sv.x - px, dy = sv.y - py, dz = sv.z - pz;
+                            const float d2 = (dx * dx + dy * dy) + dz * dz;
+                            const unsigned long long kk =
+                                ((unsigned long long)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(sv.w);
+                            if (need && kk < key) key = kk;
+                        }
+                        __builtin_amdgcn_wave_barrier();
+                    }
                 }
             }
             // every cell outside the square is at least m_next pixels away

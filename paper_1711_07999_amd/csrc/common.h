@@ -24,6 +24,7 @@ struct JointTable {
     uint32_t anc[kMaxLinks + 1][4];    // joints on the chain of each link
     double prior[kMaxJoints + 1];      // (lambda_s S_k)^2
     int active[kMaxJoints + 1];
+    int rounds;                        // ceil(log2(longest joint chain))
 };
 
 // Mesh, weights and tables in structure-of-arrays device form.
@@ -63,11 +64,11 @@ struct Accum {
 // Bucket (index/z-buffer) storage; pixels are numbered tile-major: 8x8
 // tiles in row-major order, 64 pixels per tile in Morton order.
 struct Buckets {
-    uint32_t* pcnt;    // [Npad] vertices per pixel
-    uint32_t* pzmin;   // [Npad] float bits of the smallest vertex z
-    uint32_t* pzmax;   // [Npad] float bits of the largest vertex z
+    uint32_t* pcnt;    // [Npad] vertices per pixel        } zero again once the
+    uint32_t* pzmin;   // [Npad] bits of the smallest z     } pixel records are
+    uint32_t* pzmax;   // [Npad] bits of the largest z      } built (+inf, 0, 0)
     uint4* rec;        // [Npad] (offset, count, zmin bits, zmax bits)
-    uint32_t* tsum;    // [tiles] vertices per tile
+    uint32_t* tsum;    // [tiles] vertices per tile (zero again after the tile scan)
     uint32_t* toff;    // [tiles] exclusive prefix of tsum
     float2* tz;        // [tiles] z range of the tile
     int* vpix;         // [V] bucket of each vertex or -1
@@ -141,7 +142,7 @@ __host__ __device__ __forceinline__ int phi_index(const Slot& S, int n) {
 enum KernelKind {
     KK_ONE = 0,     // one workgroup per slot (frame bookkeeping, FK, tile scan, solve)
     KK_VERT,        // ceil(V / 256) workgroups
-    KK_VERT4,       // ceil(4 V / 256)
+    KK_VERT2,       // 2 ceil(V / 256): two vertex passes in one launch
     KK_CLEAR,       // ceil(max(Npad, V) / 256)
     KK_TILE4,       // ceil(tiles / 4): one wave per tile
     KK_TILE,        // tiles: one workgroup per tile
@@ -183,7 +184,7 @@ inline int slot_blocks(const Slot& s, int kind) {
     switch (kind) {
         case KK_ONE: return 1;
         case KK_VERT: return (V + 255) / 256;
-        case KK_VERT4: return (4 * V + 255) / 256;
+        case KK_VERT2: return 2 * ((V + 255) / 256);
         case KK_CLEAR: return ((s.npad > V ? s.npad : V) + 255) / 256;
         case KK_TILE4: return (ntiles + 3) / 4;
         case KK_TILE: return ntiles;
@@ -194,19 +195,33 @@ inline int slot_blocks(const Slot& s, int kind) {
 }
 
 // ---- launchers (each defined next to its kernels) -------------------------
-// vsel: 0 = the slot's frame-start vertex buffer, 1 = the other one;
-// pn: number of offset steps taken so far in the frame (see phi_index).
+// vsel: 0 = the slot's vertex buffer at the launch's start, 1 = the other;
+// pn: number of offset steps taken so far (see phi_index).
+// Which slots take the optional part of a kernel:
+enum SlotSel { SEL_NONE = 0, SEL_ALL = 1, SEL_BEGIN = 2, SEL_NOT_END = 3 };
+__device__ __forceinline__ bool selected(const Slot& S, int sel) {
+    return sel == SEL_ALL || (sel == SEL_BEGIN && (S.flags & kSlotBeginFrame)) ||
+           (sel == SEL_NOT_END && !(S.flags & kSlotEndFrame));
+}
 void launch_frame_begin(const Launch& L);
 void launch_frame_end(const Launch& L, int first_pose, int last_pose);  // iterations of the frame, -1 = none
 void launch_fk(const Launch& L);
-void launch_skin(const Launch& L, int vsel, int pn);
+// skin into vsel for the slots selected by `which`; `count` of them also
+// enter the buckets; `clear_acc` slots have their accumulators zeroed
+void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc);  // count: a SlotSel
 void launch_normals(const Launch& L, int vsel);
-void launch_clear(const Launch& L);
+void launch_clear(const Launch& L);                 // buckets, tile sums, accumulators
+void launch_clear_acc(const Launch& L);             // accumulators only
+void launch_bucket_count(const Launch& L, int vsel, int which);
+// tile scan, pixel records (+ clearing the counters), scatter (+ normals)
 void launch_bucket(const Launch& L, int vsel);
 void launch_associate(const Launch& L, int vsel);
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
 void launch_gram_reduce(const Launch& L);
 void launch_pose_solve(const Launch& L, int fp64, int iter);
-void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn);
+// offset step from v_old / v_new (normals of v_new formed in place); the
+// slots selected by `next` also skin the new offsets into v_new ^ 1 and count
+// them into the buckets
+void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next);
 
 }  // namespace trk

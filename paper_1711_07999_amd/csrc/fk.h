@@ -13,7 +13,7 @@ namespace trk {
 // the chain products H_{0,j} = H_{0,P(j)} O_j H_j are then formed by pointer
 // jumping: every joint repeatedly left-multiplies by the product held at its
 // current ancestor and jumps to that ancestor's ancestor, so a tree of depth
-// D needs ceil(log2 D) rounds instead of D dependent steps.
+// D needs ceil(log2 D) rounds (jt->rounds) instead of D dependent steps.
 //
 // Outputs (float32): the link offsets H_{l,Delta} = H_{0,l} (H^0_{0,l})^{-1}
 // (8 per link) and, per joint k, the world-frame generator
@@ -23,10 +23,17 @@ namespace trk {
 // dH_{l,Delta}/dtheta_k = Xi_k H_{l,Delta} for every joint k on the chain of
 // link l (the derivative blocks of Section 4.2).
 // ---------------------------------------------------------------------------
+// LDS workspace of fk_block (callers provide it, so that a kernel can
+// overlay it on memory it no longer needs)
+struct FkScratch {
+    double M[2][kMaxJoints + 1][8];
+    int A[2][kMaxJoints + 1];
+};
+
 __device__ __forceinline__ void fk_block(const JointTable* __restrict__ jt, const double* __restrict__ theta,
-                         float* __restrict__ dq, float* __restrict__ xi) {
-    __shared__ double M[2][kMaxJoints + 1][8];
-    __shared__ int A[2][kMaxJoints + 1];
+                         float* __restrict__ dq, float* __restrict__ xi, FkScratch& ws) {
+    double (*M)[kMaxJoints + 1][8] = ws.M;
+    int (*A)[kMaxJoints + 1] = ws.A;
     const int P = jt->P, L = jt->L;
     const int t = threadIdx.x;
     for (int j = t; j < P; j += blockDim.x) {
@@ -34,7 +41,8 @@ __device__ __forceinline__ void fk_block(const JointTable* __restrict__ jt, cons
         double Hj[8] = {1, 0, 0, 0, 0, 0, 0, 0};
         const double* z = jt->axis[j];
         if (jt->type[j] == 0) {
-            double c = cos(0.5 * th), s = sin(0.5 * th);
+            double s, c;
+            sincos(0.5 * th, &s, &c);
             Hj[0] = c; Hj[1] = s * z[0]; Hj[2] = s * z[1]; Hj[3] = s * z[2];
         } else {
             Hj[5] = 0.5 * th * z[0]; Hj[6] = 0.5 * th * z[1]; Hj[7] = 0.5 * th * z[2];
@@ -46,7 +54,7 @@ __device__ __forceinline__ void fk_block(const JointTable* __restrict__ jt, cons
     }
     __syncthreads();
     int cur = 0;
-    for (int round = 0; round < 7; ++round) {
+    for (int round = 0; round < jt->rounds; ++round) {
         int nxt = cur ^ 1;
         for (int j = t; j < P; j += blockDim.x) {
             int a = A[cur][j];

@@ -3,6 +3,7 @@
 #include "common.h"
 #include "dq.h"
 #include "fk.h"
+#include "surface.h"
 
 namespace trk {
 
@@ -14,10 +15,11 @@ __global__ void __launch_bounds__(128) k_frame_begin(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     if (!(S.flags & kSlotBeginFrame)) return;
+    __shared__ FkScratch ws;
     const int P = S.m.P;
     for (int k = threadIdx.x; k < P; k += blockDim.x) S.theta_backup[k] = S.theta[k];
     if (threadIdx.x == 0) S.st->status = 0;
-    if (S.flags & kSlotRefreshPose) fk_block(S.jt, S.theta, S.dq, S.xi);
+    if (S.flags & kSlotRefreshPose) fk_block(S.jt, S.theta, S.dq, S.xi, ws);
 }
 
 void launch_frame_begin(const Launch& L) {
@@ -27,7 +29,8 @@ void launch_frame_begin(const Launch& L) {
 __global__ void __launch_bounds__(128) k_fk(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
-    fk_block(S.jt, S.theta, S.dq, S.xi);
+    __shared__ FkScratch ws;
+    fk_block(S.jt, S.theta, S.dq, S.xi, ws);
 }
 
 void launch_fk(const Launch& L) {
@@ -36,12 +39,16 @@ void launch_fk(const Launch& L) {
 
 // ---------------------------------------------------------------------------
 // Skinning (Eq. 3 and 5): v_i = T(sum_j w_ij H_{j,Delta}, v0_i + phi_i), one
-// vertex per lane, link offsets staged in LDS, coalesced SoA streams.
+// vertex per lane, link offsets staged in LDS, coalesced SoA streams.  The
+// vertex can also be counted into the bucket index of the next association,
+// and the per-vertex accumulators of the last association cleared, so that
+// neither needs a launch of its own.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn) {
+__global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int which, int count, int clear_acc) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    if (!selected(S, which)) return;
     const DevModel& m = S.m;
     for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
     __syncthreads();
@@ -54,57 +61,32 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn) {
     float x = m.rx[i] + phi.x[i], y = m.ry[i] + phi.y[i], z = m.rz[i] + phi.z[i];
     float ox, oy, oz;
     dq_apply(H, x, y, z, ox, oy, oz);
-    v[i] = make_float4(ox, oy, oz, 0.0f);
+    const float4 p = make_float4(ox, oy, oz, 0.0f);
+    v[i] = p;
+    if (selected(S, count)) count_vertex(S, i, p);
+    if (clear_acc) {
+        S.a.cnt[i] = 0u;
+        S.a.sx[i] = 0; S.a.sy[i] = 0; S.a.sz[i] = 0;
+    }
 }
 
-void launch_skin(const Launch& L, int vsel, int pn) {
-    hipLaunchKernelGGL(k_skin, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel, pn);
+void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
+    hipLaunchKernelGGL(k_skin, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel, pn, which, count, clear_acc);
 }
 
-// ---------------------------------------------------------------------------
-// Vertex normals: the sum over incident faces of their doubled-area normal
-// vectors, normalised (zero if the sum vanishes).  Each vertex gathers its own
-// fan (no atomics, deterministic); four lanes share one vertex's fan and
-// combine their partial sums with lane shuffles in a fixed order.
-// ---------------------------------------------------------------------------
-constexpr int kNormLanes = 4;
-
+// Vertex normals (one lane per vertex; see vertex_normal)
 __global__ void __launch_bounds__(256) k_normals(Batch B, int vsel) {
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_VERT4, blockIdx.x, local)];
-    const DevModel& m = S.m;
-    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
-    const int t = local * blockDim.x + threadIdx.x;
-    const int i = t / kNormLanes, sub = t % kNormLanes;
-    const bool live = i < m.V;
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    if (live) {
-        const float4 p = v[i];
-        const uint32_t e1 = m.fan_off[i + 1];
-        for (uint32_t e = m.fan_off[i] + sub; e < e1; e += kNormLanes) {
-            const int2 bc = m.fan[e];
-            const float4 vb = v[bc.x], vc = v[bc.y];
-            float ax = vb.x - p.x, ay = vb.y - p.y, az = vb.z - p.z;
-            float bx = vc.x - p.x, by = vc.y - p.y, bz = vc.z - p.z;
-            sx += ay * bz - az * by;
-            sy += az * bx - ax * bz;
-            sz += ax * by - ay * bx;
-        }
-    }
-    // combine the four lanes of the vertex (lanes 4i..4i+3 of one wave)
-    for (int o = 1; o < kNormLanes; o <<= 1) {
-        sx += __shfl_xor(sx, o);
-        sy += __shfl_xor(sy, o);
-        sz += __shfl_xor(sz, o);
-    }
-    if (!live || sub != 0) return;
-    float l = sqrtf(sx * sx + sy * sy + sz * sz);
-    float inv = l > 0.0f ? 1.0f / l : 0.0f;
-    S.normals.x[i] = sx * inv; S.normals.y[i] = sy * inv; S.normals.z[i] = sz * inv;
+    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const int i = local * blockDim.x + threadIdx.x;
+    if (i >= S.m.V) return;
+    float nx, ny, nz;
+    vertex_normal(S.m, S.verts[S.v_cur ^ vsel], i, nx, ny, nz);
+    S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz;
 }
 
 void launch_normals(const Launch& L, int vsel) {
-    hipLaunchKernelGGL(k_normals, dim3(L.grid[KK_VERT4]), dim3(256), 0, L.s, L.B, vsel);
+    hipLaunchKernelGGL(k_normals, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel);
 }
 
 // ---------------------------------------------------------------------------

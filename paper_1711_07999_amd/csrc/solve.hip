@@ -2,6 +2,7 @@
 #include "common.h"
 #include "dq.h"
 #include "fk.h"
+#include "surface.h"
 
 namespace trk {
 
@@ -12,29 +13,49 @@ namespace trk {
 // moves them) or marked inactive are frozen (x_k = 0).  A failed
 // factorisation leaves Theta unchanged and flags the frame.
 //
-// Blocked right-looking Cholesky in one workgroup: the matrix (padded to a
-// multiple of 8 with identity rows) is split into 8x8 blocks, thread (i, j)
-// of a 16x16 grid holds block (i, j) in registers.  For each 8-column panel:
-// the diagonal block is factored by its thread, the blocks below are solved
-// against it, and the trailing blocks take the rank-8 update, with the panel
-// exchanged through LDS -- three barriers per panel.  The right-hand side is
-// carried along (forward substitution) and back substitution runs panel by
-// panel.  The same workgroup then runs forward kinematics at the new pose.
+// One workgroup per stream.  The damped matrix (padded with identity rows to
+// a multiple of 16) sits in LDS with b appended as an extra row, and is
+// factored left-looking in 16-column panels: all four waves first subtract
+// the contribution of the finished panels from the new one (dot products out
+// of LDS), then wave 0 factors the panel in registers -- one row per lane,
+// columns broadcast between lanes with readlane, so the column-to-column
+// chain has no barrier.  The appended row becomes y = L^-1 b on the way
+// (forward substitution for free).  Back substitution runs panel by panel in
+// wave 0; the same workgroup then runs forward kinematics at the new pose.
 // ---------------------------------------------------------------------------
-constexpr int kBS = 8;                    // block size
-constexpr int kNBMax = (kMaxJoints + 1) / kBS;  // 16 blocks per side
-constexpr int kPanelStride = kBS * kBS + 1;
+constexpr int kPanel = 16;
+constexpr int kNMax = kMaxJoints + 1;   // 128
+constexpr int kLD = kNMax + 1;          // LDS row stride (elements)
+
+template <class T>
+struct SolveLds {
+    union {
+        T M[(kNMax + 1) * kLD];        // rows 0..n-1: A then L; row n: b then y
+        FkScratch fk;                  // forward kinematics after the solve
+    };
+    T x[kNMax];
+    T dinv[kNMax];                     // 1 / L_jj
+    int frozen[kNMax];
+    int fail;
+};
+
+// 1/sqrt(d): the hardware estimate for float (1 ulp), IEEE for double
+__device__ __forceinline__ float rsqrt_of(float d) { return __builtin_amdgcn_rsqf(d); }
+__device__ __forceinline__ double rsqrt_of(double d) { return 1.0 / sqrt(d); }
+
+__device__ __forceinline__ float lane_bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 template <class T>
 __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
-    // L blocks of the current panel column; block stride kBS*kBS + 1 keeps the
-    // 16 column-block reads of a wave on distinct LDS banks
-    __shared__ T s_panel[kNBMax * kPanelStride];
-    __shared__ T s_y[kNBMax * kBS];           // right-hand side -> z -> x
-    __shared__ T s_inv[kNBMax * kBS];         // 1 / L_jj: one division per column
-    __shared__ int s_frozen[kNBMax * kBS];
-    __shared__ int s_fail;
-    __shared__ double s_nrm[256];
+    __shared__ SolveLds<T> sh;
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     const JointTable* __restrict__ jt = S.jt;
@@ -42,167 +63,152 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
     const double* __restrict__ gram = S.gram;
     const float lambda_k = S.lambda_k;
     double* __restrict__ theta = S.theta;
-    double* __restrict__ step = S.step;
     DevStats* st = S.st;
     const int P = jt->P;
-    const int NB = (P + kBS - 1) / kBS;
-    const int tid = threadIdx.x;
-    const int bi = tid >> 4, bj = tid & 15;
-    const bool mine = bi < NB && bj <= bi;
-    if (tid == 0) s_fail = 0;
-    for (int k = tid; k < NB * kBS; k += 256) {
+    const int n = (P + kPanel - 1) / kPanel * kPanel;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    T* M = sh.M;
+
+    // frozen parameters and the right-hand side (row n)
+    if (tid == 0) sh.fail = 0;
+    for (int k = tid; k < n; k += 256) {
         int fz = 1;
-        T yk = T(0);
+        T bk = T(0);
         if (k < P) {
             const double pr = jt->prior[k];
             fz = (gram[k * PP + k] + pr == 0.0) || !jt->active[k];
-            yk = fz ? T(0) : T(gram[k * PP + P] + pr * theta[k]);
+            bk = fz ? T(0) : T(gram[k * PP + P] + pr * theta[k]);
         }
-        s_frozen[k] = fz;
-        s_y[k] = yk;
+        sh.frozen[k] = fz;
+        M[n * kLD + k] = bk;
     }
     __syncthreads();
-    // this thread's block of the damped, frozen and padded matrix
-    T a[kBS][kBS];
+    // the damped, frozen and padded matrix (lower triangle); row r is read
+    // by the 16 lanes of a quarter-wave, eight loads in flight per lane
+    {
+        const int q = tid & 15, row0 = tid >> 4;
+        for (int r = row0; r < n; r += 16) {
+            const bool fr = sh.frozen[r] != 0;
+            T v[kNMax / 16];
 #pragma unroll
-    for (int r = 0; r < kBS; ++r)
-#pragma unroll
-        for (int c = 0; c < kBS; ++c) {
-            const int i = bi * kBS + r, j = bj * kBS + c;
-            T val = T(0);
-            if (mine) {
-                if (i == j) {
-                    val = (i >= P || s_frozen[i]) ? T(1)
-                                                  : T((gram[i * PP + i] + jt->prior[i]) * (1.0 + (double)lambda_k));
-                } else if (i < P && j < P && !s_frozen[i] && !s_frozen[j]) {
-                    val = T(gram[i * PP + j]);
-                }
+            for (int u = 0; u < kNMax / 16; ++u) {
+                const int c = q + 16 * u;
+                v[u] = (c < r && !fr && !sh.frozen[c]) ? T(gram[r * PP + c]) : T(0);
             }
-            a[r][c] = val;
+#pragma unroll
+            for (int u = 0; u < kNMax / 16; ++u) {
+                const int c = q + 16 * u;
+                if (c < r) M[r * kLD + c] = v[u];
+            }
+            if (q == 0)
+                M[r * kLD + r] = (r >= P || fr) ? T(1) : T((gram[r * PP + r] + jt->prior[r]) * (1.0 + (double)lambda_k));
         }
-    for (int p = 0; p < NB; ++p) {
-        // (1) factor the diagonal block; forward-solve its part of y
-        if (bi == p && bj == p) {
+    }
+    __syncthreads();
+
+    for (int c0 = 0; c0 < n; c0 += kPanel) {
+        // (1) A[r][c] -= sum_{k < c0} L[r][k] L[c][k] for the panel's columns,
+        //     rows c0..n (row n: b -> y)
+        if (c0 > 0) {
+            const int rows = n + 1 - c0;
+            for (int e = tid; e < rows * kPanel; e += 256) {
+                const int r = c0 + e / kPanel, c = c0 + (e & (kPanel - 1));
+                if (c > r) continue;
+                const T* Lr = M + r * kLD;
+                const T* Lc = M + c * kLD;
+                T acc[4] = {T(0), T(0), T(0), T(0)};
+                for (int k = 0; k < c0; k += 4) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc[q] += Lr[k + q] * Lc[k + q];
+                }
+                M[r * kLD + c] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            }
+            __syncthreads();
+        }
+        // (2) factor the panel in wave 0: lane l holds rows c0 + l and
+        //     c0 + 64 + l; every lane carries the right-hand-side row
+        if (wid == 0) {
+            const int r0 = c0 + lane, r1 = c0 + 64 + lane;
+            const bool h0 = r0 < n, h1 = r1 < n;
+            T a0[kPanel], a1[kPanel], ab[kPanel];
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) {
+                a0[j] = h0 ? M[r0 * kLD + c0 + j] : T(0);
+                a1[j] = h1 ? M[r1 * kLD + c0 + j] : T(0);
+                ab[j] = M[n * kLD + c0 + j];
+            }
             bool ok = true;
 #pragma unroll
-            for (int j = 0; j < kBS; ++j) {
-                const T d = a[j][j];
+            for (int j = 0; j < kPanel; ++j) {
+                const T d = lane_bcast(a0[j], j);
                 ok = ok && (d > T(0));
-                const T s = ok ? sqrt(d) : T(1);
-                const T inv = T(1) / s;
-                a[j][j] = s;
-                s_inv[p * kBS + j] = inv;
+                const T inv = ok ? rsqrt_of(d) : T(1);
+                // column j of L: the diagonal, then the rows below it; y_j.
+                // Lanes at or above the diagonal keep their (unused) entries.
+                const T lj = lane > j ? a0[j] * inv : T(0);
+                a0[j] = lane == j ? d * inv : (lane > j ? lj : a0[j]);
+                a1[j] *= inv;
+                ab[j] *= inv;
+                if (lane == 0) sh.dinv[c0 + j] = inv;
 #pragma unroll
-                for (int i = j + 1; i < kBS; ++i) a[i][j] *= inv;
-#pragma unroll
-                for (int i = j + 1; i < kBS; ++i)
-#pragma unroll
-                    for (int k = j + 1; k <= i; ++k) a[i][k] -= a[i][j] * a[k][j];
-            }
-            T z[kBS];
-#pragma unroll
-            for (int r = 0; r < kBS; ++r) z[r] = s_y[p * kBS + r];
-#pragma unroll
-            for (int j = 0; j < kBS; ++j) {
-                z[j] *= s_inv[p * kBS + j];
-#pragma unroll
-                for (int i = j + 1; i < kBS; ++i) z[i] -= a[i][j] * z[j];
-            }
-#pragma unroll
-            for (int r = 0; r < kBS; ++r) {
-                s_y[p * kBS + r] = z[r];
-#pragma unroll
-                for (int c = 0; c < kBS; ++c) s_panel[p * kPanelStride + r * kBS + c] = a[r][c];
-            }
-            if (!ok) s_fail = 1;
-        }
-        __syncthreads();
-        if (s_fail) break;
-        // (2) blocks below the diagonal: X L_pp^T = A_ip; update y_i
-        if (bj == p && bi > p && bi < NB) {
-#pragma unroll
-            for (int r = 0; r < kBS; ++r) {
-#pragma unroll
-                for (int j = 0; j < kBS; ++j) {
-                    T t = a[r][j];
-#pragma unroll
-                    for (int k = 0; k < j; ++k) t -= a[r][k] * s_panel[p * kPanelStride + j * kBS + k];
-                    a[r][j] = t * s_inv[p * kBS + j];
+                for (int c = j + 1; c < kPanel; ++c) {
+                    const T lcj = lane_bcast(lj, c);
+                    a0[c] -= lj * lcj;
+                    a1[c] -= a1[j] * lcj;
+                    ab[c] -= ab[j] * lcj;
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kBS; ++r) {
-                T t = s_y[bi * kBS + r];
-#pragma unroll
-                for (int j = 0; j < kBS; ++j) {
-                    t -= a[r][j] * s_y[p * kBS + j];
-                    s_panel[bi * kPanelStride + r * kBS + j] = a[r][j];
-                }
-                s_y[bi * kBS + r] = t;
+            for (int j = 0; j < kPanel; ++j) {
+                if (h0 && r0 >= c0 + j) M[r0 * kLD + c0 + j] = a0[j];
+                if (h1) M[r1 * kLD + c0 + j] = a1[j];
+                if (lane == 0) M[n * kLD + c0 + j] = ab[j];
             }
+            if (!ok && lane == 0) sh.fail = 1;
         }
         __syncthreads();
-        // (3) trailing update A_ij -= L_ip L_jp^T for p < j <= i
-        if (mine && bj > p) {
-#pragma unroll
-            for (int k = 0; k < kBS; ++k) {
-                T li[kBS], lj[kBS];
-#pragma unroll
-                for (int r = 0; r < kBS; ++r) {
-                    li[r] = s_panel[bi * kPanelStride + r * kBS + k];
-                    lj[r] = s_panel[bj * kPanelStride + r * kBS + k];
-                }
-#pragma unroll
-                for (int r = 0; r < kBS; ++r)
-#pragma unroll
-                    for (int c = 0; c < kBS; ++c) a[r][c] -= li[r] * lj[c];
-            }
-        }
-        __syncthreads();
+        if (sh.fail) break;
     }
-    const bool fail = s_fail != 0;
+    const bool fail = sh.fail != 0;
+    if (!fail && wid == 0) {
+        // back substitution L^T x = y, panel by panel from the last
+        for (int c0 = n - kPanel; c0 >= 0; c0 -= kPanel) {
+            // t_c = y_c - sum_{r >= c0 + 16} L[r][c] x_r for the panel's 16 columns:
+            // lanes 16 g + l take rows r = c0 + 16 + g, +4, ...
+            const int l = lane & (kPanel - 1), g = lane >> 4;
+            T t = T(0);
+            for (int r = c0 + kPanel + g; r < n; r += 4) t += M[r * kLD + c0 + l] * sh.x[r];
+            t += __shfl_xor(t, 16);
+            t += __shfl_xor(t, 32);
+            t = M[n * kLD + c0 + l] - t;
+            // upper-triangular 16x16 solve with L_pp^T in registers (column l)
+            T lc[kPanel];
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) lc[j] = j >= l ? M[(c0 + j) * kLD + c0 + l] : T(0);
+#pragma unroll
+            for (int j = kPanel - 1; j >= 0; --j) {
+                const T xj = lane_bcast(t, j) * sh.dinv[c0 + j];
+                t = l < j ? t - lc[j] * xj : (l == j ? xj : t);
+            }
+            if (lane < kPanel) sh.x[c0 + lane] = t;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
     if (!fail) {
-        // back substitution L^T x = z, panel by panel from the last
-        for (int p = NB - 1; p >= 0; --p) {
-            if (bi == p && bj == p) {
-                T x[kBS];
-#pragma unroll
-                for (int r = 0; r < kBS; ++r) x[r] = s_y[p * kBS + r];
-#pragma unroll
-                for (int j = kBS - 1; j >= 0; --j) {
-                    x[j] *= s_inv[p * kBS + j];
-#pragma unroll
-                    for (int i = 0; i < j; ++i) x[i] -= a[j][i] * x[j];
-                }
-#pragma unroll
-                for (int r = 0; r < kBS; ++r) s_y[p * kBS + r] = x[r];
+        if (wid == 0) {
+            double part = 0.0;
+            for (int k = lane; k < P; k += 64) {
+                const double x = sh.frozen[k] ? 0.0 : (double)sh.x[k];
+                S.step[k] = x;
+                theta[k] -= x;
+                part += x * x;
             }
-            __syncthreads();
-            if (bi == p && bj < p) {
-#pragma unroll
-                for (int c = 0; c < kBS; ++c) {
-                    T t = s_y[bj * kBS + c];
-#pragma unroll
-                    for (int r = 0; r < kBS; ++r) t -= a[r][c] * s_y[p * kBS + r];
-                    s_y[bj * kBS + c] = t;
-                }
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+            if (lane == 0) {
+                st->step_norm[S.iter + iter] = (float)sqrt(part);
+                st->energy[S.iter + iter] = (float)gram[P * PP + P];
             }
-            __syncthreads();
-        }
-        double part = 0.0;
-        for (int k = tid; k < P; k += 256) {
-            const double x = s_frozen[k] ? 0.0 : (double)s_y[k];
-            step[k] = x;
-            theta[k] -= x;
-            part += x * x;
-        }
-        s_nrm[tid] = part;
-        __syncthreads();
-        if (tid == 0) {
-            double s = 0.0;
-            for (int q = 0; q < 256; ++q) s += s_nrm[q];
-            st->step_norm[S.iter + iter] = (float)sqrt(s);
-            st->energy[S.iter + iter] = (float)gram[P * PP + P];
         }
     } else if (tid == 0) {
         st->status = -4;
@@ -210,7 +216,7 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
         st->step_norm[S.iter + iter] = 0.0f;
     }
     __syncthreads();
-    fk_block(jt, theta, S.dq, S.xi);
+    fk_block(jt, theta, S.dq, S.xi, sh.fk);
 }
 
 void launch_pose_solve(const Launch& L, int fp64, int iter) {
@@ -245,14 +251,13 @@ __device__ __forceinline__ void solve3(const T M[9], const T g[3], T x[3]) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn) {
+__global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn, int next) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
     const DevModel& m = S.m;
     const float4* __restrict__ v_old = S.verts[S.v_cur ^ vo_sel];
     const float4* __restrict__ v_new = S.verts[S.v_cur ^ vn_sel];
-    const Vec3Buf n = S.normals;
     const Accum& a = S.a;
     const int src = phi_index(S, pn);
     const Vec3Buf phi = S.phi[src];
@@ -261,29 +266,35 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     const float lphi = S.lphi, lnbr = S.lnbr, lt = S.lt, lw = S.lw;
     for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
     __syncthreads();
-    int i = local * blockDim.x + threadIdx.x;
+    const int i = local * blockDim.x + threadIdx.x;
     if (i >= m.V) return;
     const T px = phi.x[i], py = phi.y[i], pz = phi.z[i];
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
     const uint32_t c = a.cnt[i];
-    const float nx = n.x[i], ny = n.y[i], nz = n.z[i];
-    if (c > 0u && (nx * nx + ny * ny + nz * nz) > 0.0f) {
-        float H[8];
-        dq_blend(sdq, m.w[i], m.links[i], H);
-        T w = H[0], x = H[1], y = H[2], z = H[3];
-        T s = T(2) / (w * w + x * x + y * y + z * z);
-        T R[9] = {T(1) - s * (y * y + z * z), s * (x * y - w * z), s * (x * z + w * y),
-                  s * (x * y + w * z), T(1) - s * (x * x + z * z), s * (y * z - w * x),
-                  s * (x * z - w * y), s * (y * z + w * x), T(1) - s * (x * x + y * y)};
-        for (int q = 0; q < 3; ++q) u[q] = -(R[q] * nx + R[3 + q] * ny + R[6 + q] * nz);
-        const T inv = T(1) / ((T)c * T(4294967296.0));
-        const float4 vo = v_old[i], vn = v_new[i];
-        T dx = (T)a.sx[i] * inv + ((T)vo.x - (T)vn.x);
-        T dy = (T)a.sy[i] * inv + ((T)vo.y - (T)vn.y);
-        T dz = (T)a.sz[i] * inv + ((T)vo.z - (T)vn.z);
-        r = (T)nx * dx + (T)ny * dy + (T)nz * dz;
+    float H[8];
+    dq_blend(sdq, m.w[i], m.links[i], H);
+    if (c > 0u) {
+        float nx, ny, nz;
+        vertex_normal(m, v_new, i, nx, ny, nz);
+        if ((nx * nx + ny * ny + nz * nz) > 0.0f) {
+            T w = H[0], x = H[1], y = H[2], z = H[3];
+            T s = T(2) / (w * w + x * x + y * y + z * z);
+            T R[9] = {T(1) - s * (y * y + z * z), s * (x * y - w * z), s * (x * z + w * y),
+                      s * (x * y + w * z), T(1) - s * (x * x + z * z), s * (y * z - w * x),
+                      s * (x * z - w * y), s * (y * z + w * x), T(1) - s * (x * x + y * y)};
+            for (int q = 0; q < 3; ++q) u[q] = -(R[q] * nx + R[3 + q] * ny + R[6 + q] * nz);
+            const T inv = T(1) / ((T)c * T(4294967296.0));
+            const float4 vo = v_old[i], vn = v_new[i];
+            T dx = (T)a.sx[i] * inv + ((T)vo.x - (T)vn.x);
+            T dy = (T)a.sy[i] * inv + ((T)vo.y - (T)vn.y);
+            T dz = (T)a.sz[i] * inv + ((T)vo.z - (T)vn.z);
+            r = (T)nx * dx + (T)ny * dy + (T)nz * dz;
+        }
     }
+    // this is the association's last reader: clear for the next one
+    a.cnt[i] = 0u;
+    a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
     T alpha = (T)lphi + (T)lt;
     T g[3] = {u[0] * r + (T)lphi * px + (T)lt * (px - (T)phi_prev.x[i]),
               u[1] * r + (T)lphi * py + (T)lt * (py - (T)phi_prev.y[i]),
@@ -305,17 +316,27 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     for (int p = 0; p < 3; ++p) M[4 * p] *= (T(1) + (T)lw);
     T xs[3];
     solve3(M, g, xs);
-    phi_out.x[i] = (float)(px - xs[0]);
-    phi_out.y[i] = (float)(py - xs[1]);
-    phi_out.z[i] = (float)(pz - xs[2]);
+    const float fx = (float)(px - xs[0]), fy = (float)(py - xs[1]), fz = (float)(pz - xs[2]);
+    phi_out.x[i] = fx;
+    phi_out.y[i] = fy;
+    phi_out.z[i] = fz;
+    if (selected(S, next)) {
+        // the next iteration's surface: skin the new offsets (same blend) into
+        // the buffer not read here by other vertices, and count it
+        float ox, oy, oz;
+        dq_apply(H, m.rx[i] + fx, m.ry[i] + fy, m.rz[i] + fz, ox, oy, oz);
+        const float4 q = make_float4(ox, oy, oz, 0.0f);
+        S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
+        count_vertex(S, i, q);
+    }
 }
 
-void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn) {
+void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next) {
     const dim3 g(L.grid[KK_VERT]);
     if (fp64)
-        hipLaunchKernelGGL(k_shape<double>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn);
+        hipLaunchKernelGGL(k_shape<double>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn, next);
     else
-        hipLaunchKernelGGL(k_shape<float>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn);
+        hipLaunchKernelGGL(k_shape<float>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn, next);
 }
 
 }  // namespace trk

@@ -203,6 +203,7 @@ struct Stream {
     float *depth_buf = nullptr, *xyz_buf = nullptr;
     int v_cur = 0, phi_cur = 0, phi_prev = 0;
     bool surface_valid = false, refresh_pose = true;
+    bool dirty = true;             // buckets / accumulators not known to be clear
     int input_mode = 0;            // per-pass interface: 0 depth, 1 xyz
 };
 
@@ -243,6 +244,15 @@ void build_joint_table(Stream* c, const track_model* m) {
         std::memcpy(t.binv[l], inv, sizeof(inv));
         for (int k = j; k >= 0; k = t.parent[k]) t.anc[l][k >> 5] |= 1u << (k & 31);
     }
+    // pointer-jumping rounds of forward kinematics: ceil(log2(chain length))
+    int longest = 1;
+    for (int j = 0; j < t.P; ++j) {
+        int d = 1;
+        for (int k = t.parent[j]; k >= 0; k = t.parent[k]) ++d;
+        longest = std::max(longest, d);
+    }
+    t.rounds = 0;
+    while ((1 << t.rounds) < longest) ++t.rounds;
     // default-pose prior weights: share of vertices with weight on a link
     // whose chain holds joint k; zero for the joints carrying the root link
     c->prior_S.assign(t.P, 0.0);
@@ -655,23 +665,14 @@ Launch stage_table(Runner& R, int off, const TableEntry* e, int n) {
 // The schedule (Section 4): associate, then pose and/or offset steps.
 // ---------------------------------------------------------------------------
 struct SurfaceState {
-    int vsel = 0;      // vertex buffer relative to the launch's start
-    int pn = 0;        // offset steps taken since the launch's start
-    bool valid = false;
+    int vsel = 0;          // vertex buffer relative to the launch's start
+    int pn = 0;            // offset steps taken since the launch's start
+    bool counted = false;  // vsel holds the current surface, counted into the buckets
+    bool valid = false;    // vsel holds the current surface
 };
-
-void enqueue_surface(Runner& R, const Launch& L, int vsel, int pn) {
-    timed_begin(R, TRACK_K_SKIN);
-    launch_skin(L, vsel, pn);
-    timed_end(R, TRACK_K_SKIN);
-    timed_begin(R, TRACK_K_NORMALS);
-    launch_normals(L, vsel);
-    timed_end(R, TRACK_K_NORMALS);
-}
 
 void enqueue_associate(Runner& R, const Launch& L, int vsel) {
     timed_begin(R, TRACK_K_BUCKET);
-    launch_clear(L);
     launch_bucket(L, vsel);
     timed_end(R, TRACK_K_BUCKET);
     timed_begin(R, TRACK_K_ASSOC);
@@ -692,14 +693,26 @@ void enqueue_pose_step(Runner& R, const Launch& L, int fp64, int iter) {
     timed_end(R, TRACK_K_SOLVE);
 }
 
-// One iteration; `iter` is added to each slot's own iteration index.  With
-// issue == false only the buffer bookkeeping runs (the state a captured
-// launch leaves behind).
+void enqueue_skin(Runner& R, const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
+    timed_begin(R, TRACK_K_SKIN);
+    launch_skin(L, vsel, pn, which, count, clear_acc);
+    timed_end(R, TRACK_K_SKIN);
+}
+
+// One iteration; `iter` is added to each slot's own iteration index.
+// `first`: slots that start here skin and count the surface (the others
+// were counted by the step before).  `next`: slots that have another
+// iteration after this one -- the kernel that produces their next surface
+// counts it into the buckets as well.  Every reader of the buckets and the
+// accumulators clears them for the next iteration.  With issue == false only
+// the buffer bookkeeping runs (the state a captured launch leaves behind;
+// `next` must then be SEL_ALL or SEL_NONE).
 void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool shape, int iter, SurfaceState& st,
-               bool issue) {
-    if (!st.valid) {
-        if (issue) enqueue_surface(R, L, st.vsel, st.pn);
-        st.valid = true;
+               int first, int next, bool issue) {
+    const bool more = next != SEL_NONE;
+    if (!st.counted) {
+        if (issue) enqueue_skin(R, L, st.vsel, st.pn, first, first, 0);
+        st.counted = st.valid = true;
     }
     if (issue) enqueue_associate(R, L, st.vsel);
     if (pose && issue) {
@@ -708,32 +721,41 @@ void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool s
     }
     if (shape) {
         // re-skin at the new pose into the other vertex buffer, then one
-        // offset step; afterwards the surface must be re-skinned
+        // offset step, which also skins (and counts) the next surface
         int vn = st.vsel;
         if (pose) {
             vn = st.vsel ^ 1;
-            if (issue) enqueue_surface(R, L, vn, st.pn);
+            if (issue) enqueue_skin(R, L, vn, st.pn, SEL_ALL, SEL_NONE, 0);
         }
         if (issue) {
             timed_begin(R, TRACK_K_SHAPE);
-            launch_shape(L, sc.shape_fp64, st.vsel, vn, st.pn);
+            launch_shape(L, sc.shape_fp64, st.vsel, vn, st.pn, next);
             timed_end(R, TRACK_K_SHAPE);
         }
         st.pn += 1;
-        st.vsel = vn;
-        st.valid = false;
+        st.vsel = more ? vn ^ 1 : vn;
+        st.counted = st.valid = more;
     } else if (pose) {
         st.vsel ^= 1;
-        if (issue) enqueue_surface(R, L, st.vsel, st.pn);
+        if (issue) enqueue_skin(R, L, st.vsel, st.pn, SEL_ALL, next, 1);
+        st.counted = more;
+        st.valid = true;
+    } else {
+        if (issue) {
+            launch_clear_acc(L);
+            launch_bucket_count(L, st.vsel, next);
+        }
+        st.counted = more;
     }
 }
 
 // whole frame of a batch whose slots all start a frame
-SurfaceState frame(Runner& R, const Launch& L, const Schedule& sc, bool surface_valid, bool issue) {
+SurfaceState frame(Runner& R, const Launch& L, const Schedule& sc, bool issue) {
     SurfaceState st;
-    st.valid = surface_valid;
     if (issue) launch_frame_begin(L);
-    for (int t = 0; t < sc.n_iters; ++t) iteration(R, L, sc, sc.do_pose[t] != 0, sc.do_shape[t] != 0, t, st, issue);
+    for (int t = 0; t < sc.n_iters; ++t)
+        iteration(R, L, sc, sc.do_pose[t] != 0, sc.do_shape[t] != 0, t, st, SEL_ALL,
+                  t + 1 < sc.n_iters ? SEL_ALL : SEL_NONE, issue);
     if (issue) launch_frame_end(L, sc.first_pose, sc.last_pose);
     return st;
 }
@@ -868,7 +890,8 @@ int refresh_surface(track_ctx* c) {
     if (c->st.surface_valid) return TRACK_OK;
     Launch L = stage_one(c, 0, nullptr, nullptr);
     if (c->st.refresh_pose) launch_fk(L);
-    enqueue_surface(c->run, L, 0, 0);
+    enqueue_skin(c->run, L, 0, 0, SEL_ALL, SEL_NONE, 0);
+    launch_normals(L, 0);
     c->st.surface_valid = true;
     c->st.refresh_pose = false;
     HIP_TRY(hipStreamSynchronize(c->run.s));
@@ -879,14 +902,17 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
     Runner& R = c->run;
     Stream& s = c->st;
     const int flags = kSlotBeginFrame | kSlotEndFrame | (s.refresh_pose ? kSlotRefreshPose : 0);
+    if (s.dirty) {  // buckets and accumulators zero before a frame
+        launch_clear(stage_one(c, 0, nullptr, nullptr));
+        s.dirty = false;
+    }
     Launch L = stage_one(c, flags, depth, xyz);
     GraphKey key{};
-    key.n = 1; key.off = 0; key.kind = 0; key.skin_first = s.surface_valid ? 0 : 1;
+    key.n = 1; key.off = 0; key.kind = 0; key.skin_first = 1;
     for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
-    const bool valid0 = s.surface_valid;
-    const SurfaceState st = frame(R, L, c->sched, valid0, false);
+    const SurfaceState st = frame(R, L, c->sched, false);
     HIP_TRY(hipEventRecord(R.f0, R.s));
-    int rc = run_cached(R, key, [&]() { frame(R, L, c->sched, valid0, true); });
+    int rc = run_cached(R, key, [&]() { frame(R, L, c->sched, true); });
     if (rc) return rc;
     HIP_TRY(hipEventRecord(R.f1, R.s));
     HIP_TRY(hipMemcpyAsync(R.hsum, R.dsum, sizeof(DevSummary), hipMemcpyDeviceToHost, R.s));
@@ -1012,6 +1038,11 @@ int server_admit(track_server* sv) {
         sv->used += (int64_t)ss->bytes;
         ss->model.release();
         sv->waiting.pop_front();
+        // buckets and accumulators start clear
+        TableEntry e{d, 0, 0, nullptr, nullptr};
+        launch_clear(stage_table(sv->run, sv->run.cap - 1, &e, 1));
+        HIP_TRY(hipStreamSynchronize(sv->run.s));
+        d->dirty = false;
     }
     return TRACK_OK;
 }
@@ -1137,6 +1168,7 @@ int track_dbg_set(track_ctx* c, int32_t buf, const void* host, size_t bytes) {
     Slot& S = s.slot;
     const size_t V = s.V, N = (size_t)s.W * s.H;
     HIP_TRY(hipStreamSynchronize(c->run.s));
+    s.dirty = true;
     switch (buf) {
         case TRACK_BUF_THETA:
             if (bytes != 8 * (size_t)s.P) return fail(TRACK_E_INVALID, "size");
@@ -1271,11 +1303,13 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
     const float* depth = s.input_mode == 0 ? s.depth_buf : nullptr;
     const float* xyz = s.input_mode == 1 ? s.xyz_buf : nullptr;
     HIP_TRY(hipStreamSynchronize(R.s));
+    s.dirty = true;
     switch (pass) {
         case TRACK_PASS_SKIN: {
             Launch L = stage_one(c, 0, depth, xyz);
             launch_fk(L);
-            enqueue_surface(R, L, 0, 0);
+            enqueue_skin(R, L, 0, 0, SEL_ALL, SEL_NONE, 0);
+            launch_normals(L, 0);
             s.surface_valid = true;
             s.refresh_pose = false;
             break;
@@ -1283,9 +1317,13 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
         case TRACK_PASS_NORMALS:
             launch_normals(stage_one(c, 0, depth, xyz), 0);
             break;
-        case TRACK_PASS_ASSOCIATE:
-            enqueue_associate(R, stage_one(c, 0, depth, xyz), 0);
+        case TRACK_PASS_ASSOCIATE: {
+            Launch L = stage_one(c, 0, depth, xyz);
+            launch_clear(L);
+            launch_bucket_count(L, 0, SEL_ALL);
+            enqueue_associate(R, L, 0);
             break;
+        }
         case TRACK_PASS_NORMAL_EQ: {
             Launch L = stage_one(c, 0, depth, xyz);
             launch_fk(L);
@@ -1302,9 +1340,9 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
         case TRACK_PASS_SHAPE: {
             Launch L = stage_one(c, 0, depth, xyz);
             launch_fk(L);
-            enqueue_surface(R, L, 1, 0);
+            enqueue_skin(R, L, 1, 0, SEL_ALL, SEL_NONE, 0);
             timed_begin(R, TRACK_K_SHAPE);
-            launch_shape(L, c->sched.shape_fp64, 0, 1, 0);
+            launch_shape(L, c->sched.shape_fp64, 0, 1, 0, SEL_NONE);
             timed_end(R, TRACK_K_SHAPE);
             s.v_cur ^= 1;
             s.phi_cur = phi_next(s.phi_cur, s.phi_prev);
@@ -1345,8 +1383,9 @@ int track_server_create(const track_params* params, int64_t hbm_budget_bytes, in
     sv->sched.set(params);
     sv->budget = hbm_budget_bytes;
     sv->max_streams = max_streams;
-    // three iteration kinds (pose, offset, both) can share a step
-    if ((rc = runner_init(sv->run, 3 * max_streams, hip_stream))) {
+    // four iteration kinds can share a step; one more entry for clearing a
+    // newly admitted stream
+    if ((rc = runner_init(sv->run, 4 * max_streams + 1, hip_stream))) {
         runner_free(sv->run);
         delete sv;
         return rc;
@@ -1401,8 +1440,9 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
     Runner& R = sv->run;
     const Schedule& sc = sv->sched;
     // streams with work, grouped by the kind of their next iteration
-    std::vector<TableEntry> group[3];
-    std::vector<ServerStream*> who[3];
+    // (bit 0: pose step, bit 1: offset step)
+    std::vector<TableEntry> group[4];
+    std::vector<ServerStream*> who[4];
     for (ServerStream* ss : sv->streams) {
         if (!ss || !ss->dev) continue;
         if (ss->iter < 0) {
@@ -1418,34 +1458,35 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
         int flags = 0;
         if (t == 0) flags |= kSlotBeginFrame | (ss->dev->refresh_pose ? kSlotRefreshPose : 0);
         if (t == sc.n_iters - 1) flags |= kSlotEndFrame;
-        const int kind = (sc.do_pose[t] ? 1 : 0) | (sc.do_shape[t] ? 2 : 0);
-        const int g = kind == 3 ? 0 : kind;  // 0: pose+offset (or neither), 1: pose, 2: offset
+        const int g = (sc.do_pose[t] ? 1 : 0) | (sc.do_shape[t] ? 2 : 0);
         group[g].push_back(TableEntry{ss->dev, flags, t, f.dev ? f.dev : ss->dev->depth_buf, nullptr});
         who[g].push_back(ss);
     }
     int off = 0;
     int nentries = 0;
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < 4; ++g) {
         const int n = (int)group[g].size();
         if (n == 0) continue;
-        const bool pose = g == 1 || (g == 0 && sc.do_pose[who[g][0]->iter]);
-        const bool shape = g == 2 || (g == 0 && sc.do_shape[who[g][0]->iter]);
+        const bool pose = (g & 1) != 0, shape = (g & 2) != 0;
         Launch L = stage_table(R, off, group[g].data(), n);
         GraphKey key{};
-        key.n = n; key.off = off; key.kind = 1 + (pose ? 1 : 0) + (shape ? 2 : 0); key.skin_first = 1;
+        key.n = n; key.off = off; key.kind = 1 + g; key.skin_first = 1;
         for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
         rc = run_cached(R, key, [&]() {
             SurfaceState st;
             launch_frame_begin(L);
-            iteration(R, L, sc, pose, shape, 0, st, true);
+            iteration(R, L, sc, pose, shape, 0, st, SEL_BEGIN, SEL_NOT_END, true);
             launch_frame_end(L, sc.first_pose, sc.last_pose);
         });
         if (rc) return rc;
-        // the iteration's effect on each stream's buffers
-        SurfaceState it;
-        iteration(R, L, sc, pose, shape, 0, it, false);
+        // the iteration's effect on each stream's buffers (a stream's last
+        // iteration prepares no next surface)
+        SurfaceState more, last;
+        iteration(R, L, sc, pose, shape, 0, more, SEL_ALL, SEL_ALL, false);
+        iteration(R, L, sc, pose, shape, 0, last, SEL_ALL, SEL_NONE, false);
         for (ServerStream* ss : who[g]) {
             Stream* d = ss->dev;
+            const SurfaceState& it = ss->iter == sc.n_iters - 1 ? last : more;
             d->v_cur ^= it.vsel;
             if (it.pn) d->phi_cur = phi_next(d->phi_cur, d->phi_prev);
         }
@@ -1458,7 +1499,7 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
     timed_collect(R);
     int ndone = 0;
     off = 0;
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < 4; ++g) {
         for (size_t q = 0; q < who[g].size(); ++q) {
             ServerStream* ss = who[g][q];
             const int t = ss->iter;

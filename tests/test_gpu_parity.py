@@ -41,6 +41,11 @@ def human():
 
 
 @pytest.fixture(scope="module")
+def highres():
+    return synth.workload_highres(n_frames=2)
+
+
+@pytest.fixture(scope="module")
 def ragged():
     cam = dict(width=100, height=75, fx=90.0, fy=90.0, cx=49.5, cy=37.0)
     body = synth.make_body(3001, cam, 2.6)
@@ -51,25 +56,29 @@ def ragged():
     return body, th, depth
 
 
-def _cases(tiny, ragged, human):
+def _cases(tiny, ragged, human, highres=None):
     b, th, d = ragged
-    return {
+    out = {
         "tiny": (tiny.body.model, tiny.body.camera, tiny.params, 0.5 * tiny.theta_true[0], tiny.frames[0]),
         "ragged": (b.model, b.camera, synth.default_params(len(th), 2, 0.05), 0.5 * th, d),
         "human": (human.body.model, human.body.camera, human.params, human.theta0, human.frames[0]),
     }
+    if highres is not None:
+        out["highres"] = (highres.body.model, highres.body.camera, highres.params, highres.theta0,
+                          highres.frames[0])
+    return out
 
 
 ULP3 = np.spacing(np.float32(4.0))  # float32 spacing at the largest coordinate magnitudes here
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged", "human"])
-def test_skin_and_normals(T, tiny, ragged, human, case):
+@pytest.mark.parametrize("case", ["tiny", "ragged", "human", "highres"])
+def test_skin_and_normals(T, tiny, ragged, human, highres, case):
     """Skinning at the same (theta, phi): float32 blend of float32-rounded
     link offsets, |dv| <= 16 ulp at 4 m.  Normals from the same float32
     vertices: float32 cross products and sums, |dn| <= 1e-5."""
     _say(f"[skin] {case}")
-    m, cam, prm, th, _ = _cases(tiny, ragged, human)[case]
+    m, cam, prm, th, _ = _cases(tiny, ragged, human, highres)[case]
     rng = np.random.default_rng(3)
     V = m["rest_xyz"].shape[0]
     phi = rng.normal(0, 0.003, (V, 3)).astype(np.float32)
@@ -91,14 +100,14 @@ def test_skin_and_normals(T, tiny, ragged, human, case):
         trk.close()
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged", "human"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "human", "highres"])
 @pytest.mark.parametrize("source", ["depth", "xyz"])
-def test_association_is_bit_exact(T, tiny, ragged, human, case, source):
+def test_association_is_bit_exact(T, tiny, ragged, human, highres, case, source):
     """Same float32 vertices and frame: identical nearest-vertex index per
     pixel and identical counts; mean offsets within 1e-8 m (fixed-point sums
     quantised at 2^-32 m, float32 output)."""
     _say(f"[assoc] {case} {source}")
-    m, cam, prm, th, depth = _cases(tiny, ragged, human)[case]
+    m, cam, prm, th, depth = _cases(tiny, ragged, human, highres)[case]
     v_or, _ = oracle.skin(m, th)
     v32 = v_or.astype(np.float32)
     H, W = cam["height"], cam["width"]
@@ -143,9 +152,9 @@ def _assoc_inputs(m, cam, prm, th, depth, phi):
     return v32, n32, cnt, delta.astype(np.float32)
 
 
-@pytest.mark.parametrize("case", ["tiny", "ragged", "human"])
+@pytest.mark.parametrize("case", ["tiny", "ragged", "human", "highres"])
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_normal_equations(T, tiny, ragged, human, case, mode):
+def test_normal_equations(T, tiny, ragged, human, highres, case, mode):
     """[J r]^T [J r] from identical (theta, phi, v, n, c, delta).
     float32 rows and MFMA accumulation:
       |dA_kl| <= 1e-4 (|J|^T|J|)_kl,  |db_k| <= 1e-4 (|J|^T|r|)_k + 1e-9,
@@ -153,7 +162,7 @@ def test_normal_equations(T, tiny, ragged, human, case, mode):
     The split-bfloat16 forms carry about 2^-17 (hi/lo) and 2^-24 (hi/mid/lo)
     relative error per product, inside the same bound."""
     _say(f"[normal_eq] {case} mode={mode}")
-    m, cam, prm, th, depth = _cases(tiny, ragged, human)[case]
+    m, cam, prm, th, depth = _cases(tiny, ragged, human, highres)[case]
     prm = dict(prm, gram_mode=mode)
     V, P = m["rest_xyz"].shape[0], len(th)
     rng = np.random.default_rng(11)
@@ -289,35 +298,26 @@ def _oracle_frame(m, cam, prm, th, phi, depth):
     return th, phi, v, r
 
 
-@pytest.mark.parametrize("mode,fp64", list(E2E_FLOOR))
-def test_frame_end_to_end(T, human, mode, fp64):
-    """Frames of the human workload against the float64 oracle, each frame
-    from the oracle's state at its start.  Five Gauss-Newton iterations of
-    a 75-DoF body can amplify rounding-level differences (weakly observed
-    distal joints and limb twists), so the bound is certified per frame by
-    the oracle itself: its own change when the starting pose moves by
-    E2E_PERTURB (random direction, two draws) is the frame's amplification;
-    the GPU may differ by E2E_GAIN times that change, and at least by the
-    floor of its configuration (E2E_FLOOR).  Prints both."""
-    _say(f"[frame] gram mode={mode} fp64 solves={fp64}")
-    m, cam = human.body.model, human.body.camera
-    prm = dict(human.params, gram_mode=mode, pose_solve_fp64=fp64, shape_solve_fp64=fp64)
-    V, P = m["rest_xyz"].shape[0], len(human.theta0)
-    ang = human.body.angular
-    trk = T.Tracker(m, cam, prm, human.theta0)
-    th_or, phi_or = human.theta0.copy(), np.zeros((V, 3))
-    f_ang, f_lin = E2E_FLOOR[(mode, fp64)]
+def _frames_against_oracle(T, w, prm, nframes, floor):
+    """Frames of workload w against the float64 oracle, each frame from the
+    oracle's state at its start; returns the frames that break the bound."""
+    m, cam = w.body.model, w.body.camera
+    V, P = m["rest_xyz"].shape[0], len(w.theta0)
+    ang = w.body.angular
+    trk = T.Tracker(m, cam, prm, w.theta0)
+    th_or, phi_or = w.theta0.copy(), np.zeros((V, 3))
+    f_ang, f_lin = floor
     failures = []
     try:
-        for f in range(3):
+        for f in range(nframes):
             trk.reset(th_or, phi_or.astype(np.float32))
             phi_or = phi_or.astype(np.float32).astype(np.float64)
-            assert trk.frame(human.frames[f]) == 0, T.track_last_error()
-            th1, phi1, v1, r = _oracle_frame(m, cam, prm, th_or, phi_or, human.frames[f])
+            assert trk.frame(w.frames[f]) == 0, T.track_last_error()
+            th1, phi1, v1, r = _oracle_frame(m, cam, prm, th_or, phi_or, w.frames[f])
             s_ang = s_lin = s_v = 0.0
             for seed in (0, 1):
                 dth = E2E_PERTURB * np.random.default_rng(100 + 10 * f + seed).standard_normal(P)
-                th2, _, v2, _ = _oracle_frame(m, cam, prm, th_or + dth, phi_or, human.frames[f])
+                th2, _, v2, _ = _oracle_frame(m, cam, prm, th_or + dth, phi_or, w.frames[f])
                 d = np.abs(th2 - th1)
                 s_ang, s_lin = max(s_ang, d[ang].max()), max(s_lin, d[~ang].max())
                 s_v = max(s_v, np.abs(v2 - v1).max())
@@ -335,6 +335,30 @@ def test_frame_end_to_end(T, human, mode, fp64):
             th_or, phi_or = th1, phi1   # the oracle's state starts the next frame
     finally:
         trk.close()
+    return failures
+
+
+@pytest.mark.parametrize("mode,fp64", list(E2E_FLOOR))
+def test_frame_end_to_end(T, human, mode, fp64):
+    """Frames of the human workload against the float64 oracle, each frame
+    from the oracle's state at its start.  Five Gauss-Newton iterations of
+    a 75-DoF body can amplify rounding-level differences (weakly observed
+    distal joints and limb twists), so the bound is certified per frame by
+    the oracle itself: its own change when the starting pose moves by
+    E2E_PERTURB (random direction, two draws) is the frame's amplification;
+    the GPU may differ by E2E_GAIN times that change, and at least by the
+    floor of its configuration (E2E_FLOOR).  Prints both."""
+    _say(f"[frame] gram mode={mode} fp64 solves={fp64}")
+    prm = dict(human.params, gram_mode=mode, pose_solve_fp64=fp64, shape_solve_fp64=fp64)
+    failures = _frames_against_oracle(T, human, prm, 3, E2E_FLOOR[(mode, fp64)])
+    assert not failures, failures
+
+
+def test_highres_frames_end_to_end(T, highres):
+    """The 200k-vertex, 512x424 workload (temporal weight 0.5, float64 pose
+    solve) against the oracle, with the certified bound of the test above."""
+    _say("[frame] highres")
+    failures = _frames_against_oracle(T, highres, dict(highres.params), 2, E2E_FLOOR[(0, 1)])
     assert not failures, failures
 
 
