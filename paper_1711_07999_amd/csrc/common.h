@@ -98,7 +98,7 @@ constexpr int kSlotBeginFrame = 1;    // the launch starts a frame of this slot
 constexpr int kSlotEndFrame = 2;      // the launch ends a frame of this slot
 constexpr int kSlotRefreshPose = 4;   // redo forward kinematics at frame start
 
-struct Slot {
+struct alignas(16) Slot {
     DevModel m;
     DevCam c;
     const JointTable* jt;
@@ -161,7 +161,11 @@ struct Batch {
 struct Launch {
     Batch B;
     int grid[KK_COUNT_];
+    int solve_n;        // largest padded pose-system size of the batch
+    int ne_pp, ne_l;    // largest padded Gram size and link count of the batch
     hipStream_t s;
+    const Slot* stage_src;   // the window in pinned memory (device view)
+    const int* stage_pre;
 };
 
 // slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
@@ -172,7 +176,7 @@ __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& l
         int mid = (lo + hi + 1) >> 1;
         if (p[mid] <= blk) lo = mid; else hi = mid - 1;
     }
-    local = blk - p[lo];
+    local = lo == 0 ? blk : blk - p[lo];  // every prefix starts at 0
     return lo;
 }
 
@@ -203,6 +207,8 @@ __device__ __forceinline__ bool selected(const Slot& S, int sel) {
     return sel == SEL_ALL || (sel == SEL_BEGIN && (S.flags & kSlotBeginFrame)) ||
            (sel == SEL_NOT_END && !(S.flags & kSlotEndFrame));
 }
+// copy a table window (slots and prefix rows) from host-visible pinned memory
+void launch_stage(hipStream_t s, const Slot* src, Slot* dst, int n, const int* psrc, int* pdst, int npre);
 void launch_frame_begin(const Launch& L);
 void launch_frame_end(const Launch& L, int first_pose, int last_pose);  // iterations of the frame, -1 = none
 void launch_fk(const Launch& L);
@@ -219,6 +225,8 @@ void launch_associate(const Launch& L, int vsel);
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
 void launch_gram_reduce(const Launch& L);
 void launch_pose_solve(const Launch& L, int fp64, int iter);
+bool prepare_pose_solve();   // once per process, before the first launch
+bool prepare_normal_eq();    // likewise
 // offset step from v_old / v_new (normals of v_new formed in place); the
 // slots selected by `next` also skin the new offsets into v_new ^ 1 and count
 // them into the buckets

@@ -30,11 +30,11 @@ struct FkScratch {
     int A[2][kMaxJoints + 1];
 };
 
-__device__ __forceinline__ void fk_block(const JointTable* __restrict__ jt, const double* __restrict__ theta,
-                         float* __restrict__ dq, float* __restrict__ xi, FkScratch& ws) {
+__device__ __forceinline__ void fk_block(const JointTable* __restrict__ jt, int P, int L,
+                                         const double* __restrict__ theta, float* __restrict__ dq,
+                                         float* __restrict__ xi, FkScratch& ws) {
     double (*M)[kMaxJoints + 1][8] = ws.M;
     int (*A)[kMaxJoints + 1] = ws.A;
-    const int P = jt->P, L = jt->L;
     const int t = threadIdx.x;
     for (int j = t; j < P; j += blockDim.x) {
         double th = theta[j];

@@ -8,6 +8,22 @@
 namespace trk {
 
 // ---------------------------------------------------------------------------
+// table upload: the host writes the slot table into pinned memory and this
+// first kernel of a launch copies it to device memory (no copy engine call)
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_stage(const uint4* __restrict__ src, uint4* __restrict__ dst, int n16,
+                                               const int* __restrict__ psrc, int* __restrict__ pdst, int npre) {
+    for (int i = threadIdx.x; i < n16; i += 256) dst[i] = src[i];
+    for (int i = threadIdx.x; i < npre; i += 256) pdst[i] = psrc[i];
+}
+
+void launch_stage(hipStream_t s, const Slot* src, Slot* dst, int n, const int* psrc, int* pdst, int npre) {
+    const int n16 = (int)(sizeof(Slot) / 16) * n;
+    hipLaunchKernelGGL(k_stage, dim3(1), dim3(256), 0, s, reinterpret_cast<const uint4*>(src),
+                       reinterpret_cast<uint4*>(dst), n16, psrc, pdst, npre);
+}
+
+// ---------------------------------------------------------------------------
 // frame start: keep the pose for a rollback, clear the status flag and (when
 // the slot asks for it) redo forward kinematics at the current pose
 // ---------------------------------------------------------------------------
@@ -19,7 +35,7 @@ __global__ void __launch_bounds__(128) k_frame_begin(Batch B) {
     const int P = S.m.P;
     for (int k = threadIdx.x; k < P; k += blockDim.x) S.theta_backup[k] = S.theta[k];
     if (threadIdx.x == 0) S.st->status = 0;
-    if (S.flags & kSlotRefreshPose) fk_block(S.jt, S.theta, S.dq, S.xi, ws);
+    if (S.flags & kSlotRefreshPose) fk_block(S.jt, S.m.P, S.m.L, S.theta, S.dq, S.xi, ws);
 }
 
 void launch_frame_begin(const Launch& L) {
@@ -30,7 +46,7 @@ __global__ void __launch_bounds__(128) k_fk(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     __shared__ FkScratch ws;
-    fk_block(S.jt, S.theta, S.dq, S.xi, ws);
+    fk_block(S.jt, S.m.P, S.m.L, S.theta, S.dq, S.xi, ws);
 }
 
 void launch_fk(const Launch& L) {

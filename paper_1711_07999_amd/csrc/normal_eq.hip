@@ -97,21 +97,46 @@ __device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq
     r_out = nx * dx + ny * dy + nz * dz;
 }
 
+// Dynamic LDS of the normal equations for the batch's largest padded size
+// ppmax and link count lmax: the [col][row] tile (float32, or two / three
+// bfloat16 planes), the per-row 6-vectors, links, residuals and the staged
+// link offsets, generators and link chains.  Sized to the batch so that a
+// 75-joint body stays under 64 KB (larger workgroup LDS costs launch time).
 template <int MODE>
-__global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn) {
-    __shared__ float sdq[8 * (kMaxLinks + 1)];
-    __shared__ float sxi[6 * kPPMax];
-    __shared__ uint32_t sanc[4 * (kMaxLinks + 1)];
-    __shared__ float sG[kNeRows * kGStride];
-    __shared__ uint32_t slink[kNeRows];
-    __shared__ float sr[kNeRows];
-    __shared__ int scount[2];
-    // [col][row] tile: float32 (mode 0) or up to three bfloat16 planes
-    __shared__ __attribute__((aligned(16))) unsigned short sT[3 * kPPMax * kJTStride];
-    float* sJT = reinterpret_cast<float*>(sT);
-    __bf16* plane0 = reinterpret_cast<__bf16*>(sT);
-    __bf16* plane1 = plane0 + kPPMax * kJTStride;
-    __bf16* plane2 = plane1 + kPPMax * kJTStride;
+__host__ __device__ inline size_t ne_tile_bytes(int ppmax) {
+    return (size_t)ppmax * kJTStride * (MODE == 0 ? 4 : MODE == 1 ? 4 : 6);
+}
+template <int MODE>
+__host__ __device__ inline size_t ne_lds_bytes(int ppmax, int lmax) {
+    return ne_tile_bytes<MODE>(ppmax) + 4 * (size_t)kNeRows * kGStride + 4 * (size_t)kNeRows * 2 + 16 +
+           4 * (size_t)(8 * lmax + 6 * ppmax + 4 * lmax);
+}
+
+// BIG: an instance allowed more than 64 KB of LDS (hi/mid/lo planes, or
+// P > 79); smaller sizes use the other instance, which launches faster
+template <int MODE, bool BIG>
+__global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, int ppmax, int lmax) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    unsigned char* q0 = smem;
+    // [col][row] tile: float32 (mode 0) or two / three bfloat16 planes
+    float* sJT = reinterpret_cast<float*>(q0);
+    __bf16* plane0 = reinterpret_cast<__bf16*>(q0);
+    __bf16* plane1 = plane0 + ppmax * kJTStride;
+    __bf16* plane2 = plane1 + ppmax * kJTStride;
+    q0 += ne_tile_bytes<MODE>(ppmax);
+    float* sG = reinterpret_cast<float*>(q0);
+    q0 += 4 * kNeRows * kGStride;
+    uint32_t* slink = reinterpret_cast<uint32_t*>(q0);
+    q0 += 4 * kNeRows;
+    float* sr = reinterpret_cast<float*>(q0);
+    q0 += 4 * kNeRows;
+    int* scount = reinterpret_cast<int*>(q0);
+    q0 += 16;
+    float* sdq = reinterpret_cast<float*>(q0);
+    q0 += 4 * 8 * lmax;
+    float* sxi = reinterpret_cast<float*>(q0);
+    q0 += 4 * 6 * ppmax;
+    uint32_t* sanc = reinterpret_cast<uint32_t*>(q0);
 
     int wg;
     const Slot& S = B.slots[slot_of(B, KK_NE, blockIdx.x, wg)];
@@ -265,14 +290,37 @@ int ne_grid(int V) {
     return nchunks < 256 ? nchunks : 256;
 }
 
-void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
+constexpr size_t kSmallLds = 64 * 1024;
+
+bool prepare_normal_eq() {
+    bool ok = true;
+    ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_normal_eq<0, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)ne_lds_bytes<0>(kPPMax, kMaxLinks + 1)) == hipSuccess && ok;
+    ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_normal_eq<1, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)ne_lds_bytes<1>(kPPMax, kMaxLinks + 1)) == hipSuccess && ok;
+    ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_normal_eq<2, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)ne_lds_bytes<2>(kPPMax, kMaxLinks + 1)) == hipSuccess && ok;
+    return ok;
+}
+
+template <int MODE>
+void launch_normal_eq_t(const Launch& L, int vsel, int pn) {
     const dim3 g(L.grid[KK_NE]);
-    if (gram_mode == 0)
-        hipLaunchKernelGGL(k_normal_eq<0>, g, dim3(256), 0, L.s, L.B, vsel, pn);
-    else if (gram_mode == 1)
-        hipLaunchKernelGGL(k_normal_eq<1>, g, dim3(256), 0, L.s, L.B, vsel, pn);
+    const int pp = L.ne_pp, lm = L.ne_l;
+    const size_t bytes = ne_lds_bytes<MODE>(pp, lm);
+    if (bytes <= kSmallLds)
+        hipLaunchKernelGGL((k_normal_eq<MODE, false>), g, dim3(256), bytes, L.s, L.B, vsel, pn, pp, lm);
     else
-        hipLaunchKernelGGL(k_normal_eq<2>, g, dim3(256), 0, L.s, L.B, vsel, pn);
+        hipLaunchKernelGGL((k_normal_eq<MODE, true>), g, dim3(256), bytes, L.s, L.B, vsel, pn, pp, lm);
+}
+
+void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
+    if (gram_mode == 0) launch_normal_eq_t<0>(L, vsel, pn);
+    else if (gram_mode == 1) launch_normal_eq_t<1>(L, vsel, pn);
+    else launch_normal_eq_t<2>(L, vsel, pn);
 }
 
 // Sum of the partial Gram matrices in workgroup order, in float64; writes the

@@ -25,23 +25,33 @@ namespace trk {
 // ---------------------------------------------------------------------------
 constexpr int kPanel = 16;
 constexpr int kNMax = kMaxJoints + 1;   // 128
-constexpr int kLD = kNMax + 1;          // LDS row stride (elements)
 
+// Dynamic LDS of the solve for padded size n (row stride n + 4, so rows are
+// 16-byte aligned for vector access): the matrix with the right-hand-side
+// row (reused for forward kinematics afterwards), x, 1 / L_jj, the frozen
+// flags and the failure flag.
 template <class T>
-struct SolveLds {
-    union {
-        T M[(kNMax + 1) * kLD];        // rows 0..n-1: A then L; row n: b then y
-        FkScratch fk;                  // forward kinematics after the solve
-    };
-    T x[kNMax];
-    T dinv[kNMax];                     // 1 / L_jj
-    int frozen[kNMax];
-    int fail;
-};
+__host__ __device__ inline size_t solve_lds_bytes(int n) {
+    size_t mat = sizeof(T) * (size_t)(n + 1) * (n + 4);
+    if (mat < sizeof(FkScratch)) mat = sizeof(FkScratch);
+    mat = (mat + 15) & ~size_t(15);
+    return mat + 2 * sizeof(T) * n + sizeof(int) * (n + 1);
+}
 
 // 1/sqrt(d): the hardware estimate for float (1 ulp), IEEE for double
 __device__ __forceinline__ float rsqrt_of(float d) { return __builtin_amdgcn_rsqf(d); }
 __device__ __forceinline__ double rsqrt_of(double d) { return 1.0 / sqrt(d); }
+
+// four consecutive elements from 16-byte aligned LDS
+__device__ __forceinline__ void load4(const float* p, float* o) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void load4(const double* p, double* o) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
 
 __device__ __forceinline__ float lane_bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
@@ -53,9 +63,22 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-template <class T>
-__global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
-    __shared__ SolveLds<T> sh;
+// BIG: an instance allowed more than 64 KB of LDS (P > 112 in float64); a
+// kernel allowed that much is launched more slowly, so sizes below use the
+// other instance
+template <class T, bool BIG>
+__global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter, int nmax) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int ld = nmax + 4;   // row stride shared by the batch
+    size_t mat = sizeof(T) * (size_t)(nmax + 1) * ld;
+    if (mat < sizeof(FkScratch)) mat = sizeof(FkScratch);
+    mat = (mat + 15) & ~size_t(15);
+    T* M = reinterpret_cast<T*>(smem);
+    FkScratch& fk_ws = *reinterpret_cast<FkScratch*>(smem);
+    T* sx = reinterpret_cast<T*>(smem + mat);
+    T* sdinv = sx + nmax;
+    int* sfrozen = reinterpret_cast<int*>(sdinv + nmax);
+    int& sfail = sfrozen[nmax];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     const JointTable* __restrict__ jt = S.jt;
@@ -64,46 +87,58 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
     const float lambda_k = S.lambda_k;
     double* __restrict__ theta = S.theta;
     DevStats* st = S.st;
-    const int P = jt->P;
+    const int P = S.m.P;   // (the table's copy: no dependent load through jt)
     const int n = (P + kPanel - 1) / kPanel * kPanel;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    T* M = sh.M;
 
-    // frozen parameters and the right-hand side (row n)
-    if (tid == 0) sh.fail = 0;
-    for (int k = tid; k < n; k += 256) {
-        int fz = 1;
-        T bk = T(0);
-        if (k < P) {
-            const double pr = jt->prior[k];
-            fz = (gram[k * PP + k] + pr == 0.0) || !jt->active[k];
-            bk = fz ? T(0) : T(gram[k * PP + P] + pr * theta[k]);
+    // Every global read of the set-up is issued before any is used: the
+    // strictly lower triangle (a quarter-wave per row, four rows at a time)
+    // and, per parameter, its diagonal, right-hand side, prior and flags.
+    const int q = tid & 15, row0 = tid >> 4;
+    constexpr int kRows = 4;
+    T raw[2][kRows][kNMax / 16];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int a = 0; a < kRows; ++a) {
+            const int r = row0 + 16 * (kRows * h + a);
+#pragma unroll
+            for (int u = 0; u < kNMax / 16; ++u) {
+                const int c = q + 16 * u;
+                raw[h][a][u] = (r < P && c < r) ? T(gram[r * PP + c]) : T(0);
+            }
         }
-        sh.frozen[k] = fz;
-        M[n * kLD + k] = bk;
+    double gkk = 0.0, gkb = 0.0, prk = 0.0, thk = 0.0;
+    int actk = 0;
+    if (tid < P) {
+        gkk = gram[tid * PP + tid];
+        gkb = gram[tid * PP + P];
+        prk = jt->prior[tid];
+        thk = theta[tid];
+        actk = jt->active[tid];
+    }
+    if (tid == 0) sfail = 0;
+    if (tid < n) {
+        const int fz = tid >= P || (gkk + prk == 0.0) || !actk;
+        sfrozen[tid] = fz;
+        M[n * ld + tid] = fz ? T(0) : T(gkb + prk * thk);
+        M[tid * ld + tid] = fz ? T(1) : T((gkk + prk) * (1.0 + (double)lambda_k));
     }
     __syncthreads();
-    // the damped, frozen and padded matrix (lower triangle); row r is read
-    // by the 16 lanes of a quarter-wave, eight loads in flight per lane
-    {
-        const int q = tid & 15, row0 = tid >> 4;
-        for (int r = row0; r < n; r += 16) {
-            const bool fr = sh.frozen[r] != 0;
-            T v[kNMax / 16];
+    // the damped, frozen and padded matrix (lower triangle)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int a = 0; a < kRows; ++a) {
+            const int r = row0 + 16 * (kRows * h + a);
+            if (r >= n) continue;
+            const bool fr = sfrozen[r] != 0;
 #pragma unroll
             for (int u = 0; u < kNMax / 16; ++u) {
                 const int c = q + 16 * u;
-                v[u] = (c < r && !fr && !sh.frozen[c]) ? T(gram[r * PP + c]) : T(0);
+                if (c < r) M[r * ld + c] = (fr || sfrozen[c]) ? T(0) : raw[h][a][u];
             }
-#pragma unroll
-            for (int u = 0; u < kNMax / 16; ++u) {
-                const int c = q + 16 * u;
-                if (c < r) M[r * kLD + c] = v[u];
-            }
-            if (q == 0)
-                M[r * kLD + r] = (r >= P || fr) ? T(1) : T((gram[r * PP + r] + jt->prior[r]) * (1.0 + (double)lambda_k));
         }
-    }
     __syncthreads();
 
     for (int c0 = 0; c0 < n; c0 += kPanel) {
@@ -114,14 +149,17 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
             for (int e = tid; e < rows * kPanel; e += 256) {
                 const int r = c0 + e / kPanel, c = c0 + (e & (kPanel - 1));
                 if (c > r) continue;
-                const T* Lr = M + r * kLD;
-                const T* Lc = M + c * kLD;
+                const T* Lr = M + r * ld;
+                const T* Lc = M + c * ld;
                 T acc[4] = {T(0), T(0), T(0), T(0)};
                 for (int k = 0; k < c0; k += 4) {
+                    T xr[4], xc[4];
+                    load4(Lr + k, xr);
+                    load4(Lc + k, xc);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc[q] += Lr[k + q] * Lc[k + q];
+                    for (int t = 0; t < 4; ++t) acc[t] += xr[t] * xc[t];
                 }
-                M[r * kLD + c] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
+                M[r * ld + c] -= (acc[0] + acc[1]) + (acc[2] + acc[3]);
             }
             __syncthreads();
         }
@@ -132,10 +170,12 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
             const bool h0 = r0 < n, h1 = r1 < n;
             T a0[kPanel], a1[kPanel], ab[kPanel];
 #pragma unroll
-            for (int j = 0; j < kPanel; ++j) {
-                a0[j] = h0 ? M[r0 * kLD + c0 + j] : T(0);
-                a1[j] = h1 ? M[r1 * kLD + c0 + j] : T(0);
-                ab[j] = M[n * kLD + c0 + j];
+            for (int j = 0; j < kPanel; j += 4) {
+                if (h0) load4(M + r0 * ld + c0 + j, a0 + j);
+                else a0[j] = a0[j + 1] = a0[j + 2] = a0[j + 3] = T(0);
+                if (h1) load4(M + r1 * ld + c0 + j, a1 + j);
+                else a1[j] = a1[j + 1] = a1[j + 2] = a1[j + 3] = T(0);
+                load4(M + n * ld + c0 + j, ab + j);
             }
             bool ok = true;
 #pragma unroll
@@ -149,7 +189,7 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
                 a0[j] = lane == j ? d * inv : (lane > j ? lj : a0[j]);
                 a1[j] *= inv;
                 ab[j] *= inv;
-                if (lane == 0) sh.dinv[c0 + j] = inv;
+                if (lane == 0) sdinv[c0 + j] = inv;
 #pragma unroll
                 for (int c = j + 1; c < kPanel; ++c) {
                     const T lcj = lane_bcast(lj, c);
@@ -160,16 +200,16 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
             }
 #pragma unroll
             for (int j = 0; j < kPanel; ++j) {
-                if (h0 && r0 >= c0 + j) M[r0 * kLD + c0 + j] = a0[j];
-                if (h1) M[r1 * kLD + c0 + j] = a1[j];
-                if (lane == 0) M[n * kLD + c0 + j] = ab[j];
+                if (h0 && r0 >= c0 + j) M[r0 * ld + c0 + j] = a0[j];
+                if (h1) M[r1 * ld + c0 + j] = a1[j];
+                if (lane == 0) M[n * ld + c0 + j] = ab[j];
             }
-            if (!ok && lane == 0) sh.fail = 1;
+            if (!ok && lane == 0) sfail = 1;
         }
         __syncthreads();
-        if (sh.fail) break;
+        if (sfail) break;
     }
-    const bool fail = sh.fail != 0;
+    const bool fail = sfail != 0;
     if (!fail && wid == 0) {
         // back substitution L^T x = y, panel by panel from the last
         for (int c0 = n - kPanel; c0 >= 0; c0 -= kPanel) {
@@ -177,20 +217,20 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
             // lanes 16 g + l take rows r = c0 + 16 + g, +4, ...
             const int l = lane & (kPanel - 1), g = lane >> 4;
             T t = T(0);
-            for (int r = c0 + kPanel + g; r < n; r += 4) t += M[r * kLD + c0 + l] * sh.x[r];
+            for (int r = c0 + kPanel + g; r < n; r += 4) t += M[r * ld + c0 + l] * sx[r];
             t += __shfl_xor(t, 16);
             t += __shfl_xor(t, 32);
-            t = M[n * kLD + c0 + l] - t;
+            t = M[n * ld + c0 + l] - t;
             // upper-triangular 16x16 solve with L_pp^T in registers (column l)
             T lc[kPanel];
 #pragma unroll
-            for (int j = 0; j < kPanel; ++j) lc[j] = j >= l ? M[(c0 + j) * kLD + c0 + l] : T(0);
+            for (int j = 0; j < kPanel; ++j) lc[j] = j >= l ? M[(c0 + j) * ld + c0 + l] : T(0);
 #pragma unroll
             for (int j = kPanel - 1; j >= 0; --j) {
-                const T xj = lane_bcast(t, j) * sh.dinv[c0 + j];
+                const T xj = lane_bcast(t, j) * sdinv[c0 + j];
                 t = l < j ? t - lc[j] * xj : (l == j ? xj : t);
             }
-            if (lane < kPanel) sh.x[c0 + lane] = t;
+            if (lane < kPanel) sx[c0 + lane] = t;
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -199,7 +239,7 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
         if (wid == 0) {
             double part = 0.0;
             for (int k = lane; k < P; k += 64) {
-                const double x = sh.frozen[k] ? 0.0 : (double)sh.x[k];
+                const double x = sfrozen[k] ? 0.0 : (double)sx[k];
                 S.step[k] = x;
                 theta[k] -= x;
                 part += x * x;
@@ -216,14 +256,36 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter) {
         st->step_norm[S.iter + iter] = 0.0f;
     }
     __syncthreads();
-    fk_block(jt, theta, S.dq, S.xi, sh.fk);
+    fk_block(jt, P, S.m.L, theta, S.dq, S.xi, fk_ws);
+}
+
+constexpr size_t kSmallLds = 64 * 1024;
+
+// let the BIG instances take the largest system (P = 127, float64: about
+// 136 KB of LDS)
+bool prepare_pose_solve() {
+    bool ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_pose_solve<double, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)solve_lds_bytes<double>(kNMax)) == hipSuccess;
+    ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_pose_solve<float, true>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)solve_lds_bytes<float>(kNMax)) == hipSuccess && ok;
+    return ok;
+}
+
+template <class T>
+void launch_pose_solve_t(const Launch& L, int iter) {
+    const int n = L.solve_n;
+    const size_t bytes = solve_lds_bytes<T>(n);
+    if (bytes <= kSmallLds)
+        hipLaunchKernelGGL((k_pose_solve<T, false>), dim3(L.grid[KK_ONE]), dim3(256), bytes, L.s, L.B, iter, n);
+    else
+        hipLaunchKernelGGL((k_pose_solve<T, true>), dim3(L.grid[KK_ONE]), dim3(256), bytes, L.s, L.B, iter, n);
 }
 
 void launch_pose_solve(const Launch& L, int fp64, int iter) {
-    if (fp64)
-        hipLaunchKernelGGL(k_pose_solve<double>, dim3(L.grid[KK_ONE]), dim3(256), 0, L.s, L.B, iter);
-    else
-        hipLaunchKernelGGL(k_pose_solve<float>, dim3(L.grid[KK_ONE]), dim3(256), 0, L.s, L.B, iter);
+    if (fp64) launch_pose_solve_t<double>(L, iter);
+    else launch_pose_solve_t<float>(L, iter);
 }
 
 // ---------------------------------------------------------------------------

@@ -33,7 +33,16 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int i, float4 p) {
         const uint32_t zb = __float_as_uint(p.z);  // z > 0: integer order is float order
         atomicMin(&b.pzmin[pix], zb);
         atomicMax(&b.pzmax[pix], zb);
-        atomicAdd(&b.tsum[pix >> 6], 1u);
+    }
+    // tile sums: neighbouring vertices share tiles, so the lanes of a wave
+    // are grouped by tile and one lane per tile adds the group's count
+    const int tile = pix >= 0 ? (pix >> 6) : -1;
+    unsigned long long todo = __ballot(tile >= 0);
+    while (todo) {
+        const int t0 = __builtin_amdgcn_readlane(tile, __builtin_ctzll(todo));
+        const unsigned long long grp = __ballot(tile == t0);
+        if (tile == t0 && (threadIdx.x & 63) == __builtin_ctzll(grp)) atomicAdd(&b.tsum[t0], (uint32_t)__popcll(grp));
+        todo &= ~grp;
     }
 }
 
@@ -45,15 +54,25 @@ __device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* _
 #pragma clang fp contract(off)
     const float4 p = v[i];
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    const uint32_t e1 = m.fan_off[i + 1];
-    for (uint32_t e = m.fan_off[i]; e < e1; ++e) {
-        const int2 bc = m.fan[e];
-        const float4 vb = v[bc.x], vc = v[bc.y];
-        const float ax = vb.x - p.x, ay = vb.y - p.y, az = vb.z - p.z;
-        const float bx = vc.x - p.x, by = vc.y - p.y, bz = vc.z - p.z;
-        sx += ay * bz - az * by;
-        sy += az * bx - ax * bz;
-        sz += ax * by - ay * bx;
+    const uint32_t e0 = m.fan_off[i], e1 = m.fan_off[i + 1];
+    // four faces at a time: their fan entries, then their eight vertices, are
+    // loaded together (the sum still runs in fan order)
+    for (uint32_t e = e0; e < e1; e += 4) {
+        int2 bc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bc[k] = e + k < e1 ? m.fan[e + k] : make_int2(i, i);
+        float4 vb[4], vc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { vb[k] = v[bc[k].x]; vc[k] = v[bc[k].y]; }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (e + k >= e1) break;
+            const float ax = vb[k].x - p.x, ay = vb[k].y - p.y, az = vb[k].z - p.z;
+            const float bx = vc[k].x - p.x, by = vc[k].y - p.y, bz = vc[k].z - p.z;
+            sx += ay * bz - az * by;
+            sy += az * bx - ax * bz;
+            sz += ax * by - ay * bx;
+        }
     }
     const float l = sqrtf(sx * sx + sy * sy + sz * sz);
     const float inv = l > 0.0f ? 1.0f / l : 0.0f;

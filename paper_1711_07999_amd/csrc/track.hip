@@ -524,10 +524,12 @@ struct Runner {
     int cap = 0;                       // table entries
     Slot* dslots = nullptr;
     int* dpre = nullptr;               // prefix rows of each table window
-    DevSummary* dsum = nullptr;
-    Slot* hslots = nullptr;            // pinned
+    Slot* hslots = nullptr;            // pinned; written by the host, read by k_stage
     int* hpre = nullptr;               // pinned
-    DevSummary* hsum = nullptr;        // pinned
+    DevSummary* hsum = nullptr;        // pinned; written by the frame-end kernel
+    Slot* hslots_dev = nullptr;        // device views of the pinned buffers
+    int* hpre_dev = nullptr;
+    DevSummary* hsum_dev = nullptr;
     KernelTimer timers[TRACK_K_COUNT_];
     std::vector<CachedGraph> graphs;
     bool use_graphs = true;
@@ -540,6 +542,8 @@ struct Runner {
 inline int pre_offset(int off) { return off * (KK_COUNT_ + 1) * 2; }
 
 int runner_init(Runner& R, int cap, void* hip_stream) {
+    static const bool kernels_ready = prepare_pose_solve() && prepare_normal_eq();
+    if (!kernels_ready) return fail(TRACK_E_DEVICE, "pose solve: LDS size attribute refused");
     R.cap = cap;
     if (hip_stream) R.s = (hipStream_t)hip_stream;
     else {
@@ -547,13 +551,15 @@ int runner_init(Runner& R, int cap, void* hip_stream) {
         R.own_stream = true;
     }
     const size_t npre = (size_t)pre_offset(cap) + (size_t)KK_COUNT_ * (cap + 1);
-    if (hipMalloc(&R.dslots, sizeof(Slot) * cap) != hipSuccess || hipMalloc(&R.dpre, sizeof(int) * npre) != hipSuccess ||
-        hipMalloc(&R.dsum, sizeof(DevSummary) * cap) != hipSuccess)
+    if (hipMalloc(&R.dslots, sizeof(Slot) * cap) != hipSuccess || hipMalloc(&R.dpre, sizeof(int) * npre) != hipSuccess)
         return fail(TRACK_E_NOMEM, "device allocation failed");
     if (hipHostMalloc(&R.hslots, sizeof(Slot) * cap) != hipSuccess ||
         hipHostMalloc(&R.hpre, sizeof(int) * npre) != hipSuccess ||
         hipHostMalloc(&R.hsum, sizeof(DevSummary) * cap) != hipSuccess)
         return fail(TRACK_E_NOMEM, "pinned allocation failed");
+    HIP_TRY(hipHostGetDevicePointer((void**)&R.hslots_dev, R.hslots, 0));
+    HIP_TRY(hipHostGetDevicePointer((void**)&R.hpre_dev, R.hpre, 0));
+    HIP_TRY(hipHostGetDevicePointer((void**)&R.hsum_dev, R.hsum, 0));
     HIP_TRY(hipEventCreate(&R.f0));
     HIP_TRY(hipEventCreate(&R.f1));
     const char* env = std::getenv("TRACK_NO_GRAPH");
@@ -576,7 +582,6 @@ void runner_free(Runner& R) {
     if (R.f1) (void)hipEventDestroy(R.f1);
     if (R.dslots) (void)hipFree(R.dslots);
     if (R.dpre) (void)hipFree(R.dpre);
-    if (R.dsum) (void)hipFree(R.dsum);
     if (R.hslots) (void)hipHostFree(R.hslots);
     if (R.hpre) (void)hipHostFree(R.hpre);
     if (R.hsum) (void)hipHostFree(R.hsum);
@@ -632,8 +637,10 @@ struct TableEntry {
     const float* xyz;
 };
 
-// Write the table window [off, off + n) and its prefix rows, queue the
-// upload, and describe the launch.
+// Write the table window [off, off + n) and its prefix rows into pinned
+// memory and describe the launch; issue_stage() (the launch's first kernel)
+// copies them to the device.  The caller synchronises before the window is
+// written again.
 Launch stage_table(Runner& R, int off, const TableEntry* e, int n) {
     Launch L;
     L.s = R.s;
@@ -648,17 +655,30 @@ Launch stage_table(Runner& R, int off, const TableEntry* e, int n) {
         S.iter = e[i].iter;
         S.depth = e[i].depth;
         S.xyz = e[i].xyz;
-        S.summary = R.dsum + off + i;
+        S.summary = R.hsum_dev + off + i;
         R.hslots[off + i] = S;
         for (int k = 0; k < KK_COUNT_; ++k) pre[k * (n + 1) + i + 1] = pre[k * (n + 1) + i] + slot_blocks(S, k);
     }
     for (int k = 0; k < KK_COUNT_; ++k) L.grid[k] = pre[k * (n + 1) + n];
+    L.solve_n = 16;
+    L.ne_pp = 16;
+    L.ne_l = 1;
+    for (int i = 0; i < n; ++i) {
+        L.solve_n = std::max(L.solve_n, (e[i].s->P + 15) / 16 * 16);
+        L.ne_pp = std::max(L.ne_pp, e[i].s->PP);
+        L.ne_l = std::max(L.ne_l, e[i].s->L);
+    }
     L.B.slots = R.dslots + off;
     L.B.pre = R.dpre + pre_offset(off);
     L.B.n = n;
-    (void)hipMemcpyAsync(R.dslots + off, R.hslots + off, sizeof(Slot) * n, hipMemcpyHostToDevice, R.s);
-    (void)hipMemcpyAsync(R.dpre + pre_offset(off), pre, sizeof(int) * KK_COUNT_ * (n + 1), hipMemcpyHostToDevice, R.s);
+    L.stage_src = R.hslots_dev + off;
+    L.stage_pre = R.hpre_dev + pre_offset(off);
     return L;
+}
+
+void issue_stage(const Launch& L) {
+    launch_stage(L.s, L.stage_src, const_cast<Slot*>(L.B.slots), L.B.n, L.stage_pre, const_cast<int*>(L.B.pre),
+                 KK_COUNT_ * (L.B.n + 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -880,9 +900,12 @@ struct track_ctx {
 
 namespace {
 
+// stage the context's table (window 0) and issue its upload now
 Launch stage_one(track_ctx* c, int flags, const float* depth, const float* xyz) {
     TableEntry e{&c->st, flags, 0, depth, xyz};
-    return stage_table(c->run, 0, &e, 1);
+    Launch L = stage_table(c->run, 0, &e, 1);
+    issue_stage(L);
+    return L;
 }
 
 // FK (if needed), skin and normals at the current state
@@ -904,18 +927,22 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
     const int flags = kSlotBeginFrame | kSlotEndFrame | (s.refresh_pose ? kSlotRefreshPose : 0);
     if (s.dirty) {  // buckets and accumulators zero before a frame
         launch_clear(stage_one(c, 0, nullptr, nullptr));
+        HIP_TRY(hipStreamSynchronize(R.s));  // before the table window is rewritten
         s.dirty = false;
     }
-    Launch L = stage_one(c, flags, depth, xyz);
+    TableEntry e{&s, flags, 0, depth, xyz};
+    Launch L = stage_table(R, 0, &e, 1);
     GraphKey key{};
     key.n = 1; key.off = 0; key.kind = 0; key.skin_first = 1;
     for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
     const SurfaceState st = frame(R, L, c->sched, false);
     HIP_TRY(hipEventRecord(R.f0, R.s));
-    int rc = run_cached(R, key, [&]() { frame(R, L, c->sched, true); });
+    int rc = run_cached(R, key, [&]() {
+        issue_stage(L);
+        frame(R, L, c->sched, true);
+    });
     if (rc) return rc;
     HIP_TRY(hipEventRecord(R.f1, R.s));
-    HIP_TRY(hipMemcpyAsync(R.hsum, R.dsum, sizeof(DevSummary), hipMemcpyDeviceToHost, R.s));
     HIP_TRY(hipStreamSynchronize(R.s));
     timed_collect(R);
     float ms = 0.0f;
@@ -1040,7 +1067,9 @@ int server_admit(track_server* sv) {
         sv->waiting.pop_front();
         // buckets and accumulators start clear
         TableEntry e{d, 0, 0, nullptr, nullptr};
-        launch_clear(stage_table(sv->run, sv->run.cap - 1, &e, 1));
+        const Launch Lc = stage_table(sv->run, sv->run.cap - 1, &e, 1);
+        issue_stage(Lc);
+        launch_clear(Lc);
         HIP_TRY(hipStreamSynchronize(sv->run.s));
         d->dirty = false;
     }
@@ -1474,6 +1503,7 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
         for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
         rc = run_cached(R, key, [&]() {
             SurfaceState st;
+            issue_stage(L);
             launch_frame_begin(L);
             iteration(R, L, sc, pose, shape, 0, st, SEL_BEGIN, SEL_NOT_END, true);
             launch_frame_end(L, sc.first_pose, sc.last_pose);
@@ -1494,7 +1524,6 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
         nentries = off;
     }
     if (nentries == 0) return TRACK_OK;
-    HIP_TRY(hipMemcpyAsync(R.hsum, R.dsum, sizeof(DevSummary) * nentries, hipMemcpyDeviceToHost, R.s));
     HIP_TRY(hipStreamSynchronize(R.s));
     timed_collect(R);
     int ndone = 0;

@@ -1,14 +1,18 @@
 """Precision form: the split-bfloat16 Gram with float64 solves against the
 float64 oracle, beside the plain float32 path.
 
-Ten frames of the 50k-vertex body, each frame from the oracle's state at its
-start (so the comparison measures one frame's arithmetic, not the drift of
-weakly observed joints).  Per frame and per operand form: the largest
-joint-angle error (rad), root-translation error (m) and vertex error (m)
-against the oracle, and the oracle's own response to a 1e-6 perturbation of
-the starting pose (the frame's amplification of rounding).  Prints the table
-and a summary; every frame must stay inside the certified bound of the
-end-to-end parity test.
+The 50k-vertex body, 10 frames x 5 Gauss-Newton iterations.  Every
+iteration starts from the oracle's own state; the GPU receives the oracle's
+association of that iteration (vertices, normals, counts, mean offsets:
+the discrete part of the step, whose near-ties could otherwise flip between
+float32 and float64 vertices) and runs the normal equations, the pose step
+and the offset step in each operand form.  Its pose and surface are then
+compared with the oracle's: largest joint-angle error (rad), root
+translation error (m) and vertex error (m, both surfaces skinned in float64).
+Bar for every form: 1e-4 rad and 0.1 mm.  Whole frames on the GPU's own
+association (five iterations from the oracle's state at the frame's start)
+are printed beside it for information: there a weakly observed joint can
+amplify a near-tie flip (bounded by the end-to-end parity test).
 """
 import sys
 
@@ -21,8 +25,7 @@ from paper_1711_07999_amd import synth
 pytestmark = pytest.mark.gpu
 
 MODES = {"fp32": (0, 0), "fp32+fp64 solves": (0, 1), "bf16x3+fp64 solves": (1, 1), "bf16x6+fp64 solves": (2, 1)}
-FLOOR = {(0, 0): (2e-3, 2e-3), (0, 1): (2e-3, 2e-3), (1, 1): (2e-2, 5e-3), (2, 1): (2e-3, 2e-3)}
-PERTURB, GAIN = 1e-6, 10.0
+BAR_ANG, BAR_LIN = 1e-4, 1e-4
 
 
 def _say(msg):
@@ -39,7 +42,7 @@ def T():
     return track
 
 
-def _oracle_frame(m, cam, prm, th, phi, depth):
+def _oracle(m, cam, prm, th, phi, depth):
     th, phi = th.copy(), phi.copy()
     oracle.track_frame(m, cam, prm, th, phi, phi.copy(), depth=depth)
     v, _ = oracle.skin(m, th, phi)
@@ -49,43 +52,65 @@ def _oracle_frame(m, cam, prm, th, phi, depth):
 def test_precision_forms_against_the_float64_oracle(T):
     w = synth.workload_human(n_frames=10)
     m, cam = w.body.model, w.body.camera
-    V, P = m["rest_xyz"].shape[0], len(w.theta0)
+    V = m["rest_xyz"].shape[0]
     ang = w.body.angular
-    trackers = {name: T.Tracker(m, cam, dict(w.params, gram_mode=g, pose_solve_fp64=f, shape_solve_fp64=f),
-                                w.theta0) for name, (g, f) in MODES.items()}
-    th_or, phi_or = w.theta0.copy(), np.zeros((V, 3))
-    rows, failures = [], []
+    one = dict(w.params, n_iters=1, do_pose=np.ones(1, np.uint8), do_shape=np.ones(1, np.uint8))
+    trk = {name: T.Tracker(m, cam, dict(one, gram_mode=g, pose_solve_fp64=f, shape_solve_fp64=f), w.theta0)
+           for name, (g, f) in MODES.items()}
+    err_it = {name: [] for name in MODES}
+    err_fr = {name: [] for name in MODES}
+    th_f, phi_f = w.theta0.copy(), np.zeros((V, 3))
     try:
-        _say("frame | oracle sensitivity (rad, m) | " + " | ".join(f"{k}: joint rad, root m, vertex m" for k in MODES))
         for f in range(len(w.frames)):
-            phi_or = phi_or.astype(np.float32).astype(np.float64)
-            prm = dict(w.params)
-            th1, phi1, v1 = _oracle_frame(m, cam, prm, th_or, phi_or, w.frames[f])
-            th2, _, v2 = _oracle_frame(m, cam, prm, th_or + PERTURB * np.random.default_rng(f).standard_normal(P),
-                                       phi_or, w.frames[f])
-            s_ang, s_v = np.abs(th2 - th1)[ang].max(), np.abs(v2 - v1).max()
-            cells = []
+            depth = w.frames[f]
+            # whole frame, for information
+            th5, phi5, v5 = _oracle(m, cam, dict(w.params), th_f, phi_f, depth)
             for name, (g, fp) in MODES.items():
-                trk = trackers[name]
-                trk.reset(th_or, phi_or.astype(np.float32))
-                assert trk.frame(w.frames[f]) == 0, T.track_last_error()
-                th_g, _, v_g, _ = trk.state()
-                e = (np.abs(th_g - th1)[ang].max(), np.abs(th_g - th1)[~ang].max(), np.abs(v_g - v1).max())
-                cells.append(e)
-                f_ang, f_lin = FLOOR[(g, fp)]
-                if not (e[0] <= max(f_ang, GAIN * s_ang) and e[2] <= max(f_lin, GAIN * s_v)):
-                    failures.append((f, name))
-            rows.append((s_ang, s_v, cells))
-            _say(f"{f:5d} | {s_ang:.1e}, {s_v:.1e} | " +
-                 " | ".join(f"{a:.1e}, {b:.1e}, {c:.1e}" for a, b, c in cells))
-            th_or, phi_or = th1, phi1
+                trk[name].set_params(dict(w.params, gram_mode=g, pose_solve_fp64=fp, shape_solve_fp64=fp))
+                trk[name].reset(th_f, phi_f.astype(np.float32))
+                assert trk[name].frame(depth) == 0, T.track_last_error()
+                th_g, _, v_g, _ = trk[name].state()
+                err_fr[name].append((np.abs(th_g - th5)[ang].max(), np.abs(v_g - v5).max()))
+                trk[name].set_params(dict(one, gram_mode=g, pose_solve_fp64=fp, shape_solve_fp64=fp))
+            # iteration by iteration from the oracle's state and association
+            th_i, phi_i = th_f.copy(), phi_f.copy()
+            P = len(th_i)
+            for it in range(int(w.params["n_iters"])):
+                phi_i = phi_i.astype(np.float32).astype(np.float64)
+                v, _ = oracle.skin(m, th_i, phi_i)
+                v32 = v.astype(np.float32)
+                n32 = oracle.normals(m, v32.astype(np.float64)).astype(np.float32)
+                a = oracle.associate(cam, one["tau"], v32, depth=depth)
+                cnt, delta = oracle.average(cam, a, v32.astype(np.float64), depth=depth)
+                th1, phi1, v1 = _oracle(m, cam, one, th_i, phi_i, depth)
+                for name in MODES:
+                    ctx = trk[name].ctx
+                    for buf, arr in ((T.TRACK_BUF_THETA, th_i), (T.TRACK_BUF_PHI, phi_i.astype(np.float32)),
+                                     (T.TRACK_BUF_PHI_PREV, phi_i.astype(np.float32)), (T.TRACK_BUF_VERTS, v32),
+                                     (T.TRACK_BUF_NORMALS, n32), (T.TRACK_BUF_COUNT, cnt.astype(np.int32)),
+                                     (T.TRACK_BUF_DELTA, delta.astype(np.float32))):
+                        T.track_dbg_set(ctx, buf, arr)
+                    for pas in (T.TRACK_PASS_NORMAL_EQ, T.TRACK_PASS_POSE_STEP, T.TRACK_PASS_SHAPE):
+                        assert T.track_dbg_run(ctx, pas) == 0, T.track_last_error()
+                    th_g = T.track_dbg_get(ctx, T.TRACK_BUF_THETA, (P,), np.float64)
+                    phi_g = T.track_dbg_get(ctx, T.TRACK_BUF_PHI, (V, 3), np.float32)
+                    v_g, _ = oracle.skin(m, th_g, phi_g.astype(np.float64))
+                    d = np.abs(th_g - th1)
+                    err_it[name].append((d[ang].max(), d[~ang].max(), np.abs(v_g - v1).max()))
+                th_i, phi_i = th1, phi1
+            th_f, phi_f = th5, phi5.astype(np.float32).astype(np.float64)
     finally:
-        for trk in trackers.values():
-            trk.close()
-    for q, name in enumerate(MODES):
-        ea = np.array([r[2][q][0] for r in rows])
-        ev = np.array([r[2][q][2] for r in rows])
-        ok = np.mean((ea <= 1e-4) & (ev <= 1e-4))
-        _say(f"{name:20s} joint rad median {np.median(ea):.1e} max {ea.max():.1e}; vertex m median "
-             f"{np.median(ev):.1e} max {ev.max():.1e}; frames within 1e-4 rad and 0.1 mm: {ok:.0%}")
-    assert not failures, failures
+        for t in trk.values():
+            t.close()
+    _say("operand form        | per iteration: joint rad (median / max), root m (max), vertex m (median / max)"
+         " | whole frame: joint rad (median / max), vertex m (median / max)")
+    bad = []
+    for name in MODES:
+        e = np.array(err_it[name])
+        fr = np.array(err_fr[name])
+        _say(f"{name:20s}| {np.median(e[:, 0]):.1e} / {e[:, 0].max():.1e}, {e[:, 1].max():.1e}, "
+             f"{np.median(e[:, 2]):.1e} / {e[:, 2].max():.1e} | {np.median(fr[:, 0]):.1e} / {fr[:, 0].max():.1e}, "
+             f"{np.median(fr[:, 1]):.1e} / {fr[:, 1].max():.1e}")
+        if not (e[:, 0].max() <= BAR_ANG and e[:, 1].max() <= BAR_LIN and e[:, 2].max() <= BAR_LIN):
+            bad.append(name)
+    assert not bad, bad
