@@ -285,9 +285,11 @@ __global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, in
     }
 }
 
+// one chunk per workgroup up to 512 workgroups (two per CU fit with the LDS
+// of a 75-joint body); larger meshes loop over chunks
 int ne_grid(int V) {
     int nchunks = (V + kNeRows - 1) / kNeRows;
-    return nchunks < 256 ? nchunks : 256;
+    return nchunks < 512 ? nchunks : 512;
 }
 
 constexpr size_t kSmallLds = 64 * 1024;

@@ -177,6 +177,7 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter, int nmax)
                 else a1[j] = a1[j + 1] = a1[j + 2] = a1[j + 3] = T(0);
                 load4(M + n * ld + c0 + j, ab + j);
             }
+            const bool two = c0 + 64 < n;   // the second row set holds rows
             bool ok = true;
 #pragma unroll
             for (int j = 0; j < kPanel; ++j) {
@@ -190,12 +191,21 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter, int nmax)
                 a1[j] *= inv;
                 ab[j] *= inv;
                 if (lane == 0) sdinv[c0 + j] = inv;
+                if (two) {
 #pragma unroll
-                for (int c = j + 1; c < kPanel; ++c) {
-                    const T lcj = lane_bcast(lj, c);
-                    a0[c] -= lj * lcj;
-                    a1[c] -= a1[j] * lcj;
-                    ab[c] -= ab[j] * lcj;
+                    for (int c = j + 1; c < kPanel; ++c) {
+                        const T lcj = lane_bcast(lj, c);
+                        a0[c] -= lj * lcj;
+                        a1[c] -= a1[j] * lcj;
+                        ab[c] -= ab[j] * lcj;
+                    }
+                } else {
+#pragma unroll
+                    for (int c = j + 1; c < kPanel; ++c) {
+                        const T lcj = lane_bcast(lj, c);
+                        a0[c] -= lj * lcj;
+                        ab[c] -= ab[j] * lcj;
+                    }
                 }
             }
 #pragma unroll
