@@ -275,9 +275,12 @@ int track_dbg_get(const track_ctx *ctx, int32_t buf, void *host, size_t bytes);
 int track_dbg_run(track_ctx *ctx, int32_t pass);
 
 /* ------------------------------------------------------------------------
- * Kernel timing: when enabled, every launch of the named kernel is bracketed
- * by HIP events on the context's stream; track_kernel_time returns the
- * number of timed launches and their summed duration since the last reset.
+ * Kernel timing: when enabled, every launch of the named pass is timed by a
+ * pair of HIP events that its first and last kernels stamp from their own
+ * dispatch packets on the context's stream (the kernels' execution span);
+ * while any timer is on, launches are issued directly, not from graphs.
+ * track_kernel_time returns the number of timed launches and their summed
+ * duration since the last reset.
  * ---------------------------------------------------------------------- */
 enum {
     TRACK_K_SKIN = 0,
@@ -291,6 +294,17 @@ enum {
 };
 int track_kernel_timing(track_ctx *ctx, int32_t kernel, int32_t enable);
 int track_kernel_time(track_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
+
+/* Mean duration of one launch of a pass, from `reps` back-to-back launches on
+ * the context's stream between a single pair of HIP events (so the events'
+ * own cost is spread over the launches).  Only passes whose repeated launches
+ * redo the same work: TRACK_K_SKIN, TRACK_K_ASSOC (reads `depth`, the device
+ * image of the last tracked frame, and the buckets that frame left),
+ * TRACK_K_NORMAL_EQ (after one association of `depth`) and TRACK_K_SOLVE (the
+ * last Gram matrix); other ids give TRACK_E_INVALID, as does an untracked
+ * context for the two passes that read `depth`.  reps in 1..100000.  The
+ * tracked state is consumed: reset it (track_reset) before tracking again. */
+int track_kernel_bench(track_ctx *ctx, int32_t kernel, const float *depth, int32_t reps, double *ms_per_launch);
 
 #ifdef __cplusplus
 }

@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(256) k_clear(Batch B) {
 }
 
 void launch_clear(const Launch& L) {
-    hipLaunchKernelGGL(k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.s, L.B);
+    launch_kernel(L, true, true, k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B);
 }
 
 __global__ void __launch_bounds__(256) k_clear_acc(Batch B) {
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_clear_acc(Batch B) {
 }
 
 void launch_clear_acc(const Launch& L) {
-    hipLaunchKernelGGL(k_clear_acc, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B);
+    launch_kernel(L, true, true, k_clear_acc, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B);
 }
 
 // ---------------------------------------------------------------------------
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int whi
 }
 
 void launch_bucket_count(const Launch& L, int vsel, int which) {
-    hipLaunchKernelGGL(k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel, which);
+    launch_kernel(L, true, true, k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel, which);
 }
 
 // exclusive prefix over tiles, one workgroup of 1024 threads; the tile sums
@@ -188,9 +188,9 @@ __global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
 }
 
 void launch_bucket(const Launch& L, int vsel) {
-    hipLaunchKernelGGL(k_tile_scan, dim3(L.grid[KK_ONE]), dim3(1024), 0, L.s, L.B);
-    hipLaunchKernelGGL(k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.s, L.B);
-    hipLaunchKernelGGL(k_scatter_normals, dim3(L.grid[KK_VERT2]), dim3(256), 0, L.s, L.B, vsel);
+    launch_kernel(L, true, false, k_tile_scan, dim3(L.grid[KK_ONE]), dim3(1024), 0, L.B);
+    launch_kernel(L, false, false, k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.B);
+    launch_kernel(L, false, true, k_scatter_normals, dim3(L.grid[KK_VERT2]), dim3(256), 0, L.B, vsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +396,7 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
 }
 
 void launch_associate(const Launch& L, int vsel) {
-    hipLaunchKernelGGL(k_associate, dim3(L.grid[KK_TILE]), dim3(256), 0, L.s, L.B, vsel);
+    launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_TILE]), dim3(256), 0, L.B, vsel);
 }
 
 }  // namespace trk

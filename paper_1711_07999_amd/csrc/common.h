@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP translation units of libtrack.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 
 namespace trk {
@@ -166,7 +167,20 @@ struct Launch {
     hipStream_t s;
     const Slot* stage_src;   // the window in pinned memory (device view)
     const int* stage_pre;
+    // a timed pass: its first kernel stamps t_start and its last kernel
+    // t_stop with the kernels' own dispatch timestamps
+    hipEvent_t t_start = nullptr, t_stop = nullptr;
 };
+
+// Launch `kernel` on L's stream; `first` / `last` mark the kernel's place in
+// its pass, so a timed pass's events go to the dispatch packets themselves.
+template <typename F, typename... Args>
+inline void launch_kernel(const Launch& L, bool first, bool last, F kernel, dim3 grid, dim3 block, uint32_t lds,
+                          Args... args) {
+    hipEvent_t e0 = first ? L.t_start : nullptr, e1 = last ? L.t_stop : nullptr;
+    if (e0 || e1) hipExtLaunchKernelGGL(kernel, grid, block, lds, L.s, e0, e1, 0u, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, lds, L.s, args...);
+}
 
 // slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
 __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& local) {

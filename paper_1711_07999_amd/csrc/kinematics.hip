@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(128) k_frame_begin(Batch B) {
 }
 
 void launch_frame_begin(const Launch& L) {
-    hipLaunchKernelGGL(k_frame_begin, dim3(L.grid[KK_ONE]), dim3(128), 0, L.s, L.B);
+    launch_kernel(L, true, true, k_frame_begin, dim3(L.grid[KK_ONE]), dim3(128), 0, L.B);
 }
 
 __global__ void __launch_bounds__(128) k_fk(Batch B) {
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(128) k_fk(Batch B) {
 }
 
 void launch_fk(const Launch& L) {
-    hipLaunchKernelGGL(k_fk, dim3(L.grid[KK_ONE]), dim3(128), 0, L.s, L.B);
+    launch_kernel(L, true, true, k_fk, dim3(L.grid[KK_ONE]), dim3(128), 0, L.B);
 }
 
 // ---------------------------------------------------------------------------
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
 }
 
 void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
-    hipLaunchKernelGGL(k_skin, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel, pn, which, count, clear_acc);
+    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel, pn, which, count, clear_acc);
 }
 
 // Vertex normals (one lane per vertex; see vertex_normal)
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(256) k_normals(Batch B, int vsel) {
 }
 
 void launch_normals(const Launch& L, int vsel) {
-    hipLaunchKernelGGL(k_normals, dim3(L.grid[KK_VERT]), dim3(256), 0, L.s, L.B, vsel);
+    launch_kernel(L, true, true, k_normals, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int 
 }
 
 void launch_frame_end(const Launch& L, int first_pose, int last_pose) {
-    hipLaunchKernelGGL(k_frame_end, dim3(L.grid[KK_ONE]), dim3(256), 0, L.s, L.B, first_pose, last_pose);
+    launch_kernel(L, true, true, k_frame_end, dim3(L.grid[KK_ONE]), dim3(256), 0, L.B, first_pose, last_pose);
 }
 
 }  // namespace trk

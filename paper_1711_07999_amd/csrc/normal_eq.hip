@@ -314,9 +314,9 @@ void launch_normal_eq_t(const Launch& L, int vsel, int pn) {
     const int pp = L.ne_pp, lm = L.ne_l;
     const size_t bytes = ne_lds_bytes<MODE>(pp, lm);
     if (bytes <= kSmallLds)
-        hipLaunchKernelGGL((k_normal_eq<MODE, false>), g, dim3(256), bytes, L.s, L.B, vsel, pn, pp, lm);
+        launch_kernel(L, true, true, k_normal_eq<MODE, false>, g, dim3(256), bytes, L.B, vsel, pn, pp, lm);
     else
-        hipLaunchKernelGGL((k_normal_eq<MODE, true>), g, dim3(256), bytes, L.s, L.B, vsel, pn, pp, lm);
+        launch_kernel(L, true, true, k_normal_eq<MODE, true>, g, dim3(256), bytes, L.B, vsel, pn, pp, lm);
 }
 
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
 }
 
 void launch_gram_reduce(const Launch& L) {
-    hipLaunchKernelGGL(k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(256), 0, L.s, L.B);
+    launch_kernel(L, true, true, k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(256), 0, L.B);
 }
 
 }  // namespace trk

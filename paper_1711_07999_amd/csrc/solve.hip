@@ -288,9 +288,9 @@ void launch_pose_solve_t(const Launch& L, int iter) {
     const int n = L.solve_n;
     const size_t bytes = solve_lds_bytes<T>(n);
     if (bytes <= kSmallLds)
-        hipLaunchKernelGGL((k_pose_solve<T, false>), dim3(L.grid[KK_ONE]), dim3(256), bytes, L.s, L.B, iter, n);
+        launch_kernel(L, true, true, k_pose_solve<T, false>, dim3(L.grid[KK_ONE]), dim3(256), bytes, L.B, iter, n);
     else
-        hipLaunchKernelGGL((k_pose_solve<T, true>), dim3(L.grid[KK_ONE]), dim3(256), bytes, L.s, L.B, iter, n);
+        launch_kernel(L, true, true, k_pose_solve<T, true>, dim3(L.grid[KK_ONE]), dim3(256), bytes, L.B, iter, n);
 }
 
 void launch_pose_solve(const Launch& L, int fp64, int iter) {
@@ -406,9 +406,9 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
 void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next) {
     const dim3 g(L.grid[KK_VERT]);
     if (fp64)
-        hipLaunchKernelGGL(k_shape<double>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn, next);
+        launch_kernel(L, true, true, k_shape<double>, g, dim3(256), 0, L.B, v_old, v_new, pn, next);
     else
-        hipLaunchKernelGGL(k_shape<float>, g, dim3(256), 0, L.s, L.B, v_old, v_new, pn, next);
+        launch_kernel(L, true, true, k_shape<float>, g, dim3(256), 0, L.B, v_old, v_new, pn, next);
 }
 
 }  // namespace trk

@@ -204,6 +204,7 @@ struct Stream {
     int v_cur = 0, phi_cur = 0, phi_prev = 0;
     bool surface_valid = false, refresh_pose = true;
     bool dirty = true;             // buckets / accumulators not known to be clear
+    bool buckets_ready = false;    // the buckets hold a cleared or filled index
     int input_mode = 0;            // per-pass interface: 0 depth, 1 xyz
 };
 
@@ -595,25 +596,31 @@ bool timing_on(const Runner& R) {
     return false;
 }
 
-// Kernel timing brackets launches with HIP events; launches are then issued
-// directly (never from a graph) so that every bracket is a recorded pair.
-void timed_begin(Runner& R, int k) {
+// Kernel timing: a timed pass carries a pair of HIP events that its first and
+// last kernels stamp from their own dispatch packets (so the pair spans the
+// kernels' execution, not the queue's gaps); launches are then issued
+// directly (never from a graph) so that every pair is recorded.
+Launch timed(Runner& R, int k, const Launch& L) {
     KernelTimer& t = R.timers[k];
-    if (!t.on) return;
+    Launch T = L;
+    if (!t.on) return T;
     if (t.used + 2 > t.ev.size()) {
         for (int q = 0; q < 64; ++q) {
             hipEvent_t e;
-            if (hipEventCreate(&e) == hipSuccess) t.ev.push_back(e);
+            // no system-scope fence at the stamps: the pair then times the
+            // kernels alone, as a profiler's dispatch trace does
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess) t.ev.push_back(e);
         }
     }
-    if (t.used + 2 <= t.ev.size()) (void)hipEventRecord(t.ev[t.used], R.s);
+    if (t.used + 2 <= t.ev.size()) {
+        T.t_start = t.ev[t.used];
+        T.t_stop = t.ev[t.used + 1];
+    }
+    return T;
 }
 
-void timed_end(Runner& R, int k) {
-    KernelTimer& t = R.timers[k];
-    if (!t.on || t.used + 2 > t.ev.size()) return;
-    (void)hipEventRecord(t.ev[t.used + 1], R.s);
-    t.used += 2;
+void timed_done(Runner& R, int k, const Launch& T) {
+    if (T.t_start) R.timers[k].used += 2;
 }
 
 // after a stream synchronisation: fold the recorded pairs into totals
@@ -692,31 +699,37 @@ struct SurfaceState {
 };
 
 void enqueue_associate(Runner& R, const Launch& L, int vsel) {
-    timed_begin(R, TRACK_K_BUCKET);
-    launch_bucket(L, vsel);
-    timed_end(R, TRACK_K_BUCKET);
-    timed_begin(R, TRACK_K_ASSOC);
-    launch_associate(L, vsel);
-    timed_end(R, TRACK_K_ASSOC);
+    {
+        const Launch T = timed(R, TRACK_K_BUCKET, L);
+        launch_bucket(T, vsel);
+        timed_done(R, TRACK_K_BUCKET, T);
+    }
+    {
+        const Launch T = timed(R, TRACK_K_ASSOC, L);
+        launch_associate(T, vsel);
+        timed_done(R, TRACK_K_ASSOC, T);
+    }
 }
 
 void enqueue_normal_eq(Runner& R, const Launch& L, int gram_mode, int vsel, int pn) {
-    timed_begin(R, TRACK_K_NORMAL_EQ);
-    launch_normal_eq(L, gram_mode, vsel, pn);
-    timed_end(R, TRACK_K_NORMAL_EQ);
+    {
+        const Launch T = timed(R, TRACK_K_NORMAL_EQ, L);
+        launch_normal_eq(T, gram_mode, vsel, pn);
+        timed_done(R, TRACK_K_NORMAL_EQ, T);
+    }
     launch_gram_reduce(L);
 }
 
 void enqueue_pose_step(Runner& R, const Launch& L, int fp64, int iter) {
-    timed_begin(R, TRACK_K_SOLVE);
-    launch_pose_solve(L, fp64, iter);
-    timed_end(R, TRACK_K_SOLVE);
+    const Launch T = timed(R, TRACK_K_SOLVE, L);
+    launch_pose_solve(T, fp64, iter);
+    timed_done(R, TRACK_K_SOLVE, T);
 }
 
 void enqueue_skin(Runner& R, const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
-    timed_begin(R, TRACK_K_SKIN);
-    launch_skin(L, vsel, pn, which, count, clear_acc);
-    timed_end(R, TRACK_K_SKIN);
+    const Launch T = timed(R, TRACK_K_SKIN, L);
+    launch_skin(T, vsel, pn, which, count, clear_acc);
+    timed_done(R, TRACK_K_SKIN, T);
 }
 
 // One iteration; `iter` is added to each slot's own iteration index.
@@ -748,9 +761,9 @@ void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool s
             if (issue) enqueue_skin(R, L, vn, st.pn, SEL_ALL, SEL_NONE, 0);
         }
         if (issue) {
-            timed_begin(R, TRACK_K_SHAPE);
-            launch_shape(L, sc.shape_fp64, st.vsel, vn, st.pn, next);
-            timed_end(R, TRACK_K_SHAPE);
+            const Launch T = timed(R, TRACK_K_SHAPE, L);
+            launch_shape(T, sc.shape_fp64, st.vsel, vn, st.pn, next);
+            timed_done(R, TRACK_K_SHAPE, T);
         }
         st.pn += 1;
         st.vsel = more ? vn ^ 1 : vn;
@@ -929,6 +942,7 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
         launch_clear(stage_one(c, 0, nullptr, nullptr));
         HIP_TRY(hipStreamSynchronize(R.s));  // before the table window is rewritten
         s.dirty = false;
+        s.buckets_ready = true;
     }
     TableEntry e{&s, flags, 0, depth, xyz};
     Launch L = stage_table(R, 0, &e, 1);
@@ -1072,6 +1086,7 @@ int server_admit(track_server* sv) {
         launch_clear(Lc);
         HIP_TRY(hipStreamSynchronize(sv->run.s));
         d->dirty = false;
+        d->buckets_ready = true;
     }
     return TRACK_OK;
 }
@@ -1187,6 +1202,44 @@ int track_kernel_time(track_ctx* c, int32_t k, int64_t* launches, double* total_
     timed_collect(c->run);
     if (launches) *launches = c->run.timers[k].launches;
     if (total_ms) *total_ms = c->run.timers[k].total_ms;
+    return TRACK_OK;
+}
+
+int track_kernel_bench(track_ctx* c, int32_t k, const float* depth, int32_t reps, double* ms_per_launch) {
+    if (!c || !ms_per_launch) return fail(TRACK_E_INVALID, "ctx/ms_per_launch is NULL");
+    if (reps < 1 || reps > 100000) return fail(TRACK_E_INVALID, "reps must be in 1..100000");
+    if (k != TRACK_K_SKIN && k != TRACK_K_ASSOC && k != TRACK_K_NORMAL_EQ && k != TRACK_K_SOLVE)
+        return fail(TRACK_E_INVALID, "kernel cannot be repeated with the same work");
+    if (k == TRACK_K_ASSOC || k == TRACK_K_NORMAL_EQ) {
+        if (!depth) return fail(TRACK_E_INVALID, "depth is NULL");
+        if (!c->st.buckets_ready) return fail(TRACK_E_INVALID, "no tracked frame to repeat");
+    }
+    Stream& s = c->st;
+    Runner& R = c->run;
+    HIP_TRY(hipStreamSynchronize(R.s));
+    Launch L = stage_one(c, 0, depth, nullptr);
+    if (k == TRACK_K_NORMAL_EQ) {  // one association, as inside a frame
+        launch_clear_acc(L);
+        launch_associate(L, 0);
+    }
+    HIP_TRY(hipEventRecord(R.f0, R.s));
+    for (int r = 0; r < reps; ++r) {
+        switch (k) {
+            case TRACK_K_SKIN: launch_skin(L, 0, 0, SEL_ALL, SEL_NONE, 0); break;
+            case TRACK_K_ASSOC: launch_associate(L, 0); break;
+            case TRACK_K_NORMAL_EQ: launch_normal_eq(L, c->sched.gram_mode, 0, 0); break;
+            default: launch_pose_solve(L, c->sched.pose_fp64, 0); break;
+        }
+    }
+    HIP_TRY(hipEventRecord(R.f1, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, R.f0, R.f1));
+    *ms_per_launch = (double)ms / reps;
+    // the repeated passes leave partial sums, a moved pose and the like behind
+    s.dirty = true;
+    s.surface_valid = false;
+    s.refresh_pose = true;
     return TRACK_OK;
 }
 
@@ -1351,6 +1404,7 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
             launch_clear(L);
             launch_bucket_count(L, 0, SEL_ALL);
             enqueue_associate(R, L, 0);
+            s.buckets_ready = true;
             break;
         }
         case TRACK_PASS_NORMAL_EQ: {
@@ -1370,9 +1424,11 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
             Launch L = stage_one(c, 0, depth, xyz);
             launch_fk(L);
             enqueue_skin(R, L, 1, 0, SEL_ALL, SEL_NONE, 0);
-            timed_begin(R, TRACK_K_SHAPE);
-            launch_shape(L, c->sched.shape_fp64, 0, 1, 0, SEL_NONE);
-            timed_end(R, TRACK_K_SHAPE);
+            {
+                const Launch T = timed(R, TRACK_K_SHAPE, L);
+                launch_shape(T, c->sched.shape_fp64, 0, 1, 0, SEL_NONE);
+                timed_done(R, TRACK_K_SHAPE, T);
+            }
             s.v_cur ^= 1;
             s.phi_cur = phi_next(s.phi_cur, s.phi_prev);
             s.surface_valid = false;

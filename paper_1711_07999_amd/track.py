@@ -32,7 +32,7 @@ KERNEL_NAMES = ["skin", "normals", "bucket", "assoc", "normal_eq", "solve", "sha
 EXPORTED = [
     "track_init", "track_frame", "track_frame_xyz", "track_state", "track_reset",
     "track_set_params", "track_destroy", "track_last_error", "track_dbg_set",
-    "track_dbg_get", "track_dbg_run", "track_kernel_timing", "track_kernel_time",
+    "track_dbg_get", "track_dbg_run", "track_kernel_timing", "track_kernel_time", "track_kernel_bench",
     "track_server_create", "track_server_open", "track_server_submit", "track_server_step",
     "track_server_poll", "track_server_state", "track_server_close", "track_server_info",
     "track_server_destroy",
@@ -121,6 +121,7 @@ def lib():
             "track_dbg_run": [vp, i32],
             "track_kernel_timing": [vp, i32, i32],
             "track_kernel_time": [vp, i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+            "track_kernel_bench": [vp, i32, vp, i32, ctypes.POINTER(ctypes.c_double)],
             "track_server_create": [vp, ctypes.c_int64, i32, vp, ctypes.POINTER(vp)],
             "track_server_open": [vp, vp, vp, vp, vp, ctypes.POINTER(i32)],
             "track_server_submit": [vp, i32, vp, i32, ctypes.c_int64],
@@ -311,6 +312,19 @@ def track_kernel_time(ctx, kernel: int):
     ms = ctypes.c_double(0.0)
     _check(lib().track_kernel_time(ctx, int(kernel), ctypes.byref(n), ctypes.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def track_kernel_bench(ctx, kernel: int, depth, reps: int) -> float:
+    """Mean ms of one launch of `kernel` over `reps` back-to-back launches;
+    `depth` is a device tensor (or None for passes that read no image)."""
+    ms = ctypes.c_double(0.0)
+    ptr = None
+    if depth is not None:
+        if not (hasattr(depth, "is_cuda") and depth.is_cuda and depth.is_contiguous()):
+            raise ValueError("depth must be a contiguous device tensor")
+        ptr = ctypes.c_void_p(depth.data_ptr())
+    _check(lib().track_kernel_bench(ctx, int(kernel), ptr, int(reps), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 class Tracker:
