@@ -28,6 +28,49 @@ struct JointTable {
     int rounds;                        // ceil(log2(longest joint chain))
 };
 
+// Tree-ordered factorisation of the pose system (built on the host from the
+// skeleton and the skin weights, read by the pose-solve kernel).  Joints are
+// eliminated children first; chains of the elimination tree form supernodes,
+// each with a dense front: its pivot rows, the later rows they touch, and the
+// right-hand side as a last row, stored row-major with `fw` columns.
+constexpr int kFrontRows = 32;       // rows of a front, right-hand side included
+constexpr int kSolveWaves = 8;       // waves of the tree-form pose-solve workgroup
+constexpr int kSolveThreads = 64 * kSolveWaves;
+constexpr int kFrontWords = 8;       // words of a front record in the blob
+
+// A front record: storage offset, pivots, rows (without the right-hand
+// side), row width, first assembly word and number of 64-entry assembly
+// rounds, byte offset of its row-to-joint map in the blob.
+struct FrontRec { int off, np, f, fw, amap0, nround, row0, pad; };
+
+// What the kernels read of a stream's tree plan (in its slot, so that no
+// read waits on another).
+struct TreeRef {
+    const uint2* entry;              // set-up entries (TreePlan::entry)
+    const uint32_t* blob;            // TreePlan::blob
+    double* gfront;                  // [nentry] the entries' Gram values, written by the Gram reduction
+    const int* gfmap;                // [PP*PP] Gram position -> entry, -1 none; null: dense form
+    int nentry, nwords, nlev, elems, o_sched, o_front;
+};
+
+struct alignas(16) TreePlan {
+    int ok;                          // the tree form applies to this model
+    int nsn, nlev, elems;            // supernodes, levels, front storage (elements)
+    int nentry;                      // set-up entries
+    int nwords;                      // words of `blob`
+    int o_sched, o_front;            // word offsets of the schedule and the front records
+    // set-up entries: x = Gram offset | row << 14 | col << 21 (col 127: the
+    // right-hand side), y = storage index in the fronts
+    const uint2* entry;
+    // what the kernel copies to LDS: per level and wave the first schedule
+    // entry (wstart, kSolveWaves * nlev + 1 words), the schedule, the front
+    // records, the assembly rounds (per parent, 64 entries a round: child
+    // storage index | parent storage index << 16, 0xFFFF = none; a parent
+    // entry appears at most once per round, children's shares in child
+    // order), then the row maps (bytes)
+    const uint32_t* blob;
+};
+
 // Mesh, weights and tables in structure-of-arrays device form.
 struct DevModel {
     int P, L, V, F;
@@ -103,6 +146,7 @@ struct alignas(16) Slot {
     DevModel m;
     DevCam c;
     const JointTable* jt;
+    TreeRef tree;                 // tree form of the pose solve
     const uint32_t* anc;          // [L*4] joints on each link's chain
     Buckets b;
     Accum a;
@@ -163,6 +207,8 @@ struct Launch {
     Batch B;
     int grid[KK_COUNT_];
     int solve_n;        // largest padded pose-system size of the batch
+    int solve_elems;    // largest tree-form front storage of the batch; 0: dense form
+    int solve_words;    // largest tree-form plan blob of the batch
     int ne_pp, ne_l;    // largest padded Gram size and link count of the batch
     hipStream_t s;
     const Slot* stage_src;   // the window in pinned memory (device view)
@@ -239,6 +285,7 @@ void launch_associate(const Launch& L, int vsel);
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
 void launch_gram_reduce(const Launch& L);
 void launch_pose_solve(const Launch& L, int fp64, int iter);
+bool tree_solve_fits(int elems, int words);   // the tree form's LDS fits the kernel in both precisions
 bool prepare_pose_solve();   // once per process, before the first launch
 bool prepare_normal_eq();    // likewise
 // offset step from v_old / v_new (normals of v_new formed in place); the

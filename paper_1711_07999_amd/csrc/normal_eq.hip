@@ -361,10 +361,12 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
     part[grp][threadIdx.x & 31] = s;
     __syncthreads();
     if (grp == 0 && i <= j) {
+        const int fe = S.tree.gfmap ? S.tree.gfmap[i * PP + j] : -1;
         double tot = 0.0;
         for (int g = 0; g < 8; ++g) tot += part[g][threadIdx.x & 31];
         gram[i * PP + j] = tot;
         gram[j * PP + i] = tot;
+        if (fe >= 0) S.tree.gfront[fe] = tot;   // the pose solve's tree form reads it in entry order
     }
 }
 

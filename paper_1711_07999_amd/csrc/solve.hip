@@ -63,6 +63,16 @@ __device__ __forceinline__ double lane_bcast(double v, int lane) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ __forceinline__ void store4(float* p, const float* v) {
+    *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ __forceinline__ void store4(double* p, const double* v) {
+    *reinterpret_cast<double2*>(p) = make_double2(v[0], v[1]);
+    *reinterpret_cast<double2*>(p + 2) = make_double2(v[2], v[3]);
+}
+
+constexpr size_t kSmallLds = 64 * 1024;
+
 // BIG: an instance allowed more than 64 KB of LDS (P > 112 in float64); a
 // kernel allowed that much is launched more slowly, so sizes below use the
 // other instance
@@ -269,7 +279,234 @@ __global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter, int nmax)
     fk_block(jt, P, S.m.L, theta, S.dq, S.xi, fk_ws);
 }
 
-constexpr size_t kSmallLds = 64 * 1024;
+// ---------------------------------------------------------------------------
+// Tree form of the same solve.  J_ik vanishes unless joint k lies on the
+// chain of a link weighting vertex i (Section 4.2), so A_kj vanishes unless
+// some vertex's chains hold both joints: limbs do not touch each other, only
+// their common ancestors.  Eliminated children first, the factor stays
+// inside that pattern and its elimination tree follows the skeleton (the
+// host plan, TreePlan).  Each supernode -- a chain of the elimination tree --
+// owns a dense front: its pivot rows, the later rows they touch, and the
+// right-hand side as one more row.  Level by level, each wave takes its
+// supernodes: it adds the children's update blocks to the front, loads one
+// front row per lane into registers, factors the pivots with lane
+// broadcasts (the right-hand-side row turns into y on the way, the rest of
+// the front into the update block for the parent) and stores the front
+// back; 1 / L_jj goes into the front's spare last column.  Back
+// substitution walks the levels downwards.  Only structural zeros are
+// skipped: the arithmetic per entry is that of the dense form.
+// ---------------------------------------------------------------------------
+// Dynamic LDS of the tree form: the fronts (reused for forward kinematics),
+// a copy of the plan, x, the damped diagonal, the right-hand side, flags.
+template <class T>
+__host__ __device__ inline size_t tree_front_bytes(int elems) {
+    size_t mat = sizeof(T) * (size_t)elems;
+    if (mat < sizeof(FkScratch)) mat = sizeof(FkScratch);
+    return (mat + 15) & ~size_t(15);
+}
+template <class T>
+__host__ __device__ inline size_t tree_lds_bytes(int elems, int words) {
+    return tree_front_bytes<T>(elems) + 16 * (size_t)((words + 3) / 4) + 3 * sizeof(T) * kNMax +
+           sizeof(T) * 64 * kSolveWaves + sizeof(int) * (kNMax + 1);
+}
+
+bool tree_solve_fits(int elems, int words) { return tree_lds_bytes<double>(elems, words) <= kSmallLds; }
+
+// Factor the np pivots of a front of f rows (+ the right-hand-side row f),
+// row-major with FW columns, FW > f.  Lane i holds row i in registers; each
+// pivot's update also shifts the row one column to the left, so the pivot
+// column is always r[0].  The new column of L goes to the wave's buffer
+// `wb`, written shifted so that every lane reads the multipliers of the
+// columns still to come from its start (wide broadcast reads, one lane
+// broadcast per pivot).  Column j of L is stored as it is found, the update
+// block (columns np..f-1 of rows np..f) at the end, and 1 / L_jj into the
+// spare column FW - 1.
+template <class T, int FW>
+__device__ __forceinline__ void tree_factor(T* Fr, T* wb, int np, int f, int lane, bool& ok) {
+    T r[FW];
+    const bool live = lane <= f;
+#pragma unroll
+    for (int c = 0; c < FW; c += 4) {
+        if (live) load4(Fr + lane * FW + c, r + c);
+        else r[c] = r[c + 1] = r[c + 2] = r[c + 3] = T(0);
+    }
+    T myinv = T(0);
+    for (int j = 0; j < np; ++j) {
+        const T d = lane_bcast(r[0], j);
+        ok = ok && (d > T(0));
+        const T inv = ok ? rsqrt_of(d) : T(1);
+        // column j of L below the diagonal (the right-hand-side row: y_j)
+        const T lj = lane > j ? r[0] * inv : T(0);
+        if (lane == j) myinv = inv;
+        if (live && lane >= j) Fr[lane * FW + j] = lane == j ? d * inv : lj;
+        if (lane > j) wb[lane - j - 1] = lj;   // wb[k] = L_{j+1+k, j}; lanes j+1..63 cover k < FW
+        T cv[FW];
+#pragma unroll
+        for (int c = 0; c < FW; c += 4) load4(wb + c, cv + c);
+#pragma unroll
+        for (int c = 1; c < FW; ++c) r[c - 1] = r[c] - lj * cv[c - 1];
+        r[FW - 1] = T(0);
+    }
+    const int nU = f - np;
+#pragma unroll
+    for (int c = 0; c < FW - 1; ++c)
+        if (c < nU && live) Fr[lane * FW + np + c] = r[c];
+    if (lane < np) Fr[lane * FW + FW - 1] = myinv;
+}
+
+// L^T x = y for the front's pivots (row stride fw), given x of its later
+// rows; lane c < np takes pivot c.  `row` maps front rows to joints; `wb`
+// is the wave's buffer.
+template <class T>
+__device__ __forceinline__ void tree_back(const T* Fr, T* wb, int np, int f, int fw, const unsigned char* row,
+                                          T* sx, int lane) {
+    const int nU = f - np;
+    // x of the later rows, broadcast through the wave's buffer
+    if (lane < nU) wb[lane] = sx[row[np + lane]];
+    const int cl = lane < np ? lane : 0;
+    T t = Fr[f * fw + cl];
+    for (int k = 0; k < nU; ++k) t -= Fr[(np + k) * fw + cl] * wb[k];
+    // the pivots' own triangle, last pivot first
+    for (int j = np - 1; j >= 0; --j) {
+        const T dinv = Fr[j * fw + fw - 1];
+        const T lij = Fr[j * fw + cl];
+        const T xj = lane_bcast(t, j) * dinv;
+        t = lane < j ? t - lij * xj : (lane == j ? xj : t);
+    }
+    if (lane < np) sx[row[lane]] = t;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int iter, int elems_max, int words_max) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const size_t mat = tree_front_bytes<T>(elems_max);
+    T* Fs = reinterpret_cast<T*>(smem);
+    FkScratch& fk_ws = *reinterpret_cast<FkScratch*>(smem);
+    uint32_t* lb = reinterpret_cast<uint32_t*>(smem + mat);   // the plan's blob, copied to LDS
+    T* sx = reinterpret_cast<T*>(smem + mat + 16 * (size_t)((words_max + 3) / 4));
+    T* sdiag = sx + kNMax;
+    T* srhs = sdiag + kNMax;
+    int* sfrozen = reinterpret_cast<int*>(srhs + kNMax + 64 * kSolveWaves);
+    int& sfail = sfrozen[kNMax];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
+    const TreeRef& tr = S.tree;
+    const JointTable* __restrict__ jt = S.jt;
+    const int PP = S.PP;
+    const double* __restrict__ gram = S.gram;
+    const float lambda_k = S.lambda_k;
+    double* __restrict__ theta = S.theta;
+    DevStats* st = S.st;
+    const int P = S.m.P;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    T* wb = srhs + kNMax + 64 * wid;   // this wave's broadcast buffer
+
+    // set-up.  Every global read is issued before any is used: the plan's
+    // blob, the entries and their Gram values (in entry order), and per
+    // joint the diagonal, right-hand side, prior and flags.
+    const uint2* __restrict__ entry = tr.entry;
+    const double* __restrict__ gfront = tr.gfront;
+    const int nentry = tr.nentry;
+    constexpr int kPre = 8;
+    uint2 en[kPre];
+    double gv[kPre];
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+        const int e = tid + kSolveThreads * k;
+        en[k] = e < nentry ? entry[e] : make_uint2(0u, ~0u);
+        gv[k] = e < nentry ? gfront[e] : 0.0;
+    }
+    {
+        const uint32_t* __restrict__ src = tr.blob;
+        const int nwords = tr.nwords;
+        for (int i = tid; i < nwords; i += kSolveThreads) lb[i] = src[i];
+    }
+    if (tid < P) {
+        const double gkk = gram[tid * PP + tid], gkb = gram[tid * PP + P];
+        const double prk = jt->prior[tid], thk = theta[tid];
+        const int fz = (gkk + prk == 0.0) || !jt->active[tid];
+        sfrozen[tid] = fz;
+        sdiag[tid] = fz ? T(1) : T((gkk + prk) * (1.0 + (double)lambda_k));
+        srhs[tid] = fz ? T(0) : T(gkb + prk * thk);
+    }
+    if (tid == 0) sfail = 0;
+    const int elems = tr.elems;
+    for (int e = tid; e < elems; e += kSolveThreads) Fs[e] = T(0);
+    __syncthreads();
+    auto place = [&](uint2 q, double g) {
+        const int gi = (q.x >> 14) & 127, gj = (q.x >> 21) & 127;
+        const T off = (sfrozen[gi] | sfrozen[gj]) ? T(0) : T(g);   // (unused for gj == 127)
+        Fs[q.y] = gj == 127 ? srhs[gi] : (gi == gj ? sdiag[gi] : off);
+    };
+#pragma unroll
+    for (int k = 0; k < kPre; ++k)
+        if (en[k].y != ~0u) place(en[k], gv[k]);
+    for (int e = tid + kSolveThreads * kPre; e < nentry; e += kSolveThreads) place(entry[e], gfront[e]);
+    __syncthreads();
+
+    // factor, level by level
+    const int nlev = tr.nlev;
+    const int* wstart = reinterpret_cast<const int*>(lb);
+    const int* sched = wstart + tr.o_sched;
+    const FrontRec* fronts = reinterpret_cast<const FrontRec*>(lb + tr.o_front);
+    const unsigned char* lbytes = reinterpret_cast<const unsigned char*>(lb);
+    bool ok = true;
+    for (int l = 0; l < nlev; ++l) {
+        const int q1 = wstart[l * kSolveWaves + wid + 1];
+        for (int q = wstart[l * kSolveWaves + wid]; q < q1; ++q) {
+            const FrontRec F = fronts[sched[q]];
+            T* Fr = Fs + F.off;
+            // the children's update blocks, 64 entries a round (each parent
+            // entry at most once per round, children in a fixed order)
+            for (int r = 0; r < F.nround; ++r) {
+                const uint32_t a = lb[F.amap0 + 64 * r + lane];
+                const uint32_t src = a & 0xFFFFu, dst = a >> 16;
+                if (dst != 0xFFFFu) Fs[dst] += Fs[src];
+            }
+            switch (F.fw) {
+                case 8: tree_factor<T, 8>(Fr, wb, F.np, F.f, lane, ok); break;
+                case 16: tree_factor<T, 16>(Fr, wb, F.np, F.f, lane, ok); break;
+                case 24: tree_factor<T, 24>(Fr, wb, F.np, F.f, lane, ok); break;
+                default: tree_factor<T, 32>(Fr, wb, F.np, F.f, lane, ok); break;
+            }
+        }
+        if (!ok && lane == 0) sfail = 1;
+        __syncthreads();
+    }
+    const bool fail = sfail != 0;
+    if (!fail) {
+        for (int l = nlev - 1; l >= 0; --l) {
+            const int q1 = wstart[l * kSolveWaves + wid + 1];
+            for (int q = wstart[l * kSolveWaves + wid]; q < q1; ++q) {
+                const FrontRec F = fronts[sched[q]];
+                tree_back<T>(Fs + F.off, wb, F.np, F.f, F.fw, lbytes + F.row0, sx, lane);
+            }
+            __syncthreads();
+        }
+    }
+    if (!fail) {
+        if (wid == 0) {
+            double part = 0.0;
+            for (int k = lane; k < P; k += 64) {
+                const double x = sfrozen[k] ? 0.0 : (double)sx[k];
+                S.step[k] = x;
+                theta[k] -= x;
+                part += x * x;
+            }
+            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+            if (lane == 0) {
+                st->step_norm[S.iter + iter] = (float)sqrt(part);
+                st->energy[S.iter + iter] = (float)gram[P * PP + P];
+            }
+        }
+    } else if (tid == 0) {
+        st->status = -4;
+        st->energy[S.iter + iter] = (float)gram[P * PP + P];
+        st->step_norm[S.iter + iter] = 0.0f;
+    }
+    __syncthreads();
+    fk_block(jt, P, S.m.L, theta, S.dq, S.xi, fk_ws);
+}
 
 // let the BIG instances take the largest system (P = 127, float64: about
 // 136 KB of LDS)
@@ -285,6 +522,12 @@ bool prepare_pose_solve() {
 
 template <class T>
 void launch_pose_solve_t(const Launch& L, int iter) {
+    if (L.solve_elems > 0) {
+        const size_t bytes = tree_lds_bytes<T>(L.solve_elems, L.solve_words);
+        launch_kernel(L, true, true, k_pose_solve_tree<T>, dim3(L.grid[KK_ONE]), dim3(kSolveThreads), bytes, L.B,
+                      iter, L.solve_elems, L.solve_words);
+        return;
+    }
     const int n = L.solve_n;
     const size_t bytes = solve_lds_bytes<T>(n);
     if (bytes <= kSmallLds)

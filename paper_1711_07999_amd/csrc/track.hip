@@ -11,11 +11,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <bitset>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -196,6 +199,10 @@ struct Stream {
     int P = 0, L = 0, V = 0, F = 0, K = 0, PP = 0, W = 0, H = 0, npad = 0, ntiles = 0, negrid = 0;
     JointTable hjt{};
     JointTable* djt = nullptr;
+    TreePlan hplan{};             // tree form of the pose solve (pointers: device addresses once carved)
+    std::vector<uint2> hentry;
+    std::vector<uint32_t> hblob;
+    std::vector<int> hgfmap;
     std::vector<double> prior_S;  // S_k: share of vertices each joint moves
     void* arena = nullptr;
     size_t arena_bytes = 0, arena_used = 0;
@@ -215,6 +222,8 @@ T* carve(Stream* s, size_t n) {
     s->arena_used += bytes;
     return p;
 }
+
+void build_tree_plan(Stream* c, const track_model* m);
 
 void build_joint_table(Stream* c, const track_model* m) {
     JointTable& t = c->hjt;
@@ -271,6 +280,203 @@ void build_joint_table(Stream* c, const track_model* m) {
         bool root = (t.anc[0][k >> 5] >> (k & 31)) & 1u;
         c->prior_S[k] = root ? 0.0 : (double)cnt[k] / (double)m->n_verts;
     }
+    build_tree_plan(c, m);
+}
+
+// Tree form of the pose solve.  A_kj can be non-zero only if some vertex
+// has weight on links whose chains (Section 3.1) hold both k and j; with the
+// joints eliminated children first (parent indices are smaller) the factor
+// keeps to the fill of that pattern, computed here symbolically, and its
+// elimination tree follows the limbs.  Chains of the elimination tree whose
+// nodes have one child each become supernodes.  Fronts wider than
+// kFrontRows - 1 rows, or storage beyond what the kernel's LDS allows, leave
+// the model to the dense form.
+void build_tree_plan(Stream* c, const track_model* m) {
+    TreePlan& t = c->hplan;
+    std::memset(&t, 0, sizeof(t));
+    c->hentry.clear();
+    c->hblob.clear();
+    c->hgfmap.clear();
+    const char* env = std::getenv("TRACK_DENSE_SOLVE");
+    if (env && env[0] == '1') return;
+    const int P = c->P;
+    const JointTable& jt = c->hjt;
+    // distinct chain unions over the vertices
+    std::set<std::array<uint32_t, 4>> masks;
+    for (int i = 0; i < m->n_verts; ++i) {
+        std::array<uint32_t, 4> mk{0, 0, 0, 0};
+        for (int k = 0; k < m->max_infl; ++k) {
+            const int l = m->skin_link[i * m->max_infl + k];
+            if (l >= 0 && m->skin_w[i * m->max_infl + k] > 0.0f)
+                for (int q = 0; q < 4; ++q) mk[q] |= jt.anc[l][q];
+        }
+        masks.insert(mk);
+    }
+    // column structure in elimination positions: joint j sits at P - 1 - j
+    std::vector<std::bitset<kMaxJoints + 1>> st(P);
+    for (const auto& mk : masks) {
+        std::vector<int> js;
+        for (int j = 0; j < P; ++j)
+            if ((mk[j >> 5] >> (j & 31)) & 1u) js.push_back(P - 1 - j);
+        for (int a : js)
+            for (int b : js)
+                if (a > b) st[b].set(a);
+    }
+    std::vector<int> epar(P, -1), nchild(P, 0);
+    for (int p = 0; p < P; ++p) {
+        if (st[p].none()) continue;
+        int q = p + 1;
+        while (!st[p].test(q)) ++q;
+        epar[p] = q;
+        nchild[q] += 1;
+        auto rest = st[p];
+        rest.reset(q);
+        st[q] |= rest;
+    }
+    // supernodes: runs p, p + 1, ... where p + 1 is the only child's parent
+    std::vector<int> sfirst, slast, snof(P);
+    for (int p = 0; p < P;) {
+        const int a = p;
+        if ((int)st[p].count() + 2 > kFrontRows) return;
+        while (p + 1 < P && epar[p] == p + 1 && nchild[p + 1] == 1 &&
+               (p + 2 - a) + (int)st[p + 1].count() + 1 <= kFrontRows)
+            ++p;
+        for (int q = a; q <= p; ++q) snof[q] = (int)sfirst.size();
+        sfirst.push_back(a);
+        slast.push_back(p);
+        ++p;
+    }
+    const int nsn = (int)sfirst.size();
+    std::vector<int> spar(nsn, -1), lev(nsn, 0);
+    std::vector<std::vector<int>> rows(nsn);   // elimination positions, increasing
+    for (int s = 0; s < nsn; ++s) {
+        for (int q = sfirst[s]; q <= slast[s]; ++q) rows[s].push_back(q);
+        for (int q = slast[s] + 1; q < P; ++q)
+            if (st[slast[s]].test(q)) rows[s].push_back(q);
+        if (epar[slast[s]] >= 0) spar[s] = snof[epar[slast[s]]];
+    }
+    for (int s = 0; s < nsn; ++s)   // children come before their parents
+        if (spar[s] >= 0) lev[spar[s]] = std::max(lev[spar[s]], lev[s] + 1);
+    int nlev = 0;
+    for (int s = 0; s < nsn; ++s) nlev = std::max(nlev, lev[s] + 1);
+    // fronts
+    struct Fr { int off, np, f, fw; };
+    std::vector<Fr> fr(nsn);
+    std::vector<std::vector<int>> joint(nsn);   // front row -> joint
+    int elems = 0;
+    for (int s = 0; s < nsn; ++s) {
+        Fr& F = fr[s];
+        F.np = slast[s] - sfirst[s] + 1;
+        F.f = (int)rows[s].size();
+        F.fw = F.f + 1 <= 8 ? 8 : F.f + 1 <= 16 ? 16 : F.f + 1 <= 24 ? 24 : 32;   // the kernel's register widths
+        F.off = elems;
+        elems += (F.f + 1) * F.fw;
+        for (int r = 0; r < F.f; ++r) joint[s].push_back(P - 1 - rows[s][r]);
+    }
+    if (elems >= (1 << 15)) return;
+    // assembly rounds of each parent: its children's update blocks (lower
+    // triangle and right-hand-side row), children in index order, each parent
+    // entry at most once per round
+    std::vector<std::vector<uint32_t>> rounds(nsn);
+    for (int s = 0; s < nsn; ++s) {
+        std::vector<std::vector<uint32_t>> rr;
+        std::vector<int> last_round((size_t)(fr[s].f + 1) * fr[s].fw, -1);
+        for (int ch = 0; ch < nsn; ++ch) {
+            if (spar[ch] != s) continue;
+            const Fr& C = fr[ch];
+            const int nU = C.f - C.np;
+            std::vector<int> pos(nU);
+            for (int u = 0; u < nU; ++u)
+                pos[u] = (int)(std::lower_bound(rows[s].begin(), rows[s].end(), rows[ch][C.np + u]) - rows[s].begin());
+            for (int i = 0; i <= nU; ++i)
+                for (int j = 0; j < nU && j <= i; ++j) {
+                    const int prow = i < nU ? pos[i] : fr[s].f;
+                    const int dst = prow * fr[s].fw + pos[j];
+                    const int src = C.off + (C.np + i) * C.fw + C.np + j;
+                    int r = last_round[dst] + 1;
+                    while (r < (int)rr.size() && rr[r].size() >= 64) ++r;
+                    if (r == (int)rr.size()) rr.emplace_back();
+                    rr[r].push_back((uint32_t)src | ((uint32_t)(fr[s].off + dst) << 16));
+                    last_round[dst] = r;
+                }
+        }
+        for (auto& q : rr) {
+            q.resize(64, 0xFFFF0000u);
+            rounds[s].insert(rounds[s].end(), q.begin(), q.end());
+        }
+    }
+    // per level, longest processing time first over the waves (cost: pivots x width)
+    std::vector<int> wstart((size_t)nlev * kSolveWaves + 1), sched;
+    for (int l = 0; l < nlev; ++l) {
+        std::vector<int> ids;
+        for (int s = 0; s < nsn; ++s)
+            if (lev[s] == l) ids.push_back(s);
+        auto cost = [&](int s) { return (int64_t)fr[s].np * fr[s].fw + (int64_t)rounds[s].size(); };
+        std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        std::vector<std::vector<int>> per(kSolveWaves);
+        std::vector<int64_t> load(kSolveWaves, 0);
+        for (int s : ids) {
+            const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            per[w].push_back(s);
+            load[w] += cost(s);
+        }
+        for (int w = 0; w < kSolveWaves; ++w) {
+            wstart[l * kSolveWaves + w] = (int)sched.size();
+            for (int s : per[w]) sched.push_back(s);
+        }
+    }
+    wstart[(size_t)nlev * kSolveWaves] = (int)sched.size();
+    // the blob
+    std::vector<uint32_t>& B = c->hblob;
+    B.assign(wstart.begin(), wstart.end());
+    t.o_sched = (int)B.size();
+    B.insert(B.end(), sched.begin(), sched.end());
+    t.o_front = (int)B.size();
+    B.resize(B.size() + (size_t)kFrontWords * nsn, 0u);
+    std::vector<int> amap0(nsn);
+    for (int s = 0; s < nsn; ++s) {
+        amap0[s] = (int)B.size();
+        B.insert(B.end(), rounds[s].begin(), rounds[s].end());
+    }
+    std::vector<int> row0(nsn);
+    std::vector<unsigned char> bytes;
+    const int rbase = (int)B.size() * 4;
+    for (int s = 0; s < nsn; ++s) {
+        row0[s] = rbase + (int)bytes.size();
+        for (int r = 0; r < fr[s].f; ++r) bytes.push_back((unsigned char)joint[s][r]);
+    }
+    bytes.resize((bytes.size() + 3) & ~size_t(3), 0);
+    for (size_t q = 0; q < bytes.size(); q += 4)
+        B.push_back((uint32_t)bytes[q] | ((uint32_t)bytes[q + 1] << 8) | ((uint32_t)bytes[q + 2] << 16) |
+                    ((uint32_t)bytes[q + 3] << 24));
+    for (int s = 0; s < nsn; ++s) {
+        uint32_t* w = &B[(size_t)t.o_front + (size_t)kFrontWords * s];
+        w[0] = fr[s].off; w[1] = fr[s].np; w[2] = fr[s].f; w[3] = fr[s].fw;
+        w[4] = amap0[s]; w[5] = (uint32_t)(rounds[s].size() / 64); w[6] = row0[s]; w[7] = 0;
+    }
+    // set-up entries: the lower triangle of each front's pivot columns from
+    // the Gram matrix, and the right-hand side of its pivots (column P)
+    for (int s = 0; s < nsn; ++s) {
+        const Fr& F = fr[s];
+        for (int i = 0; i <= F.f; ++i)
+            for (int j = 0; j < F.np; ++j) {
+                if (i < F.f && j > i) continue;
+                const uint32_t gi = i < F.f ? joint[s][i] : joint[s][j];
+                const uint32_t gj = i < F.f ? joint[s][j] : 127u;
+                const uint32_t at = gi * (uint32_t)c->PP + (gj == 127u ? (uint32_t)P : gj);
+                c->hentry.push_back(make_uint2(at | (gi << 14) | (gj << 21), (uint32_t)(F.off + i * F.fw + j)));
+            }
+    }
+    // the Gram reduction writes each entry's value (all at or above the
+    // diagonal: a front's later rows hold smaller joint indices)
+    c->hgfmap.assign((size_t)c->PP * c->PP, -1);
+    for (size_t e = 0; e < c->hentry.size(); ++e) c->hgfmap[c->hentry[e].x & 0x3FFFu] = (int)e;
+    t.nsn = nsn;
+    t.nlev = nlev;
+    t.elems = elems;
+    t.nentry = (int)c->hentry.size();
+    t.nwords = (int)B.size();
+    t.ok = (c->PP * c->PP <= (1 << 14) && tree_solve_fits(elems, t.nwords)) ? 1 : 0;
 }
 
 // per-stream constants: association cutoff, weights, prior and active mask
@@ -306,6 +512,19 @@ void stream_layout(Stream* c) {
     uint32_t* anc = carve<uint32_t>(c, 4 * c->L);
     S.anc = anc;
     S.partials = carve<float>(c, (size_t)c->negrid * c->PP * c->PP);
+    c->hplan.entry = carve<uint2>(c, (size_t)std::max(1, c->hplan.nentry));
+    c->hplan.blob = carve<uint32_t>(c, (size_t)std::max(1, c->hplan.nwords));
+    {
+        TreeRef& tr = S.tree;
+        const TreePlan& t = c->hplan;
+        tr.entry = t.entry;
+        tr.blob = t.blob;
+        tr.gfront = carve<double>(c, (size_t)std::max(1, t.nentry));
+        int* gfmap = carve<int>(c, (size_t)c->PP * c->PP);
+        tr.gfmap = t.ok ? gfmap : nullptr;
+        tr.nentry = t.nentry; tr.nwords = t.nwords; tr.nlev = t.nlev; tr.elems = t.elems;
+        tr.o_sched = t.o_sched; tr.o_front = t.o_front;
+    }
     c->depth_buf = carve<float>(c, N);
     c->xyz_buf = carve<float>(c, 3 * N);
     auto v3 = [&]() { Vec3Buf b; b.x = carve<float>(c, V); b.y = carve<float>(c, V); b.z = carve<float>(c, V); return b; };
@@ -469,6 +688,9 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
               up(S.m.w, hw.data(), 16 * V) && up(S.m.links, hl.data(), 4 * V) && up(S.m.nbr, hn.data(), 16 * V) &&
               up(S.m.fan_off, hoff.data(), 4 * (V + 1)) && (c->F == 0 || up(S.m.fan, hfan.data(), 8 * 3 * (size_t)c->F)) &&
               up(S.anc, hanc.data(), 4 * hanc.size()) && up(S.theta, theta0, 8 * (size_t)c->P) &&
+              (!S.tree.gfmap || up(S.tree.gfmap, c->hgfmap.data(), sizeof(int) * c->hgfmap.size())) &&
+              (c->hentry.empty() || up(c->hplan.entry, c->hentry.data(), sizeof(uint2) * c->hentry.size())) &&
+              (c->hblob.empty() || up(c->hplan.blob, c->hblob.data(), sizeof(uint32_t) * c->hblob.size())) &&
               hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess;
     if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
     S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F;
@@ -502,13 +724,26 @@ struct KernelTimer {
 struct GraphKey {
     int n, off, kind, skin_first;
     int grid[KK_COUNT_];
+    int solve_n, solve_elems, solve_words, ne_pp, ne_l;   // the launch sizes the captured kernels were given
     bool operator==(const GraphKey& o) const {
         if (n != o.n || off != o.off || kind != o.kind || skin_first != o.skin_first) return false;
+        if (solve_n != o.solve_n || solve_elems != o.solve_elems || solve_words != o.solve_words || ne_pp != o.ne_pp ||
+            ne_l != o.ne_l)
+            return false;
         for (int k = 0; k < KK_COUNT_; ++k)
             if (grid[k] != o.grid[k]) return false;
         return true;
     }
 };
+
+GraphKey key_of(const Launch& L, int n, int off, int kind) {
+    GraphKey k{};
+    k.n = n; k.off = off; k.kind = kind; k.skin_first = 1;
+    for (int q = 0; q < KK_COUNT_; ++q) k.grid[q] = L.grid[q];
+    k.solve_n = L.solve_n; k.solve_elems = L.solve_elems; k.solve_words = L.solve_words;
+    k.ne_pp = L.ne_pp; k.ne_l = L.ne_l;
+    return k;
+}
 
 struct CachedGraph {
     GraphKey key;
@@ -668,13 +903,20 @@ Launch stage_table(Runner& R, int off, const TableEntry* e, int n) {
     }
     for (int k = 0; k < KK_COUNT_; ++k) L.grid[k] = pre[k * (n + 1) + n];
     L.solve_n = 16;
+    L.solve_elems = 0;
     L.ne_pp = 16;
     L.ne_l = 1;
+    L.solve_words = 0;
+    bool tree = true;
     for (int i = 0; i < n; ++i) {
+        tree = tree && e[i].s->hplan.ok;
+        L.solve_elems = std::max(L.solve_elems, e[i].s->hplan.elems);
+        L.solve_words = std::max(L.solve_words, e[i].s->hplan.nwords);
         L.solve_n = std::max(L.solve_n, (e[i].s->P + 15) / 16 * 16);
         L.ne_pp = std::max(L.ne_pp, e[i].s->PP);
         L.ne_l = std::max(L.ne_l, e[i].s->L);
     }
+    if (!tree) L.solve_elems = L.solve_words = 0;
     L.B.slots = R.dslots + off;
     L.B.pre = R.dpre + pre_offset(off);
     L.B.n = n;
@@ -946,9 +1188,7 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
     }
     TableEntry e{&s, flags, 0, depth, xyz};
     Launch L = stage_table(R, 0, &e, 1);
-    GraphKey key{};
-    key.n = 1; key.off = 0; key.kind = 0; key.skin_first = 1;
-    for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
+    const GraphKey key = key_of(L, 1, 0, 0);
     const SurfaceState st = frame(R, L, c->sched, false);
     HIP_TRY(hipEventRecord(R.f0, R.s));
     int rc = run_cached(R, key, [&]() {
@@ -1554,9 +1794,7 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
         if (n == 0) continue;
         const bool pose = (g & 1) != 0, shape = (g & 2) != 0;
         Launch L = stage_table(R, off, group[g].data(), n);
-        GraphKey key{};
-        key.n = n; key.off = off; key.kind = 1 + g; key.skin_first = 1;
-        for (int k = 0; k < KK_COUNT_; ++k) key.grid[k] = L.grid[k];
+        const GraphKey key = key_of(L, n, off, 1 + g);
         rc = run_cached(R, key, [&]() {
             SurfaceState st;
             issue_stage(L);

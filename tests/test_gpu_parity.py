@@ -188,18 +188,42 @@ def test_normal_equations(T, tiny, ragged, human, highres, case, mode):
     assert abs(G[P, P] - ps["rr"]) <= 1e-4 * ps["rr"] + 1e-12
 
 
+def _blended_everywhere(m):
+    """The same body with every vertex also weighted (lightly) on both hands
+    and both feet: every pair of joints is then coupled, the tree form of the
+    solve has no front that fits, and the dense form is taken."""
+    m = dict(m)
+    links, w = m["skin_link"].copy(), m["skin_w"].copy()
+    far = [10, 15, 19, 23]
+    for q in range(4):
+        put = w[:, q] == 0.0
+        links[put, q] = far[q]
+        w[put, q] = 1e-3
+    m["skin_link"], m["skin_w"] = links, (w / w.sum(1, keepdims=True)).astype(np.float32)
+    return m
+
+
 @pytest.mark.parametrize("fp64", [0, 1])
-def test_pose_step(T, human, fp64):
+@pytest.mark.parametrize("form", ["tree", "dense", "dense-pattern"])
+def test_pose_step(T, human, fp64, form, monkeypatch):
     """The damped Cholesky step on the GPU's own Gram matrix equals the
     oracle's solve of that matrix (float64: 1e-9 relative to |x|; float32:
-    1e-3 relative, the conditioning of the 75x75 system times 1e-7)."""
-    _say(f"[pose_step] fp64={fp64}")
+    1e-3 relative, the conditioning of the 75x75 system times 1e-7).  Forms:
+    the tree-ordered factorisation (the default for the body), the dense
+    one forced by TRACK_DENSE_SOLVE=1, and the dense one chosen because the
+    skin couples every pair of joints."""
+    _say(f"[pose_step] fp64={fp64} form={form}")
     m, cam, prm, th, depth = (human.body.model, human.body.camera, dict(human.params, pose_solve_fp64=fp64),
                               human.theta0, human.frames[0])
+    if form == "dense":
+        monkeypatch.setenv("TRACK_DENSE_SOLVE", "1")
+    if form == "dense-pattern":
+        m = _blended_everywhere(m)
     V, P = m["rest_xyz"].shape[0], len(th)
     phi = np.zeros((V, 3), np.float32)
     v32, n32, cnt, delta = _assoc_inputs(m, cam, prm, th, depth, phi.astype(np.float64))
     trk = T.Tracker(m, cam, prm, th)
+    monkeypatch.delenv("TRACK_DENSE_SOLVE", raising=False)
     try:
         for buf, arr in ((T.TRACK_BUF_THETA, th), (T.TRACK_BUF_VERTS, v32), (T.TRACK_BUF_NORMALS, n32),
                          (T.TRACK_BUF_COUNT, cnt.astype(np.int32)), (T.TRACK_BUF_DELTA, delta)):
