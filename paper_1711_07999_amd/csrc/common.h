@@ -46,22 +46,19 @@ struct FrontRec { int off, np, f, fw, amap0, nround, row0, pad; };
 // What the kernels read of a stream's tree plan (in its slot, so that no
 // read waits on another).
 struct TreeRef {
-    const uint2* entry;              // set-up entries (TreePlan::entry)
     const uint32_t* blob;            // TreePlan::blob
-    double* gfront;                  // [nentry] the entries' Gram values, written by the Gram reduction
-    const int* gfmap;                // [PP*PP] Gram position -> entry, -1 none; null: dense form
-    int nentry, nwords, nlev, elems, o_sched, o_front;
+    double* fimg;                    // [elems] the fronts as the solve starts them, written by the
+                                     // Gram reduction (damped, frozen); zero outside the entries
+    const int* gfmap;                // [PP*PP] Gram position (at or above the diagonal, or the
+                                     // right-hand side) -> front storage index, -1 none; null: dense form
+    int nwords, nlev, elems, o_sched, o_front;
 };
 
 struct alignas(16) TreePlan {
     int ok;                          // the tree form applies to this model
     int nsn, nlev, elems;            // supernodes, levels, front storage (elements)
-    int nentry;                      // set-up entries
     int nwords;                      // words of `blob`
     int o_sched, o_front;            // word offsets of the schedule and the front records
-    // set-up entries: x = Gram offset | row << 14 | col << 21 (col 127: the
-    // right-hand side), y = storage index in the fronts
-    const uint2* entry;
     // what the kernel copies to LDS: per level and wave the first schedule
     // entry (wstart, kSolveWaves * nlev + 1 words), the schedule, the front
     // records, the assembly rounds (per parent, 64 entries a round: child

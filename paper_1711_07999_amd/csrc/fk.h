@@ -93,4 +93,94 @@ __device__ __forceinline__ void fk_block(const JointTable* __restrict__ jt, int 
     }
 }
 
+// The same forward kinematics with the constants read ahead of time (a
+// kernel issues fk_prefetch early, so the reads overlap other work) and the
+// pose taken from LDS.  Joint j's data sit in thread j, link l's in thread
+// kLinkThread + l (so the joint and link outputs are formed side by side when
+// the workgroup has kLinkThread + L threads).
+constexpr int kLinkThread = 256;
+
+struct FkJoint { double off[8], z[3]; int type, parent; };
+struct FkLink { double binv[8]; int joint; };
+
+__device__ __forceinline__ void fk_prefetch(const JointTable* __restrict__ jt, int P, int L, FkJoint& fj, FkLink& fl) {
+    const int t = threadIdx.x;
+    if (t < P) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) fj.off[c] = jt->off[t][c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fj.z[c] = jt->axis[t][c];
+        fj.type = jt->type[t];
+        fj.parent = jt->parent[t];
+    }
+    const int l = t - kLinkThread;
+    if (l >= 0 && l < L) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) fl.binv[c] = jt->binv[l][c];
+        fl.joint = jt->link_joint[l];
+    }
+}
+
+__device__ __forceinline__ void fk_block_pre(int P, int L, int rounds, const double* __restrict__ sth,
+                                             const FkJoint& fj, const FkLink& fl, float* __restrict__ dq,
+                                             float* __restrict__ xi, FkScratch& ws) {
+    double (*M)[kMaxJoints + 1][8] = ws.M;
+    int (*A)[kMaxJoints + 1] = ws.A;
+    const int t = threadIdx.x;
+    if (t < P) {
+        const double th = sth[t];
+        double Hj[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+        if (fj.type == 0) {
+            double s, c;
+            sincos(0.5 * th, &s, &c);
+            Hj[0] = c; Hj[1] = s * fj.z[0]; Hj[2] = s * fj.z[1]; Hj[3] = s * fj.z[2];
+        } else {
+            Hj[5] = 0.5 * th * fj.z[0]; Hj[6] = 0.5 * th * fj.z[1]; Hj[7] = 0.5 * th * fj.z[2];
+        }
+        double loc[8];
+        dqmul(fj.off, Hj, loc);
+        for (int c = 0; c < 8; ++c) M[0][t][c] = loc[c];
+        A[0][t] = fj.parent;
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int round = 0; round < rounds; ++round) {
+        const int nxt = cur ^ 1;
+        if (t < P) {
+            const int a = A[cur][t];
+            if (a >= 0) {
+                double o[8];
+                dqmul(M[cur][a], M[cur][t], o);
+                for (int c = 0; c < 8; ++c) M[nxt][t][c] = o[c];
+                A[nxt][t] = A[cur][a];
+            } else {
+                for (int c = 0; c < 8; ++c) M[nxt][t][c] = M[cur][t][c];
+                A[nxt][t] = -1;
+            }
+        }
+        __syncthreads();
+        cur = nxt;
+    }
+    if (t < P) {
+        const double* H = M[cur][t];
+        double g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (fj.type == 0) { g[1] = 0.5 * fj.z[0]; g[2] = 0.5 * fj.z[1]; g[3] = 0.5 * fj.z[2]; }
+        else { g[5] = 0.5 * fj.z[0]; g[6] = 0.5 * fj.z[1]; g[7] = 0.5 * fj.z[2]; }
+        double hc[8], tmp[8], o[8];
+        dqconj(H, hc);
+        dqmul(H, g, tmp);
+        dqmul(tmp, hc, o);
+        float* dst = xi + 8 * t;
+        dst[0] = (float)o[1]; dst[1] = (float)o[2]; dst[2] = (float)o[3];
+        dst[3] = (float)o[5]; dst[4] = (float)o[6]; dst[5] = (float)o[7];
+        dst[6] = 0.0f; dst[7] = 0.0f;
+    }
+    const int l = t - kLinkThread;
+    if (l >= 0 && l < L) {
+        double o[8];
+        dqmul(M[cur][fl.joint], fl.binv, o);
+        for (int c = 0; c < 8; ++c) dq[8 * l + c] = (float)o[c];
+    }
+}
+
 }  // namespace trk

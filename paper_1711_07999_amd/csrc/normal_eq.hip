@@ -344,6 +344,17 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
     int I, J;
     block_of(blk, nb, I, J);
     const int i = I * 16 + (el >> 4), j = J * 16 + (el & 15);
+    // the tree-form pose solve takes this element (damped, frozen) in its front image
+    const int fe = (S.tree.gfmap && grp == 0 && i <= j) ? S.tree.gfmap[i * PP + j] : -1;
+    const int P = S.m.P;
+    double prior_i = 0.0, theta_i = 0.0;
+    int act_i = 0, act_j = 0;
+    if (fe >= 0) {
+        prior_i = S.jt->prior[i];
+        act_i = S.jt->active[i];
+        act_j = j < P ? S.jt->active[j] : 1;
+        theta_i = S.theta[i];
+    }
     const size_t stride = (size_t)PP * PP;
     const int per = (nparts + 7) / 8;
     const int q0 = grp * per, q1 = min(nparts, q0 + per);
@@ -361,12 +372,20 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
     part[grp][threadIdx.x & 31] = s;
     __syncthreads();
     if (grp == 0 && i <= j) {
-        const int fe = S.tree.gfmap ? S.tree.gfmap[i * PP + j] : -1;
         double tot = 0.0;
         for (int g = 0; g < 8; ++g) tot += part[g][threadIdx.x & 31];
         gram[i * PP + j] = tot;
         gram[j * PP + i] = tot;
-        if (fe >= 0) S.tree.gfront[fe] = tot;   // the pose solve's tree form reads it in entry order
+        if (fe >= 0) {
+            // as the dense solve sets up its matrix: a joint with no weight
+            // (zero diagonal: its whole row is zero) or masked inactive is
+            // frozen to an identity row with a zero right-hand side
+            double v;
+            if (j == P) v = act_i ? tot + prior_i * theta_i : 0.0;
+            else if (i == j) v = (tot + prior_i == 0.0 || !act_i) ? 1.0 : (tot + prior_i) * (1.0 + (double)S.lambda_k);
+            else v = (act_i && act_j) ? tot : 0.0;
+            S.tree.fimg[fe] = v;
+        }
     }
 }
 

@@ -306,8 +306,8 @@ __host__ __device__ inline size_t tree_front_bytes(int elems) {
 }
 template <class T>
 __host__ __device__ inline size_t tree_lds_bytes(int elems, int words) {
-    return tree_front_bytes<T>(elems) + 16 * (size_t)((words + 3) / 4) + 3 * sizeof(T) * kNMax +
-           sizeof(T) * 64 * kSolveWaves + sizeof(int) * (kNMax + 1);
+    return tree_front_bytes<T>(elems) + 16 * (size_t)((words + 3) / 4) + sizeof(T) * kNMax +
+           sizeof(double) * (kNMax + kSolveWaves) + sizeof(T) * 64 * kSolveWaves + 16;
 }
 
 bool tree_solve_fits(int elems, int words) { return tree_lds_bytes<double>(elems, words) <= kSmallLds; }
@@ -338,8 +338,9 @@ __device__ __forceinline__ void tree_factor(T* Fr, T* wb, int np, int f, int lan
         // column j of L below the diagonal (the right-hand-side row: y_j)
         const T lj = lane > j ? r[0] * inv : T(0);
         if (lane == j) myinv = inv;
-        if (live && lane >= j) Fr[lane * FW + j] = lane == j ? d * inv : lj;
-        if (lane > j) wb[lane - j - 1] = lj;   // wb[k] = L_{j+1+k, j}; lanes j+1..63 cover k < FW
+        // masked lanes store to wb[63], which no lane reads
+        *(live && lane >= j ? Fr + lane * FW + j : wb + 63) = lane == j ? d * inv : lj;
+        *(lane > j ? wb + (lane - j - 1) : wb + 63) = lj;   // wb[k] = L_{j+1+k, j}; lanes j+1..63 cover k < FW
         T cv[FW];
 #pragma unroll
         for (int c = 0; c < FW; c += 4) load4(wb + c, cv + c);
@@ -365,7 +366,18 @@ __device__ __forceinline__ void tree_back(const T* Fr, T* wb, int np, int f, int
     if (lane < nU) wb[lane] = sx[row[np + lane]];
     const int cl = lane < np ? lane : 0;
     T t = Fr[f * fw + cl];
-    for (int k = 0; k < nU; ++k) t -= Fr[(np + k) * fw + cl] * wb[k];
+    // four independent partial sums, so four rows' loads are in flight
+    T t1 = T(0), t2 = T(0), t3 = T(0);
+    int k = 0;
+    for (; k + 4 <= nU; k += 4) {
+        const T* R = Fr + (np + k) * fw + cl;
+        t -= R[0] * wb[k];
+        t1 -= R[fw] * wb[k + 1];
+        t2 -= R[2 * fw] * wb[k + 2];
+        t3 -= R[3 * fw] * wb[k + 3];
+    }
+    for (; k < nU; ++k) t -= Fr[(np + k) * fw + cl] * wb[k];
+    t = (t + t1) + (t2 + t3);
     // the pivots' own triangle, last pivot first
     for (int j = np - 1; j >= 0; --j) {
         const T dinv = Fr[j * fw + fw - 1];
@@ -384,64 +396,60 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
     FkScratch& fk_ws = *reinterpret_cast<FkScratch*>(smem);
     uint32_t* lb = reinterpret_cast<uint32_t*>(smem + mat);   // the plan's blob, copied to LDS
     T* sx = reinterpret_cast<T*>(smem + mat + 16 * (size_t)((words_max + 3) / 4));
-    T* sdiag = sx + kNMax;
-    T* srhs = sdiag + kNMax;
-    int* sfrozen = reinterpret_cast<int*>(srhs + kNMax + 64 * kSolveWaves);
-    int& sfail = sfrozen[kNMax];
+    double* sth = reinterpret_cast<double*>(sx + kNMax);      // the new pose
+    double* spart = sth + kNMax;                               // per-wave sums of x^2
+    T* wbase = reinterpret_cast<T*>(spart + kSolveWaves);
+    int& sfail = *reinterpret_cast<int*>(wbase + 64 * kSolveWaves);
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     const TreeRef& tr = S.tree;
     const JointTable* __restrict__ jt = S.jt;
     const int PP = S.PP;
     const double* __restrict__ gram = S.gram;
-    const float lambda_k = S.lambda_k;
     double* __restrict__ theta = S.theta;
     DevStats* st = S.st;
-    const int P = S.m.P;
+    const int P = S.m.P, NL = S.m.L;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    T* wb = srhs + kNMax + 64 * wid;   // this wave's broadcast buffer
+    T* wb = wbase + 64 * wid;   // this wave's broadcast buffer
 
-    // set-up.  Every global read is issued before any is used: the plan's
-    // blob, the entries and their Gram values (in entry order), and per
-    // joint the diagonal, right-hand side, prior and flags.
-    const uint2* __restrict__ entry = tr.entry;
-    const double* __restrict__ gfront = tr.gfront;
-    const int nentry = tr.nentry;
+    // set-up: every global read is issued before any is used -- the fronts'
+    // starting image (from the Gram reduction), the plan, and per joint the
+    // pose and whether it is frozen
+    const int elems = tr.elems;   // even: rows are multiples of 8 wide
+    const double2* __restrict__ img = reinterpret_cast<const double2*>(tr.fimg);
     constexpr int kPre = 8;
-    uint2 en[kPre];
-    double gv[kPre];
+    double2 iv[kPre];
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
         const int e = tid + kSolveThreads * k;
-        en[k] = e < nentry ? entry[e] : make_uint2(0u, ~0u);
-        gv[k] = e < nentry ? gfront[e] : 0.0;
+        iv[k] = 2 * e < elems ? img[e] : make_double2(0.0, 0.0);
     }
-    {
-        const uint32_t* __restrict__ src = tr.blob;
-        const int nwords = tr.nwords;
-        for (int i = tid; i < nwords; i += kSolveThreads) lb[i] = src[i];
-    }
+    const uint4* __restrict__ bsrc = reinterpret_cast<const uint4*>(tr.blob);
+    const int nw4 = (tr.nwords + 3) / 4;
+    uint4 bw = tid < nw4 ? bsrc[tid] : make_uint4(0u, 0u, 0u, 0u);
+    double thk = 0.0;
+    int fz = 1;
     if (tid < P) {
-        const double gkk = gram[tid * PP + tid], gkb = gram[tid * PP + P];
-        const double prk = jt->prior[tid], thk = theta[tid];
-        const int fz = (gkk + prk == 0.0) || !jt->active[tid];
-        sfrozen[tid] = fz;
-        sdiag[tid] = fz ? T(1) : T((gkk + prk) * (1.0 + (double)lambda_k));
-        srhs[tid] = fz ? T(0) : T(gkb + prk * thk);
+        thk = theta[tid];
+        fz = (gram[tid * PP + tid] + jt->prior[tid] == 0.0) || !jt->active[tid];
     }
-    if (tid == 0) sfail = 0;
-    const int elems = tr.elems;
-    for (int e = tid; e < elems; e += kSolveThreads) Fs[e] = T(0);
-    __syncthreads();
-    auto place = [&](uint2 q, double g) {
-        const int gi = (q.x >> 14) & 127, gj = (q.x >> 21) & 127;
-        const T off = (sfrozen[gi] | sfrozen[gj]) ? T(0) : T(g);   // (unused for gj == 127)
-        Fs[q.y] = gj == 127 ? srhs[gi] : (gi == gj ? sdiag[gi] : off);
-    };
+    const double energy = tid == 0 ? gram[P * PP + P] : 0.0;
 #pragma unroll
-    for (int k = 0; k < kPre; ++k)
-        if (en[k].y != ~0u) place(en[k], gv[k]);
-    for (int e = tid + kSolveThreads * kPre; e < nentry; e += kSolveThreads) place(entry[e], gfront[e]);
+    for (int k = 0; k < kPre; ++k) {
+        const int e = tid + kSolveThreads * k;
+        if (2 * e < elems) {
+            Fs[2 * e] = T(iv[k].x);
+            Fs[2 * e + 1] = T(iv[k].y);
+        }
+    }
+    for (int e = tid + kSolveThreads * kPre; 2 * e < elems; e += kSolveThreads) {
+        const double2 v = img[e];
+        Fs[2 * e] = T(v.x);
+        Fs[2 * e + 1] = T(v.y);
+    }
+    if (tid < nw4) reinterpret_cast<uint4*>(lb)[tid] = bw;
+    for (int i = tid + kSolveThreads; i < nw4; i += kSolveThreads) reinterpret_cast<uint4*>(lb)[i] = bsrc[i];
+    if (tid == 0) sfail = 0;
     __syncthreads();
 
     // factor, level by level
@@ -474,6 +482,10 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
         __syncthreads();
     }
     const bool fail = sfail != 0;
+    // forward kinematics' constants, read while the back substitution runs
+    FkJoint fj;
+    FkLink fl;
+    fk_prefetch(jt, P, NL, fj, fl);
     if (!fail) {
         for (int l = nlev - 1; l >= 0; --l) {
             const int q1 = wstart[l * kSolveWaves + wid + 1];
@@ -484,28 +496,28 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
             __syncthreads();
         }
     }
-    if (!fail) {
-        if (wid == 0) {
-            double part = 0.0;
-            for (int k = lane; k < P; k += 64) {
-                const double x = sfrozen[k] ? 0.0 : (double)sx[k];
-                S.step[k] = x;
-                theta[k] -= x;
-                part += x * x;
-            }
-            for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-            if (lane == 0) {
-                st->step_norm[S.iter + iter] = (float)sqrt(part);
-                st->energy[S.iter + iter] = (float)gram[P * PP + P];
-            }
+    // the step: Theta <- Theta - x (frozen parameters keep their value)
+    const double x = (tid < P && !fail && !fz) ? (double)sx[tid] : 0.0;
+    if (tid < P) {
+        const double th = thk - x;
+        sth[tid] = th;
+        if (!fail) {
+            S.step[tid] = x;
+            theta[tid] = th;
         }
-    } else if (tid == 0) {
-        st->status = -4;
-        st->energy[S.iter + iter] = (float)gram[P * PP + P];
-        st->step_norm[S.iter + iter] = 0.0f;
     }
+    double part = x * x;
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if (lane == 0) spart[wid] = part;
     __syncthreads();
-    fk_block(jt, P, S.m.L, theta, S.dq, S.xi, fk_ws);
+    if (tid == 0) {
+        double norm2 = 0.0;
+        for (int w = 0; w < kSolveWaves; ++w) norm2 += spart[w];
+        st->energy[S.iter + iter] = (float)energy;
+        st->step_norm[S.iter + iter] = fail ? 0.0f : (float)sqrt(norm2);
+        if (fail) st->status = -4;
+    }
+    fk_block_pre(P, NL, jt->rounds, sth, fj, fl, S.dq, S.xi, fk_ws);
 }
 
 // let the BIG instances take the largest system (P = 127, float64: about

@@ -200,7 +200,6 @@ struct Stream {
     JointTable hjt{};
     JointTable* djt = nullptr;
     TreePlan hplan{};             // tree form of the pose solve (pointers: device addresses once carved)
-    std::vector<uint2> hentry;
     std::vector<uint32_t> hblob;
     std::vector<int> hgfmap;
     std::vector<double> prior_S;  // S_k: share of vertices each joint moves
@@ -294,7 +293,6 @@ void build_joint_table(Stream* c, const track_model* m) {
 void build_tree_plan(Stream* c, const track_model* m) {
     TreePlan& t = c->hplan;
     std::memset(&t, 0, sizeof(t));
-    c->hentry.clear();
     c->hblob.clear();
     c->hgfmap.clear();
     const char* env = std::getenv("TRACK_DENSE_SOLVE");
@@ -454,29 +452,26 @@ void build_tree_plan(Stream* c, const track_model* m) {
         w[0] = fr[s].off; w[1] = fr[s].np; w[2] = fr[s].f; w[3] = fr[s].fw;
         w[4] = amap0[s]; w[5] = (uint32_t)(rounds[s].size() / 64); w[6] = row0[s]; w[7] = 0;
     }
-    // set-up entries: the lower triangle of each front's pivot columns from
-    // the Gram matrix, and the right-hand side of its pivots (column P)
+    // where the Gram reduction puts each element: the lower triangle of
+    // each front's pivot columns and the right-hand side of its pivots
+    // (column P).  All sit at or above the Gram diagonal: a front's later
+    // rows hold smaller joint indices.
+    c->hgfmap.assign((size_t)c->PP * c->PP, -1);
     for (int s = 0; s < nsn; ++s) {
         const Fr& F = fr[s];
         for (int i = 0; i <= F.f; ++i)
             for (int j = 0; j < F.np; ++j) {
                 if (i < F.f && j > i) continue;
-                const uint32_t gi = i < F.f ? joint[s][i] : joint[s][j];
-                const uint32_t gj = i < F.f ? joint[s][j] : 127u;
-                const uint32_t at = gi * (uint32_t)c->PP + (gj == 127u ? (uint32_t)P : gj);
-                c->hentry.push_back(make_uint2(at | (gi << 14) | (gj << 21), (uint32_t)(F.off + i * F.fw + j)));
+                const int gi = i < F.f ? joint[s][i] : joint[s][j];
+                const int gj = i < F.f ? joint[s][j] : P;
+                c->hgfmap[(size_t)gi * c->PP + gj] = F.off + i * F.fw + j;
             }
     }
-    // the Gram reduction writes each entry's value (all at or above the
-    // diagonal: a front's later rows hold smaller joint indices)
-    c->hgfmap.assign((size_t)c->PP * c->PP, -1);
-    for (size_t e = 0; e < c->hentry.size(); ++e) c->hgfmap[c->hentry[e].x & 0x3FFFu] = (int)e;
     t.nsn = nsn;
     t.nlev = nlev;
     t.elems = elems;
-    t.nentry = (int)c->hentry.size();
     t.nwords = (int)B.size();
-    t.ok = (c->PP * c->PP <= (1 << 14) && tree_solve_fits(elems, t.nwords)) ? 1 : 0;
+    t.ok = tree_solve_fits(elems, t.nwords) ? 1 : 0;
 }
 
 // per-stream constants: association cutoff, weights, prior and active mask
@@ -512,17 +507,15 @@ void stream_layout(Stream* c) {
     uint32_t* anc = carve<uint32_t>(c, 4 * c->L);
     S.anc = anc;
     S.partials = carve<float>(c, (size_t)c->negrid * c->PP * c->PP);
-    c->hplan.entry = carve<uint2>(c, (size_t)std::max(1, c->hplan.nentry));
-    c->hplan.blob = carve<uint32_t>(c, (size_t)std::max(1, c->hplan.nwords));
+    c->hplan.blob = carve<uint32_t>(c, (size_t)std::max(4, (c->hplan.nwords + 3) / 4 * 4));
     {
         TreeRef& tr = S.tree;
         const TreePlan& t = c->hplan;
-        tr.entry = t.entry;
         tr.blob = t.blob;
-        tr.gfront = carve<double>(c, (size_t)std::max(1, t.nentry));
+        tr.fimg = carve<double>(c, (size_t)std::max(2, t.elems));
         int* gfmap = carve<int>(c, (size_t)c->PP * c->PP);
         tr.gfmap = t.ok ? gfmap : nullptr;
-        tr.nentry = t.nentry; tr.nwords = t.nwords; tr.nlev = t.nlev; tr.elems = t.elems;
+        tr.nwords = t.nwords; tr.nlev = t.nlev; tr.elems = t.elems;
         tr.o_sched = t.o_sched; tr.o_front = t.o_front;
     }
     c->depth_buf = carve<float>(c, N);
@@ -689,8 +682,8 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
               up(S.m.fan_off, hoff.data(), 4 * (V + 1)) && (c->F == 0 || up(S.m.fan, hfan.data(), 8 * 3 * (size_t)c->F)) &&
               up(S.anc, hanc.data(), 4 * hanc.size()) && up(S.theta, theta0, 8 * (size_t)c->P) &&
               (!S.tree.gfmap || up(S.tree.gfmap, c->hgfmap.data(), sizeof(int) * c->hgfmap.size())) &&
-              (c->hentry.empty() || up(c->hplan.entry, c->hentry.data(), sizeof(uint2) * c->hentry.size())) &&
               (c->hblob.empty() || up(c->hplan.blob, c->hblob.data(), sizeof(uint32_t) * c->hblob.size())) &&
+              (!S.tree.gfmap || hipMemset(S.tree.fimg, 0, sizeof(double) * c->hplan.elems) == hipSuccess) &&
               hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess;
     if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
     S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F;
