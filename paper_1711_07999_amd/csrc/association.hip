@@ -217,15 +217,29 @@ __device__ __forceinline__ bool z_pruned(float zmn, float zmx, float pz, float b
     return g2s > bound || (!found && g2s >= bound);
 }
 
-// One workgroup per 8x8 tile; its four waves hold the same 64 pixels (one per
-// lane) and split the 4x4 cells of each search ring between them.  A cell's
-// vertices are loaded coalesced (one per lane), broadcast through LDS and
-// compared against every lane's point; each lane keeps the key
-// (d2 bits << 32 | vertex id), whose minimum is the nearest vertex with ties
-// to the lower index.  The four waves' keys are combined with an LDS minimum.
-__global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
-    __shared__ float4 scand[4][64];
-    __shared__ unsigned long long skey[64];
+// One workgroup per 8x8 tile, two waves per 4x4 quadrant of it (one cell of
+// the bucket index), each taking two of its pixel rows.  Lane = pixel (8) x
+// slot (8): candidate vertices, loaded coalesced and broadcast through LDS,
+// go through the wave eight at a time, each lane comparing its pixel's point
+// with the candidate of its slot and keeping the key (d2 bits << 32 | vertex
+// id), whose minimum is the nearest vertex with ties to the lower index; the
+// slots of a pixel are combined by shuffles.  The search walks square rings
+// of cells around the quadrant's own cell.
+constexpr int kAssocWaves = 8;
+constexpr int kAssocPass = 256;   // candidates per pass (LDS per wave: 4 KB)
+
+__device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+__device__ __forceinline__ unsigned long long slot_min(unsigned long long k) {
+    k = min_u64(k, __shfl_xor(k, 8));
+    k = min_u64(k, __shfl_xor(k, 16));
+    return min_u64(k, __shfl_xor(k, 32));
+}
+
+__global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vsel) {
+    __shared__ float4 scand[kAssocWaves][kAssocPass];
+    __shared__ int4 scount[kAssocWaves];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_TILE, blockIdx.x, local)];
     const DevCam& c = S.c;
@@ -237,9 +251,11 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
     const float4* __restrict__ verts = S.verts[S.v_cur ^ vsel];
     int32_t* __restrict__ assoc = S.assoc;
     const int lane = wave_lane(), wid = threadIdx.x >> 6;
-    const int tile = local;
+    const int tile = b.torder[local];
     const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
-    const int u = tx * 8 + (lane & 7), v = ty * 8 + (lane >> 3);
+    const int q = lane & 7, slot = lane >> 3, quad = wid >> 1, rows = 2 * (wid & 1);
+    const int ccx = 2 * tx + (quad & 1), ccy = 2 * ty + (quad >> 1);   // the quadrant's cell
+    const int u = ccx * 4 + (q & 3), v = ccy * 4 + rows + (q >> 2);
     const bool inimg = u < c.W && v < c.H;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     bool valid = false;
@@ -260,9 +276,11 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
     }
     const float tau2 = tau * tau;
     const uint32_t tau2_bits = __float_as_uint(tau2);
-    // key of the best candidate so far; an unmatched valid pixel holds
-    // (tau^2, 0), which no candidate at distance >= tau can undercut
+    // key of the best candidate so far (this slot's, and the pixel's as of
+    // the last finished ring); an unmatched valid pixel holds (tau^2, 0),
+    // which no candidate at distance >= tau can undercut
     unsigned long long key = valid ? ((unsigned long long)tau2_bits << 32) : ~0ull;
+    unsigned long long best = key;
     // pixel rings that can hold a vertex closer than tau (over-estimate is
     // harmless), capped by the image; the wave's widest need sets the cells
     int rmax = 0;
@@ -273,12 +291,13 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
     }
     int rw = rmax;
     for (int o = 32; o > 0; o >>= 1) rw = max(rw, __shfl_xor(rw, o));
+    // rings 0..Rc of cells cover every pixel within 4 Rc of the quadrant
     const int Rc = (rw + 3) / 4 + 1;
     bool done = !valid;
     const int cells_x = 2 * c.tiles_x, cells_y = 2 * c.tiles_y;
-    // cheap rejection of background tiles: if no tile of the wave's window has
-    // a z range within tau of the z range of the wave's points, nothing can
-    // be found.  One tile of the window per lane, all loads in flight at once.
+    // cheap rejection of background: if no tile of the wave's window has a z
+    // range within tau of the z range of the wave's points, nothing can be
+    // found.  One tile of the window per lane, all loads in flight at once.
     bool candidate_tiles = false;
     if (__any(valid)) {
         float pmin = valid ? pz : INFINITY, pmax = valid ? pz : -INFINITY;
@@ -292,111 +311,161 @@ __global__ void __launch_bounds__(256) k_associate(Batch B, int vsel) {
         const int wy0 = max(ty - tr, 0), wy1 = min(ty + tr, c.tiles_y - 1);
         const int nwx = wx1 - wx0 + 1, nwin = nwx * (wy1 - wy0 + 1);
         for (int base = 0; base < nwin && !candidate_tiles; base += 64) {
-            const int q = base + lane;
+            const int qw = base + lane;
             bool cand = false;
-            if (q < nwin) {
-                const int wy = q / nwx;
-                const float2 tz = b.tz[(wy0 + wy) * c.tiles_x + wx0 + (q - wy * nwx)];
+            if (qw < nwin) {
+                const int wy = qw / nwx;
+                const float2 tz = b.tz[(wy0 + wy) * c.tiles_x + wx0 + (qw - wy * nwx)];
                 cand = tz.x <= tz.y && tz.x < pmax + tz_tol && tz.y > pmin - tz_tol;
             }
             candidate_tiles = __any(cand);
         }
     }
     if (candidate_tiles) {
-        for (int R = 0; R <= Rc; ++R) {
-            // perimeter of the cell square [2tx - R, 2tx + 1 + R] x [2ty - R, 2ty + 1 + R]
-            const int side = 2 + 2 * R;
-            const int ncell = R == 0 ? 4 : 4 * side - 4;
-            const int x0 = 2 * tx - R, y0 = 2 * ty - R;
-            // the wave's cells of this ring are q = wid + 4 k; lane k loads the
-            // record of its cell, so a ring costs one round trip per 64 cells
-            for (int cbase = 0; cbase < ncell; cbase += 256) {
-                const int qm = cbase + wid + 4 * lane;
-                uint4 myrec = make_uint4(0u, 0u, 0u, 0u);
-                int mycx = 0, mycy = 0;
-                if (qm < ncell) {
-                    if (R == 0) { mycx = x0 + (qm & 1); mycy = y0 + (qm >> 1); }
-                    else if (qm < side) { mycx = x0 + qm; mycy = y0; }
-                    else if (qm < 2 * side) { mycx = x0 + (qm - side); mycy = y0 + side - 1; }
-                    else if (qm < 3 * side - 2) { mycx = x0; mycy = y0 + 1 + (qm - 2 * side); }
-                    else { mycx = x0 + side - 1; mycy = y0 + 1 + (qm - (3 * side - 2)); }
-                    if (mycx >= 0 && mycy >= 0 && mycx < cells_x && mycy < cells_y)
-                        myrec = b.cellrec[(((mycy >> 1) * c.tiles_x + (mycx >> 1)) << 2) | ((mycy & 1) << 1) | (mycx & 1)];
-                }
-                unsigned long long pending = __ballot(myrec.y != 0u);
-                while (pending) {
-                    const int k = __builtin_ctzll(pending);
-                    pending &= pending - 1ull;
-                    const uint32_t c_off = (uint32_t)__builtin_amdgcn_readlane((int)myrec.x, k);
-                    const uint32_t c_cnt = (uint32_t)__builtin_amdgcn_readlane((int)myrec.y, k);
-                    const float c_zmn = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)myrec.z, k));
-                    const float c_zmx = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)myrec.w, k));
-                    const int ccx = __builtin_amdgcn_readlane(mycx, k), ccy = __builtin_amdgcn_readlane(mycy, k);
-                    bool need = false;
-                    if (!done) {
-                        const int X0 = ccx * 4, Y0 = ccy * 4;
-                        const int mx = max(max(X0 - u, u - (X0 + 3)), 0), my = max(max(Y0 - v, v - (Y0 + 3)), 0);
-                        const float bound = __uint_as_float((uint32_t)(key >> 32));
-                        const bool found = (uint32_t)(key >> 32) < tau2_bits;
-                        const float lb = ring_lb(c, pz, max(mx, my));
-                        need = !(lb * lb >= bound) && !z_pruned(c_zmn, c_zmx, pz, bound, found);
-                    }
-                    if (!__any(need)) continue;
-                    for (uint32_t base = 0; base < c_cnt; base += 64) {
-                        const int n = min(64u, c_cnt - base);
-                        if (lane < n) scand[wid][lane] = b.sorted[c_off + base + lane];
-                        __builtin_amdgcn_wave_barrier();
-                        for (int kk2 = 0; kk2 < n; ++kk2) {
-                            const float4 sv = scand[wid][kk2];
-                            const float dx = sv.x - px, dy = sv.y - py, dz = sv.z - pz;
-                            const float d2 = (dx * dx + dy * dy) + dz * dz;
-                            const unsigned long long kk =
-                                ((unsigned long long)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(sv.w);
-                            if (need && kk < key) key = kk;
-                        }
-                        __builtin_amdgcn_wave_barrier();
-                    }
-                }
+        // The cells of the (2 Rc + 1)^2 square around the quadrant's cell, in
+        // ring order (ring R >= 1, the perimeter of the (2R+1)^2 square,
+        // starts at entry (2R-1)^2), come 64 at a time, one record per lane.
+        // A block is searched in batches -- in the first block, rings 0 and 1
+        // (entries 0..8) first, then the rest -- and a batch takes every cell
+        // some pixel still needs under the bound left by the batches before,
+        // loading all of its candidates before comparing any.
+        auto run_batch = [&](unsigned long long cells, const uint4& rec, int rcx, int rcy) {
+            // lane = cell: is it needed by one of the wave's 8 pixels (the
+            // pixel-distance and z-range bounds cannot exclude a better vertex)?
+            // A finished pixel counts with bound 0, which excludes everything.
+            const uint32_t bbits = done ? 0u : (uint32_t)(best >> 32);
+            const float c_zmn = __uint_as_float(rec.z), c_zmx = __uint_as_float(rec.w);
+            const int X0 = rcx * 4, Y0 = rcy * 4;
+            bool need = false;
+#pragma unroll
+            for (int pq = 0; pq < 8; ++pq) {
+                const int up = ccx * 4 + (pq & 3), vp = ccy * 4 + rows + (pq >> 2);
+                const float pzp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pz), pq));
+                const uint32_t bp = (uint32_t)__builtin_amdgcn_readlane((int)bbits, pq);
+                const float bound = __uint_as_float(bp);
+                const int mx = max(max(X0 - up, up - (X0 + 3)), 0), my = max(max(Y0 - vp, vp - (Y0 + 3)), 0);
+                const float lb = ring_lb(c, pzp, max(mx, my));
+                need = need || (!(lb * lb >= bound) && !z_pruned(c_zmn, c_zmx, pzp, bound, bp < tau2_bits));
             }
-            // every cell outside the square is at least m_next pixels away
+            const unsigned long long needed = __ballot(need) & cells;
+            uint32_t total = 0u;
+            for (unsigned long long m = needed; m; m &= m - 1ull)
+                total += (uint32_t)__builtin_amdgcn_readlane((int)rec.y, __builtin_ctzll(m));
+            // the needed cells' candidates in cell order, up to kAssocPass per
+            // pass, copied from the sorted vertices straight into LDS (one DMA
+            // load per cell, all in flight together); every pixel compares
+            // every candidate (extra candidates are real vertices: the minimum
+            // stays exact)
+            for (uint32_t pass = 0; pass < total; pass += kAssocPass) {
+                const uint32_t pend = pass + (uint32_t)kAssocPass;
+                uint32_t pre = 0u;
+                for (unsigned long long m = needed; m; m &= m - 1ull) {
+                    const int k = __builtin_ctzll(m);
+                    const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, k);
+                    const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rec.y, k);
+                    const uint32_t a0 = max(pre, pass), a1 = min(pre + cnt, pend);
+                    for (uint32_t s0 = a0; s0 < a1; s0 += 64u) {
+                        if ((uint32_t)lane < a1 - s0)
+                            __builtin_amdgcn_global_load_lds(
+                                (const void*)(b.sorted + off + (s0 - pre) + lane),
+                                (__attribute__((address_space(3))) void*)&scand[wid][s0 - pass], 16, 0, 0);
+                    }
+                    pre += cnt;
+                    if (pre >= pend) break;   // the rest belongs to later passes
+                }
+                __builtin_amdgcn_s_waitcnt(0);   // the copies have landed in LDS
+                __builtin_amdgcn_wave_barrier();
+                const int n = (int)min((uint32_t)kAssocPass, total - pass);
+                // eight slots x four steps per trip, the LDS reads issued together
+                for (int i0 = 0; i0 < n; i0 += 32) {
+                    float4 sv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) sv[j] = scand[wid][min(i0 + 8 * j + slot, kAssocPass - 1)];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float dx = sv[j].x - px, dy = sv[j].y - py, dz = sv[j].z - pz;
+                        const float d2 = (dx * dx + dy * dy) + dz * dz;
+                        const unsigned long long kk =
+                            ((unsigned long long)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(sv[j].w);
+                        if (valid && i0 + 8 * j + slot < n && kk < key) key = kk;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            best = slot_min(key);
+        };
+        const int last = (2 * Rc + 1) * (2 * Rc + 1);
+        for (int cur = 0; cur < last; cur += 64) {
+            const int l2 = cur + lane;
+            int sq = (int)sqrtf((float)l2);
+            while ((sq + 1) * (sq + 1) <= l2) ++sq;
+            while (sq * sq > l2) --sq;
+            const int rr = (sq + 1) >> 1;
+            uint4 myrec = make_uint4(0u, 0u, 0u, 0u);
+            int mycx = 0, mycy = 0;
+            if (l2 < last) {
+                const int kq = rr == 0 ? 0 : l2 - (2 * rr - 1) * (2 * rr - 1);
+                const int side = 2 * rr + 1;
+                if (rr == 0) { mycx = ccx; mycy = ccy; }
+                else if (kq < side) { mycx = ccx - rr + kq; mycy = ccy - rr; }
+                else if (kq < 2 * side) { mycx = ccx - rr + (kq - side); mycy = ccy + rr; }
+                else if (kq < 3 * side - 2) { mycx = ccx - rr; mycy = ccy - rr + 1 + (kq - 2 * side); }
+                else { mycx = ccx + rr; mycy = ccy - rr + 1 + (kq - (3 * side - 2)); }
+                if (mycx >= 0 && mycy >= 0 && mycx < cells_x && mycy < cells_y)
+                    myrec = b.cellrec[(((mycy >> 1) * c.tiles_x + (mycx >> 1)) << 2) | ((mycy & 1) << 1) | (mycx & 1)];
+            }
+            const unsigned long long todo = __ballot(myrec.y != 0u);
+            if (cur == 0) {
+                run_batch(todo & 0x1FFull, myrec, mycx, mycy);
+                run_batch(todo & ~0x1FFull, myrec, mycx, mycy);
+            } else {
+                run_batch(todo, myrec, mycx, mycy);
+            }
+            // the complete rings so far; every cell outside their square is
+            // at least m_next pixels away
+            const int end = min(cur + 64, last);
+            int Rd = 0;
+            while ((2 * Rd + 3) * (2 * Rd + 3) <= end) ++Rd;
             if (!done) {
-                const int X0b = (2 * tx - R) * 4, X1b = (2 * tx + 2 + R) * 4 - 1;
-                const int Y0b = (2 * ty - R) * 4, Y1b = (2 * ty + 2 + R) * 4 - 1;
+                const int X0b = (ccx - Rd) * 4, X1b = (ccx + Rd) * 4 + 3;
+                const int Y0b = (ccy - Rd) * 4, Y1b = (ccy + Rd) * 4 + 3;
                 const int m_next = min(min(u - X0b, X1b - u), min(v - Y0b, Y1b - v)) + 1;
                 const float lb = ring_lb(c, pz, m_next);
-                done = lb * lb >= __uint_as_float((uint32_t)(key >> 32));
+                done = lb * lb >= __uint_as_float((uint32_t)(best >> 32));
             }
             if (__all(done)) break;
         }
     }
-    // combine the four waves' keys
-    if (wid == 0) skey[lane] = key;
-    __syncthreads();
-    if (wid != 0 && valid) atomicMin(&skey[lane], key);
-    __syncthreads();
-    if (wid != 0) return;
-    key = skey[lane];
-    int best = -1;
+    key = slot_min(key);
+    // slot 0 lanes hold the pixels
+    int bestv = -1;
     bool first = false;
-    if (valid && (uint32_t)(key >> 32) < tau2_bits) {
-        best = (int)(uint32_t)key;
-        const float4 s = verts[best];
-        const float dx = s.x - px, dy = s.y - py, dz = s.z - pz;
-        uint32_t old = atomicAdd(&a.cnt[best], 1u);
-        atomicAdd((unsigned long long*)&a.sx[best], (unsigned long long)(long long)rintf(-dx * 4294967296.0f));
-        atomicAdd((unsigned long long*)&a.sy[best], (unsigned long long)(long long)rintf(-dy * 4294967296.0f));
-        atomicAdd((unsigned long long*)&a.sz[best], (unsigned long long)(long long)rintf(-dz * 4294967296.0f));
+    const bool mine = slot == 0;
+    if (mine && valid && (uint32_t)(key >> 32) < tau2_bits) {
+        bestv = (int)(uint32_t)key;
+        const float4 sv = verts[bestv];
+        const float dx = sv.x - px, dy = sv.y - py, dz = sv.z - pz;
+        uint32_t old = atomicAdd(&a.cnt[bestv], 1u);
+        atomicAdd((unsigned long long*)&a.sx[bestv], (unsigned long long)(long long)rintf(-dx * 4294967296.0f));
+        atomicAdd((unsigned long long*)&a.sy[bestv], (unsigned long long)(long long)rintf(-dy * 4294967296.0f));
+        atomicAdd((unsigned long long*)&a.sz[bestv], (unsigned long long)(long long)rintf(-dz * 4294967296.0f));
         first = old == 0u;
     }
-    if (inimg) assoc[v * c.W + u] = best;
+    if (mine && inimg) assoc[v * c.W + u] = bestv;
     // per-workgroup counts go to this workgroup's own slot (no shared counter:
     // device-wide atomics on one address serialise across the chip)
-    const unsigned long long vb = __ballot(valid), ab = __ballot(best >= 0), fb = __ballot(first);
-    if (lane == 0) b.bstat[tile] = make_int4(__popcll(vb), __popcll(ab), __popcll(fb), 0);
+    const unsigned long long vb = __ballot(mine && valid), ab = __ballot(bestv >= 0), fb = __ballot(first);
+    if (lane == 0) scount[wid] = make_int4(__popcll(vb), __popcll(ab), __popcll(fb), 0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int4 t = scount[0];
+        for (int w = 1; w < kAssocWaves; ++w) { t.x += scount[w].x; t.y += scount[w].y; t.z += scount[w].z; }
+        b.bstat[tile] = t;
+    }
 }
 
 void launch_associate(const Launch& L, int vsel) {
-    launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_TILE]), dim3(256), 0, L.B, vsel);
+    launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_TILE]), dim3(64 * kAssocWaves), 0, L.B, vsel);
 }
 
 }  // namespace trk

@@ -117,6 +117,8 @@ struct Buckets {
     float4* sorted;    // [V] (x, y, z, vertex id bits) grouped by bucket
     uint4* cellrec;    // [tiles*4] per 4x4 cell: (offset, count, zmin bits, zmax bits)
     int4* bstat;       // [tiles] valid, matched, newly observed pixels per tile
+    const int* torder; // [tiles] the order association takes tiles in: nearest the image centre
+                       // first (where the subject and the longest searches usually are)
 };
 
 // Summary of one frame, written by the frame-end kernel.

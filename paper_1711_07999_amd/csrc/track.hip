@@ -540,6 +540,7 @@ void stream_layout(Stream* c) {
     b.tsum = carve<uint32_t>(c, c->ntiles);
     b.toff = carve<uint32_t>(c, c->ntiles);
     b.tz = carve<float2>(c, c->ntiles);
+    b.torder = carve<int>(c, c->ntiles);
     b.vpix = carve<int>(c, V);
     b.vslot = carve<uint32_t>(c, V);
     b.sorted = carve<float4>(c, V);
@@ -693,6 +694,18 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
     const double rmax = std::sqrt(1.0 + ex * ex + ey * ey);
     S.c = DevCam{c->W, c->H, tx, ty, camera->fx, camera->fy, camera->cx, camera->cy,
                  (float)((1.0 - 1e-4) / (fmax * rmax))};
+    {
+        // tiles by distance of their centre from the principal point (ties: index)
+        std::vector<int> order(c->ntiles);
+        std::vector<double> dist(c->ntiles);
+        for (int t = 0; t < c->ntiles; ++t) {
+            order[t] = t;
+            const double dx = (t % tx) * 8 + 3.5 - camera->cx, dy = (t / tx) * 8 + 3.5 - camera->cy;
+            dist[t] = dx * dx + dy * dy;
+        }
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return dist[a] < dist[b2]; });
+        if (!up(S.b.torder, order.data(), sizeof(int) * order.size())) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
+    }
     int rc;
     if ((rc = stream_set_params(c, params))) { stream_free(c); return rc; }
     std::vector<float> z3(3 * V, 0.0f);
