@@ -180,10 +180,10 @@ __global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
         b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
     } else {
         const int i = (local - half) * blockDim.x + threadIdx.x;
-        if (i >= S.m.V) return;
+        const bool live = i < S.m.V;
         float nx, ny, nz;
-        vertex_normal(S.m, v, i, nx, ny, nz);
-        S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz;
+        vertex_normal(S.m, v, i, live, nx, ny, nz);   // the whole wave
+        if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
     }
 }
 

@@ -68,6 +68,8 @@ struct alignas(16) TreePlan {
     const uint32_t* blob;
 };
 
+constexpr int kFanInline = 8;   // incident faces of a vertex held in the inline (per-slot) table
+
 // Mesh, weights and tables in structure-of-arrays device form.
 struct DevModel {
     int P, L, V, F;
@@ -76,6 +78,7 @@ struct DevModel {
     const uint32_t *links;         // four link bytes per vertex, 0xFF = unused
     const int4 *nbr;               // neighbours, -1 = none
     const uint32_t *fan_off;       // [V+1] incident-face list per vertex
+    const int2 *fan8;              // [kFanInline][V] its first kFanInline entries, padded with (i, i)
     const int2 *fan;               // (b, c) with face (i, b, c) counter-clockwise
 };
 

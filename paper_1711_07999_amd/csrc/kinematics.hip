@@ -95,10 +95,10 @@ __global__ void __launch_bounds__(256) k_normals(Batch B, int vsel) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
     const int i = local * blockDim.x + threadIdx.x;
-    if (i >= S.m.V) return;
+    const bool live = i < S.m.V;
     float nx, ny, nz;
-    vertex_normal(S.m, S.verts[S.v_cur ^ vsel], i, nx, ny, nz);
-    S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz;
+    vertex_normal(S.m, S.verts[S.v_cur ^ vsel], i, live, nx, ny, nz);   // the whole wave
+    if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
 }
 
 void launch_normals(const Launch& L, int vsel) {

@@ -594,16 +594,17 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
     __syncthreads();
     const int i = local * blockDim.x + threadIdx.x;
-    if (i >= m.V) return;
+    const bool live = i < m.V;
+    const uint32_t c = live ? a.cnt[i] : 0u;
+    float nx, ny, nz;
+    vertex_normal(m, v_new, i, live && c > 0u, nx, ny, nz);   // the whole wave
+    if (!live) return;
     const T px = phi.x[i], py = phi.y[i], pz = phi.z[i];
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
-    const uint32_t c = a.cnt[i];
     float H[8];
     dq_blend(sdq, m.w[i], m.links[i], H);
     if (c > 0u) {
-        float nx, ny, nz;
-        vertex_normal(m, v_new, i, nx, ny, nz);
         if ((nx * nx + ny * ny + nz * nz) > 0.0f) {
             T w = H[0], x = H[1], y = H[2], z = H[3];
             T s = T(2) / (w * w + x * x + y * y + z * z);

@@ -46,33 +46,62 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int i, float4 p) {
     }
 }
 
-// Sum over the incident faces (b, c) of (v_b - v_i) x (v_c - v_i), in fan
-// order, normalised; zero if the sum vanishes.  One operation order (no
-// contraction) wherever it is inlined, so every kernel gets the same bits.
-__device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* __restrict__ v, int i, float& nx,
-                                              float& ny, float& nz) {
+// Sum over the incident faces (b, c) of (v_b - v_i) x (v_c - v_i),
+// normalised; zero if the sum vanishes.  One operation order (no
+// contraction) wherever it is inlined, so every kernel gets the same bits:
+// the first kFanInline faces in fan order from the inline table (its padding
+// entries (i, i) add an exact zero; all loads issued at once), then, for a
+// vertex of more faces, the rest summed by the whole wave (lane l takes
+// faces l, l + 64, ... of the rest; a fixed tree adds the lanes' sums).
+// Every lane of the wave must call it together; lanes with live == false
+// compute nothing of their own but take part in the shared work.
+__device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* __restrict__ v, int i, bool live,
+                                              float& nx, float& ny, float& nz) {
 #pragma clang fp contract(off)
-    const float4 p = v[i];
+    const int ii = live ? i : 0;
+    const float4 p = v[ii];
+    const uint32_t e0 = live ? m.fan_off[i] : 0u, e1 = live ? m.fan_off[i + 1] : 0u;
+    int2 bc[kFanInline];
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) bc[k] = live ? m.fan8[(size_t)k * m.V + i] : make_int2(0, 0);
+    float4 vb[kFanInline], vc[kFanInline];
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) { vb[k] = v[bc[k].x]; vc[k] = v[bc[k].y]; }
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    const uint32_t e0 = m.fan_off[i], e1 = m.fan_off[i + 1];
-    // four faces at a time: their fan entries, then their eight vertices, are
-    // loaded together (the sum still runs in fan order)
-    for (uint32_t e = e0; e < e1; e += 4) {
-        int2 bc[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) bc[k] = e + k < e1 ? m.fan[e + k] : make_int2(i, i);
-        float4 vb[4], vc[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) { vb[k] = v[bc[k].x]; vc[k] = v[bc[k].y]; }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (e + k >= e1) break;
-            const float ax = vb[k].x - p.x, ay = vb[k].y - p.y, az = vb[k].z - p.z;
-            const float bx = vc[k].x - p.x, by = vc[k].y - p.y, bz = vc[k].z - p.z;
-            sx += ay * bz - az * by;
-            sy += az * bx - ax * bz;
-            sz += ax * by - ay * bx;
+    for (int k = 0; k < kFanInline; ++k) {
+        const float ax = vb[k].x - p.x, ay = vb[k].y - p.y, az = vb[k].z - p.z;
+        const float bx = vc[k].x - p.x, by = vc[k].y - p.y, bz = vc[k].z - p.z;
+        sx += ay * bz - az * by;
+        sy += az * bx - ax * bz;
+        sz += ax * by - ay * bx;
+    }
+    const int lane = threadIdx.x & 63;
+    for (unsigned long long h = __ballot(live && e1 - e0 > (uint32_t)kFanInline); h; h &= h - 1ull) {
+        const int k = __builtin_ctzll(h);
+        const int hv = __builtin_amdgcn_readlane(ii, k);
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)e0, k) + kFanInline;
+        const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)e1, k);
+        const float4 ph = v[hv];
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+        for (uint32_t e = a + (uint32_t)lane; e < z; e += 64u) {
+            const int2 f = m.fan[e];
+            const float4 b = v[f.x], c = v[f.y];
+            const float ax = b.x - ph.x, ay = b.y - ph.y, az = b.z - ph.z;
+            const float bx = c.x - ph.x, by = c.y - ph.y, bz = c.z - ph.z;
+            tx += ay * bz - az * by;
+            ty += az * bx - ax * bz;
+            tz += ax * by - ay * bx;
         }
+        for (int o = 32; o > 0; o >>= 1) {
+            tx += __shfl_down(tx, o);
+            ty += __shfl_down(ty, o);
+            tz += __shfl_down(tz, o);
+        }
+        const float ex = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tx), 0));
+        const float ey = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ty), 0));
+        const float ez = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tz), 0));
+        if (lane == k) { sx += ex; sy += ey; sz += ez; }
     }
     const float l = sqrtf(sx * sx + sy * sy + sz * sz);
     const float inv = l > 0.0f ? 1.0f / l : 0.0f;

@@ -532,6 +532,7 @@ void stream_layout(Stream* c) {
     S.m.nbr = carve<int4>(c, V);
     S.m.fan_off = carve<uint32_t>(c, V + 1);
     S.m.fan = carve<int2>(c, 3 * (size_t)c->F);
+    S.m.fan8 = carve<int2>(c, (size_t)kFanInline * V);
     Buckets& b = S.b;
     b.pcnt = carve<uint32_t>(c, c->npad);
     b.pzmin = carve<uint32_t>(c, c->npad);
@@ -672,6 +673,14 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
         hfan[fill[b]++] = make_int2(d, a);
         hfan[fill[d]++] = make_int2(a, b);
     }
+    // the first kFanInline fan entries of each vertex, slot-major so that a
+    // thread's loads are independent and a wave's coalesced
+    std::vector<int2> hfan8((size_t)kFanInline * V);
+    for (size_t i = 0; i < V; ++i)
+        for (int k = 0; k < kFanInline; ++k) {
+            const uint32_t e = hoff[i] + (uint32_t)k;
+            hfan8[(size_t)k * V + i] = e < hoff[i + 1] ? hfan[e] : make_int2((int)i, (int)i);
+        }
     std::vector<uint32_t> hanc(4 * (size_t)c->L);
     for (int l = 0; l < c->L; ++l)
         for (int q = 0; q < 4; ++q) hanc[4 * l + q] = c->hjt.anc[l][q];
@@ -681,6 +690,7 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
     bool ok = up(S.m.rx, h.data(), 4 * V) && up(S.m.ry, h.data() + V, 4 * V) && up(S.m.rz, h.data() + 2 * V, 4 * V) &&
               up(S.m.w, hw.data(), 16 * V) && up(S.m.links, hl.data(), 4 * V) && up(S.m.nbr, hn.data(), 16 * V) &&
               up(S.m.fan_off, hoff.data(), 4 * (V + 1)) && (c->F == 0 || up(S.m.fan, hfan.data(), 8 * 3 * (size_t)c->F)) &&
+              up(S.m.fan8, hfan8.data(), sizeof(int2) * hfan8.size()) &&
               up(S.anc, hanc.data(), 4 * hanc.size()) && up(S.theta, theta0, 8 * (size_t)c->P) &&
               (!S.tree.gfmap || up(S.tree.gfmap, c->hgfmap.data(), sizeof(int) * c->hgfmap.size())) &&
               (c->hblob.empty() || up(c->hplan.blob, c->hblob.data(), sizeof(uint32_t) * c->hblob.size())) &&
