@@ -41,18 +41,34 @@ __device__ __forceinline__ void block_of(int idx, int nb, int& I, int& J) {
     I = J = 0;
 }
 
+// what a vertex's row needs, read in one round of loads
+struct VertexIn {
+    float4 w, v;
+    uint32_t links, cnt;
+    float nx, ny, nz, x0, x1, x2;   // normal; template point + offset
+    long long sx, sy, sz;           // fixed-point sums of its points' offsets
+};
+
+__device__ __forceinline__ void vertex_load(const DevModel& m, int i, const float4* v, const Vec3Buf& n,
+                                            const Vec3Buf& phi, const Accum& a, VertexIn& in) {
+    in.w = m.w[i];
+    in.links = m.links[i];
+    in.v = v[i];
+    in.nx = n.x[i]; in.ny = n.y[i]; in.nz = n.z[i];
+    in.x0 = m.rx[i] + phi.x[i]; in.x1 = m.ry[i] + phi.y[i]; in.x2 = m.rz[i] + phi.z[i];
+    in.cnt = a.cnt[i];
+    in.sx = (long long)a.sx[i]; in.sy = (long long)a.sy[i]; in.sz = (long long)a.sz[i];
+}
+
 // per-vertex 6-vectors of the Jacobian (one per influence) and the residual
-__device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq, int i, const float4* v,
-                                             const Vec3Buf& n, const Vec3Buf& phi, const Accum& a, float* G,
-                                             float& r_out) {
+__device__ __forceinline__ void vertex_terms(const float* sdq, const VertexIn& in, float* G, float& r_out) {
     float H[8], sg[4];
-    const float4 w = m.w[i];
-    const uint32_t lk = m.links[i];
+    const float4 w = in.w;
+    const uint32_t lk = in.links;
     dq_blend(sdq, w, lk, H, sg);
-    const float nx = n.x[i], ny = n.y[i], nz = n.z[i];
-    const float4 vi = v[i];
-    const float vx = vi.x, vy = vi.y, vz = vi.z;
-    const float x[4] = {0.0f, m.rx[i] + phi.x[i], m.ry[i] + phi.y[i], m.rz[i] + phi.z[i]};
+    const float nx = in.nx, ny = in.ny, nz = in.nz;
+    const float vx = in.v.x, vy = in.v.y, vz = in.v.z;
+    const float x[4] = {0.0f, in.x0, in.x1, in.x2};
     const float nq[4] = {0.0f, nx, ny, nz};
     const float N = H[0] * H[0] + H[1] * H[1] + H[2] * H[2] + H[3] * H[3];
     const float s2 = 2.0f / N;
@@ -92,8 +108,8 @@ __device__ __forceinline__ void vertex_terms(const DevModel& m, const float* sdq
         g[4] = ww * t3[2];
         g[5] = ww * t3[3];
     }
-    const float inv = 1.0f / ((float)a.cnt[i] * 4294967296.0f);
-    const float dx = (float)a.sx[i] * inv, dy = (float)a.sy[i] * inv, dz = (float)a.sz[i] * inv;
+    const float inv = 1.0f / ((float)in.cnt * 4294967296.0f);
+    const float dx = (float)in.sx * inv, dy = (float)in.sy * inv, dz = (float)in.sz * inv;
     r_out = nx * dx + ny * dy + nz * dz;
 }
 
@@ -165,12 +181,14 @@ __global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, in
 
     for (int chunk = wg; chunk < nchunks; chunk += S.negrid) {
         __syncthreads();  // the previous chunk's tile and counts are consumed
-        // 1. compact the observed vertices of this chunk
+        // 1. compact the observed vertices of this chunk (every read of a
+        //    vertex's row issued before the compaction)
         bool obs = false;
         int i = chunk * kNeRows + tid;
-        if (tid < kNeRows && i < m.V && a.cnt[i] > 0u) {
-            float nx = n.x[i], ny = n.y[i], nz = n.z[i];
-            obs = (nx * nx + ny * ny + nz * nz) > 0.0f;
+        VertexIn in;
+        if (tid < kNeRows && i < m.V) {
+            vertex_load(m, i, v, n, phi, a, in);
+            obs = in.cnt > 0u && (in.nx * in.nx + in.ny * in.ny + in.nz * in.nz) > 0.0f;
         }
         unsigned long long bal = __ballot(obs);
         if (lane == 0 && wid < 2) scount[wid] = __popcll(bal);
@@ -179,9 +197,9 @@ __global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, in
         if (obs) {
             int row = __popcll(bal & ((1ull << lane) - 1ull)) + (wid == 1 ? scount[0] : 0);
             float r;
-            vertex_terms(m, sdq, i, v, n, phi, a, &sG[row * kGStride], r);
+            vertex_terms(sdq, in, &sG[row * kGStride], r);
             sr[row] = r;
-            slink[row] = m.links[i];
+            slink[row] = in.links;
         }
         __syncthreads();
         if (nrows == 0) continue;
