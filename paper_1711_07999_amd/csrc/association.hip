@@ -86,54 +86,35 @@ void launch_bucket_count(const Launch& L, int vsel, int which) {
 
 // exclusive prefix over tiles, one workgroup of 1024 threads; the tile sums
 // are zeroed for the next count
-__global__ void __launch_bounds__(1024) k_tile_scan(Batch B) {
-    int local;
-    const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
-    const Buckets& b = S.b;
-    const int ntiles = S.c.tiles_x * S.c.tiles_y;
-    __shared__ uint32_t wsum[16];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    const int lane = wave_lane(), wid = threadIdx.x >> 6;
-    for (int base = 0; base < ntiles; base += 1024) {
-        int i = base + threadIdx.x;
-        uint32_t x = 0u;
-        if (i < ntiles) {
-            x = b.tsum[i];
-            b.tsum[i] = 0u;
-        }
-        uint32_t incl = x;
-        for (int o = 1; o < 64; o <<= 1) {
-            uint32_t y = __shfl_up(incl, o);
-            if (lane >= o) incl += y;
-        }
-        if (lane == 63) wsum[wid] = incl;
-        __syncthreads();
-        uint32_t wpre = 0, total = 0;
-        for (int w = 0; w < 16; ++w) {
-            uint32_t s = wsum[w];
-            if (w < wid) wpre += s;
-            total += s;
-        }
-        if (i < ntiles) b.toff[i] = carry + wpre + incl - x;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += total;
-        __syncthreads();
-    }
-}
 
 // Per-pixel (offset, count, zmin, zmax), the same record per 4x4 cell (the 16
 // consecutive Morton positions of a tile quadrant) and the tile's z range;
 // one wave per tile.  The pixel counters are reset for the next count.
 __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
+    __shared__ uint32_t spart[4];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_TILE4, blockIdx.x, local)];
     const Buckets& b = S.b;
     const int ntiles = S.c.tiles_x * S.c.tiles_y;
-    const int tile = local * 4 + (threadIdx.x >> 6);
+    const int wid = threadIdx.x >> 6, lane = wave_lane();
+    // this workgroup's first offset: the vertices of every earlier tile (the
+    // workgroup sums the tile counts itself; they are cleared by the scatter)
+    const int t0 = local * 4;
+    uint32_t part = 0u;
+    for (int t = threadIdx.x; t < t0; t += 1024) {   // four loads in flight per thread
+        const uint32_t a0 = b.tsum[t];
+        const uint32_t a1 = t + 256 < t0 ? b.tsum[t + 256] : 0u;
+        const uint32_t a2 = t + 512 < t0 ? b.tsum[t + 512] : 0u;
+        const uint32_t a3 = t + 768 < t0 ? b.tsum[t + 768] : 0u;
+        part += (a0 + a1) + (a2 + a3);
+    }
+    for (int o = 32; o > 0; o >>= 1) part += (uint32_t)__shfl_xor((int)part, o);
+    if (lane == 0) spart[wid] = part;
+    __syncthreads();
+    const int tile = t0 + wid;
     if (tile >= ntiles) return;
-    const int lane = wave_lane();
+    uint32_t tile_off = spart[0] + spart[1] + spart[2] + spart[3];
+    for (int w = 0; w < wid; ++w) tile_off += b.tsum[t0 + w];
     const int p = (tile << 6) + lane;
     const uint32_t cnt = b.pcnt[p];
     uint32_t incl = cnt;
@@ -141,7 +122,7 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
         uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
-    const uint32_t off = b.toff[tile] + incl - cnt;
+    const uint32_t off = tile_off + incl - cnt;
     const uint32_t zmn = b.pzmin[p], zmx = b.pzmax[p];
     b.rec[p] = make_uint4(off, cnt, zmn, zmx);
     b.pcnt[p] = 0u;
@@ -172,6 +153,9 @@ __global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
     if (local < half) {
         const Buckets& b = S.b;
         const int i = local * blockDim.x + threadIdx.x;
+        // the tile counts were last read by the pixel records: zero them for
+        // the next count
+        for (int t = i; t < S.c.tiles_x * S.c.tiles_y; t += half * 256) b.tsum[t] = 0u;
         if (i >= S.m.V) return;
         const int pix = b.vpix[i];
         if (pix < 0) return;
@@ -188,8 +172,7 @@ __global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
 }
 
 void launch_bucket(const Launch& L, int vsel) {
-    launch_kernel(L, true, false, k_tile_scan, dim3(L.grid[KK_ONE]), dim3(1024), 0, L.B);
-    launch_kernel(L, false, false, k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.B);
+    launch_kernel(L, true, false, k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.B);
     launch_kernel(L, false, true, k_scatter_normals, dim3(L.grid[KK_VERT2]), dim3(256), 0, L.B, vsel);
 }
 

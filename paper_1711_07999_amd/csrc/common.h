@@ -112,8 +112,7 @@ struct Buckets {
     uint32_t* pzmin;   // [Npad] bits of the smallest z     } pixel records are
     uint32_t* pzmax;   // [Npad] bits of the largest z      } built (+inf, 0, 0)
     uint4* rec;        // [Npad] (offset, count, zmin bits, zmax bits)
-    uint32_t* tsum;    // [tiles] vertices per tile (zero again after the tile scan)
-    uint32_t* toff;    // [tiles] exclusive prefix of tsum
+    uint32_t* tsum;    // [tiles] vertices per tile (zero again after the scatter)
     float2* tz;        // [tiles] z range of the tile
     int* vpix;         // [V] bucket of each vertex or -1
     uint32_t* vslot;   // [V] rank inside its bucket

@@ -539,7 +539,6 @@ void stream_layout(Stream* c) {
     b.pzmax = carve<uint32_t>(c, c->npad);
     b.rec = carve<uint4>(c, c->npad);
     b.tsum = carve<uint32_t>(c, c->ntiles);
-    b.toff = carve<uint32_t>(c, c->ntiles);
     b.tz = carve<float2>(c, c->ntiles);
     b.torder = carve<int>(c, c->ntiles);
     b.vpix = carve<int>(c, V);
