@@ -113,19 +113,27 @@ void launch_normals(const Launch& L, int vsel) {
 // last association are summed into the slot's summary.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int last_pose) {
-    __shared__ int s_sum[3][256];
+    __shared__ int s_sum[3][4];
     __shared__ int s_bad;
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     if (!(S.flags & kSlotEndFrame)) return;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ntiles = S.c.tiles_x * S.c.tiles_y;
     int nv = 0, na = 0, no = 0;
-    for (int t = tid; t < ntiles; t += 256) {
-        const int4 b = S.b.bstat[t];
-        nv += b.x; na += b.y; no += b.z;
+    for (int t = tid; t < ntiles; t += 1024) {   // four tiles' counts in flight per thread
+        int4 q[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q[j] = t + 256 * j < ntiles ? S.b.bstat[t + 256 * j] : make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { nv += q[j].x; na += q[j].y; no += q[j].z; }
     }
-    s_sum[0][tid] = nv; s_sum[1][tid] = na; s_sum[2][tid] = no;
+    for (int o = 32; o > 0; o >>= 1) {
+        nv += __shfl_xor(nv, o);
+        na += __shfl_xor(na, o);
+        no += __shfl_xor(no, o);
+    }
+    if (lane == 0) { s_sum[0][wid] = nv; s_sum[1][wid] = na; s_sum[2][wid] = no; }
     if (tid == 0) s_bad = 0;
     __syncthreads();
     for (int k = tid; k < S.m.P; k += 256)
@@ -133,7 +141,7 @@ __global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int 
     __syncthreads();
     if (tid == 0) {
         nv = na = no = 0;
-        for (int q = 0; q < 256; ++q) { nv += s_sum[0][q]; na += s_sum[1][q]; no += s_sum[2][q]; }
+        for (int q = 0; q < 4; ++q) { nv += s_sum[0][q]; na += s_sum[1][q]; no += s_sum[2][q]; }
         DevStats* st = S.st;
         DevSummary& out = *S.summary;
         out.n_valid_px = nv;

@@ -595,15 +595,32 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     __syncthreads();
     const int i = local * blockDim.x + threadIdx.x;
     const bool live = i < m.V;
+    const int ii = live ? i : 0;   // lanes past the end read vertex 0 and store nothing
+    // every per-vertex load that does not wait on another goes out first, so
+    // their latencies overlap the normal's gathers below
     const uint32_t c = live ? a.cnt[i] : 0u;
+    const T px = phi.x[ii], py = phi.y[ii], pz = phi.z[ii];
+    const T qx = phi_prev.x[ii], qy = phi_prev.y[ii], qz = phi_prev.z[ii];
+    const int4 nb = m.nbr[ii];
+    const float4 vo = v_old[ii], vn = v_new[ii];
+    const long long ax = a.sx[ii], ay = a.sy[ii], az = a.sz[ii];
+    const float4 wv = m.w[ii];
+    const uint32_t lk = m.links[ii];
+    const float rx = m.rx[ii], ry = m.ry[ii], rz = m.rz[ii];
+    const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+    T nphi[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = nbs[q] < 0 ? ii : nbs[q];
+        nphi[q][0] = (T)phi.x[j]; nphi[q][1] = (T)phi.y[j]; nphi[q][2] = (T)phi.z[j];
+    }
     float nx, ny, nz;
     vertex_normal(m, v_new, i, live && c > 0u, nx, ny, nz);   // the whole wave
     if (!live) return;
-    const T px = phi.x[i], py = phi.y[i], pz = phi.z[i];
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
     float H[8];
-    dq_blend(sdq, m.w[i], m.links[i], H);
+    dq_blend(sdq, wv, lk, H);
     if (c > 0u) {
         if ((nx * nx + ny * ny + nz * nz) > 0.0f) {
             T w = H[0], x = H[1], y = H[2], z = H[3];
@@ -613,10 +630,9 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
                       s * (x * z - w * y), s * (y * z + w * x), T(1) - s * (x * x + y * y)};
             for (int q = 0; q < 3; ++q) u[q] = -(R[q] * nx + R[3 + q] * ny + R[6 + q] * nz);
             const T inv = T(1) / ((T)c * T(4294967296.0));
-            const float4 vo = v_old[i], vn = v_new[i];
-            T dx = (T)a.sx[i] * inv + ((T)vo.x - (T)vn.x);
-            T dy = (T)a.sy[i] * inv + ((T)vo.y - (T)vn.y);
-            T dz = (T)a.sz[i] * inv + ((T)vo.z - (T)vn.z);
+            T dx = (T)ax * inv + ((T)vo.x - (T)vn.x);
+            T dy = (T)ay * inv + ((T)vo.y - (T)vn.y);
+            T dz = (T)az * inv + ((T)vo.z - (T)vn.z);
             r = (T)nx * dx + (T)ny * dy + (T)nz * dz;
         }
     }
@@ -624,19 +640,16 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     a.cnt[i] = 0u;
     a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
     T alpha = (T)lphi + (T)lt;
-    T g[3] = {u[0] * r + (T)lphi * px + (T)lt * (px - (T)phi_prev.x[i]),
-              u[1] * r + (T)lphi * py + (T)lt * (py - (T)phi_prev.y[i]),
-              u[2] * r + (T)lphi * pz + (T)lt * (pz - (T)phi_prev.z[i])};
-    const int4 nb = m.nbr[i];
-    const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
+    T g[3] = {u[0] * r + (T)lphi * px + (T)lt * (px - qx),
+              u[1] * r + (T)lphi * py + (T)lt * (py - qy),
+              u[2] * r + (T)lphi * pz + (T)lt * (pz - qz)};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        int j = nbs[q];
-        if (j < 0) continue;
+        if (nbs[q] < 0) continue;
         alpha += (T)lnbr;
-        g[0] += (T)lnbr * (px - (T)phi.x[j]);
-        g[1] += (T)lnbr * (py - (T)phi.y[j]);
-        g[2] += (T)lnbr * (pz - (T)phi.z[j]);
+        g[0] += (T)lnbr * (px - nphi[q][0]);
+        g[1] += (T)lnbr * (py - nphi[q][1]);
+        g[2] += (T)lnbr * (pz - nphi[q][2]);
     }
     T M[9];
     for (int p = 0; p < 3; ++p)
@@ -652,7 +665,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         // the next iteration's surface: skin the new offsets (same blend) into
         // the buffer not read here by other vertices, and count it
         float ox, oy, oz;
-        dq_apply(H, m.rx[i] + fx, m.ry[i] + fy, m.rz[i] + fz, ox, oy, oz);
+        dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         const float4 q = make_float4(ox, oy, oz, 0.0f);
         S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
         count_vertex(S, i, q);
