@@ -30,6 +30,10 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int kJTStride = kNeRows + 8;  // floats per LDS column of the row tile
 constexpr int kGStride = 25;            // floats per row of per-influence 6-vectors
+constexpr int kNeWaves = 8;             // waves per chunk's workgroup
+constexpr int kNeThreads = 64 * kNeWaves;
+// upper 16x16 Gram blocks each wave owns at most
+constexpr int kNeBlocks = ((kPPMax / 16) * (kPPMax / 16 + 1) / 2 + kNeWaves - 1) / kNeWaves;
 
 __device__ __forceinline__ void block_of(int idx, int nb, int& I, int& J) {
     int q = idx;
@@ -131,7 +135,7 @@ __host__ __device__ inline size_t ne_lds_bytes(int ppmax, int lmax) {
 // BIG: an instance allowed more than 64 KB of LDS (hi/mid/lo planes, or
 // P > 79); smaller sizes use the other instance, which launches faster
 template <int MODE, bool BIG>
-__global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, int ppmax, int lmax) {
+__global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int pn, int ppmax, int lmax) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     unsigned char* q0 = smem;
     // [col][row] tile: float32 (mode 0) or two / three bfloat16 planes
@@ -168,15 +172,15 @@ __global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, in
     const int nchunks = (m.V + kNeRows - 1) / kNeRows;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int P = m.P;
-    for (int q = tid; q < 8 * m.L; q += 256) sdq[q] = dq[q];
-    for (int q = tid; q < 6 * P; q += 256) sxi[q] = xi[8 * (q / 6) + (q % 6)];
-    for (int q = tid; q < 4 * m.L; q += 256) sanc[q] = anc[q];
+    for (int q = tid; q < 8 * m.L; q += kNeThreads) sdq[q] = dq[q];
+    for (int q = tid; q < 6 * P; q += kNeThreads) sxi[q] = xi[8 * (q / 6) + (q % 6)];
+    for (int q = tid; q < 4 * m.L; q += kNeThreads) sanc[q] = anc[q];
 
     const int nb = PP >> 4;
     const int nbt = nb * (nb + 1) / 2;
-    f4 acc[9];
+    f4 acc[kNeBlocks];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int q = 0; q < kNeBlocks; ++q) acc[q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
     __syncthreads();
 
     for (int chunk = wg; chunk < nchunks; chunk += S.negrid) {
@@ -206,46 +210,73 @@ __global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, in
         const int kstep = MODE == 0 ? 16 : 32;
         const int npad = (nrows + kstep - 1) / kstep * kstep;
 
-        // 2. rows of [J r] into the [col][row] tile
-        for (int e = tid; e < PP * npad; e += 256) {
-            const int col = e / npad, row = e - col * npad;
-            float val = 0.0f;
-            if (row < nrows) {
-                if (col < P) {
-                    const uint32_t lk = slink[row];
-                    const float* g = &sG[row * kGStride];
-                    const float* xk = &sxi[6 * col];
+        // 2. rows of [J r] into the [col][row] tile.  Thread = (row, group of
+        //    columns): a row's per-influence 6-vectors and its links'
+        //    ancestor masks stay in registers while it walks its columns.
+        {
+            const int R = npad <= 64 ? 64 : 128;
+            const int row = tid & (R - 1), ng = kNeThreads / R;
+            const int cpg = (PP + ng - 1) / ng;
+            const int c0 = (tid / R) * cpg, c1 = min(PP, c0 + cpg);
+            if (row < npad && c0 < c1) {
+                const bool have = row < nrows;
+                const uint32_t lk = have ? slink[row] : 0xFFFFFFFFu;
+                float g[24];
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        int l = (lk >> (8 * k)) & 0xFF;
-                        if (l == 0xFF) continue;
-                        if (!((sanc[4 * l + (col >> 5)] >> (col & 31)) & 1u)) continue;
-                        const float* gk = g + 6 * k;
-                        val -= gk[0] * xk[0] + gk[1] * xk[1] + gk[2] * xk[2] + gk[3] * xk[3] + gk[4] * xk[4] +
-                               gk[5] * xk[5];
-                    }
-                } else if (col == P) {
-                    val = sr[row];
+                for (int q = 0; q < 24; ++q) g[q] = have ? sG[row * kGStride + q] : 0.0f;
+                const float rr = have ? sr[row] : 0.0f;
+                // ancestor bits of the four links from column c0 on (shifted
+                // one per column, reloaded at each 32-column boundary)
+                int lb[4];
+                uint32_t cur[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int l = (lk >> (8 * k)) & 0xFF;
+                    lb[k] = l == 0xFF ? -1 : 4 * l;
+                    cur[k] = lb[k] < 0 ? 0u : sanc[lb[k] + (c0 >> 5)] >> (c0 & 31);
                 }
-            }
-            const int at = col * kJTStride + row;
-            if (MODE == 0) {
-                sJT[at] = val;
-            } else {
-                __bf16 h = (__bf16)val;
-                float rem = val - (float)h;
-                __bf16 m = (__bf16)rem;
-                plane0[at] = h;
-                plane1[at] = m;
-                if (MODE == 2) plane2[at] = (__bf16)(rem - (float)m);
+                for (int col = c0; col < c1; ++col) {
+                    float val = 0.0f;
+                    if (col < P) {
+                        const float* xk = &sxi[6 * col];
+                        const float x0 = xk[0], x1 = xk[1], x2 = xk[2], x3 = xk[3], x4 = xk[4], x5 = xk[5];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float* gk = g + 6 * k;
+                            const float dt = gk[0] * x0 + gk[1] * x1 + gk[2] * x2 + gk[3] * x3 + gk[4] * x4 + gk[5] * x5;
+                            const float nv = val - dt;
+                            val = (cur[k] & 1u) ? nv : val;
+                        }
+                    } else if (col == P) {
+                        val = rr;
+                    }
+                    if (((col + 1) & 31) == 0 && col + 1 < c1) {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) cur[k] = lb[k] < 0 ? 0u : sanc[lb[k] + ((col + 1) >> 5)];
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) cur[k] >>= 1;
+                    }
+                    const int at = col * kJTStride + row;
+                    if (MODE == 0) {
+                        sJT[at] = val;
+                    } else {
+                        __bf16 h = (__bf16)val;
+                        float rem = val - (float)h;
+                        __bf16 m = (__bf16)rem;
+                        plane0[at] = h;
+                        plane1[at] = m;
+                        if (MODE == 2) plane2[at] = (__bf16)(rem - (float)m);
+                    }
+                }
             }
         }
         __syncthreads();
 
         // 3. Gram blocks (I <= J) owned by this wave
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int idx = wid + 4 * q;
+        for (int q = 0; q < kNeBlocks; ++q) {
+            const int idx = wid + kNeWaves * q;
             if (idx < nbt) {
                 int I, J;
                 block_of(idx, nb, I, J);
@@ -288,8 +319,8 @@ __global__ void __launch_bounds__(256) k_normal_eq(Batch B, int vsel, int pn, in
     // 4. this workgroup's partial Gram (upper blocks only)
     float* out = S.partials + (size_t)wg * PP * PP;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        const int idx = wid + 4 * q;
+    for (int q = 0; q < kNeBlocks; ++q) {
+        const int idx = wid + kNeWaves * q;
         if (idx < nbt) {
             int I, J;
             block_of(idx, nb, I, J);
@@ -332,9 +363,9 @@ void launch_normal_eq_t(const Launch& L, int vsel, int pn) {
     const int pp = L.ne_pp, lm = L.ne_l;
     const size_t bytes = ne_lds_bytes<MODE>(pp, lm);
     if (bytes <= kSmallLds)
-        launch_kernel(L, true, true, k_normal_eq<MODE, false>, g, dim3(256), bytes, L.B, vsel, pn, pp, lm);
+        launch_kernel(L, true, true, k_normal_eq<MODE, false>, g, dim3(kNeThreads), bytes, L.B, vsel, pn, pp, lm);
     else
-        launch_kernel(L, true, true, k_normal_eq<MODE, true>, g, dim3(256), bytes, L.B, vsel, pn, pp, lm);
+        launch_kernel(L, true, true, k_normal_eq<MODE, true>, g, dim3(kNeThreads), bytes, L.B, vsel, pn, pp, lm);
 }
 
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
