@@ -186,7 +186,7 @@ __host__ __device__ __forceinline__ int phi_index(const Slot& S, int n) {
 }
 
 enum KernelKind {
-    KK_ONE = 0,     // one workgroup per slot (frame bookkeeping, FK, tile scan, solve)
+    KK_ONE = 0,     // one workgroup per slot (frame bookkeeping, FK, solve)
     KK_VERT,        // ceil(V / 256) workgroups
     KK_VERT2,       // 2 ceil(V / 256): two vertex passes in one launch
     KK_CLEAR,       // ceil(max(Npad, V) / 256)
@@ -194,6 +194,7 @@ enum KernelKind {
     KK_TILE,        // tiles: one workgroup per tile
     KK_NE,          // normal-equation workgroups
     KK_REDUCE,      // Gram reduction workgroups
+    KK_VERT64,      // ceil(V / 64): one wave per 64 vertices
     KK_COUNT_
 };
 
@@ -255,6 +256,7 @@ inline int slot_blocks(const Slot& s, int kind) {
         case KK_TILE: return ntiles;
         case KK_NE: return s.negrid;
         case KK_REDUCE: { int nb = s.PP >> 4; return nb * (nb + 1) / 2 * 8; }
+        case KK_VERT64: return (V + 63) / 64;
     }
     return 0;
 }

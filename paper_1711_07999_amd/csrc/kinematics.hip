@@ -63,18 +63,21 @@ void launch_fk(const Launch& L) {
 __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int which, int count, int clear_acc) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
     if (!selected(S, which)) return;
     const DevModel& m = S.m;
+    const int i = local * blockDim.x + threadIdx.x;
+    const int ii = i < m.V ? i : 0;   // the vertex's own loads go out before the table copy
+    const Vec3Buf phi = S.phi[phi_index(S, pn)];
+    const float4 w = m.w[ii];
+    const uint32_t lk = m.links[ii];
+    float x = m.rx[ii] + phi.x[ii], y = m.ry[ii] + phi.y[ii], z = m.rz[ii] + phi.z[ii];
     for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
     __syncthreads();
-    const int i = local * blockDim.x + threadIdx.x;
     if (i >= m.V) return;
-    const Vec3Buf phi = S.phi[phi_index(S, pn)];
     float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
     float H[8];
-    dq_blend(sdq, m.w[i], m.links[i], H);
-    float x = m.rx[i] + phi.x[i], y = m.ry[i] + phi.y[i], z = m.rz[i] + phi.z[i];
+    dq_blend(sdq, w, lk, H);
     float ox, oy, oz;
     dq_apply(H, x, y, z, ox, oy, oz);
     const float4 p = make_float4(ox, oy, oz, 0.0f);
@@ -87,7 +90,8 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
 }
 
 void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
-    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel, pn, which, count, clear_acc);
+    // one wave per workgroup: the vertices spread over every compute unit
+    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT64]), dim3(64), 0, L.B, vsel, pn, which, count, clear_acc);
 }
 
 // Vertex normals (one lane per vertex; see vertex_normal)

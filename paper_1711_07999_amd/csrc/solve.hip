@@ -581,7 +581,7 @@ template <class T>
 __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn, int next) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
+    const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
     const DevModel& m = S.m;
     const float4* __restrict__ v_old = S.verts[S.v_cur ^ vo_sel];
     const float4* __restrict__ v_new = S.verts[S.v_cur ^ vn_sel];
@@ -673,11 +673,12 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
 }
 
 void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next) {
-    const dim3 g(L.grid[KK_VERT]);
+    // one wave per workgroup: the vertices spread over every compute unit
+    const dim3 g(L.grid[KK_VERT64]);
     if (fp64)
-        launch_kernel(L, true, true, k_shape<double>, g, dim3(256), 0, L.B, v_old, v_new, pn, next);
+        launch_kernel(L, true, true, k_shape<double>, g, dim3(64), 0, L.B, v_old, v_new, pn, next);
     else
-        launch_kernel(L, true, true, k_shape<float>, g, dim3(256), 0, L.B, v_old, v_new, pn, next);
+        launch_kernel(L, true, true, k_shape<float>, g, dim3(64), 0, L.B, v_old, v_new, pn, next);
 }
 
 }  // namespace trk
