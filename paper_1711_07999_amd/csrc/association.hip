@@ -97,33 +97,42 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
     const Buckets& b = S.b;
     const int ntiles = S.c.tiles_x * S.c.tiles_y;
     const int wid = threadIdx.x >> 6, lane = wave_lane();
-    // this workgroup's first offset: the vertices of every earlier tile (the
-    // workgroup sums the tile counts itself; they are cleared by the scatter)
     const int t0 = local * 4;
+    const int tile = t0 + wid;
+    const bool live = tile < ntiles;
+    const int p = (tile << 6) + lane;
+    const uint32_t* __restrict__ tsum = b.tsum;
+    // every load of the kernel is issued before the first wait, none of them
+    // under a branch: this tile's pixels, the counts of this workgroup's
+    // earlier tiles and of every earlier workgroup's tiles (which the
+    // workgroup sums itself; the scatter clears them)
+    const int pl = live ? p : 0;
+    const uint32_t cnt = b.pcnt[pl], zmn = b.pzmin[pl], zmx = b.pzmax[pl];
+    uint32_t own = 0u;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+        const uint32_t c = tsum[t0 + (w < wid ? w : 0)];
+        own += w < wid ? c : 0u;
+    }
     uint32_t part = 0u;
-    for (int t = threadIdx.x; t < t0; t += 1024) {   // four loads in flight per thread
-        const uint32_t a0 = b.tsum[t];
-        const uint32_t a1 = t + 256 < t0 ? b.tsum[t + 256] : 0u;
-        const uint32_t a2 = t + 512 < t0 ? b.tsum[t + 512] : 0u;
-        const uint32_t a3 = t + 768 < t0 ? b.tsum[t + 768] : 0u;
-        part += (a0 + a1) + (a2 + a3);
+    for (int t = threadIdx.x; t < t0; t += 256 * 16) {
+        uint32_t a[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = tsum[min(t + 256 * k, t0 - 1)];   // past t0: a repeat, not added
+#pragma unroll
+        for (int k = 0; k < 16; ++k) part += t + 256 * k < t0 ? a[k] : 0u;
     }
     for (int o = 32; o > 0; o >>= 1) part += (uint32_t)__shfl_xor((int)part, o);
     if (lane == 0) spart[wid] = part;
     __syncthreads();
-    const int tile = t0 + wid;
-    if (tile >= ntiles) return;
-    uint32_t tile_off = spart[0] + spart[1] + spart[2] + spart[3];
-    for (int w = 0; w < wid; ++w) tile_off += b.tsum[t0 + w];
-    const int p = (tile << 6) + lane;
-    const uint32_t cnt = b.pcnt[p];
+    if (!live) return;
+    const uint32_t tile_off = spart[0] + spart[1] + spart[2] + spart[3] + own;
     uint32_t incl = cnt;
     for (int o = 1; o < 64; o <<= 1) {
         uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
     const uint32_t off = tile_off + incl - cnt;
-    const uint32_t zmn = b.pzmin[p], zmx = b.pzmax[p];
     b.rec[p] = make_uint4(off, cnt, zmn, zmx);
     b.pcnt[p] = 0u;
     b.pzmin[p] = 0x7F800000u;
@@ -158,9 +167,10 @@ __global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
         for (int t = i; t < S.c.tiles_x * S.c.tiles_y; t += half * 256) b.tsum[t] = 0u;
         if (i >= S.m.V) return;
         const int pix = b.vpix[i];
-        if (pix < 0) return;
-        const uint32_t dst = b.rec[pix].x + b.vslot[i];
+        const uint32_t slot = b.vslot[i];   // (stale when pix < 0: unused)
         const float4 p = v[i];
+        if (pix < 0) return;
+        const uint32_t dst = b.rec[pix].x + slot;
         b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
     } else {
         const int i = (local - half) * blockDim.x + threadIdx.x;
