@@ -225,38 +225,7 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
 #pragma unroll
                 for (int q = 0; q < 24; ++q) g[q] = have ? sG[row * kGStride + q] : 0.0f;
                 const float rr = have ? sr[row] : 0.0f;
-                // ancestor bits of the four links from column c0 on (shifted
-                // one per column, reloaded at each 32-column boundary)
-                int lb[4];
-                uint32_t cur[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int l = (lk >> (8 * k)) & 0xFF;
-                    lb[k] = l == 0xFF ? -1 : 4 * l;
-                    cur[k] = lb[k] < 0 ? 0u : sanc[lb[k] + (c0 >> 5)] >> (c0 & 31);
-                }
-                for (int col = c0; col < c1; ++col) {
-                    float val = 0.0f;
-                    if (col < P) {
-                        const float* xk = &sxi[6 * col];
-                        const float x0 = xk[0], x1 = xk[1], x2 = xk[2], x3 = xk[3], x4 = xk[4], x5 = xk[5];
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const float* gk = g + 6 * k;
-                            const float dt = gk[0] * x0 + gk[1] * x1 + gk[2] * x2 + gk[3] * x3 + gk[4] * x4 + gk[5] * x5;
-                            const float nv = val - dt;
-                            val = (cur[k] & 1u) ? nv : val;
-                        }
-                    } else if (col == P) {
-                        val = rr;
-                    }
-                    if (((col + 1) & 31) == 0 && col + 1 < c1) {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) cur[k] = lb[k] < 0 ? 0u : sanc[lb[k] + ((col + 1) >> 5)];
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < 4; ++k) cur[k] >>= 1;
-                    }
+                auto put = [&](int col, float val) {
                     const int at = col * kJTStride + row;
                     if (MODE == 0) {
                         sJT[at] = val;
@@ -268,7 +237,47 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
                         plane1[at] = m;
                         if (MODE == 2) plane2[at] = (__bf16)(rem - (float)m);
                     }
+                };
+                int lb[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int l = (lk >> (8 * k)) & 0xFF;
+                    lb[k] = l == 0xFF ? -1 : 4 * l;
                 }
+                // the columns of J in runs of up to 32 that share a word of the
+                // links' ancestor masks (shifted one bit per column); the next
+                // column's twists are read before this column is stored, so
+                // the read overlaps this column's arithmetic
+                const int cj = min(c1, P);
+                float xn[6];
+                if (c0 < cj) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) xn[e] = sxi[6 * c0 + e];
+                }
+                for (int col = c0; col < cj;) {
+                    const int run_end = min(cj, (col & ~31) + 32);
+                    uint32_t cur[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) cur[k] = lb[k] < 0 ? 0u : sanc[lb[k] + (col >> 5)] >> (col & 31);
+                    for (; col < run_end; ++col) {
+                        const float x0 = xn[0], x1 = xn[1], x2 = xn[2], x3 = xn[3], x4 = xn[4], x5 = xn[5];
+                        const int cn = min(col + 1, cj - 1);
+#pragma unroll
+                        for (int e = 0; e < 6; ++e) xn[e] = sxi[6 * cn + e];
+                        float val = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) {
+                            const float* gk = g + 6 * k;
+                            const float dt = gk[0] * x0 + gk[1] * x1 + gk[2] * x2 + gk[3] * x3 + gk[4] * x4 + gk[5] * x5;
+                            const float nv = val - dt;
+                            val = (cur[k] & 1u) ? nv : val;
+                            cur[k] >>= 1;
+                        }
+                        put(col, val);
+                    }
+                }
+                // the residual column, then the padding
+                for (int col = max(c0, P); col < c1; ++col) put(col, col == P ? rr : 0.0f);
             }
         }
         __syncthreads();
