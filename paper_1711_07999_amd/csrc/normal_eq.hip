@@ -386,10 +386,12 @@ void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
 // Sum of the partial Gram matrices in workgroup order, in float64; writes the
 // full symmetric matrix (the upper triangle is summed and mirrored, so the
 // result is exactly symmetric).  A workgroup handles 32 elements of one
-// 16x16 block; each element's partials are split into 8 contiguous groups
-// summed by 8 threads, and the 8 group sums are added in group order.
-__global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
-    __shared__ double part[8][32];
+// 16x16 block; each element's partials are split into kRedGroups contiguous
+// groups summed by as many threads (a few rounds of eight loads each), and
+// the group sums are added in group order.
+constexpr int kRedGroups = 16;
+__global__ void __launch_bounds__(32 * kRedGroups) k_gram_reduce(Batch B) {
+    __shared__ double part[kRedGroups][32];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_REDUCE, blockIdx.x, local)];
     const int PP = S.PP, nparts = S.negrid;
@@ -414,7 +416,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
         theta_i = S.theta[i];
     }
     const size_t stride = (size_t)PP * PP;
-    const int per = (nparts + 7) / 8;
+    const int per = (nparts + kRedGroups - 1) / kRedGroups;
     const int q0 = grp * per, q1 = min(nparts, q0 + per);
     const float* p = partials + (size_t)i * PP + j;
     double s = 0.0;
@@ -431,7 +433,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
     __syncthreads();
     if (grp == 0 && i <= j) {
         double tot = 0.0;
-        for (int g = 0; g < 8; ++g) tot += part[g][threadIdx.x & 31];
+        for (int g = 0; g < kRedGroups; ++g) tot += part[g][threadIdx.x & 31];
         gram[i * PP + j] = tot;
         gram[j * PP + i] = tot;
         if (fe >= 0) {
@@ -448,7 +450,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(Batch B) {
 }
 
 void launch_gram_reduce(const Launch& L) {
-    launch_kernel(L, true, true, k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(256), 0, L.B);
+    launch_kernel(L, true, true, k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(32 * kRedGroups), 0, L.B);
 }
 
 }  // namespace trk

@@ -403,7 +403,10 @@ void build_tree_plan(Stream* c, const track_model* m) {
             rounds[s].insert(rounds[s].end(), q.begin(), q.end());
         }
     }
-    // per level, longest processing time first over the waves (cost: pivots x width)
+    // per level, longest processing time first over the waves (cost: pivots x
+    // width); a front goes to the least loaded SIMD (waves w and w + 4 of the
+    // workgroup share one), then to its less loaded wave, so the longest
+    // fronts do not share an issue port
     std::vector<int> wstart((size_t)nlev * kSolveWaves + 1), sched;
     for (int l = 0; l < nlev; ++l) {
         std::vector<int> ids;
@@ -413,8 +416,17 @@ void build_tree_plan(Stream* c, const track_model* m) {
         std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return cost(a) > cost(b); });
         std::vector<std::vector<int>> per(kSolveWaves);
         std::vector<int64_t> load(kSolveWaves, 0);
+        auto simd_load = [&](int w) {
+            int64_t t = 0;
+            for (int v = w % 4; v < kSolveWaves; v += 4) t += load[v];
+            return t;
+        };
         for (int s : ids) {
-            const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            int w = 0;
+            for (int v = 1; v < kSolveWaves; ++v) {
+                const int64_t lv = simd_load(v), lw = simd_load(w);
+                if (lv < lw || (lv == lw && load[v] < load[w])) w = v;
+            }
             per[w].push_back(s);
             load[w] += cost(s);
         }
