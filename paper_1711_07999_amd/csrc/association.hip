@@ -69,7 +69,7 @@ void launch_clear_acc(const Launch& L) {
 
 // ---------------------------------------------------------------------------
 // bucket construction: count (fused into skinning, or this kernel for a
-// given surface) -> tile prefix -> per-pixel records -> scatter
+// given surface) -> tile prefix -> per-pixel offsets -> scatter
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int which) {
     int local;
@@ -115,12 +115,12 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
         own += w < wid ? c : 0u;
     }
     uint32_t part = 0u;
-    for (int t = threadIdx.x; t < t0; t += 256 * 16) {
-        uint32_t a[16];
+    for (int t = threadIdx.x; t < t0; t += 256 * 20) {   // one round up to 5120 tiles
+        uint32_t a[20];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) a[k] = tsum[min(t + 256 * k, t0 - 1)];   // past t0: a repeat, not added
+        for (int k = 0; k < 20; ++k) a[k] = tsum[min(t + 256 * k, t0 - 1)];   // past t0: a repeat, not added
 #pragma unroll
-        for (int k = 0; k < 16; ++k) part += t + 256 * k < t0 ? a[k] : 0u;
+        for (int k = 0; k < 20; ++k) part += t + 256 * k < t0 ? a[k] : 0u;
     }
     for (int o = 32; o > 0; o >>= 1) part += (uint32_t)__shfl_xor((int)part, o);
     if (lane == 0) spart[wid] = part;
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
         if (lane >= o) incl += y;
     }
     const uint32_t off = tile_off + incl - cnt;
-    b.rec[p] = make_uint4(off, cnt, zmn, zmx);
+    b.poff[p] = off;
     b.pcnt[p] = 0u;
     b.pzmin[p] = 0x7F800000u;
     b.pzmax[p] = 0u;
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
         const uint32_t slot = b.vslot[i];   // (stale when pix < 0: unused)
         const float4 p = v[i];
         if (pix < 0) return;
-        const uint32_t dst = b.rec[pix].x + slot;
+        const uint32_t dst = b.poff[pix] + slot;
         b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
     } else {
         const int i = (local - half) * blockDim.x + threadIdx.x;

@@ -111,7 +111,7 @@ struct Buckets {
     uint32_t* pcnt;    // [Npad] vertices per pixel        } zero again once the
     uint32_t* pzmin;   // [Npad] bits of the smallest z     } pixel records are
     uint32_t* pzmax;   // [Npad] bits of the largest z      } built (+inf, 0, 0)
-    uint4* rec;        // [Npad] (offset, count, zmin bits, zmax bits)
+    uint32_t* poff;    // [Npad] first slot of each pixel's vertices in `sorted`
     uint32_t* tsum;    // [tiles] vertices per tile (zero again after the scatter)
     float2* tz;        // [tiles] z range of the tile
     int* vpix;         // [V] bucket of each vertex or -1

@@ -549,7 +549,7 @@ void stream_layout(Stream* c) {
     b.pcnt = carve<uint32_t>(c, c->npad);
     b.pzmin = carve<uint32_t>(c, c->npad);
     b.pzmax = carve<uint32_t>(c, c->npad);
-    b.rec = carve<uint4>(c, c->npad);
+    b.poff = carve<uint32_t>(c, c->npad);
     b.tsum = carve<uint32_t>(c, c->ntiles);
     b.tz = carve<float2>(c, c->ntiles);
     b.torder = carve<int>(c, c->ntiles);
