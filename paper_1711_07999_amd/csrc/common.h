@@ -282,7 +282,7 @@ void launch_normals(const Launch& L, int vsel);
 void launch_clear(const Launch& L);                 // buckets, tile sums, accumulators
 void launch_clear_acc(const Launch& L);             // accumulators only
 void launch_bucket_count(const Launch& L, int vsel, int which);
-// tile scan, pixel records (+ clearing the counters), scatter (+ normals)
+// pixel offsets with the tile prefix (+ clearing the counters), scatter (+ normals)
 void launch_bucket(const Launch& L, int vsel);
 void launch_associate(const Launch& L, int vsel);
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
