@@ -607,6 +607,8 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     const float4 wv = m.w[ii];
     const uint32_t lk = m.links[ii];
     const float rx = m.rx[ii], ry = m.ry[ii], rz = m.rz[ii];
+    FanIn fan;
+    vertex_fan_load(m, v_new, i, live, fan);   // not waiting for the count
     const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
     T nphi[4][3];
 #pragma unroll
@@ -615,7 +617,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         nphi[q][0] = (T)phi.x[j]; nphi[q][1] = (T)phi.y[j]; nphi[q][2] = (T)phi.z[j];
     }
     float nx, ny, nz;
-    vertex_normal(m, v_new, i, live && c > 0u, nx, ny, nz);   // the whole wave
+    vertex_normal_fan(m, v_new, i, live && c > 0u, fan, nx, ny, nz);   // the whole wave
     if (!live) return;
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);

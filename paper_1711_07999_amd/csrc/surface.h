@@ -46,6 +46,23 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int i, float4 p) {
     }
 }
 
+// A vertex's own position and its inline fan (the loads that wait on
+// nothing), so that a caller can issue them with its other first reads.
+struct FanIn {
+    float4 p;
+    uint32_t e0, e1;
+    int2 bc[kFanInline];
+};
+
+__device__ __forceinline__ void vertex_fan_load(const DevModel& m, const float4* __restrict__ v, int i, bool live,
+                                                FanIn& f) {
+    f.p = v[live ? i : 0];
+    f.e0 = live ? m.fan_off[i] : 0u;
+    f.e1 = live ? m.fan_off[i + 1] : 0u;
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) f.bc[k] = live ? m.fan8[(size_t)k * m.V + i] : make_int2(0, 0);
+}
+
 // Sum over the incident faces (b, c) of (v_b - v_i) x (v_c - v_i),
 // normalised; zero if the sum vanishes.  One operation order (no
 // contraction) wherever it is inlined, so every kernel gets the same bits:
@@ -53,17 +70,19 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int i, float4 p) {
 // entries (i, i) add an exact zero; all loads issued at once), then, for a
 // vertex of more faces, the rest summed by the whole wave (lane l takes
 // faces l, l + 64, ... of the rest; a fixed tree adds the lanes' sums).
-// Every lane of the wave must call it together; lanes with live == false
-// compute nothing of their own but take part in the shared work.
-__device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* __restrict__ v, int i, bool live,
-                                              float& nx, float& ny, float& nz) {
+// Every lane of the wave must call it together.  This form takes the loads
+// made by vertex_fan_load (with a `live` at least as wide as this one);
+// lanes with live == false gather nothing of their own (their result is not
+// meaningful) but take part in the shared work.
+__device__ __forceinline__ void vertex_normal_fan(const DevModel& m, const float4* __restrict__ v, int i, bool live,
+                                                  const FanIn& f, float& nx, float& ny, float& nz) {
 #pragma clang fp contract(off)
     const int ii = live ? i : 0;
-    const float4 p = v[ii];
-    const uint32_t e0 = live ? m.fan_off[i] : 0u, e1 = live ? m.fan_off[i + 1] : 0u;
+    const float4 p = f.p;
+    const uint32_t e0 = live ? f.e0 : 0u, e1 = live ? f.e1 : 0u;
     int2 bc[kFanInline];
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) bc[k] = live ? m.fan8[(size_t)k * m.V + i] : make_int2(0, 0);
+    for (int k = 0; k < kFanInline; ++k) bc[k] = live ? f.bc[k] : make_int2(0, 0);
     float4 vb[kFanInline], vc[kFanInline];
 #pragma unroll
     for (int k = 0; k < kFanInline; ++k) { vb[k] = v[bc[k].x]; vc[k] = v[bc[k].y]; }
@@ -106,6 +125,13 @@ __device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* _
     const float l = sqrtf(sx * sx + sy * sy + sz * sz);
     const float inv = l > 0.0f ? 1.0f / l : 0.0f;
     nx = sx * inv; ny = sy * inv; nz = sz * inv;
+}
+
+__device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* __restrict__ v, int i, bool live,
+                                              float& nx, float& ny, float& nz) {
+    FanIn f;
+    vertex_fan_load(m, v, i, live, f);
+    vertex_normal_fan(m, v, i, live, f, nx, ny, nz);
 }
 
 }  // namespace trk
