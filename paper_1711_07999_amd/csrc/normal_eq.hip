@@ -128,7 +128,7 @@ __host__ __device__ inline size_t ne_tile_bytes(int ppmax) {
 }
 template <int MODE>
 __host__ __device__ inline size_t ne_lds_bytes(int ppmax, int lmax) {
-    return ne_tile_bytes<MODE>(ppmax) + 4 * (size_t)kNeRows * kGStride + 4 * (size_t)kNeRows * 2 + 16 +
+    return ne_tile_bytes<MODE>(ppmax) + 4 * (size_t)kNeRows * kGStride + 4 * (size_t)kNeRows * 2 + 48 +
            4 * (size_t)(8 * lmax + 6 * ppmax + 4 * lmax);
 }
 
@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
     float* sr = reinterpret_cast<float*>(q0);
     q0 += 4 * kNeRows;
     int* scount = reinterpret_cast<int*>(q0);
-    q0 += 16;
+    uint32_t* smask = reinterpret_cast<uint32_t*>(q0 + 16);   // [2][4] columns the waves' rows touch
+    q0 += 48;
     float* sdq = reinterpret_cast<float*>(q0);
     q0 += 4 * 8 * lmax;
     float* sxi = reinterpret_cast<float*>(q0);
@@ -195,9 +196,32 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
             obs = in.cnt > 0u && (in.nx * in.nx + in.ny * in.ny + in.nz * in.nz) > 0.0f;
         }
         unsigned long long bal = __ballot(obs);
-        if (lane == 0 && wid < 2) scount[wid] = __popcll(bal);
+        // the columns of J the chunk's rows can touch: the union of their
+        // links' ancestor masks (the other columns are zero in the tile)
+        uint32_t mk[4] = {0u, 0u, 0u, 0u};
+        if (obs) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int l = (in.links >> (8 * k)) & 0xFF;
+                if (l != 0xFF) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) mk[w] |= sanc[4 * l + w];
+                }
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+            for (int o = 32; o > 0; o >>= 1) mk[w] |= (uint32_t)__shfl_xor((int)mk[w], o);
+        if (lane == 0 && wid < 2) {
+            scount[wid] = __popcll(bal);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) smask[4 * wid + w] = mk[w];
+        }
         __syncthreads();
         const int nrows = scount[0] + scount[1];
+        uint32_t um[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) um[w] = smask[w] | smask[4 + w];
         if (obs) {
             int row = __popcll(bal & ((1ull << lane) - 1ull)) + (wid == 1 ? scount[0] : 0);
             float r;
@@ -259,20 +283,25 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
                     uint32_t cur[4];
 #pragma unroll
                     for (int k = 0; k < 4; ++k) cur[k] = lb[k] < 0 ? 0u : sanc[lb[k] + (col >> 5)] >> (col & 31);
+                    const uint32_t uw = um[col >> 5];
                     for (; col < run_end; ++col) {
                         const float x0 = xn[0], x1 = xn[1], x2 = xn[2], x3 = xn[3], x4 = xn[4], x5 = xn[5];
                         const int cn = min(col + 1, cj - 1);
 #pragma unroll
                         for (int e = 0; e < 6; ++e) xn[e] = sxi[6 * cn + e];
                         float val = 0.0f;
+                        if ((uw >> (col & 31)) & 1u) {   // a column some row of the chunk touches
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) {
-                            const float* gk = g + 6 * k;
-                            const float dt = gk[0] * x0 + gk[1] * x1 + gk[2] * x2 + gk[3] * x3 + gk[4] * x4 + gk[5] * x5;
-                            const float nv = val - dt;
-                            val = (cur[k] & 1u) ? nv : val;
-                            cur[k] >>= 1;
+                            for (int k = 0; k < 4; ++k) {
+                                const float* gk = g + 6 * k;
+                                const float dt = gk[0] * x0 + gk[1] * x1 + gk[2] * x2 + gk[3] * x3 + gk[4] * x4 +
+                                                 gk[5] * x5;
+                                const float nv = val - dt;
+                                val = (cur[k] & 1u) ? nv : val;
+                            }
                         }
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) cur[k] >>= 1;
                         put(col, val);
                     }
                 }
@@ -286,9 +315,12 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
 #pragma unroll
         for (int q = 0; q < kNeBlocks; ++q) {
             const int idx = wid + kNeWaves * q;
-            if (idx < nbt) {
-                int I, J;
-                block_of(idx, nb, I, J);
+            int I = 0, J = 0;
+            if (idx < nbt) block_of(idx, nb, I, J);
+            // a block of columns no row touches (and without the residual)
+            // is zero in the tile: its products are skipped
+            auto blk_used = [&](int K) { return ((um[K >> 1] >> ((K & 1) * 16)) & 0xFFFFu) != 0u || (P >> 4) == K; };
+            if (idx < nbt && blk_used(I) && blk_used(J)) {
                 const int ca = (I * 16 + (lane & 15)) * kJTStride;
                 const int cb = (J * 16 + (lane & 15)) * kJTStride;
                 if (MODE == 0) {
