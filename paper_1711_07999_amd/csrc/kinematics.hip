@@ -125,12 +125,13 @@ __global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int 
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ntiles = S.c.tiles_x * S.c.tiles_y;
     int nv = 0, na = 0, no = 0;
-    for (int t = tid; t < ntiles; t += 1024) {   // four tiles' counts in flight per thread
-        int4 q[4];
+    for (int t = tid; t < ntiles; t += 256 * 20) {   // one round of loads up to 5120 tiles
+        int4 q[20];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) q[j] = t + 256 * j < ntiles ? S.b.bstat[t + 256 * j] : make_int4(0, 0, 0, 0);
+        for (int j = 0; j < 20; ++j) q[j] = S.b.bstat[min(t + 256 * j, ntiles - 1)];   // past the end: not added
 #pragma unroll
-        for (int j = 0; j < 4; ++j) { nv += q[j].x; na += q[j].y; no += q[j].z; }
+        for (int j = 0; j < 20; ++j)
+            if (t + 256 * j < ntiles) { nv += q[j].x; na += q[j].y; no += q[j].z; }
     }
     for (int o = 32; o > 0; o >>= 1) {
         nv += __shfl_xor(nv, o);
