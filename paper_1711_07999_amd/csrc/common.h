@@ -230,6 +230,20 @@ inline void launch_kernel(const Launch& L, bool first, bool last, F kernel, dim3
     else hipLaunchKernelGGL(kernel, grid, block, lds, L.s, args...);
 }
 
+// n (>= 1) floats from global memory to LDS, every load of a thread issued
+// before its first store (a one-wave workgroup copies the link table in one
+// round of loads rather than one round per 64 entries)
+__device__ __forceinline__ void copy_to_lds(float* dst, const float* __restrict__ src, int n) {
+    for (int base = threadIdx.x; base < n; base += 8 * blockDim.x) {
+        float t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = src[min(base + j * (int)blockDim.x, n - 1)];   // past n: not stored
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (base + j * (int)blockDim.x < n) dst[base + j * blockDim.x] = t[j];
+    }
+}
+
 // slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
 __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& local) {
     const int* p = B.pre + kind * (B.n + 1);

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
     const float4 w = m.w[ii];
     const uint32_t lk = m.links[ii];
     float x = m.rx[ii] + phi.x[ii], y = m.ry[ii] + phi.y[ii], z = m.rz[ii] + phi.z[ii];
-    for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
+    copy_to_lds(sdq, S.dq, 8 * m.L);
     __syncthreads();
     if (i >= m.V) return;
     float4* __restrict__ v = S.verts[S.v_cur ^ vsel];

@@ -591,7 +591,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     const Vec3Buf phi_prev = S.phi[S.phi_prev];
     const Vec3Buf phi_out = S.phi[phi_next(src, S.phi_prev)];
     const float lphi = S.lphi, lnbr = S.lnbr, lt = S.lt, lw = S.lw;
-    for (int q = threadIdx.x; q < 8 * m.L; q += blockDim.x) sdq[q] = S.dq[q];
+    copy_to_lds(sdq, S.dq, 8 * m.L);
     __syncthreads();
     const int i = local * blockDim.x + threadIdx.x;
     const bool live = i < m.V;
