@@ -52,7 +52,7 @@ enum { TRACK_HINGE = 0, TRACK_PRISMATIC = 1 };
    float32; bfloat16 hi/lo split (3 products); bfloat16 hi/mid/lo split (6). */
 enum { TRACK_GRAM_FP32 = 0, TRACK_GRAM_BF16X3 = 1, TRACK_GRAM_BF16X6 = 2 };
 
-/* Limits of this build. */
+/* Compile-time limits of the library. */
 #define TRACK_MAX_JOINTS 127
 #define TRACK_MAX_LINKS 255
 #define TRACK_MAX_INFL 4
