@@ -116,7 +116,7 @@ def cpu_baseline(w, budget_s=15.0, max_frames=30):
 def single_stream(args):
     import torch
 
-    from paper_1711_07999_amd import synth
+    import synth
     from paper_1711_07999_amd import track as T
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -247,7 +247,7 @@ def _pingpong(k, n):
 def serve(args):
     import torch
 
-    from paper_1711_07999_amd import synth
+    import synth
     from paper_1711_07999_amd import track as T
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"

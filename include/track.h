@@ -90,6 +90,14 @@ typedef struct {
     const int32_t *neighbors;    /* [V*4] template neighbours (-1 = none) or NULL:
                                     the library takes the 4 nearest template
                                     vertices (ties to the lower index)              */
+    float scale;                 /* uniform size of the template (Section 5.4 fits one
+                                    such factor per subject from its height), > 0,
+                                    1 = as given.  Applied at init about c, the
+                                    translation of joint 0's offset: rest vertices
+                                    x -> c + s (x - c); offsets of joints with a
+                                    parent t -> s t; of other root joints
+                                    t -> c + s (t - c).  Prismatic values and the
+                                    camera stay in metres.                          */
 } track_model;
 
 /* Pinhole depth camera; depth frames are H x W float32 row-major, metres,
@@ -133,19 +141,44 @@ typedef struct {
 } track_frame_stats;
 
 /*
- * Create a context: validates and copies the model, camera and constants,
- * allocates device memory, and poses the template at theta0 (P doubles,
- * "an initial estimate of the skeletal pose", Section 3) with offsets phi0
- * ([V*3], or NULL for the default shape Phi = 0).  hip_stream is a
- * hipStream_t or NULL.  On success *out holds the context.
+ * Device memory provider.  alloc returns `bytes` of device memory on the
+ * current device, aligned to 256 bytes, or NULL (the call then fails with
+ * TRACK_E_NOMEM); free releases what alloc returned.  `user` is passed back
+ * unchanged.  A context takes all of its device memory through these calls
+ * (one block for the stream's buffers, one for its launch table), at
+ * track_init, and returns it at track_destroy, after its stream has drained;
+ * nothing is allocated between.  Pinned host memory for the launch table is
+ * the library's own.  With no provider the library uses hipMalloc/hipFree.
  */
-int track_init(const track_model *model, const track_camera *camera, const track_params *params,
-               const double *theta0, const float *phi0, void *hip_stream, track_ctx **out);
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} track_allocator;
 
 /*
- * Track one depth frame (H*W float32, metres).  depth_on_device != 0 means a
- * device pointer.  On success the state holds the new Theta and Phi.  On
- * TRACK_E_NOT_PD or TRACK_E_LOST the state is that of the previous frame.
+ * Create a context: validates and copies the model, camera and constants,
+ * allocates device memory (through `allocator` if not NULL), and poses the
+ * template at theta0 (P doubles: the starting pose the method needs at the
+ * head of a sequence, Section 4 opening) with offsets phi0 ([V*3], or NULL
+ * for the undeformed template Phi = 0, Section 3.3).  hip_stream is a
+ * hipStream_t or NULL.  On success *out holds the context; on failure
+ * nothing stays allocated.
+ */
+int track_init(const track_model *model, const track_camera *camera, const track_params *params,
+               const double *theta0, const float *phi0, void *hip_stream, const track_allocator *allocator,
+               track_ctx **out);
+
+/*
+ * Track one depth frame (H*W float32, metres, row-major; 0 or non-finite =
+ * no measurement).  Each pixel's point is back-projected through the camera
+ * (Section 4.1), then the iterations of the schedule run: association of
+ * every point with its nearest skinned vertex within tau, point-to-plane
+ * residuals (Eq. 6), the damped pose step (Eq. 7, 8, Section 4.2) and the
+ * per-vertex offset step (Section 4.3).  depth_on_device != 0 means a device
+ * pointer, read during the call only; a host frame is copied in.  On success
+ * the state holds the new Theta and Phi.  On TRACK_E_NOT_PD or TRACK_E_LOST
+ * the state is that of the previous frame.
  */
 int track_frame(track_ctx *ctx, const float *depth, int32_t depth_on_device);
 
@@ -153,9 +186,11 @@ int track_frame(track_ctx *ctx, const float *depth, int32_t depth_on_device);
    with z <= 0 or a non-finite coordinate has no measurement). */
 int track_frame_xyz(track_ctx *ctx, const float *xyz, int32_t on_device);
 
-/* Copy the state out: Theta [P] float64, Phi [V*3], skinned vertices [V*3]
-   at the current state, and the last frame's statistics.  Never changes the
-   state. */
+/* Copy the state out: the joint parameters Theta [P] float64 and offsets
+   Phi [V*3] that the method estimates per frame (Section 4.1 opening), the
+   skinned vertices [V*3] of Eq. (5) at that state, and the last frame's
+   statistics.  NULL skips an output.  Never changes the state; waits for the
+   context's stream. */
 int track_state(const track_ctx *ctx, double *theta, float *phi, float *verts,
                 track_frame_stats *stats);
 

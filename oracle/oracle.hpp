@@ -259,9 +259,10 @@ template <class S> void skin(const Model& m, const std::vector<DQ<S>>& D, const 
     }
 }
 
-// Vertex normals of the skinned mesh (the paper uses "the model's vertex
-// normal" without defining it): sum over incident faces (a,b,c), in face
-// order, of (v_b - v_a) x (v_c - v_a), normalised; zero if the sum is zero.
+// Vertex normals of the skinned mesh (Section 4.1 takes the residual along
+// the vertex normal without defining it): sum over incident faces (a,b,c), in
+// face order, of (v_b - v_a) x (v_c - v_a) -- each face weighted by twice its
+// area -- normalised; zero if the sum is zero.
 inline void vertex_normals(const Model& m, const double* v, double* n) {
     std::fill(n, n + 3 * m.V, 0.0);
     for (int f = 0; f < m.F; ++f) {

@@ -147,6 +147,7 @@ int validate_model(const track_model* m, const track_camera* cam) {
     if (m->neighbors)
         for (int64_t q = 0; q < 4 * (int64_t)m->n_verts; ++q)
             if (m->neighbors[q] < -1 || m->neighbors[q] >= m->n_verts) return fail(TRACK_E_INVALID, "neighbor out of range");
+    if (!(m->scale > 0.0f) || !std::isfinite(m->scale)) return fail(TRACK_E_INVALID, "model scale must be > 0");
     if (cam->width < 1 || cam->height < 1 || cam->width > 4096 || cam->height > 4096)
         return fail(TRACK_E_INVALID, "image size out of range");
     if (!(cam->fx > 0.0f) || !(cam->fy > 0.0f) || !std::isfinite(cam->fx) || !std::isfinite(cam->fy) ||
@@ -167,6 +168,61 @@ int validate_params(const track_params* p, int P) {
         if (!(l >= 0.0f) || !std::isfinite(l)) return fail(TRACK_E_INVALID, "weights must be finite and >= 0");
     (void)P;
     return TRACK_OK;
+}
+
+// The template resized by its uniform scale s about c, the translation of
+// joint 0's offset (Section 5.4 sizes the template to the subject this way):
+// rest vertices x -> c + s (x - c), offsets of joints with a parent t -> s t,
+// of other root joints t -> c + s (t - c); arithmetic in float64, rounded
+// once.  Arrays the scale leaves alone stay the caller's.
+struct ScaledModel {
+    track_model m{};
+    std::vector<float> rest, offset;
+    const track_model* apply(const track_model* in) {
+        if (in->scale == 1.0f) return in;
+        m = *in;
+        const double sc = in->scale;
+        const double c[3] = {in->joint_offset[4], in->joint_offset[5], in->joint_offset[6]};
+        rest.resize(3 * (size_t)in->n_verts);
+        for (size_t q = 0; q < rest.size(); ++q) rest[q] = (float)(c[q % 3] + sc * ((double)in->rest_xyz[q] - c[q % 3]));
+        offset.assign(in->joint_offset, in->joint_offset + 7 * (size_t)in->n_joints);
+        for (int j = 0; j < in->n_joints; ++j)
+            for (int d = 0; d < 3; ++d) {
+                const double t = in->joint_offset[7 * j + 4 + d];
+                offset[7 * j + 4 + d] = (float)(in->joint_parent[j] >= 0 ? sc * t : c[d] + sc * (t - c[d]));
+            }
+        m.rest_xyz = rest.data();
+        m.joint_offset = offset.data();
+        m.scale = 1.0f;
+        return &m;
+    }
+};
+
+// Device memory of a context or stream: the caller's provider, else hipMalloc.
+void* dev_alloc(const track_allocator& a, size_t bytes) {
+    void* p = nullptr;
+    if (a.alloc) {
+        p = a.alloc(bytes, a.user);
+        if (p && (reinterpret_cast<uintptr_t>(p) & 255u)) {  // the layout assumes 256-byte alignment
+            if (a.free) a.free(p, a.user);
+            p = nullptr;
+        }
+        return p;
+    }
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+void dev_free(const track_allocator& a, void* p) {
+    if (!p) return;
+    if (a.alloc) {
+        if (a.free) a.free(p, a.user);
+    } else {
+        (void)hipFree(p);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -205,6 +261,7 @@ struct Stream {
     std::vector<double> prior_S;  // S_k: share of vertices each joint moves
     void* arena = nullptr;
     size_t arena_bytes = 0, arena_used = 0;
+    track_allocator alloc{};       // where the arena came from (all null: hipMalloc)
     Slot slot{};                   // device pointers and constants of this stream
     float *depth_buf = nullptr, *xyz_buf = nullptr;
     int v_cur = 0, phi_cur = 0, phi_prev = 0;
@@ -510,6 +567,7 @@ void stream_layout(Stream* c) {
     const size_t V = c->V, N = (size_t)c->W * c->H;
     c->arena_used = 0;
     Slot& S = c->slot;
+    c->djt = carve<JointTable>(c, 1);
     S.theta = carve<double>(c, c->P);
     S.theta_backup = carve<double>(c, c->P);
     S.step = carve<double>(c, c->P);
@@ -576,7 +634,7 @@ size_t stream_bytes(const track_model* m, const track_camera* cam) {
     s.npad = s.ntiles * 64;
     s.negrid = ne_grid(s.V);
     stream_layout(&s);
-    return s.arena_used + ((sizeof(JointTable) + 255) & ~size_t(255));
+    return s.arena_used;
 }
 
 int upload_soa(int V, Vec3Buf dst, const float* aos) {
@@ -613,15 +671,14 @@ int download_v4(int V, const float4* src, float* aos) {
 
 void stream_free(Stream* c) {
     if (!c) return;
-    if (c->arena) (void)hipFree(c->arena);
-    if (c->djt) (void)hipFree(c->djt);
+    dev_free(c->alloc, c->arena);
     c->arena = nullptr;
     c->djt = nullptr;
 }
 
 // Allocate and fill a stream; on failure nothing stays allocated.
 int stream_create(Stream* c, const track_model* model, const track_camera* camera, const track_params* params,
-                  const double* theta0, const float* phi0) {
+                  const double* theta0, const float* phi0, const track_allocator* alloc) {
     c->P = model->n_joints; c->L = model->n_links; c->V = model->n_verts; c->F = model->n_faces;
     c->K = model->max_infl;
     c->PP = ((c->P + 1) + 15) / 16 * 16;
@@ -633,16 +690,9 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
     build_joint_table(c, model);
     stream_layout(c);  // size only
     c->arena_bytes = c->arena_used;
-    if (hipMalloc(&c->arena, c->arena_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        c->arena = nullptr;
-        return fail(TRACK_E_NOMEM, "device allocation failed");
-    }
-    if (hipMalloc(&c->djt, sizeof(JointTable)) != hipSuccess) {
-        (void)hipGetLastError();
-        stream_free(c);
-        return fail(TRACK_E_NOMEM, "device allocation failed");
-    }
+    c->alloc = alloc ? *alloc : track_allocator{};
+    c->arena = dev_alloc(c->alloc, c->arena_bytes);
+    if (!c->arena) return fail(TRACK_E_NOMEM, "device allocation failed");
     stream_layout(c);  // carve
     Slot& S = c->slot;
     S.jt = c->djt;
@@ -785,6 +835,8 @@ struct Runner {
     hipStream_t s = nullptr;
     bool own_stream = false;
     int cap = 0;                       // table entries
+    track_allocator alloc{};           // provider of dmem (all null: hipMalloc)
+    void* dmem = nullptr;              // dslots and dpre
     Slot* dslots = nullptr;
     int* dpre = nullptr;               // prefix rows of each table window
     Slot* hslots = nullptr;            // pinned; written by the host, read by k_stage
@@ -804,7 +856,7 @@ struct Runner {
 // prefix rows of the table window starting at entry `off`
 inline int pre_offset(int off) { return off * (KK_COUNT_ + 1) * 2; }
 
-int runner_init(Runner& R, int cap, void* hip_stream) {
+int runner_init(Runner& R, int cap, void* hip_stream, const track_allocator* alloc = nullptr) {
     static const bool kernels_ready = prepare_pose_solve() && prepare_normal_eq();
     if (!kernels_ready) return fail(TRACK_E_DEVICE, "pose solve: LDS size attribute refused");
     R.cap = cap;
@@ -814,8 +866,13 @@ int runner_init(Runner& R, int cap, void* hip_stream) {
         R.own_stream = true;
     }
     const size_t npre = (size_t)pre_offset(cap) + (size_t)KK_COUNT_ * (cap + 1);
-    if (hipMalloc(&R.dslots, sizeof(Slot) * cap) != hipSuccess || hipMalloc(&R.dpre, sizeof(int) * npre) != hipSuccess)
-        return fail(TRACK_E_NOMEM, "device allocation failed");
+    // the device copy of the table and its prefix rows, one block
+    R.alloc = alloc ? *alloc : track_allocator{};
+    const size_t slot_bytes = (sizeof(Slot) * cap + 255) & ~size_t(255);
+    R.dmem = dev_alloc(R.alloc, slot_bytes + sizeof(int) * npre);
+    if (!R.dmem) return fail(TRACK_E_NOMEM, "device allocation failed");
+    R.dslots = static_cast<Slot*>(R.dmem);
+    R.dpre = reinterpret_cast<int*>(static_cast<char*>(R.dmem) + slot_bytes);
     if (hipHostMalloc(&R.hslots, sizeof(Slot) * cap) != hipSuccess ||
         hipHostMalloc(&R.hpre, sizeof(int) * npre) != hipSuccess ||
         hipHostMalloc(&R.hsum, sizeof(DevSummary) * cap) != hipSuccess)
@@ -843,8 +900,7 @@ void runner_free(Runner& R) {
         for (auto e : t.ev) (void)hipEventDestroy(e);
     if (R.f0) (void)hipEventDestroy(R.f0);
     if (R.f1) (void)hipEventDestroy(R.f1);
-    if (R.dslots) (void)hipFree(R.dslots);
-    if (R.dpre) (void)hipFree(R.dpre);
+    dev_free(R.alloc, R.dmem);
     if (R.hslots) (void)hipHostFree(R.hslots);
     if (R.hpre) (void)hipHostFree(R.hpre);
     if (R.hsum) (void)hipHostFree(R.hsum);
@@ -1339,7 +1395,7 @@ int server_admit(track_server* sv) {
         if (sv->used + (int64_t)ss->bytes > sv->budget || server_resident(sv) >= sv->max_streams) break;
         Stream* d = new Stream();
         int rc = stream_create(d, &ss->model.m, &ss->cam, &sv->params, ss->theta0.data(),
-                               ss->phi0.empty() ? nullptr : ss->phi0.data());
+                               ss->phi0.empty() ? nullptr : ss->phi0.data(), nullptr);
         if (rc == TRACK_E_NOMEM) { delete d; break; }  // the device is fuller than the budget says
         if (rc) { delete d; return rc; }
         ss->dev = d;
@@ -1368,7 +1424,8 @@ extern "C" {
 const char* track_last_error(void) { return g_err.c_str(); }
 
 int track_init(const track_model* model, const track_camera* camera, const track_params* params,
-               const double* theta0, const float* phi0, void* hip_stream, track_ctx** out) {
+               const double* theta0, const float* phi0, void* hip_stream, const track_allocator* allocator,
+               track_ctx** out) {
     g_err.clear();
     if (!out) return fail(TRACK_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -1378,9 +1435,13 @@ int track_init(const track_model* model, const track_camera* camera, const track
     if (!theta0) return fail(TRACK_E_INVALID, "theta0 is NULL");
     for (int k = 0; k < model->n_joints; ++k)
         if (!std::isfinite(theta0[k])) return fail(TRACK_E_INVALID, "theta0 not finite");
+    if (allocator && (!allocator->alloc || !allocator->free))
+        return fail(TRACK_E_INVALID, "allocator needs both alloc and free");
+    ScaledModel scaled;
+    const track_model* mm = scaled.apply(model);
     track_ctx* c = new track_ctx();
-    if ((rc = runner_init(c->run, 1, hip_stream))) { free_ctx(c); return rc; }
-    if ((rc = stream_create(&c->st, model, camera, params, theta0, phi0))) { free_ctx(c); return rc; }
+    if ((rc = runner_init(c->run, 1, hip_stream, allocator))) { free_ctx(c); return rc; }
+    if ((rc = stream_create(&c->st, mm, camera, params, theta0, phi0, allocator))) { free_ctx(c); return rc; }
     c->sched.set(params);
     if ((rc = refresh_surface(c))) { free_ctx(c); return rc; }
     *out = c;
@@ -1760,7 +1821,8 @@ int track_server_open(track_server* sv, const track_model* model, const track_ca
     ServerStream* ss = new ServerStream();
     ss->id = (int)sv->streams.size();
     ss->open = true;
-    ss->model.take(model);
+    ScaledModel scaled;
+    ss->model.take(scaled.apply(model));
     ss->cam = *camera;
     ss->theta0.assign(theta0, theta0 + model->n_joints);
     if (phi0) ss->phi0.assign(phi0, phi0 + 3 * (size_t)model->n_verts);

@@ -54,8 +54,45 @@ class track_model(ctypes.Structure):
         ("rest_xyz", ctypes.c_void_p), ("n_faces", ctypes.c_int32),
         ("faces", ctypes.c_void_p), ("max_infl", ctypes.c_int32),
         ("skin_link", ctypes.c_void_p), ("skin_w", ctypes.c_void_p),
-        ("neighbors", ctypes.c_void_p),
+        ("neighbors", ctypes.c_void_p), ("scale", ctypes.c_float),
     ]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class track_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def torch_allocator(device: int = 0, stream=None):
+    """A track_allocator whose blocks come from PyTorch's caching allocator,
+    so that torch counts and reuses a context's device memory.  The returned
+    object counts its calls (``calls``) and must outlive the contexts made
+    with it."""
+    import torch
+
+    st = torch.cuda.current_stream(device) if stream is None else stream
+    calls = {"alloc": 0, "free": 0}
+
+    def _alloc(nbytes, _user):
+        calls["alloc"] += 1
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), device, st))
+        except RuntimeError:
+            return None
+
+    def _free(ptr, _user):
+        calls["free"] += 1
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    fns = (ALLOC_FN(_alloc), FREE_FN(_free))
+    a = track_allocator(fns[0], fns[1], None)
+    a.calls = calls
+    a._fns = fns
+    return a
 
 
 class track_camera(ctypes.Structure):
@@ -110,7 +147,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
         sig = {
-            "track_init": [vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)],
+            "track_init": [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)],
             "track_frame": [vp, vp, i32],
             "track_frame_xyz": [vp, vp, i32],
             "track_state": [vp, vp, vp, vp, vp],
@@ -192,6 +229,7 @@ def make_model(model: dict, keep: _Keep) -> track_model:
     m.skin_link = keep(_c(model["skin_link"], np.int32))
     m.skin_w = keep(_c(model["skin_w"], np.float32))
     m.neighbors = None if nb is None else keep(_c(nb, np.int32))
+    m.scale = float(model.get("scale", 1.0))
     return m
 
 
@@ -223,8 +261,9 @@ def _check_active(params: dict, P: int):
         raise ValueError("params['active'] must hold one flag per joint")
 
 
-def track_init(model: dict, camera: dict, params: dict, theta0, phi0=None, stream=None):
-    """Returns an opaque context handle (ctypes.c_void_p)."""
+def track_init(model: dict, camera: dict, params: dict, theta0, phi0=None, stream=None, allocator=None):
+    """Returns an opaque context handle (ctypes.c_void_p).  ``allocator`` is a
+    track_allocator (e.g. torch_allocator()) or None for the library's own."""
     keep = _Keep()
     m = make_model(model, keep)
     c = make_camera(camera)
@@ -236,7 +275,8 @@ def track_init(model: dict, camera: dict, params: dict, theta0, phi0=None, strea
     ph = None if phi0 is None else _c(phi0, np.float32)
     ctx = ctypes.c_void_p()
     st = None if stream is None else ctypes.c_void_p(int(stream))
-    _check(lib().track_init(ctypes.byref(m), ctypes.byref(c), ctypes.byref(p), _p(th), _p(ph), st,
+    al = None if allocator is None else ctypes.byref(allocator)
+    _check(lib().track_init(ctypes.byref(m), ctypes.byref(c), ctypes.byref(p), _p(th), _p(ph), st, al,
                             ctypes.byref(ctx)))
     return ctx
 
@@ -330,11 +370,13 @@ def track_kernel_bench(ctx, kernel: int, depth, reps: int) -> float:
 class Tracker:
     """Owns one context; convenience methods over the functions above."""
 
-    def __init__(self, model: dict, camera: dict, params: dict, theta0, phi0=None, stream=None):
+    def __init__(self, model: dict, camera: dict, params: dict, theta0, phi0=None, stream=None,
+                 allocator=None):
         self.P = len(model["joint_parent"])
         self.V = model["rest_xyz"].shape[0]
         self.W, self.H = int(camera["width"]), int(camera["height"])
-        self.ctx = track_init(model, camera, params, theta0, phi0, stream)
+        self.allocator = allocator
+        self.ctx = track_init(model, camera, params, theta0, phi0, stream, allocator)
 
     def frame(self, depth) -> int:
         return track_frame(self.ctx, depth)

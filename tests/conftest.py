@@ -15,14 +15,14 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def tiny():
-    from paper_1711_07999_amd import synth
+    import synth
     return synth.workload_tiny()
 
 
 @pytest.fixture(scope="session")
 def small_body():
     """Human-like template with 3,000 vertices on a 160x120 camera."""
-    from paper_1711_07999_amd import synth
+    import synth
     cam = dict(width=160, height=120, fx=131.25, fy=131.25, cx=79.5, cy=59.5)
     return synth.make_body(3000, cam, 2.6)
 

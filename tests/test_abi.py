@@ -8,7 +8,7 @@ import subprocess
 import numpy as np
 import pytest
 
-from paper_1711_07999_amd import synth
+import synth
 from paper_1711_07999_amd import track as T
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -48,6 +48,8 @@ def _model():
     (lambda m, c, p: c.__setitem__("fx", -1.0), "intrinsics"),
     (lambda m, c, p: p.__setitem__("tau", 0.0), "tau"),
     (lambda m, c, p: p.__setitem__("n_iters", 0), "n_iters"),
+    (lambda m, c, p: m.__setitem__("scale", 0.0), "scale"),
+    (lambda m, c, p: m.__setitem__("scale", float("nan")), "scale"),
 ])
 def test_invalid_input_is_rejected(mutate, msg):
     body = _model()
@@ -59,3 +61,13 @@ def test_invalid_input_is_rejected(mutate, msg):
         T.track_init(m, c, p, np.zeros(8))
     assert e.value.code == T.TRACK_E_INVALID
     assert msg in str(e.value)
+
+
+def test_allocator_without_free_is_rejected():
+    """A provider must give both calls; checked before any device work."""
+    body = _model()
+    half = T.track_allocator(T.ALLOC_FN(lambda n, u: None), T.FREE_FN(), None)
+    with pytest.raises(T.TrackError) as e:
+        T.track_init(body.model, body.camera, synth.default_params(8, 2, 0.1), np.zeros(8), allocator=half)
+    assert e.value.code == T.TRACK_E_INVALID
+    assert "allocator" in str(e.value)

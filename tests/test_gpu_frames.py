@@ -1,0 +1,226 @@
+"""Whole tracking frames on the GPU against the float64 oracle, certified
+iteration by iteration.
+
+Within a frame the two sides diverge only through the association: the GPU
+skins in float32, the oracle in float64, so a pixel whose two nearest
+vertices (or whose nearest vertex and the cutoff tau) are within the
+vertices' rounding difference of each other can pick differently, and the
+pose step then carries that difference into the next iteration.  The test
+therefore walks the GPU's own trajectory one iteration at a time:
+
+1. the GPU runs the frame truncated after t iterations (deterministic, so
+   its iterations 1..t are those of the full frame); its state S_t and the
+   association of iteration t are read back;
+2. the oracle runs one iteration (the flags of iteration t) from the GPU's
+   state S_{t-1};
+3. every pixel whose match differs is certified as a near-tie on the
+   oracle's float64 surface of S_{t-1}: the two candidates' distances, or a
+   distance and tau, differ by at most twice the largest difference between
+   the GPU's float32 vertices and the float64 ones (eps), or the candidate's
+   projection lies within eps f / z + 1e-5 px of the image border;
+4. the GPU's pose and surface after iteration t are held to the oracle's
+   one-iteration result from the same state: 1e-4 rad per joint angle,
+   1e-4 m per root translation and per vertex (both surfaces skinned by the
+   oracle in float64).
+
+Beside it the whole frame (all iterations, each side from the frame's start
+state) is printed with the oracle's own response to a 1e-6 perturbation of
+its start pose; a frame whose iterations all pass step 4 differs at the end
+by the composition of its steps, which a weakly observed joint can amplify
+(the printed response shows by how much).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+BAR_ANG, BAR_LIN = 1e-4, 1e-4
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1711_07999_amd import track
+    track.lib()
+    return track
+
+
+@pytest.fixture(scope="module")
+def human():
+    return synth.workload_human(n_frames=3)
+
+
+@pytest.fixture(scope="module")
+def highres():
+    return synth.workload_highres(n_frames=2)
+
+
+def _truncated(prm, t):
+    return dict(prm, n_iters=t, do_pose=np.asarray(prm["do_pose"])[:t].copy(),
+                do_shape=np.asarray(prm["do_shape"])[:t].copy())
+
+
+def _points(cam, depth):
+    f32 = np.float32
+    H, W = depth.shape
+    u = np.arange(W, dtype=f32)[None, :]
+    v = np.arange(H, dtype=f32)[:, None]
+    d = depth.astype(f32)
+    return np.stack([((u - f32(cam["cx"])) * d) / f32(cam["fx"]), ((v - f32(cam["cy"])) * d) / f32(cam["fy"]), d],
+                    -1).reshape(-1, 3).astype(np.float64)
+
+
+def _certify(cam, tau, v64, eps, pts, a_g, a_o):
+    """Indices of mismatched pixels that are not near-ties (see module doc)."""
+    bad = []
+    W, H = cam["width"], cam["height"]
+    for k in np.flatnonzero(a_g != a_o):
+        p = pts[k]
+        ds = [np.linalg.norm(v64[i] - p) if i >= 0 else None for i in (a_g[k], a_o[k])]
+        if ds[0] is not None and ds[1] is not None:
+            if abs(ds[0] - ds[1]) <= 2 * eps:
+                continue
+        else:
+            i = a_g[k] if a_g[k] >= 0 else a_o[k]
+            dd = ds[0] if ds[0] is not None else ds[1]
+            if abs(dd - tau) <= 2 * eps:
+                continue
+            x, y, z = v64[i]
+            if z > 1e-3:
+                uu = cam["fx"] * x / z + cam["cx"] + 0.5
+                vv = cam["fy"] * y / z + cam["cy"] + 0.5
+                edge = min(abs(uu), abs(uu - W), abs(vv), abs(vv - H))
+                if edge <= 2 * eps * max(cam["fx"], cam["fy"]) / z + 1e-5:
+                    continue
+        bad.append(int(k))
+    return bad
+
+
+def _walk_frame(T, trk, w, prm, th0, phi0, depth, log):
+    """Per-iteration certification of one frame from (th0, phi0); returns the
+    worst per-iteration differences and the list of failures."""
+    m, cam = w.body.model, w.body.camera
+    V, P = m["rest_xyz"].shape[0], len(th0)
+    ang = w.body.angular
+    n = int(prm["n_iters"])
+    pts = _points(cam, depth)
+    th_prev, phi_prev_state = th0.copy(), phi0.astype(np.float32).astype(np.float64)
+    v_gpu_prev = None
+    worst = [0.0, 0.0, 0.0]
+    fails = []
+    n_mis = 0
+    for t in range(1, n + 1):
+        trk.set_params(_truncated(prm, t))
+        trk.reset(th0, phi0.astype(np.float32))
+        assert trk.frame(depth) == 0, T.track_last_error()
+        th_g, phi_g, v_g, st = trk.state()
+        a_g = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (cam["height"] * cam["width"],), np.int32)
+        # the oracle: one iteration from the GPU's state before iteration t
+        one = dict(prm, n_iters=1, do_pose=np.asarray(prm["do_pose"])[t - 1:t].copy(),
+                   do_shape=np.asarray(prm["do_shape"])[t - 1:t].copy())
+        th_o, phi_o = th_prev.copy(), phi_prev_state.copy()
+        r = oracle.track_frame(m, cam, one, th_o, phi_o, phi0.astype(np.float32).astype(np.float64).copy(),
+                               depth=depth)
+        a_o = r["assoc_first"]
+        v64, _ = oracle.skin(m, th_prev, phi_prev_state)
+        if v_gpu_prev is None:
+            # the GPU's float32 surface at the frame's start state
+            trk.reset(th0, phi0.astype(np.float32))
+            v_gpu_prev = trk.state()[2]
+        eps = float(np.abs(v_gpu_prev.astype(np.float64) - v64).max())
+        bad = _certify(cam, float(prm["tau"]), v64, eps, pts, a_g, a_o)
+        mis = int((a_g != a_o).sum())
+        n_mis += mis
+        # pose and surface after iteration t, both skinned in float64
+        vg64, _ = oracle.skin(m, th_g, phi_g.astype(np.float64))
+        vo64, _ = oracle.skin(m, th_o, phi_o)
+        d = np.abs(th_g - th_o)
+        e = (d[ang].max(), d[~ang].max(), np.abs(vg64 - vo64).max())
+        worst = [max(a, b) for a, b in zip(worst, e)]
+        log(f"    it {t}: assoc mismatches {mis} ({len(bad)} uncertified, eps {eps:.1e} m); "
+            f"joint {e[0]:.1e} rad, root {e[1]:.1e} m, vertex {e[2]:.1e} m")
+        if bad:
+            fails.append(f"iteration {t}: {len(bad)} mismatches are not near-ties (first pixel {bad[0]})")
+        if not (e[0] <= BAR_ANG and e[1] <= BAR_LIN and e[2] <= BAR_LIN):
+            fails.append(f"iteration {t}: joint {e[0]:.2e} rad, root {e[1]:.2e} m, vertex {e[2]:.2e} m")
+        th_prev, phi_prev_state = th_g.copy(), phi_g.astype(np.float64)
+        v_gpu_prev = v_g
+    trk.set_params(prm)
+    return worst, n_mis, fails
+
+
+def _whole_frame(T, trk, w, prm, th0, phi0, depth, log):
+    """Whole frame from the same start on both sides, with the oracle's own
+    response to a 1e-6 perturbation of the start pose (printed)."""
+    m, cam = w.body.model, w.body.camera
+    ang = w.body.angular
+    trk.reset(th0, phi0.astype(np.float32))
+    assert trk.frame(depth) == 0, T.track_last_error()
+    th_g, phi_g, _, _ = trk.state()
+    p0 = phi0.astype(np.float32).astype(np.float64)
+    th_o, phi_o = th0.copy(), p0.copy()
+    oracle.track_frame(m, cam, prm, th_o, phi_o, p0.copy(), depth=depth)
+    th_p, phi_p = th0 + 1e-6 * np.random.default_rng(5).standard_normal(len(th0)), p0.copy()
+    oracle.track_frame(m, cam, prm, th_p, phi_p, p0.copy(), depth=depth)
+    vg, _ = oracle.skin(m, th_g, phi_g.astype(np.float64))
+    vo, _ = oracle.skin(m, th_o, phi_o)
+    vp, _ = oracle.skin(m, th_p, phi_p)
+    dg, dp = np.abs(th_g - th_o), np.abs(th_p - th_o)
+    log(f"    whole frame: GPU vs oracle joint {dg[ang].max():.1e} rad, vertex {np.abs(vg - vo).max():.1e} m; "
+        f"oracle's response to 1e-6 rad: joint {dp[ang].max():.1e} rad, vertex {np.abs(vp - vo).max():.1e} m")
+    return th_o, phi_o
+
+
+def _run(T, w, prm, nframes):
+    m, cam = w.body.model, w.body.camera
+    V = m["rest_xyz"].shape[0]
+    trk = T.Tracker(m, cam, prm, w.theta0)
+    th, phi = w.theta0.copy(), np.zeros((V, 3))
+    fails, worst_all = [], [0.0, 0.0, 0.0]
+    try:
+        for f in range(nframes):
+            _say(f"  frame {f}")
+            worst, n_mis, fl = _walk_frame(T, trk, w, prm, th, phi, w.frames[f], _say)
+            worst_all = [max(a, b) for a, b in zip(worst_all, worst)]
+            fails += [f"frame {f}, {x}" for x in fl]
+            th, phi = _whole_frame(T, trk, w, prm, th, phi, w.frames[f], _say)
+    finally:
+        trk.close()
+    _say(f"  worst per iteration: joint {worst_all[0]:.2e} rad, root {worst_all[1]:.2e} m, "
+         f"vertex {worst_all[2]:.2e} m (bar {BAR_ANG:g} rad, {BAR_LIN:g} m)")
+    return fails
+
+
+MODES = {"fp32": (0, 0), "fp32+fp64 solves": (0, 1), "bf16x3+fp64 solves": (1, 1), "bf16x6+fp64 solves": (2, 1)}
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_human_frames_certified_per_iteration(T, human, mode):
+    g, f = MODES[mode]
+    _say(f"[frames] human-50k, {mode}")
+    prm = dict(human.params, gram_mode=g, pose_solve_fp64=f, shape_solve_fp64=f)
+    fails = _run(T, human, prm, 2)
+    assert not fails, fails
+
+
+def test_highres_frames_certified_per_iteration(T, highres):
+    _say("[frames] highres-200k (temporal weight 0.5, float64 pose solve)")
+    fails = _run(T, highres, dict(highres.params), 2)
+    assert not fails, fails
+
+
+def test_tiny_frame_certified_per_iteration(T, tiny):
+    _say("[frames] arm-2k, 10 iterations")
+    fails = _run(T, tiny, dict(tiny.params), 1)
+    assert not fails, fails

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1711_07999_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -143,6 +143,126 @@ def test_association_is_bit_exact(T, tiny, ragged, human, highres, case, source)
         trk.close()
 
 
+def test_skin_with_antipodal_influences(T, tiny):
+    """Hinges past a half turn (3.5 and -3.4 rad) put the blend zones'
+    influences on opposite quaternion hemispheres (cos(3.5 / 2) = -0.18), so
+    the sign alignment of the blend decides every such vertex; adding a full
+    turn to a hinge negates its quaternion and must leave the surface alone.
+    Bound as for the skinning above: 16 ulp at 4 m."""
+    _say("[skin] antipodal blend")
+    m, cam, prm = tiny.body.model, tiny.body.camera, tiny.params
+    V = m["rest_xyz"].shape[0]
+    th = 0.5 * tiny.theta_true[0]
+    th[6], th[7] = 3.5, -3.4
+    multi = (m["skin_w"] > 0).sum(1) > 1
+    assert multi.sum() > 100
+    trk = T.Tracker(m, cam, prm, th)
+    try:
+        out = []
+        for t in (th, th + 2 * math.pi * np.eye(len(th))[6]):
+            T.track_dbg_set(trk.ctx, T.TRACK_BUF_THETA, t)
+            assert T.track_dbg_run(trk.ctx, T.TRACK_PASS_SKIN) == 0
+            out.append(T.track_dbg_get(trk.ctx, T.TRACK_BUF_VERTS, (V, 3), np.float32))
+    finally:
+        trk.close()
+    v_or, _ = oracle.skin(m, th)
+    assert np.abs(out[0] - v_or).max() <= 16 * ULP3
+    assert np.abs(out[1] - v_or).max() <= 16 * ULP3
+
+
+def _planted_cloud():
+    """A hand-built association case on the tiny arm's 160x120 camera with
+    tau = 0.125 m (exact in binary).  2,000 vertices are scattered in front of
+    the camera at z in [0.6, 1.4] with points near them; the planted cases
+    sit 0.5 m or more from all of those:
+      (a) exact ties: vertices 1500.. are copies of vertices 0..; pairs
+          placed symmetrically about a point (z = 2.5), which lies midway;
+      (b) never candidates: vertices behind the camera, at z = 0, at exactly
+          z_near = 1e-3 and one float below it, off the image on every side,
+          each with a point 2 mm away;
+      (c) vertices projecting exactly onto the image's outer pixel edges
+          (z = 2.05078125 makes the float32 projection exact): u = -0.5 and
+          v = -0.5 fall in the first pixel, u = W - 0.5 and v = H - 0.5 out;
+      (d) a point at exactly tau from a lone vertex (not matched) and one a
+          float nearer (matched)."""
+    rng = np.random.default_rng(99)
+    cam = dict(width=160, height=120, fx=131.25, fy=131.25, cx=79.5, cy=59.5)
+    W, H = 160, 120
+    V = 2000
+    z = rng.uniform(0.6, 1.4, V)
+    u = rng.uniform(-0.4, W - 0.6, V)
+    vv = rng.uniform(-0.4, H - 0.6, V)
+    v = np.stack([(u - cam["cx"]) * z / cam["fx"], (vv - cam["cy"]) * z / cam["fy"], z], 1).astype(np.float32)
+    xyz = np.zeros((H, W, 3), np.float32)
+    for i in rng.choice(1500, 4000):
+        pu, pv = int(rng.integers(0, W)), int(rng.integers(16, H))
+        xyz[pv, pu] = v[i] + rng.normal(0, 0.004, 3).astype(np.float32)
+    planted = []
+    for q in range(60):                                   # (a) copies
+        v[1500 + q] = v[q]
+        planted.append(v[q] + np.float32(0.001))
+    d = np.array([0.0078125, 0.0, 0.0], np.float32)      # (a) symmetric pairs
+    for q in range(40):
+        p = np.array([(q - 20) * 0.0625, 0.125 * ((q % 5) - 2), 2.5], np.float32)
+        v[1600 + 2 * q] = p + d
+        v[1601 + 2 * q] = p - d
+        planted.append(p)
+    specials = [(0.0, 0.0, -0.5), (0.05, 0.02, 0.0), (0.0, 0.0, 1e-3),   # (b)
+                (0.0, 0.0, float(np.nextafter(np.float32(1e-3), np.float32(0)))),
+                (5.0, 0.0, 0.9), (-5.0, 0.0, 0.9), (0.0, 5.0, 0.9), (0.0, -5.0, 0.9)]
+    for q, sp in enumerate(specials):
+        v[1700 + q] = np.array(sp, np.float32)
+        planted.append(v[1700 + q] + np.float32(0.002))
+    ze = np.float32(2.05078125)                           # (c) fx / ze = 64
+    for q, (pu, pv) in enumerate(((-0.5, 60.0), (W - 0.5, 60.0), (80.0, -0.5), (80.0, H - 0.5))):
+        v[1720 + q] = np.array([(pu - cam["cx"]) / 64.0, (pv - cam["cy"]) / 64.0, ze], np.float32)
+        planted.append(v[1720 + q] + np.float32(0.001))
+    v[1730] = np.array([0.0, 0.3, 2.0], np.float32)       # (d)
+    planted.append(np.array([0.0, 0.3, 2.125], np.float32))
+    v[1731] = np.array([0.0, -0.3, 2.0], np.float32)
+    planted.append(np.array([0.0, -0.3, np.nextafter(np.float32(2.125), np.float32(0))], np.float32))
+    where = []
+    for q, p in enumerate(planted):                       # rows 2..10, clear of the others
+        xyz[2 + 4 * (q // 40), 2 + 4 * (q % 40)] = p
+        where.append((2 + 4 * (q // 40)) * W + 2 + 4 * (q % 40))
+    return cam, v, xyz, np.array(where)
+
+
+def test_association_planted_ties_cutoff_and_non_candidates(T, tiny):
+    _say("[assoc] planted cloud")
+    cam, v32, xyz, where = _planted_cloud()
+    prm = dict(tiny.params, tau=0.125)
+    trk = T.Tracker(tiny.body.model, cam, prm, tiny.theta0)
+    try:
+        T.track_dbg_set(trk.ctx, T.TRACK_BUF_XYZ, xyz)
+        T.track_dbg_set(trk.ctx, T.TRACK_BUF_VERTS, v32)
+        assert T.track_dbg_run(trk.ctx, T.TRACK_PASS_ASSOCIATE) == 0
+        a = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (cam["height"] * cam["width"],), np.int32)
+        cnt = T.track_dbg_get(trk.ctx, T.TRACK_BUF_COUNT, (2000,), np.int32)
+    finally:
+        trk.close()
+    a_or = _planted_expectations(cam, v32, xyz, where)
+    np.testing.assert_array_equal(a, a_or)
+    c_or, _ = oracle.average(cam, a_or, v32.astype(np.float64), xyz=xyz)
+    np.testing.assert_array_equal(cnt, c_or)
+
+
+def _planted_expectations(cam, v32, xyz, where):
+    """The oracle's association of the planted cloud, checked against brute
+    force and against what each planted case is for."""
+    a = oracle.associate(cam, 0.125, v32, xyz=xyz)
+    np.testing.assert_array_equal(a, oracle.associate(cam, 0.125, v32, xyz=xyz, brute=True))
+    assert (a >= 0).sum() > 1000
+    pl = a[where]
+    assert not np.isin(a, np.arange(1500, 1560)).any()                  # ties: the lower copy
+    np.testing.assert_array_equal(pl[:60], np.arange(60))
+    np.testing.assert_array_equal(pl[60:100], 1600 + 2 * np.arange(40))  # midway: the lower index
+    assert not np.isin(a, np.arange(1700, 1708)).any() and (pl[100:108] == -1).all()
+    np.testing.assert_array_equal(pl[108:112], [1720, -1, 1722, -1])     # pixel edges
+    np.testing.assert_array_equal(pl[112:114], [-1, 1731])               # exactly tau, one float inside
+    return a
+
+
 def _assoc_inputs(m, cam, prm, th, depth, phi):
     v, n = oracle.skin(m, th, phi)
     v32 = v.astype(np.float32)
@@ -208,7 +328,9 @@ def _blended_everywhere(m):
 def test_pose_step(T, human, fp64, form, monkeypatch):
     """The damped Cholesky step on the GPU's own Gram matrix equals the
     oracle's solve of that matrix (float64: 1e-9 relative to |x|; float32:
-    1e-3 relative, the conditioning of the 75x75 system times 1e-7).  Forms:
+    1e-4 relative -- the damped 75x75 system has condition number about 130
+    once its diagonal is scaled to one, which a Cholesky factorisation does
+    implicitly, so float32 carries about 130 x 6e-8 = 8e-6).  Forms:
     the tree-ordered factorisation (the default for the body), the dense
     one forced by TRACK_DENSE_SOLVE=1, and the dense one chosen because the
     skin couples every pair of joints."""
@@ -237,7 +359,8 @@ def test_pose_step(T, human, fp64, form, monkeypatch):
         trk.close()
     # the library holds the damping constant in float32
     x = oracle.lm_solve(G[:P, :P], G[:P, P], float(np.float32(prm["lambda_k"])))
-    tol = 1e-9 if fp64 else 1e-3
+    tol = 1e-9 if fp64 else 1e-4
+    _say(f"  step difference {np.abs(step - x).max() / np.abs(x).max():.2e} relative")
     assert np.abs(step - x).max() <= tol * np.abs(x).max()
     np.testing.assert_allclose(th_new, th - step, rtol=0, atol=1e-15)
 
@@ -290,119 +413,6 @@ def test_shape_step(T, tiny, human, case, fp64):
     worst = int(np.argmax(err.max(axis=1) / (x[:, 0] + 1e-12)))
     assert bad.size == 0, (f"{bad.size} vertices, worst {worst}: err {err[worst].max():.3e} step {x[worst, 0]:.3e} "
                            f"count {cnt[worst]} |n| {np.linalg.norm(n_new[worst]):.3f}")
-
-
-def _near_tie_certified(m, cam, tau, v, depth, a_gpu, a_or):
-    """Mismatched pixels must be near-ties: both candidates' distances (or a
-    distance and the cutoff) within 1e-6 m, judged on the oracle's vertices."""
-    bad = np.flatnonzero(a_gpu != a_or)
-    W = cam["width"]
-    for k in bad:
-        d = float(depth.reshape(-1)[k])
-        u, vv = k % W, k // W
-        p = np.array([(u - cam["cx"]) * d / cam["fx"], (vv - cam["cy"]) * d / cam["fy"], d])
-        ds = [np.linalg.norm(v[i] - p) if i >= 0 else tau for i in (a_gpu[k], a_or[k])]
-        if abs(ds[0] - ds[1]) > 1e-6:
-            return False, k, ds
-    return True, len(bad), None
-
-
-# end-to-end floors (joint angle rad, root translation and vertex m) per
-# (operand form of the Gram, float64 solves)
-E2E_FLOOR = {(0, 0): (2e-3, 2e-3), (0, 1): (2e-3, 2e-3), (1, 1): (2e-2, 5e-3), (2, 1): (2e-3, 2e-3)}
-# perturbation of the starting pose that measures the oracle's own response,
-# and the multiple of that response allowed to the float32 path
-E2E_PERTURB, E2E_GAIN = 1e-6, 10.0
-
-
-def _oracle_frame(m, cam, prm, th, phi, depth):
-    th, phi = th.copy(), phi.copy()
-    r = oracle.track_frame(m, cam, prm, th, phi, phi.copy(), depth=depth)
-    v, _ = oracle.skin(m, th, phi)
-    return th, phi, v, r
-
-
-def _frames_against_oracle(T, w, prm, nframes, floor):
-    """Frames of workload w against the float64 oracle, each frame from the
-    oracle's state at its start; returns the frames that break the bound."""
-    m, cam = w.body.model, w.body.camera
-    V, P = m["rest_xyz"].shape[0], len(w.theta0)
-    ang = w.body.angular
-    trk = T.Tracker(m, cam, prm, w.theta0)
-    th_or, phi_or = w.theta0.copy(), np.zeros((V, 3))
-    f_ang, f_lin = floor
-    failures = []
-    try:
-        for f in range(nframes):
-            trk.reset(th_or, phi_or.astype(np.float32))
-            phi_or = phi_or.astype(np.float32).astype(np.float64)
-            assert trk.frame(w.frames[f]) == 0, T.track_last_error()
-            th1, phi1, v1, r = _oracle_frame(m, cam, prm, th_or, phi_or, w.frames[f])
-            s_ang = s_lin = s_v = 0.0
-            for seed in (0, 1):
-                dth = E2E_PERTURB * np.random.default_rng(100 + 10 * f + seed).standard_normal(P)
-                th2, _, v2, _ = _oracle_frame(m, cam, prm, th_or + dth, phi_or, w.frames[f])
-                d = np.abs(th2 - th1)
-                s_ang, s_lin = max(s_ang, d[ang].max()), max(s_lin, d[~ang].max())
-                s_v = max(s_v, np.abs(v2 - v1).max())
-            th_g, phi_g, v_g, st = trk.state()
-            dth = np.abs(th_g - th1)
-            dv = np.abs(v_g - v1).max()
-            b_ang, b_lin, b_v = (max(f_ang, E2E_GAIN * s_ang), max(f_lin, E2E_GAIN * s_lin),
-                                 max(f_lin, E2E_GAIN * s_v))
-            _say(f"  frame {f}: joint {dth[ang].max():.2e} rad (bound {b_ang:.1e}), root {dth[~ang].max():.2e} m "
-                 f"(bound {b_lin:.1e}), vertex {dv:.2e} m (bound {b_v:.1e}), assoc px {st['n_assoc_px']} vs "
-                 f"{r['n_assoc_px']}")
-            if not (dth[ang].max() <= b_ang and dth[~ang].max() <= b_lin and dv <= b_v):
-                failures.append(f)
-            assert abs(st["n_assoc_px"] - r["n_assoc_px"]) <= 0.001 * r["n_assoc_px"] + 5
-            th_or, phi_or = th1, phi1   # the oracle's state starts the next frame
-    finally:
-        trk.close()
-    return failures
-
-
-@pytest.mark.parametrize("mode,fp64", list(E2E_FLOOR))
-def test_frame_end_to_end(T, human, mode, fp64):
-    """Frames of the human workload against the float64 oracle, each frame
-    from the oracle's state at its start.  Five Gauss-Newton iterations of
-    a 75-DoF body can amplify rounding-level differences (weakly observed
-    distal joints and limb twists), so the bound is certified per frame by
-    the oracle itself: its own change when the starting pose moves by
-    E2E_PERTURB (random direction, two draws) is the frame's amplification;
-    the GPU may differ by E2E_GAIN times that change, and at least by the
-    floor of its configuration (E2E_FLOOR).  Prints both."""
-    _say(f"[frame] gram mode={mode} fp64 solves={fp64}")
-    prm = dict(human.params, gram_mode=mode, pose_solve_fp64=fp64, shape_solve_fp64=fp64)
-    failures = _frames_against_oracle(T, human, prm, 3, E2E_FLOOR[(mode, fp64)])
-    assert not failures, failures
-
-
-def test_highres_frames_end_to_end(T, highres):
-    """The 200k-vertex, 512x424 workload (temporal weight 0.5, float64 pose
-    solve) against the oracle, with the certified bound of the test above."""
-    _say("[frame] highres")
-    failures = _frames_against_oracle(T, highres, dict(highres.params), 2, E2E_FLOOR[(0, 1)])
-    assert not failures, failures
-
-
-def test_first_iteration_association_matches_up_to_near_ties(T, human):
-    _say("[frame] first-iteration association")
-    m, cam = human.body.model, human.body.camera
-    prm = dict(human.params, n_iters=1, do_pose=np.zeros(1, np.uint8), do_shape=np.zeros(1, np.uint8))
-    trk = T.Tracker(m, cam, prm, human.theta0)
-    try:
-        assert trk.frame(human.frames[0]) == 0, T.track_last_error()
-        a_gpu = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (cam["height"] * cam["width"],), np.int32)
-    finally:
-        trk.close()
-    v, _ = oracle.skin(m, human.theta0)
-    a_or = oracle.associate(cam, prm["tau"], v.astype(np.float32), depth=human.frames[0])
-    same = (a_gpu == a_or).mean()
-    ok, info, ds = _near_tie_certified(m, cam, prm["tau"], v, human.frames[0], a_gpu, a_or)
-    _say(f"  identical {same * 100:.4f} %, mismatches {int((a_gpu != a_or).sum())}")
-    assert ok, (info, ds)
-    assert same > 0.999
 
 
 def test_runs_are_bit_identical_and_checkpoints_resume(T, human):

@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1711_07999_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 

@@ -13,7 +13,7 @@ import sys
 import numpy as np
 import pytest
 
-from paper_1711_07999_amd import synth
+import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -211,3 +211,60 @@ def test_rejected_frame_keeps_the_stream_state(T, streams):
     # the same frames without the empty one, tracked alone
     th_a, phi_a = _run_alone(T, (m, cam, th0, [frames[0], frames[1]], 0))
     assert np.array_equal(th_s, th_a) and np.array_equal(phi_s, phi_a)
+
+
+def test_served_stream_matches_the_oracle_iteration_by_iteration(T, streams):
+    """One stream served inside a mix (three other streams with frames in
+    flight at different iterations) against the float64 oracle: the server
+    runs one Gauss-Newton iteration per frame here, and each iteration of
+    the checked stream starts from the oracle's state (the stream is opened
+    with it), so every served result is compared with the oracle's step
+    from the same state.  Bar: 1e-4 rad per joint angle, 1e-4 m per root
+    translation and per vertex (both surfaces skinned by the oracle in
+    float64)."""
+    import oracle
+
+    _say("[server] served stream vs oracle, iteration by iteration, inside a mix")
+    one = dict(synth.default_params(1, 1, 0.05, lambda_k=0.1), active=None)
+    m, cam, th0, frames, _ = streams[1]
+    P, V = len(m["joint_parent"]), m["rest_xyz"].shape[0]
+    body_ang = np.array([t == 0 for t in m["joint_type"]])
+    sv = T.track_server_create(one, 1 << 36, 64)
+    worst = [0.0, 0.0, 0.0]
+    try:
+        for k in (0, 2, 3):   # background traffic
+            mb, cb, tb, fb, _ = streams[k]
+            sid = T.track_server_open(sv, mb, cb, tb)
+            for rep in range(40):
+                T.track_server_submit(sv, sid, fb[rep % len(fb)], tag=1000 * k + rep)
+        for _ in range(3):
+            T.track_server_step(sv)
+        th, phi = th0.copy(), np.zeros((V, 3))
+        for f, depth in enumerate(frames):
+            for it in range(5):
+                sid = T.track_server_open(sv, m, cam, th, phi.astype(np.float32))
+                T.track_server_submit(sv, sid, depth, tag=7)
+                res = None
+                for _ in range(200):
+                    T.track_server_step(sv)
+                    for c in T.track_server_poll(sv):
+                        if c["tag"] == 7:
+                            assert c["status"] == 0, c
+                            res = T.track_server_state(sv, sid, P, V)
+                    if res is not None:
+                        break
+                assert res is not None
+                assert T.track_server_info(sv)["frames_in_progress"] > 0, "the mix is still running"
+                T.track_server_close(sv, sid)
+                th_o, phi_o = th.copy(), phi.astype(np.float32).astype(np.float64)
+                oracle.track_frame(m, cam, one, th_o, phi_o, phi_o.copy(), depth=depth)
+                vg, _ = oracle.skin(m, res[0], res[1].astype(np.float64))
+                vo, _ = oracle.skin(m, th_o, phi_o)
+                d = np.abs(res[0] - th_o)
+                e = (d[body_ang].max(), d[~body_ang].max(), np.abs(vg - vo).max())
+                worst = [max(a, b) for a, b in zip(worst, e)]
+                _say(f"  frame {f} it {it}: joint {e[0]:.1e} rad, root {e[1]:.1e} m, vertex {e[2]:.1e} m")
+                th, phi = th_o, phi_o
+    finally:
+        T.track_server_destroy(sv)
+    assert worst[0] <= 1e-4 and worst[1] <= 1e-4 and worst[2] <= 1e-4, worst

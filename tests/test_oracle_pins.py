@@ -13,7 +13,7 @@ from scipy.linalg import cho_factor, cho_solve
 from scipy.spatial.transform import Rotation
 
 import oracle
-from paper_1711_07999_amd import synth
+import synth
 
 
 # ---------------------------------------------------------------------------
@@ -590,3 +590,260 @@ def test_frame_driver_composes_the_steps(tiny):
     np.testing.assert_array_equal(th, th1)
     np.testing.assert_array_equal(phi, phi1)
     np.testing.assert_array_equal(pp, phi1)
+
+
+# ---------------------------------------------------------------------------
+# blend sign rule (Section 3.2; Kavan et al.'s hemisphere alignment)
+# ---------------------------------------------------------------------------
+def _coaxial_pair(w0):
+    """Two links on hinges about the same z axis through the origin, one
+    vertex weighted w0 / 1 - w0 on them."""
+    return dict(joint_parent=np.array([-1, -1], np.int32), joint_type=np.array([0, 0], np.int32),
+                joint_axis=np.array([[0, 0, 1], [0, 0, 1]], np.float32),
+                joint_offset=np.array([[1, 0, 0, 0, 0, 0, 0]] * 2, np.float32),
+                link_joint=np.array([0, 1], np.int32),
+                rest_xyz=np.array([[0.3, 0.1, 0.2]], np.float32), faces=np.zeros((1, 3), np.int32),
+                skin_link=np.array([[0, 1]], np.int32), skin_w=np.array([[w0, 1.0 - w0]], np.float32),
+                neighbors=None)
+
+
+def test_blend_of_antipodal_hinges_takes_the_short_way():
+    """Hinges at +3.0 and -3.0 rad: their rotation quaternions lie on
+    opposite hemispheres (cos 3 < 0).  The rotations are 3.0 rad either way
+    round, 0.28 rad apart through pi, so an even blend is the half turn about
+    z.  Without the sign alignment the two quaternions' vector parts cancel
+    and the blend is the identity."""
+    m = _coaxial_pair(0.5)
+    x = m["rest_xyz"][0].astype(float)
+    v, _ = oracle.skin(m, np.array([3.0, -3.0]))
+    np.testing.assert_allclose(v[0], Rotation.from_rotvec([0, 0, math.pi]).as_matrix() @ x, atol=1e-12)
+    # -3.0 is the same rotation as 2 pi - 3.0; the blend of 3.0 and 2 pi - 3.0
+    # on one hemisphere is their mean angle, pi, whatever the pivot
+    for w0 in (0.3, 0.7):
+        m = _coaxial_pair(w0)
+        va, _ = oracle.skin(m, np.array([3.0, -3.0]))
+        vb, _ = oracle.skin(m, np.array([3.0, 2 * math.pi - 3.0]))
+        np.testing.assert_allclose(va, vb, atol=1e-12)
+
+
+def test_skinning_is_invariant_to_a_full_turn_of_any_hinge(small_body, rng):
+    """theta and theta + 2 pi give the same rotation and the negated
+    quaternion (Eq. 1); the sign alignment makes the blended surface the same
+    for every vertex, including those weighted on several links."""
+    m = small_body.model
+    th = random_pose(small_body, rng, 0.6, 0.03)
+    v0, n0 = oracle.skin(m, th)
+    multi = (m["skin_w"] > 0).sum(1) > 1
+    assert multi.sum() > 100
+    hinges = np.flatnonzero(small_body.angular)
+    for k in rng.choice(hinges, 12, replace=False):
+        t2 = th.copy()
+        t2[k] += 2 * math.pi
+        v1, n1 = oracle.skin(m, t2)
+        np.testing.assert_allclose(v1, v0, atol=1e-12)
+        np.testing.assert_allclose(n1, n0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# area weighting of vertex normals (Section 4.1 uses the model's normal;
+# reading: area-weighted face normals)
+# ---------------------------------------------------------------------------
+def _convex_mesh(rng, n=80):
+    """Closed convex triangle mesh with irregular faces: the hull of random
+    points near an ellipsoid, faces oriented outward."""
+    from scipy.spatial import ConvexHull
+
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    pts = d * np.array([0.12, 0.08, 0.05]) * rng.uniform(0.9, 1.1, (n, 1)) + np.array([0.0, 0.0, 1.0])
+    hull = ConvexHull(pts)
+    keep = np.unique(hull.simplices)
+    remap = -np.ones(n, np.int64)
+    remap[keep] = np.arange(keep.size)
+    P = pts[keep]
+    F = remap[hull.simplices]
+    c = P.mean(0)
+    for f in range(F.shape[0]):
+        a, b, e = P[F[f]]
+        if np.dot(np.cross(b - a, e - a), a - c) < 0:
+            F[f] = F[f][[0, 2, 1]]
+    return P, F.astype(np.int32)
+
+
+def test_vertex_normal_is_the_volume_gradient(rng):
+    """On a closed mesh the sum over a vertex's faces of (v_b - v_a) x
+    (v_c - v_a) is six times the gradient of the enclosed volume with
+    respect to that vertex (the fan's edge terms cancel), so the
+    area-weighted normal is the direction in which moving the vertex grows
+    the volume fastest.  The volume comes from Qhull; it is linear in each
+    vertex's coordinates, so central differences are exact up to rounding.
+    Normalising each face normal before the sum (unit weights) fails this."""
+    from scipy.spatial import ConvexHull
+
+    P, F = _convex_mesh(rng)
+    V = P.shape[0]
+    model = dict(joint_parent=np.array([-1], np.int32), joint_type=np.array([0], np.int32),
+                 joint_axis=np.array([[0, 0, 1]], np.float32),
+                 joint_offset=np.array([[1, 0, 0, 0, 0, 0, 0]], np.float32),
+                 link_joint=np.array([0], np.int32), rest_xyz=P.astype(np.float32), faces=F,
+                 skin_link=np.zeros((V, 1), np.int32), skin_w=np.ones((V, 1), np.float32), neighbors=None)
+    n = oracle.normals(model, P)
+    facets = {tuple(sorted(f)) for f in F}
+    h = 1e-5
+    checked = 0
+    for i in range(V):
+        g = np.zeros(3)
+        same = True
+        for c in range(3):
+            Pp, Pm = P.copy(), P.copy()
+            Pp[i, c] += h
+            Pm[i, c] -= h
+            hp, hm = ConvexHull(Pp), ConvexHull(Pm)
+            # a move that changes the hull's facets (nearly coplanar
+            # neighbours) makes the volume non-linear: skip that vertex
+            same = same and {tuple(sorted(f)) for f in hp.simplices} == facets
+            same = same and {tuple(sorted(f)) for f in hm.simplices} == facets
+            g[c] = (hp.volume - hm.volume) / (2 * h)
+        if not same:
+            continue
+        checked += 1
+        np.testing.assert_allclose(n[i], g / np.linalg.norm(g), atol=1e-7)
+    assert checked >= 0.8 * V
+    # the faces really are unequal (otherwise unit weights would pass too)
+    areas = 0.5 * np.linalg.norm(np.cross(P[F[:, 1]] - P[F[:, 0]], P[F[:, 2]] - P[F[:, 0]]), axis=1)
+    assert areas.max() > 3 * areas.min()
+
+
+# ---------------------------------------------------------------------------
+# per-vertex offset step derived from the energy (Section 4.3, Eq. 9 read as
+# a sum of squared residuals)
+# ---------------------------------------------------------------------------
+def test_shape_step_is_a_gauss_newton_step_on_the_vertex_energy(tiny, rng):
+    """Per vertex, with its neighbours' offsets, the mean associated point
+    and the normal frozen, the energy is
+        E_i(phi_i) = r_i(phi_i)^2 + l_phi |phi_i|^2
+                     + l_N sum_n |phi_i - phi_n|^2 + l_T |phi_i - phi_i^prev|^2,
+    r_i = n_i . (p~_i - v_i(phi_i)) with v_i from the skinning (pinned above).
+    The step must be the damped Gauss-Newton step of E_i / 2: gradient g and
+    Gauss-Newton matrix A = u u^T + alpha I, u = dr_i/dphi_i, both taken here
+    by central differences of the energy and of r_i, then
+    (A + l_w diag A) x = g and phi_i <- phi_i - x."""
+    m = oracle.Model(tiny.body.model)
+    th = random_pose(tiny.body, rng, 0.3, 0.02)
+    phi = rng.normal(0, 0.003, (m.V, 3))
+    prev = phi + rng.normal(0, 0.001, (m.V, 3))
+    v, n = oracle.skin(m, th, phi)
+    cnt = (rng.random(m.V) < 0.6).astype(np.int32)
+    delta = rng.normal(0, 0.005, (m.V, 3))
+    ptil = v + delta
+    lp, ln, lt, lw = 0.01, 1.0, 0.5, 0.1
+    out = oracle.shape_step(m, th, phi, prev, n, delta, cnt, lp, ln, lt, lw)
+    nb = tiny.body.model["neighbors"]
+    h = 1e-6
+    # skinned positions with every vertex's offset moved by +-h along axis c
+    # (each vertex's position depends on its own offset only)
+    vp = [oracle.skin(m, th, phi + h * np.eye(3)[c])[0] for c in range(3)]
+    vm = [oracle.skin(m, th, phi - h * np.eye(3)[c])[0] for c in range(3)]
+
+    def energy(i, ph_i, vi):
+        r = (n[i] @ (ptil[i] - vi)) if cnt[i] > 0 else 0.0
+        e = r * r + lp * ph_i @ ph_i + lt * (ph_i - prev[i]) @ (ph_i - prev[i])
+        for j in nb[i]:
+            if j >= 0:
+                e += ln * (ph_i - phi[j]) @ (ph_i - phi[j])
+        return e, r
+
+    for i in rng.choice(m.V, 150, replace=False):
+        g = np.zeros(3)
+        u = np.zeros(3)
+        for c in range(3):
+            e_p, r_p = energy(i, phi[i] + h * np.eye(3)[c], vp[c][i])
+            e_m, r_m = energy(i, phi[i] - h * np.eye(3)[c], vm[c][i])
+            g[c] = 0.25 * (e_p - e_m) / h
+            u[c] = 0.5 * (r_p - r_m) / h
+        alpha = lp + lt + ln * (nb[i] >= 0).sum()
+        A = np.outer(u, u) + alpha * np.eye(3)
+        x = np.linalg.solve(A + lw * np.diag(np.diag(A)), g)
+        np.testing.assert_allclose(out[i], phi[i] - x, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# a rigid single link: point-to-plane least squares (Section 4.1 cites
+# Chen and Medioni)
+# ---------------------------------------------------------------------------
+def test_rigid_link_gauss_newton_reaches_the_point_to_plane_least_squares_pose(tiny):
+    """Every vertex on the root link (a rigid tube), association, mean points
+    p~_i and normals n_i frozen at the start: the oracle's pose system and
+    step, iterated with the offsets delta_i = p~_i - v_i(theta) recomputed
+    from the skinning, converge to the minimiser of sum_i (n_i . (p~_i -
+    v_i(theta)))^2 over the six root parameters, found here by scipy's
+    least_squares on a 4x4-matrix model of the rigid motion."""
+    from scipy.optimize import least_squares
+
+    body = tiny.body
+    m = one_hot(body.model)
+    m["skin_link"][:, 0] = 0
+    cam = body.camera
+    th0 = 0.5 * tiny.theta_true[0]
+    v0, n0 = oracle.skin(m, th0)
+    a = oracle.associate(cam, 0.10, v0.astype(np.float32), depth=tiny.frames[0])
+    cnt, d0 = oracle.average(cam, a, v0, depth=tiny.frames[0])
+    obs = cnt > 0
+    assert obs.sum() > 300
+    ptil = v0 + d0
+    th = th0.copy()
+    for _ in range(60):
+        v, _ = oracle.skin(m, th)
+        ps = oracle.pose_system(m, th, np.zeros_like(v), n0, ptil - v, cnt)
+        x = oracle.lm_solve(ps["A"], ps["b"], 1e-9)
+        th = th - x
+    assert np.abs(x).max() < 1e-12
+    x_rest = m["rest_xyz"].astype(float)[obs]
+    M0 = matrix_chain(m, np.zeros_like(th0))[5]
+
+    def resid(q):
+        t = th0.copy()
+        t[:6] = q
+        G = matrix_chain(m, t)[5] @ np.linalg.inv(M0)
+        return (n0[obs] * (ptil[obs] - apply(G, x_rest))).sum(1)
+
+    ls = least_squares(resid, th0[:6], xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    np.testing.assert_allclose(th[:6], ls.x, atol=1e-9)
+    np.testing.assert_array_equal(th[6:], th0[6:])   # nothing observed moves the hinges
+
+
+# ---------------------------------------------------------------------------
+# noise-free rendered depth: convergence up to the sampling of the surface
+# ---------------------------------------------------------------------------
+def _converge_on_own_render(body, th_true, cam, params):
+    v, _ = oracle.skin(body.model, th_true)
+    depth = synth.raster_depth(v.astype(np.float32), body.model["faces"], cam)
+    zwall = float(v[:, 2].max()) + 0.5
+    depth = np.where(np.isfinite(depth), depth, np.float32(zwall)).astype(np.float32)
+    n = 30
+    prm = dict(params, n_iters=n, do_pose=np.ones(n, np.uint8), do_shape=np.zeros(n, np.uint8))
+    th = 0.5 * th_true
+    phi = np.zeros((v.shape[0], 3))
+    r = oracle.track_frame(body.model, cam, prm, th, phi, phi.copy(), depth=depth)
+    v2, _ = oracle.skin(body.model, th)
+    return np.abs(th - th_true).max(), np.abs(v2 - v).max(), r["step_norm_last"]
+
+
+def test_noise_free_rendered_depth_converges_within_the_mesh_sampling_bias(tiny):
+    """Depth rendered (triangle z-buffer, no noise, no missing pixels) from
+    the model's own surface at theta*.  Pixels sample the flat triangles
+    between vertices while the residual measures them against the vertex's
+    tangent plane, which lies off the triangles by about the sagitta
+    s^2 / (8 R) of the vertex spacing s on a section of radius R (0.2 mm on
+    the 2,000-vertex arm): pose-only Gauss-Newton from half the perturbation
+    stops there, not at theta*.  The bias is below 0.5 mm per vertex and
+    3e-3 rad per joint at 2,000 vertices and shrinks with the square of the
+    spacing: at twice the sampling in each direction (7,994 vertices) it is
+    below 0.3 times the first."""
+    th_true = tiny.theta_true[0]
+    cam = dict(width=320, height=240, fx=262.5, fy=262.5, cx=159.5, cy=119.5)
+    ang0, vert0, step0 = _converge_on_own_render(synth.make_arm(), th_true, cam, tiny.params)
+    ang1, vert1, step1 = _converge_on_own_render(synth.make_arm(74, 108), th_true, cam, tiny.params)
+    assert step0 < 1e-6 and step1 < 1e-6          # converged
+    assert vert0 < 5e-4 and ang0 < 3e-3
+    assert vert1 < 0.3 * vert0 and ang1 < 0.3 * ang0
