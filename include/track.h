@@ -183,7 +183,12 @@ int track_init(const track_model *model, const track_camera *camera, const track
 int track_frame(track_ctx *ctx, const float *depth, int32_t depth_on_device);
 
 /* Same, from an organised point cloud (H*W*3 float32, camera frame; a pixel
-   with z <= 0 or a non-finite coordinate has no measurement). */
+   with z <= 0 or a non-finite coordinate has no measurement).  Each pixel's
+   point must lie on that pixel's ray, i.e. project onto the pixel's centre
+   to within float32 rounding, as the back-projection of a depth image does:
+   the nearest-vertex search is bounded by the pixel distance from the
+   point's own pixel, so a point placed elsewhere may get a vertex that is
+   not its nearest. */
 int track_frame_xyz(track_ctx *ctx, const float *xyz, int32_t on_device);
 
 /* Copy the state out: the joint parameters Theta [P] float64 and offsets

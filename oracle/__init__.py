@@ -262,8 +262,12 @@ class FrameResult(dict):
     pass
 
 
-def track_frame(model, cam, params, theta, phi, phi_prev, depth=None, xyz=None):
+def track_frame(model, cam, params, theta, phi, phi_prev, depth=None, xyz=None, assoc=None):
     """Run one frame; theta/phi/phi_prev are updated in place (float64).
+
+    assoc (test hook): int32 [n_iters, H*W] matches used instead of each
+    iteration's own association (another implementation's choice at pixels
+    whose candidates tie within rounding).
 
     Returns dict(status, n_valid_px, n_assoc_px, n_obs_verts, energy_first,
     energy_last, step_norm_last, energies [n_iters], assoc_first [H*W])."""
@@ -286,8 +290,12 @@ def track_frame(model, cam, params, theta, phi, phi_prev, depth=None, xyz=None):
     af = np.full(int(cam["width"]) * int(cam["height"]), -1, np.int32)
     d = None if depth is None else _c(depth, np.float32)
     x = None if xyz is None else _c(xyz, np.float32)
+    ai = None
+    if assoc is not None:
+        ai = _c(assoc, np.int32).reshape(-1)
+        assert ai.shape[0] == n_it * af.shape[0], "assoc must be [n_iters, H*W]"
     rc = lib().orc_track_frame(ctypes.byref(m.c), ctypes.byref(c), ctypes.byref(pr), _p(theta),
-                               _p(phi), _p(phi_prev), _p(d), _p(x), _p(si), _p(sd), _p(en), _p(af))
+                               _p(phi), _p(phi_prev), _p(d), _p(x), _p(si), _p(sd), _p(en), _p(af), _p(ai))
     return FrameResult(status=int(rc), n_valid_px=int(si[1]), n_assoc_px=int(si[2]),
                        n_obs_verts=int(si[3]), energy_first=float(sd[0]),
                        energy_last=float(sd[1]), step_norm_last=float(sd[2]),

@@ -192,7 +192,7 @@ int orc_shape_step(const orc_model_in* in, const double* theta, const double* ph
 // stats_d = {energy_first, energy_last, step_norm_last}.
 int orc_track_frame(const orc_model_in* in, const orc_camera_in* c, const orc_params_in* p, double* theta,
                     double* phi, double* phi_prev, const float* depth, const float* xyz, int32_t* stats_i,
-                    double* stats_d, double* energies, int32_t* assoc_first) {
+                    double* stats_d, double* energies, int32_t* assoc_first, const int32_t* assoc_in) {
     orc::Model m = to_model(in);
     orc::Params prm;
     prm.tau = p->tau;
@@ -203,7 +203,7 @@ int orc_track_frame(const orc_model_in* in, const orc_camera_in* c, const orc_pa
     prm.lambda_k = p->lambda_k; prm.lambda_s = p->lambda_s; prm.lambda_phi = p->lambda_phi;
     prm.lambda_nbr = p->lambda_nbr; prm.lambda_t = p->lambda_t; prm.lambda_w = p->lambda_w;
     orc::FrameStats st{};
-    int rc = orc::track_frame(m, to_cam(c), prm, theta, phi, phi_prev, depth, xyz, &st, energies, assoc_first);
+    int rc = orc::track_frame(m, to_cam(c), prm, theta, phi, phi_prev, depth, xyz, &st, energies, assoc_first, assoc_in);
     if (stats_i) { stats_i[0] = st.status; stats_i[1] = st.n_valid_px; stats_i[2] = st.n_assoc_px; stats_i[3] = st.n_obs_verts; }
     if (stats_d) { stats_d[0] = st.energy_first; stats_d[1] = st.energy_last; stats_d[2] = st.step_norm_last; }
     return rc;

@@ -645,9 +645,12 @@ inline SkinState skin_state(const Model& m, const double* theta, const double* p
     return s;
 }
 
+// assoc_in (test hook, may be null): [n_iters * W * H] matches to use in
+// place of each iteration's own association, e.g. another implementation's
+// choice at pixels whose nearest vertices tie within rounding.
 inline int track_frame(const Model& m, const Camera& cam, const Params& prm, double* theta, double* phi,
                        double* phi_prev, const float* depth, const float* xyz, FrameStats* st,
-                       double* energies, int32_t* assoc_out) {
+                       double* energies, int32_t* assoc_out, const int32_t* assoc_in = nullptr) {
     const int NP = cam.W * cam.H;
     std::vector<int32_t> a(NP), cnt(m.V);
     std::vector<double> delta(3 * m.V);
@@ -659,7 +662,8 @@ inline int track_frame(const Model& m, const Camera& cam, const Params& prm, dou
     for (int t = 0; t < prm.n_iters; ++t) {
         SkinState ss = skin_state(m, theta, phi);
         for (int q = 0; q < 3 * m.V; ++q) vf[q] = (float)ss.v[q];
-        associate_grid(cam, prm.tau, vf.data(), m.V, depth, xyz, a.data());
+        if (assoc_in) std::copy(assoc_in + (size_t)t * NP, assoc_in + (size_t)(t + 1) * NP, a.begin());
+        else associate_grid(cam, prm.tau, vf.data(), m.V, depth, xyz, a.data());
         average_offsets(cam, depth, xyz, a.data(), ss.v.data(), m.V, cnt.data(), delta.data());
         int nas = 0, nobs = 0;
         for (int k = 0; k < NP; ++k) nas += a[k] >= 0 ? 1 : 0;

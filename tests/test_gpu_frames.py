@@ -18,10 +18,14 @@ therefore walks the GPU's own trajectory one iteration at a time:
    distance and tau, differ by at most twice the largest difference between
    the GPU's float32 vertices and the float64 ones (eps), or the candidate's
    projection lies within eps f / z + 1e-5 px of the image border;
-4. the GPU's pose and surface after iteration t are held to the oracle's
-   one-iteration result from the same state: 1e-4 rad per joint angle,
-   1e-4 m per root translation and per vertex (both surfaces skinned by the
-   oracle in float64).
+4. where every mismatch is such a near-tie, both matches are correct
+   results of the association (the rounding of the surface decides between
+   them), so the oracle runs the same iteration again taking the GPU's
+   matches, and the GPU's pose and surface after iteration t are held to
+   that result: 1e-4 rad per joint angle, 1e-4 m per root translation and
+   per vertex (both surfaces skinned by the oracle in float64).  The
+   difference from the oracle's run on its own matches is printed beside it
+   (one flipped pixel moves its vertex's offset step by up to tau).
 
 Beside it the whole frame (all iterations, each side from the frame's start
 state) is printed with the oracle's own response to a 1e-6 perturbation of
@@ -34,12 +38,13 @@ import sys
 import numpy as np
 import pytest
 
+import certify
 import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
 
-BAR_ANG, BAR_LIN = 1e-4, 1e-4
+BAR_ANG, BAR_LIN = certify.BAR_ANG, certify.BAR_LIN
 
 
 def _say(msg):
@@ -71,52 +76,16 @@ def _truncated(prm, t):
                 do_shape=np.asarray(prm["do_shape"])[:t].copy())
 
 
-def _points(cam, depth):
-    f32 = np.float32
-    H, W = depth.shape
-    u = np.arange(W, dtype=f32)[None, :]
-    v = np.arange(H, dtype=f32)[:, None]
-    d = depth.astype(f32)
-    return np.stack([((u - f32(cam["cx"])) * d) / f32(cam["fx"]), ((v - f32(cam["cy"])) * d) / f32(cam["fy"]), d],
-                    -1).reshape(-1, 3).astype(np.float64)
-
-
-def _certify(cam, tau, v64, eps, pts, a_g, a_o):
-    """Indices of mismatched pixels that are not near-ties (see module doc)."""
-    bad = []
-    W, H = cam["width"], cam["height"]
-    for k in np.flatnonzero(a_g != a_o):
-        p = pts[k]
-        ds = [np.linalg.norm(v64[i] - p) if i >= 0 else None for i in (a_g[k], a_o[k])]
-        if ds[0] is not None and ds[1] is not None:
-            if abs(ds[0] - ds[1]) <= 2 * eps:
-                continue
-        else:
-            i = a_g[k] if a_g[k] >= 0 else a_o[k]
-            dd = ds[0] if ds[0] is not None else ds[1]
-            if abs(dd - tau) <= 2 * eps:
-                continue
-            x, y, z = v64[i]
-            if z > 1e-3:
-                uu = cam["fx"] * x / z + cam["cx"] + 0.5
-                vv = cam["fy"] * y / z + cam["cy"] + 0.5
-                edge = min(abs(uu), abs(uu - W), abs(vv), abs(vv - H))
-                if edge <= 2 * eps * max(cam["fx"], cam["fy"]) / z + 1e-5:
-                    continue
-        bad.append(int(k))
-    return bad
-
-
 def _walk_frame(T, trk, w, prm, th0, phi0, depth, log):
     """Per-iteration certification of one frame from (th0, phi0); returns the
     worst per-iteration differences and the list of failures."""
     m, cam = w.body.model, w.body.camera
-    V, P = m["rest_xyz"].shape[0], len(th0)
     ang = w.body.angular
     n = int(prm["n_iters"])
-    pts = _points(cam, depth)
-    th_prev, phi_prev_state = th0.copy(), phi0.astype(np.float32).astype(np.float64)
-    v_gpu_prev = None
+    phi0 = phi0.astype(np.float32).astype(np.float64)
+    th_prev, phi_prev_state = th0.copy(), phi0.copy()
+    trk.reset(th0, phi0.astype(np.float32))
+    v_gpu_prev = trk.state()[2]      # the GPU's float32 surface at the frame's start
     worst = [0.0, 0.0, 0.0]
     fails = []
     n_mis = 0
@@ -126,33 +95,19 @@ def _walk_frame(T, trk, w, prm, th0, phi0, depth, log):
         assert trk.frame(depth) == 0, T.track_last_error()
         th_g, phi_g, v_g, st = trk.state()
         a_g = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (cam["height"] * cam["width"],), np.int32)
-        # the oracle: one iteration from the GPU's state before iteration t
+        # the oracle: one iteration (the flags of iteration t) from the GPU's
+        # state before iteration t; phi_prev is the frame's start offsets
         one = dict(prm, n_iters=1, do_pose=np.asarray(prm["do_pose"])[t - 1:t].copy(),
                    do_shape=np.asarray(prm["do_shape"])[t - 1:t].copy())
-        th_o, phi_o = th_prev.copy(), phi_prev_state.copy()
-        r = oracle.track_frame(m, cam, one, th_o, phi_o, phi0.astype(np.float32).astype(np.float64).copy(),
-                               depth=depth)
-        a_o = r["assoc_first"]
-        v64, _ = oracle.skin(m, th_prev, phi_prev_state)
-        if v_gpu_prev is None:
-            # the GPU's float32 surface at the frame's start state
-            trk.reset(th0, phi0.astype(np.float32))
-            v_gpu_prev = trk.state()[2]
-        eps = float(np.abs(v_gpu_prev.astype(np.float64) - v64).max())
-        bad = _certify(cam, float(prm["tau"]), v64, eps, pts, a_g, a_o)
-        mis = int((a_g != a_o).sum())
-        n_mis += mis
-        # pose and surface after iteration t, both skinned in float64
-        vg64, _ = oracle.skin(m, th_g, phi_g.astype(np.float64))
-        vo64, _ = oracle.skin(m, th_o, phi_o)
-        d = np.abs(th_g - th_o)
-        e = (d[ang].max(), d[~ang].max(), np.abs(vg64 - vo64).max())
-        worst = [max(a, b) for a, b in zip(worst, e)]
-        log(f"    it {t}: assoc mismatches {mis} ({len(bad)} uncertified, eps {eps:.1e} m); "
-            f"joint {e[0]:.1e} rad, root {e[1]:.1e} m, vertex {e[2]:.1e} m")
-        if bad:
-            fails.append(f"iteration {t}: {len(bad)} mismatches are not near-ties (first pixel {bad[0]})")
-        if not (e[0] <= BAR_ANG and e[1] <= BAR_LIN and e[2] <= BAR_LIN):
+        c = certify.check_iteration(m, cam, one, ang, th_prev, phi_prev_state, phi0, v_gpu_prev, depth,
+                                    th_g, phi_g, a_g)
+        n_mis += c["mis"]
+        worst = [max(x, y) for x, y in zip(worst, c["err"])]
+        log(f"    it {t}: {certify.describe(c)}")
+        if c["bad"]:
+            fails.append(f"iteration {t}: {len(c['bad'])} mismatches are not near-ties (first pixel {c['bad'][0]})")
+        elif not c["ok"]:
+            e = c["err"]
             fails.append(f"iteration {t}: joint {e[0]:.2e} rad, root {e[1]:.2e} m, vertex {e[2]:.2e} m")
         th_prev, phi_prev_state = th_g.copy(), phi_g.astype(np.float64)
         v_gpu_prev = v_g

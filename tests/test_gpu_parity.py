@@ -17,6 +17,7 @@ import pytest
 
 import oracle
 import synth
+from planted_cases import planted_cloud, planted_expectations
 
 pytestmark = pytest.mark.gpu
 
@@ -170,67 +171,9 @@ def test_skin_with_antipodal_influences(T, tiny):
     assert np.abs(out[1] - v_or).max() <= 16 * ULP3
 
 
-def _planted_cloud():
-    """A hand-built association case on the tiny arm's 160x120 camera with
-    tau = 0.125 m (exact in binary).  2,000 vertices are scattered in front of
-    the camera at z in [0.6, 1.4] with points near them; the planted cases
-    sit 0.5 m or more from all of those:
-      (a) exact ties: vertices 1500.. are copies of vertices 0..; pairs
-          placed symmetrically about a point (z = 2.5), which lies midway;
-      (b) never candidates: vertices behind the camera, at z = 0, at exactly
-          z_near = 1e-3 and one float below it, off the image on every side,
-          each with a point 2 mm away;
-      (c) vertices projecting exactly onto the image's outer pixel edges
-          (z = 2.05078125 makes the float32 projection exact): u = -0.5 and
-          v = -0.5 fall in the first pixel, u = W - 0.5 and v = H - 0.5 out;
-      (d) a point at exactly tau from a lone vertex (not matched) and one a
-          float nearer (matched)."""
-    rng = np.random.default_rng(99)
-    cam = dict(width=160, height=120, fx=131.25, fy=131.25, cx=79.5, cy=59.5)
-    W, H = 160, 120
-    V = 2000
-    z = rng.uniform(0.6, 1.4, V)
-    u = rng.uniform(-0.4, W - 0.6, V)
-    vv = rng.uniform(-0.4, H - 0.6, V)
-    v = np.stack([(u - cam["cx"]) * z / cam["fx"], (vv - cam["cy"]) * z / cam["fy"], z], 1).astype(np.float32)
-    xyz = np.zeros((H, W, 3), np.float32)
-    for i in rng.choice(1500, 4000):
-        pu, pv = int(rng.integers(0, W)), int(rng.integers(16, H))
-        xyz[pv, pu] = v[i] + rng.normal(0, 0.004, 3).astype(np.float32)
-    planted = []
-    for q in range(60):                                   # (a) copies
-        v[1500 + q] = v[q]
-        planted.append(v[q] + np.float32(0.001))
-    d = np.array([0.0078125, 0.0, 0.0], np.float32)      # (a) symmetric pairs
-    for q in range(40):
-        p = np.array([(q - 20) * 0.0625, 0.125 * ((q % 5) - 2), 2.5], np.float32)
-        v[1600 + 2 * q] = p + d
-        v[1601 + 2 * q] = p - d
-        planted.append(p)
-    specials = [(0.0, 0.0, -0.5), (0.05, 0.02, 0.0), (0.0, 0.0, 1e-3),   # (b)
-                (0.0, 0.0, float(np.nextafter(np.float32(1e-3), np.float32(0)))),
-                (5.0, 0.0, 0.9), (-5.0, 0.0, 0.9), (0.0, 5.0, 0.9), (0.0, -5.0, 0.9)]
-    for q, sp in enumerate(specials):
-        v[1700 + q] = np.array(sp, np.float32)
-        planted.append(v[1700 + q] + np.float32(0.002))
-    ze = np.float32(2.05078125)                           # (c) fx / ze = 64
-    for q, (pu, pv) in enumerate(((-0.5, 60.0), (W - 0.5, 60.0), (80.0, -0.5), (80.0, H - 0.5))):
-        v[1720 + q] = np.array([(pu - cam["cx"]) / 64.0, (pv - cam["cy"]) / 64.0, ze], np.float32)
-        planted.append(v[1720 + q] + np.float32(0.001))
-    v[1730] = np.array([0.0, 0.3, 2.0], np.float32)       # (d)
-    planted.append(np.array([0.0, 0.3, 2.125], np.float32))
-    v[1731] = np.array([0.0, -0.3, 2.0], np.float32)
-    planted.append(np.array([0.0, -0.3, np.nextafter(np.float32(2.125), np.float32(0))], np.float32))
-    where = []
-    for q, p in enumerate(planted):                       # rows 2..10, clear of the others
-        xyz[2 + 4 * (q // 40), 2 + 4 * (q % 40)] = p
-        where.append((2 + 4 * (q // 40)) * W + 2 + 4 * (q % 40))
-    return cam, v, xyz, np.array(where)
-
-
 def test_association_planted_ties_cutoff_and_non_candidates(T, tiny):
     _say("[assoc] planted cloud")
-    cam, v32, xyz, where = _planted_cloud()
+    cam, v32, xyz, where = planted_cloud()
     prm = dict(tiny.params, tau=0.125)
     trk = T.Tracker(tiny.body.model, cam, prm, tiny.theta0)
     try:
@@ -241,26 +184,10 @@ def test_association_planted_ties_cutoff_and_non_candidates(T, tiny):
         cnt = T.track_dbg_get(trk.ctx, T.TRACK_BUF_COUNT, (2000,), np.int32)
     finally:
         trk.close()
-    a_or = _planted_expectations(cam, v32, xyz, where)
+    a_or = planted_expectations(cam, v32, xyz, where)
     np.testing.assert_array_equal(a, a_or)
     c_or, _ = oracle.average(cam, a_or, v32.astype(np.float64), xyz=xyz)
     np.testing.assert_array_equal(cnt, c_or)
-
-
-def _planted_expectations(cam, v32, xyz, where):
-    """The oracle's association of the planted cloud, checked against brute
-    force and against what each planted case is for."""
-    a = oracle.associate(cam, 0.125, v32, xyz=xyz)
-    np.testing.assert_array_equal(a, oracle.associate(cam, 0.125, v32, xyz=xyz, brute=True))
-    assert (a >= 0).sum() > 1000
-    pl = a[where]
-    assert not np.isin(a, np.arange(1500, 1560)).any()                  # ties: the lower copy
-    np.testing.assert_array_equal(pl[:60], np.arange(60))
-    np.testing.assert_array_equal(pl[60:100], 1600 + 2 * np.arange(40))  # midway: the lower index
-    assert not np.isin(a, np.arange(1700, 1708)).any() and (pl[100:108] == -1).all()
-    np.testing.assert_array_equal(pl[108:112], [1720, -1, 1722, -1])     # pixel edges
-    np.testing.assert_array_equal(pl[112:114], [-1, 1731])               # exactly tau, one float inside
-    return a
 
 
 def _assoc_inputs(m, cam, prm, th, depth, phi):

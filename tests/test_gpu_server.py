@@ -214,35 +214,55 @@ def test_rejected_frame_keeps_the_stream_state(T, streams):
 
 
 def test_served_stream_matches_the_oracle_iteration_by_iteration(T, streams):
-    """One stream served inside a mix (three other streams with frames in
-    flight at different iterations) against the float64 oracle: the server
-    runs one Gauss-Newton iteration per frame here, and each iteration of
-    the checked stream starts from the oracle's state (the stream is opened
-    with it), so every served result is compared with the oracle's step
-    from the same state.  Bar: 1e-4 rad per joint angle, 1e-4 m per root
-    translation and per vertex (both surfaces skinned by the oracle in
-    float64)."""
-    import oracle
+    """The 50k-vertex body on 640x480 depth, served inside a mix (three small
+    streams whose queues are topped up before each of its frames, so every
+    step that runs it also runs them in the same launches) against the
+    float64 oracle.  The server runs one Gauss-Newton iteration per frame
+    here, and each iteration of the checked stream starts from the GPU's
+    state after the previous one (the stream is reopened with it).  The
+    served result must equal, bit for bit, the same iteration on a context of
+    its own (whose matches can be read back), and is certified against the
+    oracle as the whole-frame test does: every differing match a near-tie,
+    then pose and surface within 1e-4 rad per joint angle and 1e-4 m per root
+    translation and per vertex of the oracle's iteration on the same matches.
+    (The small bodies of the mix are no fit for that bar: with 700-900
+    observed vertices for 75 joint parameters their damped pose systems
+    reach condition numbers of 1e10-1e11, where the oracle's own step moves
+    by 4e-5 rad under a 1e-7 relative perturbation of A and b.)"""
+    import certify
 
     _say("[server] served stream vs oracle, iteration by iteration, inside a mix")
-    one = dict(synth.default_params(1, 1, 0.05, lambda_k=0.1), active=None)
-    m, cam, th0, frames, _ = streams[1]
+    w = synth.workload_human(n_frames=2)
+    one = dict(w.params, n_iters=1, do_pose=np.ones(1, np.uint8), do_shape=np.ones(1, np.uint8), active=None)
+    m, cam, th0, frames = w.body.model, w.body.camera, w.theta0, w.frames
     P, V = len(m["joint_parent"]), m["rest_xyz"].shape[0]
-    body_ang = np.array([t == 0 for t in m["joint_type"]])
+    body_ang = w.body.angular
     sv = T.track_server_create(one, 1 << 36, 64)
+    alone = T.Tracker(m, cam, one, th0)
     worst = [0.0, 0.0, 0.0]
+    fails = []
     try:
-        for k in (0, 2, 3):   # background traffic
+        bg = []
+        for k in (0, 2, 3):   # background traffic, topped up before every checked frame
             mb, cb, tb, fb, _ = streams[k]
-            sid = T.track_server_open(sv, mb, cb, tb)
-            for rep in range(40):
-                T.track_server_submit(sv, sid, fb[rep % len(fb)], tag=1000 * k + rep)
+            bg.append((k, T.track_server_open(sv, mb, cb, tb), fb))
+        sent = 0
+
+        def top_up(n):
+            nonlocal sent
+            for k, bsid, fb in bg:
+                for _ in range(n):
+                    T.track_server_submit(sv, bsid, fb[sent % len(fb)], tag=-1 - 1000 * k - sent)
+                    sent += 1
+
+        top_up(4)
         for _ in range(3):
             T.track_server_step(sv)
-        th, phi = th0.copy(), np.zeros((V, 3))
+        th, phi = th0.copy(), np.zeros((V, 3), np.float32)
         for f, depth in enumerate(frames):
             for it in range(5):
-                sid = T.track_server_open(sv, m, cam, th, phi.astype(np.float32))
+                top_up(4)
+                sid = T.track_server_open(sv, m, cam, th, phi)
                 T.track_server_submit(sv, sid, depth, tag=7)
                 res = None
                 for _ in range(200):
@@ -254,17 +274,24 @@ def test_served_stream_matches_the_oracle_iteration_by_iteration(T, streams):
                     if res is not None:
                         break
                 assert res is not None
-                assert T.track_server_info(sv)["frames_in_progress"] > 0, "the mix is still running"
+                assert T.track_server_info(sv)["frames_pending"] > 0, "the other streams still had work"
                 T.track_server_close(sv, sid)
-                th_o, phi_o = th.copy(), phi.astype(np.float32).astype(np.float64)
-                oracle.track_frame(m, cam, one, th_o, phi_o, phi_o.copy(), depth=depth)
-                vg, _ = oracle.skin(m, res[0], res[1].astype(np.float64))
-                vo, _ = oracle.skin(m, th_o, phi_o)
-                d = np.abs(res[0] - th_o)
-                e = (d[body_ang].max(), d[~body_ang].max(), np.abs(vg - vo).max())
-                worst = [max(a, b) for a, b in zip(worst, e)]
-                _say(f"  frame {f} it {it}: joint {e[0]:.1e} rad, root {e[1]:.1e} m, vertex {e[2]:.1e} m")
-                th, phi = th_o, phi_o
+                # the same iteration on a context of its own
+                alone.reset(th, phi)
+                v32 = alone.state()[2]
+                assert alone.frame(depth) == 0, T.track_last_error()
+                th_a, phi_a, _, _ = alone.state()
+                a_g = T.track_dbg_get(alone.ctx, T.TRACK_BUF_ASSOC, (cam["height"] * cam["width"],), np.int32)
+                assert np.array_equal(res[0], th_a) and np.array_equal(res[1], phi_a), "served != alone"
+                p64 = phi.astype(np.float64)
+                c = certify.check_iteration(m, cam, one, body_ang, th, p64, p64, v32, depth, res[0], res[1], a_g)
+                worst = [max(x, y) for x, y in zip(worst, c["err"])]
+                _say(f"  frame {f} it {it}: {certify.describe(c)}")
+                if not c["ok"]:
+                    fails.append((f, it, c["err"], len(c["bad"])))
+                th, phi = res[0].copy(), res[1].copy()
     finally:
+        alone.close()
         T.track_server_destroy(sv)
-    assert worst[0] <= 1e-4 and worst[1] <= 1e-4 and worst[2] <= 1e-4, worst
+    _say(f"  worst: joint {worst[0]:.1e} rad, root {worst[1]:.1e} m, vertex {worst[2]:.1e} m")
+    assert not fails, fails
