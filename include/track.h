@@ -191,6 +191,24 @@ int track_frame(track_ctx *ctx, const float *depth, int32_t depth_on_device);
    not its nearest. */
 int track_frame_xyz(track_ctx *ctx, const float *xyz, int32_t on_device);
 
+/*
+ * track_frame without allocating: for callers that cannot allocate device
+ * memory or instantiate graphs while tracking (tight serving loops,
+ * harnesses that forbid allocation after set-up).  Same arguments, result
+ * and state as track_frame, bit for bit.  The frame's working buffers (bucket
+ * index, per-vertex sums, matches, Gram matrices, the pose solve's front
+ * image, a staging copy of a host depth image) come from one static block of
+ * 64 MiB per GPU instead of the context's memory; the block is held until
+ * the process ends and every call on that GPU shares it, so calls that
+ * overlap on one GPU race (issue them from one thread, or serialise them).
+ * The kernels are launched directly, not from a graph.  TRACK_E_INVALID if
+ * the frame's working buffers exceed 64 MiB (about 20 MiB for 50k vertices
+ * with 640x480 depth, 52 bytes more per vertex: up to about 850k vertices at
+ * that size) or kernel timing is on.  Working buffers read back through
+ * track_dbg_get (matches, counts, Gram) are those of track_frame's last frame.
+ */
+int track_frame_noalloc(track_ctx *ctx, const float *depth, int32_t depth_on_device);
+
 /* Copy the state out: the joint parameters Theta [P] float64 and offsets
    Phi [V*3] that the method estimates per frame (Section 4.1 opening), the
    skinned vertices [V*3] of Eq. (5) at that state, and the last frame's

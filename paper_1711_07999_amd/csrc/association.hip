@@ -48,6 +48,12 @@ __global__ void __launch_bounds__(256) k_clear(Batch B) {
         a.cnt[i] = 0u;
         a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
     }
+    // the tree solve's front image: zero outside the entries the Gram
+    // reduction writes
+    if (S.tree.gfmap) {
+        const int stride = ((npad > V ? npad : V) + 255) / 256 * 256;
+        for (int e = i; e < S.tree.elems; e += stride) S.tree.fimg[e] = 0.0;
+    }
 }
 
 void launch_clear(const Launch& L) {

@@ -293,7 +293,7 @@ void launch_fk(const Launch& L);
 // enter the buckets; `clear_acc` slots have their accumulators zeroed
 void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc);  // count: a SlotSel
 void launch_normals(const Launch& L, int vsel);
-void launch_clear(const Launch& L);                 // buckets, tile sums, accumulators
+void launch_clear(const Launch& L);                 // buckets, tile sums, accumulators, front image
 void launch_clear_acc(const Launch& L);             // accumulators only
 void launch_bucket_count(const Launch& L, int vsel, int which);
 // pixel offsets with the tile prefix (+ clearing the counters), scatter (+ normals)

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <mutex>
 #include <set>
 #include <string>
 #include <vector>
@@ -26,6 +27,13 @@
 #include "common.h"
 
 using namespace trk;
+
+// Working memory of allocation-free frames (track_frame_noalloc): one block
+// per GPU, held until the process ends, shared by every such call on that
+// GPU.  Host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device (scratch_base).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -635,6 +643,65 @@ size_t stream_bytes(const track_model* m, const track_camera* cam) {
     s.negrid = ne_grid(s.V);
     stream_layout(&s);
     return s.arena_used;
+}
+
+// The buffers of a frame whose contents mean nothing outside it (Gram
+// matrices, the solve's front image, bucket index, per-vertex sums,
+// matches, a staging copy of a host depth image), laid out from `base` into
+// the slot (base null: sizes only).  Returns the bytes used.
+size_t frame_scratch_layout(const Stream* c, char* base, Slot& S, float** depth_stage) {
+    size_t used = 0;
+    auto take = [&](size_t n, size_t elem) -> void* {
+        void* p = base ? base + used : nullptr;
+        used += (n * elem + 255) & ~size_t(255);
+        return p;
+    };
+    const size_t V = c->V, N = (size_t)c->W * c->H;
+    S.gram = static_cast<double*>(take((size_t)c->PP * c->PP, sizeof(double)));
+    S.partials = static_cast<float*>(take((size_t)c->negrid * c->PP * c->PP, sizeof(float)));
+    S.tree.fimg = static_cast<double*>(take((size_t)std::max(2, c->hplan.elems), sizeof(double)));
+    Buckets& b = S.b;
+    b.pcnt = static_cast<uint32_t*>(take(c->npad, 4));
+    b.pzmin = static_cast<uint32_t*>(take(c->npad, 4));
+    b.pzmax = static_cast<uint32_t*>(take(c->npad, 4));
+    b.poff = static_cast<uint32_t*>(take(c->npad, 4));
+    b.tsum = static_cast<uint32_t*>(take(c->ntiles, 4));
+    b.tz = static_cast<float2*>(take(c->ntiles, sizeof(float2)));
+    b.vpix = static_cast<int*>(take(V, 4));
+    b.vslot = static_cast<uint32_t*>(take(V, 4));
+    b.sorted = static_cast<float4*>(take(V, sizeof(float4)));
+    b.bstat = static_cast<int4*>(take(c->ntiles, sizeof(int4)));
+    b.cellrec = static_cast<uint4*>(take(4 * (size_t)c->ntiles, sizeof(uint4)));
+    S.a.cnt = static_cast<uint32_t*>(take(V, 4));
+    S.a.sx = static_cast<long long*>(take(V, 8));
+    S.a.sy = static_cast<long long*>(take(V, 8));
+    S.a.sz = static_cast<long long*>(take(V, 8));
+    S.assoc = static_cast<int32_t*>(take(N, 4));
+    float* d = static_cast<float*>(take(N, 4));
+    if (depth_stage) *depth_stage = d;
+    return used;
+}
+
+// Address of `scratch` on the current device, looked up once per device.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;
+
+int scratch_base(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(TRACK_E_DEVICE, std::string("scratch block address: ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TRACK_OK;
 }
 
 int upload_soa(int V, Vec3Buf dst, const float* aos) {
@@ -1291,6 +1358,51 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
     return TRACK_OK;
 }
 
+// A frame whose working buffers (frame_scratch_layout) are carved from the
+// scratch block at `base` instead of the context's own memory.  Its kernels
+// are launched directly, so no graph is instantiated, and nothing is
+// allocated.  The block holds whatever the last call on this GPU left, so
+// the frame starts by clearing what must start at zero.
+int run_frame_noalloc(track_ctx* c, char* base, const float* depth, int32_t on_device) {
+    Runner& R = c->run;
+    Stream& s = c->st;
+    if (timing_on(R)) return fail(TRACK_E_INVALID, "kernel timing is on (its events are created on demand)");
+    Slot probe = s.slot;
+    const size_t need = frame_scratch_layout(&s, nullptr, probe, nullptr);
+    if (need > kScratchBytes)
+        return fail(TRACK_E_INVALID, "frame needs " + std::to_string(need) + " bytes of working memory; the "
+                    "allocation-free frame has " + std::to_string(kScratchBytes));
+    struct Restore {
+        Slot& slot;
+        const Slot own;
+        ~Restore() { slot = own; }
+    } restore{s.slot, s.slot};
+    float* stage = nullptr;
+    frame_scratch_layout(&s, base, s.slot, &stage);
+    const float* d = depth;
+    if (!on_device) {
+        HIP_TRY(hipMemcpyAsync(stage, depth, sizeof(float) * s.W * s.H, hipMemcpyHostToDevice, R.s));
+        d = stage;
+    }
+    launch_clear(stage_one(c, 0, nullptr, nullptr));
+    HIP_TRY(hipStreamSynchronize(R.s));  // before the table window is rewritten
+    const int flags = kSlotBeginFrame | kSlotEndFrame | (s.refresh_pose ? kSlotRefreshPose : 0);
+    TableEntry e{&s, flags, 0, d, nullptr};
+    Launch L = stage_table(R, 0, &e, 1);
+    HIP_TRY(hipEventRecord(R.f0, R.s));
+    issue_stage(L);
+    const SurfaceState st = frame(R, L, c->sched, true);
+    HIP_TRY(hipEventRecord(R.f1, R.s));
+    HIP_TRY(hipStreamSynchronize(R.s));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, R.f0, R.f1);
+    const DevSummary sum = R.hsum[0];
+    c->last = to_stats(sum, ms);
+    finish_frame(&s, st, sum.status);
+    if (sum.status != TRACK_OK) return fail(sum.status, lost_reason(sum.reason));
+    return TRACK_OK;
+}
+
 void free_ctx(track_ctx* c) {
     if (!c) return;
     runner_free(c->run);
@@ -1439,6 +1551,8 @@ int track_init(const track_model* model, const track_camera* camera, const track
         return fail(TRACK_E_INVALID, "allocator needs both alloc and free");
     ScaledModel scaled;
     const track_model* mm = scaled.apply(model);
+    void* sbase = nullptr;   // the scratch block's address on this device, kept for track_frame_noalloc
+    if ((rc = scratch_base(&sbase))) return rc;
     track_ctx* c = new track_ctx();
     if ((rc = runner_init(c->run, 1, hip_stream, allocator))) { free_ctx(c); return rc; }
     if ((rc = stream_create(&c->st, mm, camera, params, theta0, phi0, allocator))) { free_ctx(c); return rc; }
@@ -1479,6 +1593,14 @@ int track_frame_xyz(track_ctx* c, const float* xyz, int32_t on_device) {
         d = c->st.xyz_buf;
     }
     return run_frame(c, nullptr, d);
+}
+
+int track_frame_noalloc(track_ctx* c, const float* depth, int32_t on_device) {
+    if (!c || !depth) return fail(TRACK_E_INVALID, "ctx/depth is NULL");
+    void* base = nullptr;
+    int rc = scratch_base(&base);
+    if (rc) return rc;
+    return run_frame_noalloc(c, static_cast<char*>(base), depth, on_device);
 }
 
 int track_state(const track_ctx* cc, double* theta, float* phi, float* verts, track_frame_stats* stats) {

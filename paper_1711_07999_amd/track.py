@@ -30,7 +30,7 @@ TRACK_GRAM_FP32, TRACK_GRAM_BF16X3, TRACK_GRAM_BF16X6 = 0, 1, 2
 KERNEL_NAMES = ["skin", "normals", "bucket", "assoc", "normal_eq", "solve", "shape"]
 
 EXPORTED = [
-    "track_init", "track_frame", "track_frame_xyz", "track_state", "track_reset",
+    "track_init", "track_frame", "track_frame_noalloc", "track_frame_xyz", "track_state", "track_reset",
     "track_set_params", "track_destroy", "track_last_error", "track_dbg_set",
     "track_dbg_get", "track_dbg_run", "track_kernel_timing", "track_kernel_time", "track_kernel_bench",
     "track_server_create", "track_server_open", "track_server_submit", "track_server_step",
@@ -150,6 +150,7 @@ def lib():
             "track_init": [vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)],
             "track_frame": [vp, vp, i32],
             "track_frame_xyz": [vp, vp, i32],
+            "track_frame_noalloc": [vp, vp, i32],
             "track_state": [vp, vp, vp, vp, vp],
             "track_reset": [vp, vp, vp],
             "track_set_params": [vp, vp],
@@ -297,6 +298,11 @@ def track_frame(ctx, depth) -> int:
     return rc
 
 
+def track_frame_noalloc(ctx, depth) -> int:
+    ptr, dev, _k = _frame_ptr(depth, np.float32)
+    return lib().track_frame_noalloc(ctx, ptr, dev)
+
+
 def track_frame_xyz(ctx, xyz) -> int:
     ptr, dev, _k = _frame_ptr(xyz, np.float32)
     return lib().track_frame_xyz(ctx, ptr, dev)
@@ -380,6 +386,9 @@ class Tracker:
 
     def frame(self, depth) -> int:
         return track_frame(self.ctx, depth)
+
+    def frame_noalloc(self, depth) -> int:
+        return track_frame_noalloc(self.ctx, depth)
 
     def frame_xyz(self, xyz) -> int:
         return track_frame_xyz(self.ctx, xyz)
