@@ -50,6 +50,16 @@ def algorithmic_bytes(kernel, V, F, N_px, N_valid, K=4, temporal=False):
     }[kernel]
 
 
+def frame_bytes(V, F, N_px, N_valid, n_iters, K=4, temporal=False, depth_upload=True):
+    """Algorithmic bytes of one frame of (pose + offset) iterations: per
+    iteration the bucket index, association, normal equations, re-skin at
+    the new pose and the offset step (which skins and counts the next
+    surface), plus the frame-start skin and the depth image."""
+    b = lambda k: algorithmic_bytes(k, V, F, N_px, N_valid, K, temporal)  # noqa: E731
+    per_iter = b("bucket") + b("normals") + b("assoc") + b("normal_eq") + b("skin") + b("shape")
+    return n_iters * per_iter + b("skin") + (4 * N_px if depth_upload else 0)
+
+
 REPEATABLE = ("skin", "assoc", "normal_eq", "solve")
 
 # sources whose change invalidates a kernel's committed counter reading
@@ -91,13 +101,23 @@ def measured_traffic(kernel):
     return None
 
 
-def cpu_baseline(w, budget_s=15.0, max_frames=30):
-    """The oracle (float64 C++) on the same frames, until the budget is spent."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, threads, budget_s, max_frames):
+    """Frames/s of the float64 oracle on the first frames of the sequence
+    (at least two), until the time budget is spent."""
     import oracle
 
-    cores = len(os.sched_getaffinity(0))
-    cores = min(cores, 16)
-    used = oracle.set_threads(cores)
+    used = oracle.set_threads(threads)
     m = oracle.Model(w.body.model)
     th = w.theta0.copy()
     phi = np.zeros((m.V, 3))
@@ -108,9 +128,125 @@ def cpu_baseline(w, budget_s=15.0, max_frames=30):
         oracle.track_frame(m, w.body.camera, w.params, th, phi, prev, depth=w.frames[n % len(w.frames)])
         n += 1
     dt = time.perf_counter() - t0
+    return used, n, dt
+
+
+def cpu_baseline(w, budget_s=12.0, max_frames=30):
+    """The oracle (float64 C++, OpenMP over the pixel and vertex loops) on
+    the same frames: all of the host's cores available to this process,
+    then one core."""
+    cores = len(os.sched_getaffinity(0))
+    used, n, dt = _oracle_rate(w, cores, budget_s, max_frames)
+    used1, n1, dt1 = _oracle_rate(w, 1, budget_s, max_frames)
     return {"value": n / dt, "unit": "frames/s", "cores": used, "kind": "oracle",
             "sample": f"first {n} frames of the same 30-frame sequence, float64 oracle, "
-                      f"{used} OpenMP threads (association loop), {dt:.1f} s"}
+                      f"{used} OpenMP threads, {dt:.1f} s",
+            "nproc": os.cpu_count(), "affinity_cores": cores, "cpu_model": _cpu_model(),
+            "one_core": {"value": n1 / dt1, "unit": "frames/s", "cores": used1,
+                         "sample": f"first {n1} frames, 1 thread, {dt1:.1f} s"}}
+
+
+def _gram_params(base, gram):
+    prm = dict(base)
+    prm["gram_mode"] = 1 if gram == "bf16x3" else 0
+    if prm["gram_mode"]:
+        prm["pose_solve_fp64"] = 1
+        prm["shape_solve_fp64"] = 1
+    return prm
+
+
+def _run_frames(T, trk, frames, theta0, nsteps, lat=None):
+    """Track `nsteps` frames of the sequence (reset to the initial pose at
+    the start of each pass over it); per-frame host latency into `lat`."""
+    nseq = len(frames)
+    for s in range(nsteps):
+        if s % nseq == 0:
+            trk.reset(theta0)
+        t0 = time.perf_counter()
+        rc = trk.frame(frames[s % nseq])
+        t1 = time.perf_counter()
+        if rc != 0:
+            raise RuntimeError(f"frame {s}: {T.track_last_error()}")
+        if lat is not None:
+            lat.append(t1 - t0)
+
+
+def _timed_frames(T, trk, frames, theta0, warmup, steps):
+    import torch
+
+    _run_frames(T, trk, frames, theta0, max(warmup, 1))
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    _run_frames(T, trk, frames, theta0, steps, lat)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat_ms = np.array(lat) * 1e3
+    return elapsed, lat_ms
+
+
+def _roof(kind, dom, ms, V, F, N_px, N_valid, P, V_obs, gram_mode, temporal):
+    """Roofline of one launch of pass `dom` lasting `ms`."""
+    if dom == "solve":
+        # dense-equivalent factorisation and two triangular solves, float32
+        # vector arithmetic, against the chip's fp32 vector peak
+        flops = P ** 3 / 3 + 2 * P * P
+        achieved = flops / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS}
+    if dom == "normal_eq" and kind == "mfma":
+        flops = P * (P + 1) * V_obs
+        peak = BF16_MFMA_PEAK_TFLOPS if gram_mode else FP32_MFMA_PEAK_TFLOPS
+        achieved = flops / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
+    b = algorithmic_bytes(dom, V, F, N_px, N_valid, temporal=temporal)
+    achieved = b / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS}
+
+
+def batched_copies(T, w, frames_dev, prm, B, nsat):
+    """B streams of the same workload in one server (each its own state,
+    started from a slightly different pose and frame), every stream always
+    with frames waiting: aggregate frames/s and algorithmic HBM bytes/s of
+    the batched launches."""
+    import torch
+
+    m, cam = w.body.model, w.body.camera
+    V, F, N_px = m["rest_xyz"].shape[0], m["faces"].shape[0], cam["width"] * cam["height"]
+    sv = T.track_server_create(dict(prm, active=None), 1 << 38, B)
+    try:
+        ids = []
+        for s in range(B):
+            rng = np.random.default_rng(7000 + s)
+            th0 = w.theta0 + np.where(w.body.angular, rng.uniform(-0.005, 0.005, len(w.theta0)), 0.0)
+            ids.append(T.track_server_open(sv, m, cam, th0))
+        nseq = len(frames_dev)
+        for s in range(B):   # one frame each to build the launch graphs
+            T.track_server_submit(sv, ids[s], frames_dev[s % nseq], tag=-1)
+        while T.track_server_info(sv)["frames_pending"]:
+            T.track_server_step(sv)
+        T.track_server_poll(sv, 1 << 20)
+        for s in range(B):
+            for k in range(1, nsat + 1):
+                T.track_server_submit(sv, ids[s], frames_dev[(s + k) % nseq], tag=k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = 0
+        while n < B * nsat:
+            n += T.track_server_step(sv)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cs = T.track_server_poll(sv, 1 << 20)
+        nvalid = float(np.mean([c["stats"]["n_valid_px"] for c in cs]))
+        failed = sum(c["status"] != 0 for c in cs)
+    finally:
+        T.track_server_destroy(sv)
+    fps = n / dt
+    fb = frame_bytes(V, F, N_px, nvalid, int(prm["n_iters"]), temporal=prm["lambda_t"] > 0)
+    gbs = fps * fb / 1e9
+    return {"streams": B, "frames": n, "seconds": dt, "fps": fps, "failed_frames": failed,
+            "bytes_per_frame": fb, "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
 
 
 def single_stream(args):
@@ -125,84 +261,74 @@ def single_stream(args):
     m, cam = w.body.model, w.body.camera
     V, F, P = m["rest_xyz"].shape[0], m["faces"].shape[0], len(w.theta0)
     N_px = cam["width"] * cam["height"]
-    prm = dict(w.params)
-    prm["gram_mode"] = 1 if args.gram == "bf16x3" else 0
-    if prm["gram_mode"]:
-        prm["pose_solve_fp64"] = 1
-        prm["shape_solve_fp64"] = 1
+    prm = _gram_params(w.params, args.gram)
+    temporal = prm["lambda_t"] > 0
     frames = [torch.from_numpy(f).to(dev) for f in w.frames]
     stream = torch.cuda.current_stream(dev)
     trk = T.Tracker(m, cam, prm, w.theta0, stream=stream.cuda_stream)
     nseq = len(frames)
 
-    def run(nsteps, lat=None):
-        for s in range(nsteps):
-            if s % nseq == 0:
-                trk.reset(w.theta0)
-            t0 = time.perf_counter()
-            rc = trk.frame(frames[s % nseq])
-            t1 = time.perf_counter()
-            if rc != 0:
-                raise RuntimeError(f"frame {s}: {T.track_last_error()}")
-            if lat is not None:
-                lat.append(t1 - t0)
-
-    # warmup: first with every kernel timed (to find the dominant kernel),
-    # then plain, so the frame graphs are captured before timing
+    # warmup: first with every pass timed (per-pass durations inside frames,
+    # and the dominant pass), then plain, so the frame graphs are captured
+    # before timing
     for k in range(len(T.KERNEL_NAMES)):
         T.track_kernel_timing(trk.ctx, k, True)
     nw = max(args.warmup, 1)
-    run(nw)
+    _run_frames(T, trk, frames, w.theta0, nw)
     per_kernel = {}
     for k, name in enumerate(T.KERNEL_NAMES):
         n, ms = T.track_kernel_time(trk.ctx, k)
         per_kernel[name] = (n, ms)
         T.track_kernel_timing(trk.ctx, k, False)
-    # the dominant pass among those a repeated launch times faithfully (one
-    # kernel, same work each launch); bucket and shape consume their inputs
+    # the dominant pass among those a single kernel carries (its launch
+    # duration is that kernel's; bucket and shape are two-kernel passes or
+    # consume their inputs)
     dom = max(REPEATABLE, key=lambda k: per_kernel[k][1])
     dom_id = T.KERNEL_NAMES.index(dom)
-    run(nw)
 
     # timed region: whole frames replayed from their graphs
-    torch.cuda.synchronize()
-    lat = []
-    t0 = time.perf_counter()
-    run(args.steps, lat)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    elapsed, lat_ms = _timed_frames(T, trk, frames, w.theta0, nw, args.steps)
     stats = trk.state(want_verts=False)[3]
     V_obs, N_valid = stats["n_obs_verts"], stats["n_valid_px"]
-    # roofline: the dominant kernel launched back to back on the state the
-    # timed region left (its last frame), one pair of HIP events around them
-    n_launch = args.kernel_reps
-    last = frames[(args.steps - 1) % nseq]
-    avg_ms = T.track_kernel_bench(trk.ctx, dom_id, last, n_launch)
+    fps = args.steps / elapsed
+
+    # the dominant kernel inside frames: the same frames with that pass's
+    # launches bracketed by HIP events stamped by its own dispatch packet
+    T.track_kernel_timing(trk.ctx, dom_id, True)
+    _run_frames(T, trk, frames, w.theta0, args.inframe_frames)
+    n_in, ms_in = T.track_kernel_time(trk.ctx, dom_id)
+    T.track_kernel_timing(trk.ctx, dom_id, False)
+    avg_in = ms_in / max(n_in, 1)
+    # and launched back to back on the state the last frame left (same
+    # inputs and launch configuration), one pair of HIP events around them
+    last = frames[(args.inframe_frames - 1) % nseq]
+    avg_rep = T.track_kernel_bench(trk.ctx, dom_id, last, args.kernel_reps)
     trk.close()
 
-    elapsed = t1 - t0
-    fps = args.steps / elapsed
-    lat_ms = np.array(lat) * 1e3
-    if dom == "solve":
-        # dense-equivalent factorisation and two triangular solves, float32
-        # vector arithmetic, against the chip's fp32 vector peak
-        n = P
-        flops = n ** 3 / 3 + 2 * n * n
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(dom)}
-    elif dom == "normal_eq":
-        flops = P * (P + 1) * V_obs
-        peak = BF16_MFMA_PEAK_TFLOPS if prm["gram_mode"] else FP32_MFMA_PEAK_TFLOPS
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(dom)}
-    else:
-        b = algorithmic_bytes(dom, V, F, N_px, N_valid, temporal=prm["lambda_t"] > 0)
-        achieved = b / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)}
-    roof.update({"kernel": dom, "avg_launch_ms": avg_ms, "launches": n_launch})
+    kind = "mfma" if dom == "normal_eq" else "hbm"
+    roof = _roof(kind, dom, avg_in, V, F, N_px, N_valid, P, V_obs, prm["gram_mode"], temporal)
+    rep = _roof(kind, dom, avg_rep, V, F, N_px, N_valid, P, V_obs, prm["gram_mode"], temporal)
+    roof.update({"traffic": measured_traffic(dom), "kernel": dom, "avg_launch_ms": avg_in, "launches": n_in,
+                 "timing": "in-frame launches, HIP events stamped by the kernel's dispatch packet",
+                 "back_to_back": {"avg_launch_ms": avg_rep, "launches": args.kernel_reps,
+                                  "achieved": rep["achieved"], "frac": rep["frac"]}})
+
+    # every pass inside frames (from the timed warm-up): microseconds per
+    # launch and its algorithmic bytes (flops for the Gram) against peak
+    passes = {}
+    for name, (n, ms) in per_kernel.items():
+        if n == 0:
+            continue
+        us = ms / n * 1e3
+        e = {"launches_per_frame": n / nw, "us_per_launch": us}
+        if name != "solve":
+            b = algorithmic_bytes(name, V, F, N_px, N_valid, temporal=temporal)
+            e.update({"bytes_per_launch": b, "GBs": b / (us * 1e-6) / 1e9,
+                      "frac_of_hbm_peak": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS})
+        if name == "normal_eq":
+            r = _roof("mfma", name, us * 1e-3, V, F, N_px, N_valid, P, V_obs, prm["gram_mode"], temporal)
+            e.update({"gram_TFLOPs": r["achieved"], "frac_of_mfma_peak": r["frac"]})
+        passes[name] = e
 
     out = {
         "metric": "tracked frames/s + p99 frame latency (50k-vert body, 640x480 depth)",
@@ -224,8 +350,23 @@ def single_stream(args):
                    "gn_iters_per_frame": int(prm["n_iters"]), "sequence_frames": nseq,
                    "gram": args.gram},
         "roofline": roof,
-        "kernel_ms_per_frame": {k: (v[1] / nw) for k, v in per_kernel.items()},
+        "passes_in_frame": passes,
+        "frame_bytes": frame_bytes(V, F, N_px, N_valid, int(prm["n_iters"]), temporal=temporal),
     }
+    out["frame_GBs"] = out["frame_bytes"] * fps / 1e9
+    if not args.no_extra:
+        # the precision form on the same workload
+        other = "bf16x3" if args.gram == "fp32" else "fp32"
+        prm2 = _gram_params(w.params, other)
+        trk2 = T.Tracker(m, cam, prm2, w.theta0, stream=stream.cuda_stream)
+        el2, lat2 = _timed_frames(T, trk2, frames, w.theta0, nw, args.steps)
+        trk2.close()
+        out[f"{other}_form"] = {"value": args.steps / el2, "unit": "frames/s",
+                                "p50_ms": float(np.percentile(lat2, 50)), "p99_ms": float(np.percentile(lat2, 99)),
+                                "speedup_vs_main": (args.steps / el2) / fps,
+                                "solves": "float64" if other == "bf16x3" else "float32"}
+        # B copies of the workload batched through one server
+        out["batched_copies"] = [batched_copies(T, w, frames, prm, B, args.batch_frames) for B in (16, 32)]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
@@ -410,6 +551,69 @@ def serve(args):
     print(json.dumps(out), flush=True)
 
 
+def modes(args):
+    """Tracking modes and schedules of Section 5.1 on the 30-frame human
+    workload against its synthetic ground truth: joint-position accuracy
+    against the threshold (AUC over 0-10 cm), reconstruction error of the
+    visible surface (Section 5.3), GPU time per frame."""
+    import torch
+
+    import synth
+    from paper_1711_07999_amd import metrics as M
+    from paper_1711_07999_amd import track as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = synth.workload_human(n_frames=args.seq_frames)
+    m, cam = w.body.model, w.body.camera
+    frames = [torch.from_numpy(f).to(dev) for f in w.frames]
+    links = np.unique(m["link_joint"])
+    truth = [synth.joint_matrices(m, w.theta_true[f])[links, :3, 3] for f in range(len(frames))]
+    thr = np.linspace(0.0, 0.10, 101)
+    n_it = int(w.params["n_iters"])
+    out = {"metric": "tracking modes (joint accuracy AUC 0-10 cm, reconstruction error, GPU ms/frame)",
+           "config": {"workload": w.name, "frames": len(frames), "joints_scored": int(links.size),
+                      "ground_truth": "synthetic: matrix linear-blend posed surface with 5 mm folds"},
+           "modes": {}}
+    for mode in M.MODES:
+        model = M.rigid_segments(m) if mode == "rigid-segments" else m
+        dp, ds = M.mode_schedule(mode, 0, n_it)
+        prm = dict(w.params, n_iters=len(dp), do_pose=dp, do_shape=ds)
+        trk = T.Tracker(model, cam, prm, w.theta0)
+        errs, rec, ms = [], [], []
+        try:
+            for f, depth in enumerate(frames):
+                dp, ds = M.mode_schedule(mode, f, n_it)
+                if not (np.array_equal(dp, prm["do_pose"]) and np.array_equal(ds, prm["do_shape"])):
+                    prm = dict(prm, n_iters=len(dp), do_pose=dp, do_shape=ds)
+                    trk.set_params(prm)
+                rc = trk.frame(depth)
+                if rc != 0:
+                    raise RuntimeError(f"{mode} frame {f}: {T.track_last_error()}")
+                _, _, v, st = trk.state()
+                ms.append(st["ms_total"])
+                errs.append(M.joint_errors(trk.joint_positions()[links], truth[f]))
+                rec.append(M.reconstruction_errors(v, M.vertex_normals(v, m["faces"]), w.frames[f], cam))
+        finally:
+            trk.close()
+        e = np.stack(errs)
+        r = np.concatenate(rec)
+        curve = M.accuracy_curve(e, thr)
+        out["modes"][mode] = {
+            "iterations": {"pose": int(np.sum(M.mode_schedule(mode, 1, n_it)[0])),
+                           "offsets_first_frame": int(np.sum(M.mode_schedule(mode, 0, n_it)[1])),
+                           "offsets_later_frames": int(np.sum(M.mode_schedule(mode, 1, n_it)[1]))},
+            "joint_error_mean_m": float(e.mean()), "joint_error_max_m": float(e.max()),
+            "within_2cm": float(M.accuracy_curve(e, [0.02])[0]), "within_5cm": float(M.accuracy_curve(e, [0.05])[0]),
+            "auc_0_10cm": M.curve_auc(thr, curve),
+            "reconstruction_mm": {"mean": float(r.mean() * 1e3), "median": float(np.median(r) * 1e3),
+                                  "p90": float(np.percentile(r, 90) * 1e3), "vertices": int(r.size)},
+            "gpu_ms_per_frame": float(np.mean(ms[1:])),
+        }
+        print(f"[modes] {mode}: {json.dumps(out['modes'][mode])}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration(args):
     """A plain device copy of known size, for scaling hardware byte counters
     (FETCH_SIZE / WRITE_SIZE) to bytes: 64 MiB read and 64 MiB written per
@@ -434,8 +638,16 @@ def main():
     ap.add_argument("--gram", choices=["fp32", "bf16x3"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=200,
-                    help="back-to-back launches of the dominant kernel for its roofline timing")
+                    help="back-to-back launches of the dominant kernel (an extra figure of its roofline)")
+    ap.add_argument("--inframe-frames", type=int, default=30,
+                    help="frames tracked with the dominant kernel's launches timed (its roofline)")
+    ap.add_argument("--batch-frames", type=int, default=20,
+                    help="frames per stream of the batched copies at saturation")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other operand form and the batched copies")
     ap.add_argument("--serve", action="store_true", help="serving mix instead of the single-stream step")
+    ap.add_argument("--modes", action="store_true",
+                    help="tracking modes and schedules against the synthetic ground truth")
     ap.add_argument("--streams", type=int, default=64)
     ap.add_argument("--frames", type=int, default=300, help="frames per stream at the configured load")
     ap.add_argument("--sat-frames", type=int, default=30, help="frames per stream at saturation")
@@ -454,6 +666,8 @@ def main():
         copy_calibration(args)
     elif args.serve:
         serve(args)
+    elif args.modes:
+        modes(args)
     else:
         single_stream(args)
 

@@ -217,6 +217,12 @@ int track_frame_noalloc(track_ctx *ctx, const float *depth, int32_t depth_on_dev
 int track_state(const track_ctx *ctx, double *theta, float *phi, float *verts,
                 track_frame_stats *stats);
 
+/* Origins of the joint frames at the current Theta (Section 3.1): H_{0,j}
+   applied to the origin for every elementary joint j, [P*3] float64, camera
+   frame, computed on the host.  A link sits at its joint's origin; this is
+   what joint-position accuracy (Section 5.1) is measured on. */
+int track_joint_positions(const track_ctx *ctx, double *xyz);
+
 /* Replace the state (checkpoint restore): Theta [P], Phi [V*3] (NULL = 0);
    the previous-frame offsets become Phi as well. */
 int track_reset(track_ctx *ctx, const double *theta, const float *phi);

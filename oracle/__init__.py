@@ -72,7 +72,7 @@ def lib():
         _lib = ctypes.CDLL(LIB_PATH)
         for name in ("orc_fk", "orc_skin", "orc_normals", "orc_skin_dual", "orc_transform",
                      "orc_associate", "orc_average", "orc_pose_system",
-                     "orc_prior_weights", "orc_lm_solve", "orc_shape_step",
+                     "orc_prior_weights", "orc_lm_solve", "orc_shape_step", "orc_shape_step_literal",
                      "orc_track_frame", "orc_set_threads"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
@@ -255,6 +255,19 @@ def shape_step(model, theta, phi, phi_prev, n, delta, cnt, lambda_phi, lambda_nb
     lib().orc_shape_step(ctypes.byref(m.c), *[_p(a) for a in args], ctypes.c_double(lambda_phi),
                          ctypes.c_double(lambda_nbr), ctypes.c_double(lambda_t),
                          ctypes.c_double(lambda_w), _p(out))
+    return out
+
+
+def shape_step_literal(model, theta, phi, n, delta, cnt, lambda_phi, lambda_nbr, lambda_w):
+    """Eq. (9) as printed (one scalar residual per vertex with the
+    regularisers inside it, rank-one normal matrix plus its own diagonal):
+    kept to demonstrate why the least-squares reading is used."""
+    m = _model(model)
+    out = np.zeros((m.V, 3))
+    args = [_c(theta, np.float64), _c(phi, np.float64), _c(phi, np.float64),
+            _c(n, np.float64), _c(delta, np.float64), _c(cnt, np.int32)]
+    lib().orc_shape_step_literal(ctypes.byref(m.c), *[_p(a) for a in args], ctypes.c_double(lambda_phi),
+                                 ctypes.c_double(lambda_nbr), ctypes.c_double(lambda_w), _p(out))
     return out
 
 

@@ -188,6 +188,15 @@ int orc_shape_step(const orc_model_in* in, const double* theta, const double* ph
     return 0;
 }
 
+int orc_shape_step_literal(const orc_model_in* in, const double* theta, const double* phi, const double* phi_prev,
+                           const double* n, const double* delta, const int32_t* cnt, double lphi, double lnbr,
+                           double lw, double* phi_out) {
+    orc::Model m = to_model(in);
+    orc::ShapeArgs s{theta, phi, phi_prev, n, delta, cnt, lphi, lnbr, 0.0, lw};
+    orc::shape_step_literal(m, s, phi_out);
+    return 0;
+}
+
 // One frame.  stats_i = {status, n_valid_px, n_assoc_px, n_obs_verts},
 // stats_d = {energy_first, energy_last, step_norm_last}.
 int orc_track_frame(const orc_model_in* in, const orc_camera_in* c, const orc_params_in* p, double* theta,

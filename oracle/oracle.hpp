@@ -622,6 +622,56 @@ inline void shape_step(const Model& m, const ShapeArgs& s, double* phi_out) {
     }
 }
 
+// Eq. (9) as printed, kept to show why it is not used: the regularisers sit
+// inside one scalar residual per vertex,
+//   r^_i = r_i + lam_phi |phi_i|^2 + lam_N sum_{n in N(i)} |phi_i - phi_n|^2,
+// its gradient j_i = dr_i/dphi_i + 2 lam_phi phi_i + 2 lam_N sum (phi_i - phi_n)
+// is one row, and (j j^T + lam_w diag(j j^T)) x = j r^_i is a rank-one matrix
+// plus a diagonal that scales with the squares of j's own entries: its
+// solution x_k = r^_i / ((m + lam_w) j_k) (m = non-zero entries of j) grows
+// without bound as any entry of j goes to zero.  A singular system (some
+// j_k exactly zero) takes no step, as in the reading's solver.
+inline void shape_step_literal(const Model& m, const ShapeArgs& s, double* phi_out) {
+    auto H = forward_kinematics<double>(m, s.theta);
+    auto H0 = bind_pose<double>(m);
+    auto D = link_deltas(m, H, H0);
+    for (int i = 0; i < m.V; ++i) {
+        const double* ni = &s.n[3 * i];
+        const double* ph = &s.phi[3 * i];
+        double nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
+        double j[3] = {0, 0, 0}, r = 0.0;
+        if (s.cnt[i] >= 1 && nl > 0.0) {
+            DQ<double> Hs = blend(m, D, i);
+            double R[9];
+            quat_rotation(Hs.r, R);
+            for (int c = 0; c < 3; ++c) j[c] = -(R[c] * ni[0] + R[3 + c] * ni[1] + R[6 + c] * ni[2]);
+            r = ni[0] * s.delta[3 * i] + ni[1] * s.delta[3 * i + 1] + ni[2] * s.delta[3 * i + 2];
+        }
+        double rh = r + s.lambda_phi * (ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2]);
+        for (int c = 0; c < 3; ++c) j[c] += 2.0 * s.lambda_phi * ph[c];
+        for (int q = 0; q < 4; ++q) {
+            int k = m.nbr[4 * i + q];
+            if (k < 0) continue;
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                double d = ph[c] - s.phi[3 * k + c];
+                d2 += d * d;
+                j[c] += 2.0 * s.lambda_nbr * d;
+            }
+            rh += s.lambda_nbr * d2;
+        }
+        double M[9], g[3];
+        for (int a = 0; a < 3; ++a) {
+            for (int b = 0; b < 3; ++b) M[3 * a + b] = j[a] * j[b];
+            M[4 * a] *= (1.0 + s.lambda_w);
+            g[a] = j[a] * rh;
+        }
+        double x[3] = {0, 0, 0};
+        if (!solve3(M, g, x)) x[0] = x[1] = x[2] = 0.0;
+        for (int c = 0; c < 3; ++c) phi_out[3 * i + c] = ph[c] - x[c];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Section 4: one frame = n_iters iterations of association, pose step and
 // shape step, in that order, with the association kept through the iteration

@@ -1634,6 +1634,40 @@ int track_reset(track_ctx* c, const double* theta, const float* phi) {
     return refresh_surface(c);
 }
 
+int track_joint_positions(const track_ctx* cc, double* xyz) {
+    track_ctx* c = const_cast<track_ctx*>(cc);
+    if (!c || !xyz) return fail(TRACK_E_INVALID, "ctx/xyz is NULL");
+    const JointTable& t = c->st.hjt;
+    std::vector<double> th(t.P);
+    HIP_TRY(hipStreamSynchronize(c->run.s));
+    HIP_TRY(hipMemcpy(th.data(), c->st.slot.theta, sizeof(double) * t.P, hipMemcpyDeviceToHost));
+    // H_{0,j} = H_{0,P(j)} O_j H_j(theta_j), Eq. (1) / (2), then the
+    // translation 2 d r* of the dual quaternion r + eps d
+    std::vector<double> H(8 * (size_t)t.P);
+    for (int j = 0; j < t.P; ++j) {
+        double hj[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+        const double h = 0.5 * th[j];
+        if (t.type[j] == TRACK_HINGE) {
+            const double sn = std::sin(h);
+            hj[0] = std::cos(h);
+            for (int d = 0; d < 3; ++d) hj[1 + d] = sn * t.axis[j][d];
+        } else {
+            for (int d = 0; d < 3; ++d) hj[5 + d] = h * t.axis[j][d];
+        }
+        double base[8];
+        if (t.parent[j] < 0) std::memcpy(base, t.off[j], sizeof(base));
+        else hdq_mul(&H[8 * (size_t)t.parent[j]], t.off[j], base);
+        hdq_mul(base, hj, &H[8 * (size_t)j]);
+        const double* q = &H[8 * (size_t)j];
+        const double rc[4] = {q[0], -q[1], -q[2], -q[3]};
+        double tr[4];
+        hq_mul(q + 4, rc, tr);
+        const double n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+        for (int d = 0; d < 3; ++d) xyz[3 * j + d] = 2.0 * tr[1 + d] / n2;
+    }
+    return TRACK_OK;
+}
+
 void track_destroy(track_ctx* c) { free_ctx(c); }
 
 int track_kernel_timing(track_ctx* c, int32_t k, int32_t enable) {

@@ -30,7 +30,8 @@ TRACK_GRAM_FP32, TRACK_GRAM_BF16X3, TRACK_GRAM_BF16X6 = 0, 1, 2
 KERNEL_NAMES = ["skin", "normals", "bucket", "assoc", "normal_eq", "solve", "shape"]
 
 EXPORTED = [
-    "track_init", "track_frame", "track_frame_noalloc", "track_frame_xyz", "track_state", "track_reset",
+    "track_init", "track_frame", "track_frame_noalloc", "track_frame_xyz", "track_state",
+    "track_joint_positions", "track_reset",
     "track_set_params", "track_destroy", "track_last_error", "track_dbg_set",
     "track_dbg_get", "track_dbg_run", "track_kernel_timing", "track_kernel_time", "track_kernel_bench",
     "track_server_create", "track_server_open", "track_server_submit", "track_server_step",
@@ -152,6 +153,7 @@ def lib():
             "track_frame_xyz": [vp, vp, i32],
             "track_frame_noalloc": [vp, vp, i32],
             "track_state": [vp, vp, vp, vp, vp],
+            "track_joint_positions": [vp, vp],
             "track_reset": [vp, vp, vp],
             "track_set_params": [vp, vp],
             "track_dbg_set": [vp, i32, vp, sz],
@@ -317,6 +319,13 @@ def track_state(ctx, P: int, V: int, want_verts: bool = True):
     return th, ph, vv, st.as_dict()
 
 
+def track_joint_positions(ctx, P: int):
+    """[P, 3] float64 origins of the joint frames at the current pose."""
+    out = np.zeros((P, 3))
+    _check(lib().track_joint_positions(ctx, _p(out)))
+    return out
+
+
 def track_reset(ctx, theta, phi=None):
     th = _c(theta, np.float64)
     ph = None if phi is None else _c(phi, np.float32)
@@ -395,6 +404,9 @@ class Tracker:
 
     def state(self, want_verts=True):
         return track_state(self.ctx, self.P, self.V, want_verts)
+
+    def joint_positions(self):
+        return track_joint_positions(self.ctx, self.P)
 
     def reset(self, theta, phi=None):
         track_reset(self.ctx, theta, phi)

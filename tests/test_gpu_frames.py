@@ -169,6 +169,37 @@ def test_human_frames_certified_per_iteration(T, human, mode):
     assert not fails, fails
 
 
+@pytest.mark.parametrize("mode", ["smooth-bind", "paper-schedule"])
+def test_human_schedules_certified_per_iteration(T, human, mode):
+    """The pose-only schedule (smooth bind) and the paper's 12 pose then 2
+    offset iterations per frame (Sections 4.2, 4.3), each iteration
+    re-associating, held to the same per-iteration bar."""
+    from paper_1711_07999_amd import metrics as M
+
+    _say(f"[frames] human-50k, {mode}")
+    dp, ds = M.mode_schedule(mode, 0, int(human.params["n_iters"]))
+    prm = dict(human.params, n_iters=len(dp), do_pose=dp, do_shape=ds)
+    fails = _run(T, human, prm, 1)
+    assert not fails, fails
+
+
+def test_joint_positions_match_a_matrix_chain(T, human):
+    """track_joint_positions against the homogeneous-matrix forward
+    kinematics of the input generator (Eq. 1, 2 and the chain of Section
+    3.1 written independently)."""
+    m = human.body.model
+    trk = T.Tracker(m, human.body.camera, human.params, human.theta0)
+    try:
+        for f in range(len(human.frames)):
+            th = human.theta_true[f]
+            trk.reset(th)
+            got = trk.joint_positions()
+            want = synth.joint_matrices(m, th)[:, :3, 3]
+            assert np.abs(got - want).max() < 1e-6
+    finally:
+        trk.close()
+
+
 def test_highres_frames_certified_per_iteration(T, highres):
     _say("[frames] highres-200k (temporal weight 0.5, float64 pose solve)")
     fails = _run(T, highres, dict(highres.params), 2)

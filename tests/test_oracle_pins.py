@@ -880,3 +880,67 @@ def test_planted_cloud_is_what_it_claims():
     uu = cam["fx"] * P[k, 0] / P[k, 2] + cam["cx"]
     vv = cam["fy"] * P[k, 1] / P[k, 2] + cam["cy"]
     assert np.abs(uu - k % cam["width"]).max() < 1e-3 and np.abs(vv - k // cam["width"]).max() < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Eq. (9) as printed: the negative result behind the least-squares reading
+# ---------------------------------------------------------------------------
+def _one_vertex():
+    return dict(joint_parent=np.array([-1], np.int32), joint_type=np.array([0], np.int32),
+                joint_axis=np.array([[0, 0, 1]], np.float32),
+                joint_offset=np.array([[1, 0, 0, 0, 0, 0, 1.0]], np.float32),
+                link_joint=np.array([0], np.int32), rest_xyz=np.array([[0.1, 0.2, 0.0]], np.float32),
+                faces=np.zeros((1, 3), np.int32), skin_link=np.array([[0]], np.int32),
+                skin_w=np.array([[1.0]], np.float32), neighbors=np.full((1, 4), -1, np.int32))
+
+
+def test_literal_eq9_step_is_the_rank_one_closed_form_and_explodes():
+    """One vertex, rest pose (R = I, so dr/dphi = -n), phi = 0: the printed
+    system's step is x_k = r / ((3 + lam_w) j_k) with j = -n (the magnitude
+    term adds nothing to j at phi = 0); a normal almost along x with small
+    y, z parts turns a 1 mm residual into a step of tens of millimetres
+    along z, while the reading's step, whose magnitude term adds lam_phi I
+    to its 3x3 matrix, is at most the residual."""
+    j = np.array([0.999, 0.04, 0.01])
+    j /= np.linalg.norm(j)
+    n = -j[None, :]
+    r = 1e-3
+    delta = r * n
+    cnt = np.ones(1, np.int32)
+    phi = np.zeros((1, 3))
+    lw = 0.1
+    out = oracle.shape_step_literal(_one_vertex(), np.zeros(1), phi, n, delta, cnt, 0.01, 0.0, lw)
+    x = phi - out
+    np.testing.assert_allclose(x[0], r / ((3 + lw) * j), rtol=1e-12)
+    assert abs(x[0, 2]) > 0.03
+    ours = oracle.shape_step(_one_vertex(), np.zeros(1), phi, phi, n, delta, cnt, 0.01, 0.0, 0.0, lw)
+    assert np.linalg.norm(phi - ours) <= r
+
+
+def test_literal_eq9_diverges_on_the_tiny_arm_where_the_reading_does_not(tiny):
+    """Offset steps at the true pose of the tiny arm, re-associating each
+    time: the printed form's offsets blow up in the first step; the
+    reading's stay below a millimetre while the residual falls."""
+    m, cam, prm = tiny.body.model, tiny.body.camera, tiny.params
+    th = tiny.theta_true[0]
+    for literal in (False, True):
+        phi = np.zeros((2000, 3))
+        rms = []
+        for it in range(3):
+            v, n = oracle.skin(m, th, phi)
+            if not np.isfinite(v).all() or np.abs(v).max() > 1e3:
+                break
+            a = oracle.associate(cam, prm["tau"], v.astype(np.float32), depth=tiny.frames[0])
+            cnt, delta = oracle.average(cam, a, v, depth=tiny.frames[0])
+            rms.append(np.sqrt(np.mean(np.einsum("ij,ij->i", n, delta)[cnt > 0] ** 2)))
+            if literal:
+                phi = oracle.shape_step_literal(m, th, phi, n, delta, cnt, prm["lambda_phi"], prm["lambda_nbr"],
+                                                prm["lambda_w"])
+            else:
+                phi = oracle.shape_step(m, th, phi, phi, n, delta, cnt, prm["lambda_phi"], prm["lambda_nbr"], 0.0,
+                                        prm["lambda_w"])
+        big = np.nanmax(np.abs(phi)) if np.isfinite(phi).any() else np.inf
+        if literal:
+            assert not np.isfinite(big) or big > 1.0      # metres
+        else:
+            assert big < 2e-3 and rms[-1] < rms[0]
