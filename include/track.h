@@ -236,6 +236,52 @@ void track_destroy(track_ctx *ctx);
 const char *track_last_error(void);
 
 /* ------------------------------------------------------------------------
+ * Template refinement (Section 3.3): a low-resolution polygon mesh with skin
+ * weights, refined by rounds of Catmull-Clark subdivision into the
+ * high-resolution triangle mesh the tracker takes (host computation, once
+ * per template).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_verts;             /* V >= 3                                           */
+    const float *xyz;            /* [V*3]                                            */
+    int32_t n_faces;             /* F >= 1 polygons, every edge shared by <= 2 faces  */
+    const int32_t *face_start;   /* [F+1] face f is face_verts[face_start[f] ..
+                                    face_start[f+1]), >= 3 corners, counter-clockwise
+                                    seen from outside; face_start[0] = 0            */
+    const int32_t *face_verts;
+    int32_t max_infl;            /* K >= 1                                           */
+    const int32_t *skin_link;    /* [V*K] link or -1                                 */
+    const float *skin_w;         /* [V*K]                                            */
+} track_polymesh;
+
+/*
+ * `levels` (1..4) rounds of Catmull-Clark subdivision: face points are the
+ * means of their faces' corners; an interior edge point is the mean of the
+ * edge's ends and its two face points, a boundary one the edge's midpoint;
+ * an interior vertex of valence n moves to (Q + 2R + (n - 3) S) / n (Q the
+ * mean of its face points, R of its edges' midpoints, S its position), a
+ * boundary vertex with two boundary edges to (a + b) / 8 + 3 S / 4.  The
+ * skin weights are carried through with the same masks (Section 3.3), then
+ * each vertex keeps its max_infl_out (1..TRACK_MAX_INFL) largest weights (ties
+ * to the lower link) scaled to sum to one.  The final quadrilaterals are
+ * split along their shorter diagonal (ties: the one through the first
+ * corner) into two counter-clockwise triangles.
+ * Numbering per round: vertex points in input order, edge points in order of
+ * first appearance (faces in order, each face's edges from its first corner
+ * on), face points in face order; face f with corners v_0..v_{k-1} becomes
+ * the quadrilaterals (v_i, e(v_i, v_i+1), f, e(v_i-1, v_i)), i = 0..k-1, and
+ * quadrilateral q the triangles 2q, 2q + 1.
+ * *n_verts_out and *n_tris_out receive the sizes; the array outputs (caller
+ * allocated: [V'*3], [T'*3], [V'*max_infl_out] twice) may be NULL, so a first
+ * call with NULL arrays sizes them.  TRACK_E_INVALID for an edge with more
+ * than two faces or traversed twice in one direction, a face with fewer than
+ * three corners, or an index out of range.
+ */
+int track_subdivide(const track_polymesh *mesh, int32_t levels, int32_t max_infl_out, int32_t *n_verts_out,
+                    int32_t *n_tris_out, float *xyz_out, int32_t *tris_out, int32_t *skin_link_out,
+                    float *skin_w_out);
+
+/* ------------------------------------------------------------------------
  * Serving: one server tracks many independent streams (each its own model,
  * camera and state, as a context would) under one device-memory budget.
  * Every step runs one Gauss-Newton iteration (Section 4) for every resident

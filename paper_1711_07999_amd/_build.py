@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtrack.so")
-SOURCES = ["kinematics.hip", "association.hip", "normal_eq.hip", "solve.hip", "track.hip"]
+SOURCES = ["kinematics.hip", "association.hip", "normal_eq.hip", "solve.hip", "track.hip", "subdivide.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

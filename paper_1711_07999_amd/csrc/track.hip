@@ -1528,6 +1528,9 @@ int server_admit(track_server* sv) {
 
 }  // namespace
 
+// the error record of the calling thread, for the library's other sources
+int track_fail_message(int code, const char* msg) { return fail(code, msg); }
+
 // ==========================================================================
 // C ABI
 // ==========================================================================

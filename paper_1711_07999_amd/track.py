@@ -31,7 +31,7 @@ KERNEL_NAMES = ["skin", "normals", "bucket", "assoc", "normal_eq", "solve", "sha
 
 EXPORTED = [
     "track_init", "track_frame", "track_frame_noalloc", "track_frame_xyz", "track_state",
-    "track_joint_positions", "track_reset",
+    "track_joint_positions", "track_subdivide", "track_reset",
     "track_set_params", "track_destroy", "track_last_error", "track_dbg_set",
     "track_dbg_get", "track_dbg_run", "track_kernel_timing", "track_kernel_time", "track_kernel_bench",
     "track_server_create", "track_server_open", "track_server_submit", "track_server_step",
@@ -154,6 +154,7 @@ def lib():
             "track_frame_noalloc": [vp, vp, i32],
             "track_state": [vp, vp, vp, vp, vp],
             "track_joint_positions": [vp, vp],
+            "track_subdivide": [vp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp, vp, vp],
             "track_reset": [vp, vp, vp],
             "track_set_params": [vp, vp],
             "track_dbg_set": [vp, i32, vp, sz],
@@ -324,6 +325,34 @@ def track_joint_positions(ctx, P: int):
     out = np.zeros((P, 3))
     _check(lib().track_joint_positions(ctx, _p(out)))
     return out
+
+
+class track_polymesh(ctypes.Structure):
+    _fields_ = [("n_verts", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("n_faces", ctypes.c_int32),
+                ("face_start", ctypes.c_void_p), ("face_verts", ctypes.c_void_p), ("max_infl", ctypes.c_int32),
+                ("skin_link", ctypes.c_void_p), ("skin_w", ctypes.c_void_p)]
+
+
+def track_subdivide(xyz, face_start, face_verts, skin_link, skin_w, levels: int = 2, max_infl_out: int = 4):
+    """Catmull-Clark refinement of a polygon mesh with skin weights:
+    returns (xyz [V',3] float32, tris [T',3] int32, skin_link [V',K] int32,
+    skin_w [V',K] float32)."""
+    x = _c(xyz, np.float32)
+    fs = _c(face_start, np.int32)
+    fv = _c(face_verts, np.int32)
+    sl = _c(skin_link, np.int32)
+    sw = _c(skin_w, np.float32)
+    pm = track_polymesh(x.shape[0], _p(x), fs.shape[0] - 1, _p(fs), _p(fv), sl.shape[1], _p(sl), _p(sw))
+    nv, nt = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().track_subdivide(ctypes.byref(pm), levels, max_infl_out, ctypes.byref(nv), ctypes.byref(nt),
+                                 None, None, None, None))
+    ox = np.zeros((nv.value, 3), np.float32)
+    ot = np.zeros((nt.value, 3), np.int32)
+    ol = np.zeros((nv.value, max_infl_out), np.int32)
+    ow = np.zeros((nv.value, max_infl_out), np.float32)
+    _check(lib().track_subdivide(ctypes.byref(pm), levels, max_infl_out, ctypes.byref(nv), ctypes.byref(nt),
+                                 _p(ox), _p(ot), _p(ol), _p(ow)))
+    return ox, ot, ol, ow
 
 
 def track_reset(ctx, theta, phi=None):

@@ -71,50 +71,6 @@ def highres():
     return synth.workload_highres(n_frames=2)
 
 
-def _truncated(prm, t):
-    return dict(prm, n_iters=t, do_pose=np.asarray(prm["do_pose"])[:t].copy(),
-                do_shape=np.asarray(prm["do_shape"])[:t].copy())
-
-
-def _walk_frame(T, trk, w, prm, th0, phi0, depth, log):
-    """Per-iteration certification of one frame from (th0, phi0); returns the
-    worst per-iteration differences and the list of failures."""
-    m, cam = w.body.model, w.body.camera
-    ang = w.body.angular
-    n = int(prm["n_iters"])
-    phi0 = phi0.astype(np.float32).astype(np.float64)
-    th_prev, phi_prev_state = th0.copy(), phi0.copy()
-    trk.reset(th0, phi0.astype(np.float32))
-    v_gpu_prev = trk.state()[2]      # the GPU's float32 surface at the frame's start
-    worst = [0.0, 0.0, 0.0]
-    fails = []
-    n_mis = 0
-    for t in range(1, n + 1):
-        trk.set_params(_truncated(prm, t))
-        trk.reset(th0, phi0.astype(np.float32))
-        assert trk.frame(depth) == 0, T.track_last_error()
-        th_g, phi_g, v_g, st = trk.state()
-        a_g = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (cam["height"] * cam["width"],), np.int32)
-        # the oracle: one iteration (the flags of iteration t) from the GPU's
-        # state before iteration t; phi_prev is the frame's start offsets
-        one = dict(prm, n_iters=1, do_pose=np.asarray(prm["do_pose"])[t - 1:t].copy(),
-                   do_shape=np.asarray(prm["do_shape"])[t - 1:t].copy())
-        c = certify.check_iteration(m, cam, one, ang, th_prev, phi_prev_state, phi0, v_gpu_prev, depth,
-                                    th_g, phi_g, a_g)
-        n_mis += c["mis"]
-        worst = [max(x, y) for x, y in zip(worst, c["err"])]
-        log(f"    it {t}: {certify.describe(c)}")
-        if c["bad"]:
-            fails.append(f"iteration {t}: {len(c['bad'])} mismatches are not near-ties (first pixel {c['bad'][0]})")
-        elif not c["ok"]:
-            e = c["err"]
-            fails.append(f"iteration {t}: joint {e[0]:.2e} rad, root {e[1]:.2e} m, vertex {e[2]:.2e} m")
-        th_prev, phi_prev_state = th_g.copy(), phi_g.astype(np.float64)
-        v_gpu_prev = v_g
-    trk.set_params(prm)
-    return worst, n_mis, fails
-
-
 def _whole_frame(T, trk, w, prm, th0, phi0, depth, log):
     """Whole frame from the same start on both sides, with the oracle's own
     response to a 1e-6 perturbation of the start pose (printed)."""
@@ -146,7 +102,7 @@ def _run(T, w, prm, nframes):
     try:
         for f in range(nframes):
             _say(f"  frame {f}")
-            worst, n_mis, fl = _walk_frame(T, trk, w, prm, th, phi, w.frames[f], _say)
+            worst, n_mis, fl = certify.walk_frame(T, trk, w.body, prm, th, phi, w.frames[f], _say)
             worst_all = [max(a, b) for a, b in zip(worst_all, worst)]
             fails += [f"frame {f}, {x}" for x in fl]
             th, phi = _whole_frame(T, trk, w, prm, th, phi, w.frames[f], _say)
