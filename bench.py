@@ -584,7 +584,7 @@ def modes(args):
                       "ground_truth": "synthetic: matrix linear-blend posed surface with 5 mm folds"},
            "modes": {}}
     for mode in M.MODES:
-        model = M.rigid_segments(m) if mode == "rigid-segments" else m
+        model = M.model_for(mode, m)
         dp, ds = M.mode_schedule(mode, 0, n_it)
         prm = dict(w.params, n_iters=len(dp), do_pose=dp, do_shape=ds)
         trk = T.Tracker(model, cam, prm, w.theta0)

@@ -48,6 +48,11 @@ typedef enum {
 } track_status;
 
 enum { TRACK_HINGE = 0, TRACK_PRISMATIC = 1 };
+/* How a vertex's links are combined (Section 3.2): the weighted blend of the
+   links' dual quaternions applied to the point (the paper's), or the
+   weighted average of the point moved rigidly by each link (matrix linear
+   blend skinning). */
+enum { TRACK_BLEND_DQ = 0, TRACK_BLEND_LINEAR = 1 };
 /* Operand form of the J^T J / J^T r contraction on the matrix cores:
    float32; bfloat16 hi/lo split (3 products); bfloat16 hi/mid/lo split (6). */
 enum { TRACK_GRAM_FP32 = 0, TRACK_GRAM_BF16X3 = 1, TRACK_GRAM_BF16X6 = 2 };
@@ -98,6 +103,7 @@ typedef struct {
                                     parent t -> s t; of other root joints
                                     t -> c + s (t - c).  Prismatic values and the
                                     camera stay in metres.                          */
+    int32_t blend;               /* TRACK_BLEND_DQ (0) or TRACK_BLEND_LINEAR           */
 } track_model;
 
 /* Pinhole depth camera; depth frames are H x W float32 row-major, metres,

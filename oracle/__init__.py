@@ -42,7 +42,7 @@ class _Model(ctypes.Structure):
         ("rest_xyz", ctypes.c_void_p), ("n_faces", ctypes.c_int32),
         ("faces", ctypes.c_void_p), ("max_infl", ctypes.c_int32),
         ("skin_link", ctypes.c_void_p), ("skin_w", ctypes.c_void_p),
-        ("neighbors", ctypes.c_void_p),
+        ("neighbors", ctypes.c_void_p), ("blend", ctypes.c_int32),
     ]
 
 
@@ -113,7 +113,7 @@ class Model:
                         _p(a["joint_axis"]), _p(a["joint_offset"]), self.L,
                         _p(a["link_joint"]), self.V, _p(a["rest_xyz"]), self.F,
                         _p(a["faces"]), self.K, _p(a["skin_link"]),
-                        _p(a["skin_w"]), _p(a["neighbors"]))
+                        _p(a["skin_w"]), _p(a["neighbors"]), int(model.get("blend", 0)))
 
 
 def _model(m):

@@ -25,6 +25,7 @@ typedef struct {
     const int32_t* skin_link;   // [V*K]
     const float* skin_w;        // [V*K]
     const int32_t* neighbors;   // [V*4]
+    int32_t blend;              // 0 dual-quaternion blend, 1 linear blend of the links' transforms
 } orc_model_in;
 
 typedef struct { int32_t width, height; float fx, fy, cx, cy; } orc_camera_in;
@@ -59,6 +60,7 @@ static orc::Model to_model(const orc_model_in* in) {
     }
     m.rest.assign(in->rest_xyz, in->rest_xyz + 3 * (size_t)m.V);
     m.skin_w.assign(in->skin_w, in->skin_w + (size_t)m.V * m.K);
+    m.blend = in->blend;
     orc::model_derive(m);
     return m;
 }

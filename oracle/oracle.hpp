@@ -158,8 +158,11 @@ template <class S> void dq_transform_jacobian(const DQ<S>& H, const S x[3], S Jt
 // ---------------------------------------------------------------------------
 enum { HINGE = 0, PRISMATIC = 1 };
 
+enum { BLEND_DQ = 0, BLEND_LINEAR = 1 };
+
 struct Model {
     int P = 0, L = 0, V = 0, F = 0, K = 0;
+    int blend = BLEND_DQ;   // how a vertex's links are combined (see skin)
     std::vector<int> parent, type, link_joint, faces, skin_link, nbr;
     std::vector<double> axis, offq, offt, rest, skin_w;
     // derived
@@ -249,13 +252,44 @@ template <class S> DQ<S> blend(const Model& m, const std::vector<DQ<S>>& D, int 
     return acc;
 }
 
-// Eq. (5): v_i = H_{i,Sigma} (v0_i + phi_i).
+// Eq. (5): v_i = H_{i,Sigma} (v0_i + phi_i).  The linear variant (matrix
+// linear blend skinning) instead transforms the point rigidly by each link and
+// averages the results with the weights: v_i = sum_j w_ij T(H_{j,Delta}, x_i).
 template <class S> void skin(const Model& m, const std::vector<DQ<S>>& D, const S* phi, S* v) {
     for (int i = 0; i < m.V; ++i) {
-        DQ<S> H = blend(m, D, i);
         S x[3] = {S(m.rest[3 * i]) + phi[3 * i], S(m.rest[3 * i + 1]) + phi[3 * i + 1],
                   S(m.rest[3 * i + 2]) + phi[3 * i + 2]};
-        dq_transform(H, x, &v[3 * i]);
+        if (m.blend == BLEND_LINEAR) {
+            S acc[3] = {S(0), S(0), S(0)};
+            for (int k = 0; k < m.K; ++k) {
+                int l = m.skin_link[i * m.K + k];
+                if (l < 0) continue;
+                S y[3];
+                dq_transform(D[l], x, y);
+                for (int d = 0; d < 3; ++d) acc[d] = acc[d] + S(m.skin_w[i * m.K + k]) * y[d];
+            }
+            for (int d = 0; d < 3; ++d) v[3 * i + d] = acc[d];
+        } else {
+            DQ<S> H = blend(m, D, i);
+            dq_transform(H, x, &v[3 * i]);
+        }
+    }
+}
+
+// d v_i / d x_i: the rotation of the blend (dual quaternions), or the
+// weighted sum of the links' rotations (linear variant).
+inline void point_jacobian(const Model& m, const std::vector<DQ<double>>& D, int i, double R[9]) {
+    if (m.blend == BLEND_LINEAR) {
+        std::fill(R, R + 9, 0.0);
+        for (int k = 0; k < m.K; ++k) {
+            int l = m.skin_link[i * m.K + k];
+            if (l < 0) continue;
+            double Rl[9];
+            quat_rotation(D[l].r, Rl);
+            for (int q = 0; q < 9; ++q) R[q] += m.skin_w[i * m.K + k] * Rl[q];
+        }
+    } else {
+        quat_rotation(blend(m, D, i).r, R);
     }
 }
 
@@ -476,8 +510,30 @@ inline PoseSystem pose_system(const Model& m, const double* theta, const double*
         if (cnt[i] < 1 || nl == 0.0) continue;
         ps.obs[i] = 1;
         ps.r[i] = n[3 * i] * delta[3 * i] + n[3 * i + 1] * delta[3 * i + 1] + n[3 * i + 2] * delta[3 * i + 2];
-        DQ<double> Hs = blend(m, D, i);
         double x[3] = {m.rest[3 * i] + phi[3 * i], m.rest[3 * i + 1] + phi[3 * i + 1], m.rest[3 * i + 2] + phi[3 * i + 2]};
+        if (m.blend == BLEND_LINEAR) {
+            // each influence through its own rigid transform: dv = sum_m w_m dT/dH(H_m, x) dH_m
+            double Jm[4][3][8];
+            for (int q = 0; q < m.K; ++q) {
+                int l = m.skin_link[i * m.K + q];
+                if (l >= 0) dq_transform_jacobian(D[l], x, Jm[q]);
+            }
+            for (int k = 0; k < m.P; ++k) {
+                double dv[3] = {0, 0, 0};
+                for (int q = 0; q < m.K; ++q) {
+                    int l = m.skin_link[i * m.K + q];
+                    if (l < 0 || !m.anc[l][k]) continue;
+                    const DQ<double>& g = dD[(size_t)l * m.P + k];
+                    const double comp[8] = {g.r.w, g.r.x, g.r.y, g.r.z, g.d.w, g.d.x, g.d.y, g.d.z};
+                    const double w = m.skin_w[i * m.K + q];
+                    for (int d = 0; d < 3; ++d)
+                        for (int c = 0; c < 8; ++c) dv[d] += w * Jm[q][d][c] * comp[c];
+                }
+                ps.J[(size_t)i * m.P + k] = -(n[3 * i] * dv[0] + n[3 * i + 1] * dv[1] + n[3 * i + 2] * dv[2]);
+            }
+            continue;
+        }
+        DQ<double> Hs = blend(m, D, i);
         double Jt[3][8];
         dq_transform_jacobian(Hs, x, Jt);
         double sgn[4];
@@ -597,9 +653,8 @@ inline void shape_step(const Model& m, const ShapeArgs& s, double* phi_out) {
         double nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
         double u[3] = {0, 0, 0}, r = 0.0;
         if (s.cnt[i] >= 1 && nl > 0.0) {
-            DQ<double> Hs = blend(m, D, i);
             double R[9];
-            quat_rotation(Hs.r, R);
+            point_jacobian(m, D, i, R);
             for (int c = 0; c < 3; ++c) u[c] = -(R[c] * ni[0] + R[3 + c] * ni[1] + R[6 + c] * ni[2]);
             r = ni[0] * s.delta[3 * i] + ni[1] * s.delta[3 * i + 1] + ni[2] * s.delta[3 * i + 2];
         }
@@ -641,9 +696,8 @@ inline void shape_step_literal(const Model& m, const ShapeArgs& s, double* phi_o
         double nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
         double j[3] = {0, 0, 0}, r = 0.0;
         if (s.cnt[i] >= 1 && nl > 0.0) {
-            DQ<double> Hs = blend(m, D, i);
             double R[9];
-            quat_rotation(Hs.r, R);
+            point_jacobian(m, D, i, R);
             for (int c = 0; c < 3; ++c) j[c] = -(R[c] * ni[0] + R[3 + c] * ni[1] + R[6 + c] * ni[2]);
             r = ni[0] * s.delta[3 * i] + ni[1] * s.delta[3 * i + 1] + ni[2] * s.delta[3 * i + 2];
         }

@@ -71,8 +71,11 @@ struct alignas(16) TreePlan {
 constexpr int kFanInline = 8;   // incident faces of a vertex held in the inline (per-slot) table
 
 // Mesh, weights and tables in structure-of-arrays device form.
+constexpr int kBlendLinear = 1;   // TRACK_BLEND_LINEAR
+
 struct DevModel {
     int P, L, V, F;
+    int blend;                     // 0 dual-quaternion blend, kBlendLinear: linear blend of the links' motions
     const float *rx, *ry, *rz;     // template vertices
     const float4 *w;               // weights, padded to four
     const uint32_t *links;         // four link bytes per vertex, 0xFF = unused

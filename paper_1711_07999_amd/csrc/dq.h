@@ -93,4 +93,33 @@ __device__ __forceinline__ void dq_blend(const float* dq, float4 w, uint32_t lin
     }
 }
 
+// The linear variant of the blend (matrix linear blend skinning): the point
+// moved rigidly by each influence's unit link offset, averaged with the
+// weights.  No hemisphere signs: each link's motion is applied on its own.
+__device__ __forceinline__ void lbs_apply(const float* dq, float4 w, uint32_t links, float x, float y, float z,
+                                          float& ox, float& oy, float& oz) {
+    const float ws[4] = {w.x, w.y, w.z, w.w};
+    ox = 0.0f; oy = 0.0f; oz = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int l = (links >> (8 * k)) & 0xFF;
+        if (l == 0xFF) continue;
+        float tx, ty, tz;
+        dq_apply(dq + 8 * l, x, y, z, tx, ty, tz);
+        ox += ws[k] * tx;
+        oy += ws[k] * ty;
+        oz += ws[k] * tz;
+    }
+}
+
+// Rotation matrix (row-major) of the quaternion r / |r|.
+template <class T>
+__device__ __forceinline__ void quat_matrix(const float* q, T R[9]) {
+    const T w = q[0], x = q[1], y = q[2], z = q[3];
+    const T s = T(2) / (w * w + x * x + y * y + z * z);
+    R[0] = T(1) - s * (y * y + z * z); R[1] = s * (x * y - w * z); R[2] = s * (x * z + w * y);
+    R[3] = s * (x * y + w * z); R[4] = T(1) - s * (x * x + z * z); R[5] = s * (y * z - w * x);
+    R[6] = s * (x * z - w * y); R[7] = s * (y * z + w * x); R[8] = T(1) - s * (x * x + y * y);
+}
+
 }  // namespace trk

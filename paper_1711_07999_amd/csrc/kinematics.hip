@@ -76,10 +76,14 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
     __syncthreads();
     if (i >= m.V) return;
     float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
-    float H[8];
-    dq_blend(sdq, w, lk, H);
     float ox, oy, oz;
-    dq_apply(H, x, y, z, ox, oy, oz);
+    if (m.blend == kBlendLinear) {
+        lbs_apply(sdq, w, lk, x, y, z, ox, oy, oz);
+    } else {
+        float H[8];
+        dq_blend(sdq, w, lk, H);
+        dq_apply(H, x, y, z, ox, oy, oz);
+    }
     const float4 p = make_float4(ox, oy, oz, 0.0f);
     v[i] = p;
     if (selected(S, count)) count_vertex(S, i, p);

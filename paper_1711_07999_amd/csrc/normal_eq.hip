@@ -65,10 +65,41 @@ __device__ __forceinline__ void vertex_load(const DevModel& m, int i, const floa
 }
 
 // per-vertex 6-vectors of the Jacobian (one per influence) and the residual
-__device__ __forceinline__ void vertex_terms(const float* sdq, const VertexIn& in, float* G, float& r_out) {
+__device__ __forceinline__ void vertex_terms(const float* sdq, const VertexIn& in, float* G, float& r_out,
+                                             bool linear) {
     float H[8], sg[4];
     const float4 w = in.w;
     const uint32_t lk = in.links;
+    const float inv = 1.0f / ((float)in.cnt * 4294967296.0f);
+    const float dx = (float)in.sx * inv, dy = (float)in.sy * inv, dz = (float)in.sz * inv;
+    if (linear) {
+        // the linear blend: influence m moves the template point rigidly to
+        // y_m = T(H_m, x), and dy_m/dtheta_k = Xi_k acting on y_m, so its
+        // 6-vector is 2 w_m (y_m x n, n) (the one-influence case of the
+        // collapsed form above)
+        const float nx = in.nx, ny = in.ny, nz = in.nz;
+        const float ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int l = (lk >> (8 * k)) & 0xFF;
+            float* g = G + 6 * k;
+            if (l == 0xFF) {
+                g[0] = g[1] = g[2] = g[3] = g[4] = g[5] = 0.0f;
+                continue;
+            }
+            float yx, yy, yz;
+            dq_apply(sdq + 8 * l, in.x0, in.x1, in.x2, yx, yy, yz);
+            const float s2 = 2.0f * ws[k];
+            g[0] = s2 * (yy * nz - yz * ny);
+            g[1] = s2 * (yz * nx - yx * nz);
+            g[2] = s2 * (yx * ny - yy * nx);
+            g[3] = s2 * nx;
+            g[4] = s2 * ny;
+            g[5] = s2 * nz;
+        }
+        r_out = nx * dx + ny * dy + nz * dz;
+        return;
+    }
     dq_blend(sdq, w, lk, H, sg);
     const float nx = in.nx, ny = in.ny, nz = in.nz;
     const float vx = in.v.x, vy = in.v.y, vz = in.v.z;
@@ -112,8 +143,6 @@ __device__ __forceinline__ void vertex_terms(const float* sdq, const VertexIn& i
         g[4] = ww * t3[2];
         g[5] = ww * t3[3];
     }
-    const float inv = 1.0f / ((float)in.cnt * 4294967296.0f);
-    const float dx = (float)in.sx * inv, dy = (float)in.sy * inv, dz = (float)in.sz * inv;
     r_out = nx * dx + ny * dy + nz * dz;
 }
 
@@ -225,7 +254,7 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
         if (obs) {
             int row = __popcll(bal & ((1ull << lane) - 1ull)) + (wid == 1 ? scount[0] : 0);
             float r;
-            vertex_terms(sdq, in, &sG[row * kGStride], r);
+            vertex_terms(sdq, in, &sG[row * kGStride], r, S.m.blend == kBlendLinear);
             sr[row] = r;
             slink[row] = in.links;
         }

@@ -621,15 +621,27 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     if (!live) return;
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
+    const bool linear = m.blend == kBlendLinear;
     float H[8];
-    dq_blend(sdq, wv, lk, H);
+    if (!linear) dq_blend(sdq, wv, lk, H);
     if (c > 0u) {
         if ((nx * nx + ny * ny + nz * nz) > 0.0f) {
-            T w = H[0], x = H[1], y = H[2], z = H[3];
-            T s = T(2) / (w * w + x * x + y * y + z * z);
-            T R[9] = {T(1) - s * (y * y + z * z), s * (x * y - w * z), s * (x * z + w * y),
-                      s * (x * y + w * z), T(1) - s * (x * x + z * z), s * (y * z - w * x),
-                      s * (x * z - w * y), s * (y * z + w * x), T(1) - s * (x * x + y * y)};
+            // dr/dphi = -(dv/dx)^T n: the blend's rotation, or for the linear
+            // blend the weighted sum of the links' rotations
+            T R[9];
+            if (!linear) {
+                quat_matrix<T>(H, R);
+            } else {
+                const float ws[4] = {wv.x, wv.y, wv.z, wv.w};
+                for (int q = 0; q < 9; ++q) R[q] = T(0);
+                for (int k = 0; k < 4; ++k) {
+                    const int l = (lk >> (8 * k)) & 0xFF;
+                    if (l == 0xFF) continue;
+                    T Rl[9];
+                    quat_matrix<T>(sdq + 8 * l, Rl);
+                    for (int q = 0; q < 9; ++q) R[q] += (T)ws[k] * Rl[q];
+                }
+            }
             for (int q = 0; q < 3; ++q) u[q] = -(R[q] * nx + R[3 + q] * ny + R[6 + q] * nz);
             const T inv = T(1) / ((T)c * T(4294967296.0));
             T dx = (T)ax * inv + ((T)vo.x - (T)vn.x);
@@ -667,7 +679,8 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         // the next iteration's surface: skin the new offsets (same blend) into
         // the buffer not read here by other vertices, and count it
         float ox, oy, oz;
-        dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
+        if (linear) lbs_apply(sdq, wv, lk, rx + fx, ry + fy, rz + fz, ox, oy, oz);
+        else dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         const float4 q = make_float4(ox, oy, oz, 0.0f);
         S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
         count_vertex(S, i, q);

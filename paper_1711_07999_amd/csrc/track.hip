@@ -117,6 +117,7 @@ int validate_model(const track_model* m, const track_camera* cam) {
     if (m->n_verts < 1) return fail(TRACK_E_INVALID, "n_verts must be >= 1");
     if (m->n_faces < 0) return fail(TRACK_E_INVALID, "n_faces must be >= 0");
     if (m->max_infl < 1 || m->max_infl > TRACK_MAX_INFL) return fail(TRACK_E_INVALID, "max_infl out of range");
+    if (m->blend != TRACK_BLEND_DQ && m->blend != TRACK_BLEND_LINEAR) return fail(TRACK_E_INVALID, "unknown blend");
     if (!m->joint_parent || !m->joint_type || !m->joint_axis || !m->joint_offset || !m->link_joint ||
         !m->rest_xyz || (m->n_faces > 0 && !m->faces) || !m->skin_link || !m->skin_w)
         return fail(TRACK_E_INVALID, "missing model array");
@@ -261,6 +262,7 @@ struct Schedule {
 // ---------------------------------------------------------------------------
 struct Stream {
     int P = 0, L = 0, V = 0, F = 0, K = 0, PP = 0, W = 0, H = 0, npad = 0, ntiles = 0, negrid = 0;
+    int blend = TRACK_BLEND_DQ;
     JointTable hjt{};
     JointTable* djt = nullptr;
     TreePlan hplan{};             // tree form of the pose solve (pointers: device addresses once carved)
@@ -748,6 +750,7 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
                   const double* theta0, const float* phi0, const track_allocator* alloc) {
     c->P = model->n_joints; c->L = model->n_links; c->V = model->n_verts; c->F = model->n_faces;
     c->K = model->max_infl;
+    c->blend = model->blend;
     c->PP = ((c->P + 1) + 15) / 16 * 16;
     c->W = camera->width; c->H = camera->height;
     const int tx = (c->W + 7) / 8, ty = (c->H + 7) / 8;
@@ -825,7 +828,7 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
               (!S.tree.gfmap || hipMemset(S.tree.fimg, 0, sizeof(double) * c->hplan.elems) == hipSuccess) &&
               hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess;
     if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
-    S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F;
+    S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F; S.m.blend = c->blend;
     const float fmax = std::max(camera->fx, camera->fy);
     const double ex = std::max((double)camera->cx + 0.5, (double)camera->width - 0.5 - camera->cx) / camera->fx;
     const double ey = std::max((double)camera->cy + 0.5, (double)camera->height - 0.5 - camera->cy) / camera->fy;

@@ -11,11 +11,12 @@ iteration), shape match (offsets estimated on the first frame only, then
 held), smooth bind (pose only, offsets zero), rigid segments (pose only on
 a model whose vertices each follow one link), and the paper's per-frame
 iteration counts (Section 4.2: ten to fifteen pose iterations; Section 4.3:
-two offset iterations after them).
+two offset iterations after them), also with the linear variant of the
+blend (see `model_for`).
 """
 import numpy as np
 
-MODES = ("full", "shape-match", "smooth-bind", "rigid-segments", "paper-schedule")
+MODES = ("full", "shape-match", "smooth-bind", "rigid-segments", "paper-schedule", "paper-schedule-linear")
 
 
 def mode_schedule(mode: str, frame: int, n_iters: int):
@@ -29,10 +30,19 @@ def mode_schedule(mode: str, frame: int, n_iters: int):
         return one, (one.copy() if frame == 0 else zero)
     if mode in ("smooth-bind", "rigid-segments"):
         return one, zero
-    if mode == "paper-schedule":
+    if mode in ("paper-schedule", "paper-schedule-linear"):
         p = np.array([1] * 12 + [0] * 2, np.uint8)
         return p, 1 - p
     raise ValueError(f"unknown mode {mode!r}")
+
+
+def model_for(mode: str, model: dict) -> dict:
+    """The template a mode tracks with."""
+    if mode == "rigid-segments":
+        return rigid_segments(model)
+    if mode == "paper-schedule-linear":
+        return dict(model, blend=1)
+    return model
 
 
 def rigid_segments(model: dict) -> dict:

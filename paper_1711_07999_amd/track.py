@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtrack.so")
 
 TRACK_OK, TRACK_E_INVALID, TRACK_E_NOMEM, TRACK_E_DEVICE = 0, -1, -2, -3
+TRACK_BLEND_DQ, TRACK_BLEND_LINEAR = 0, 1
 TRACK_E_NOT_PD, TRACK_E_LOST, TRACK_E_BUDGET = -4, -5, -6
 TRACK_GRAM_FP32, TRACK_GRAM_BF16X3, TRACK_GRAM_BF16X6 = 0, 1, 2
 
@@ -55,7 +56,7 @@ class track_model(ctypes.Structure):
         ("rest_xyz", ctypes.c_void_p), ("n_faces", ctypes.c_int32),
         ("faces", ctypes.c_void_p), ("max_infl", ctypes.c_int32),
         ("skin_link", ctypes.c_void_p), ("skin_w", ctypes.c_void_p),
-        ("neighbors", ctypes.c_void_p), ("scale", ctypes.c_float),
+        ("neighbors", ctypes.c_void_p), ("scale", ctypes.c_float), ("blend", ctypes.c_int32),
     ]
 
 
@@ -234,6 +235,7 @@ def make_model(model: dict, keep: _Keep) -> track_model:
     m.skin_w = keep(_c(model["skin_w"], np.float32))
     m.neighbors = None if nb is None else keep(_c(nb, np.int32))
     m.scale = float(model.get("scale", 1.0))
+    m.blend = int(model.get("blend", TRACK_BLEND_DQ))
     return m
 
 

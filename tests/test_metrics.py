@@ -71,3 +71,6 @@ def test_mode_schedules():
     assert M.mode_schedule("smooth-bind", 0, 5)[1].sum() == 0
     p, s = M.mode_schedule("paper-schedule", 0, 5)
     assert p.tolist() == [1] * 12 + [0, 0] and s.tolist() == [0] * 12 + [1, 1]
+    p, s = M.mode_schedule("paper-schedule-linear", 3, 5)
+    assert p.tolist() == [1] * 12 + [0, 0] and s.tolist() == [0] * 12 + [1, 1]
+    assert M.model_for("paper-schedule-linear", {"blend": 0})["blend"] == 1

@@ -338,10 +338,11 @@ def test_averaging_matches_numpy(tiny):
 # ---------------------------------------------------------------------------
 # Section 4.2: residual, Jacobian, normal equations, damped step
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("blend", [0, 1], ids=["dq", "linear"])
 @pytest.mark.parametrize("which", ["tiny", "body"])
-def test_pose_jacobian_matches_dual_numbers_and_finite_differences(which, tiny, small_body, rng):
+def test_pose_jacobian_matches_dual_numbers_and_finite_differences(which, blend, tiny, small_body, rng):
     body = tiny.body if which == "tiny" else small_body
-    m = oracle.Model(body.model)
+    m = oracle.Model(dict(body.model, blend=blend))
     th = random_pose(body, rng, 0.5, 0.05)
     phi = rng.normal(0, 0.004, (m.V, 3))
     v, n = oracle.skin(m, th, phi)
@@ -738,7 +739,8 @@ def test_vertex_normal_is_the_volume_gradient(rng):
 # per-vertex offset step derived from the energy (Section 4.3, Eq. 9 read as
 # a sum of squared residuals)
 # ---------------------------------------------------------------------------
-def test_shape_step_is_a_gauss_newton_step_on_the_vertex_energy(tiny, rng):
+@pytest.mark.parametrize("blend", [0, 1], ids=["dq", "linear"])
+def test_shape_step_is_a_gauss_newton_step_on_the_vertex_energy(tiny, rng, blend):
     """Per vertex, with its neighbours' offsets, the mean associated point
     and the normal frozen, the energy is
         E_i(phi_i) = r_i(phi_i)^2 + l_phi |phi_i|^2
@@ -747,8 +749,9 @@ def test_shape_step_is_a_gauss_newton_step_on_the_vertex_energy(tiny, rng):
     The step must be the damped Gauss-Newton step of E_i / 2: gradient g and
     Gauss-Newton matrix A = u u^T + alpha I, u = dr_i/dphi_i, both taken here
     by central differences of the energy and of r_i, then
-    (A + l_w diag A) x = g and phi_i <- phi_i - x."""
-    m = oracle.Model(tiny.body.model)
+    (A + l_w diag A) x = g and phi_i <- phi_i - x.  The same holds for
+    the linear blend, whose d v_i / d phi_i is no longer a rotation."""
+    m = oracle.Model(dict(tiny.body.model, blend=blend))
     th = random_pose(tiny.body, rng, 0.3, 0.02)
     phi = rng.normal(0, 0.003, (m.V, 3))
     prev = phi + rng.normal(0, 0.001, (m.V, 3))
@@ -944,3 +947,30 @@ def test_literal_eq9_diverges_on_the_tiny_arm_where_the_reading_does_not(tiny):
             assert not np.isfinite(big) or big > 1.0      # metres
         else:
             assert big < 2e-3 and rms[-1] < rms[0]
+
+
+# ---------------------------------------------------------------------------
+# the linear variant of the blend (matrix linear blend skinning)
+# ---------------------------------------------------------------------------
+def test_linear_blend_equals_the_generators_matrix_skinning(small_body, rng):
+    """Each link's rigid transform applied to the point, averaged with the
+    weights: the input generator poses its ground truth this way with 4x4
+    homogeneous matrices, an implementation of its own."""
+    m = dict(small_body.model, blend=1)
+    for _ in range(3):
+        th = random_pose(small_body, rng, 0.6, 0.1)
+        phi = rng.normal(0, 0.004, (m["rest_xyz"].shape[0], 3))
+        v, _ = oracle.skin(m, th, phi)
+        np.testing.assert_allclose(v, synth.pose_surface(m, th, phi), atol=1e-12)
+    # and it differs from the dual-quaternion blend where links bend
+    v_dq, _ = oracle.skin(small_body.model, th, phi)
+    assert np.abs(v - v_dq).max() > 1e-4
+
+
+def test_linear_and_dq_blends_agree_on_rigid_vertices(small_body, rng):
+    m = one_hot(small_body.model)
+    th = random_pose(small_body, rng, 0.6, 0.1)
+    a, _ = oracle.skin(m, th)
+    b, _ = oracle.skin(dict(m, blend=1), th)
+    np.testing.assert_allclose(a, b, atol=1e-13)
+
