@@ -249,6 +249,21 @@ def batched_copies(T, w, frames_dev, prm, B, nsat):
             "bytes_per_frame": fb, "achieved_GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
 
 
+def batched_only(args):
+    import torch
+
+    import synth
+    from paper_1711_07999_amd import track as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.workload_human(n_frames=30)
+    frames = [torch.from_numpy(f).to("cuda:0") for f in w.frames]
+    prm = _gram_params(w.params, args.gram)
+    out = batched_copies(T, w, frames, prm, args.batched, args.batch_frames)
+    print(json.dumps({"metric": "batched copies of the human-50k-640x480 workload", "gram": args.gram, **out}),
+          flush=True)
+
+
 def single_stream(args):
     import torch
 
@@ -656,6 +671,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving mix instead of the single-stream step")
     ap.add_argument("--modes", action="store_true",
                     help="tracking modes and schedules against the synthetic ground truth")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="only B copies of the workload batched through one server")
     ap.add_argument("--streams", type=int, default=64)
     ap.add_argument("--frames", type=int, default=300, help="frames per stream at the configured load")
     ap.add_argument("--sat-frames", type=int, default=30, help="frames per stream at saturation")
@@ -676,6 +693,8 @@ def main():
         serve(args)
     elif args.modes:
         modes(args)
+    elif args.batched:
+        batched_only(args)
     else:
         single_stream(args)
 

@@ -75,7 +75,6 @@ constexpr int kBlendLinear = 1;   // TRACK_BLEND_LINEAR
 
 struct DevModel {
     int P, L, V, F;
-    int blend;                     // 0 dual-quaternion blend, kBlendLinear: linear blend of the links' motions
     const float *rx, *ry, *rz;     // template vertices
     const float4 *w;               // weights, padded to four
     const uint32_t *links;         // four link bytes per vertex, 0xFF = unused
@@ -171,6 +170,7 @@ struct alignas(16) Slot {
     int v_cur;                    // current vertex buffer when the launch starts
     int phi_cur, phi_prev;        // current and previous-frame offset buffers
     int iter;                     // iteration of the frame the launch starts at
+    int blend;                    // 0 dual-quaternion blend, kBlendLinear: linear blend of the links' motions
 };
 
 // Offset buffer written by the step after `src` (never the previous frame's

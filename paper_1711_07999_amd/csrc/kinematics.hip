@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
     if (i >= m.V) return;
     float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
     float ox, oy, oz;
-    if (m.blend == kBlendLinear) {
+    if (S.blend == kBlendLinear) {
         lbs_apply(sdq, w, lk, x, y, z, ox, oy, oz);
     } else {
         float H[8];

@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
         if (obs) {
             int row = __popcll(bal & ((1ull << lane) - 1ull)) + (wid == 1 ? scount[0] : 0);
             float r;
-            vertex_terms(sdq, in, &sG[row * kGStride], r, S.m.blend == kBlendLinear);
+            vertex_terms(sdq, in, &sG[row * kGStride], r, S.blend == kBlendLinear);
             sr[row] = r;
             slink[row] = in.links;
         }

@@ -621,7 +621,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     if (!live) return;
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
-    const bool linear = m.blend == kBlendLinear;
+    const bool linear = S.blend == kBlendLinear;
     float H[8];
     if (!linear) dq_blend(sdq, wv, lk, H);
     if (c > 0u) {

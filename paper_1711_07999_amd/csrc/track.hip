@@ -828,7 +828,7 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
               (!S.tree.gfmap || hipMemset(S.tree.fimg, 0, sizeof(double) * c->hplan.elems) == hipSuccess) &&
               hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess;
     if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
-    S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F; S.m.blend = c->blend;
+    S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F; S.blend = c->blend;
     const float fmax = std::max(camera->fx, camera->fy);
     const double ex = std::max((double)camera->cx + 0.5, (double)camera->width - 0.5 - camera->cx) / camera->fx;
     const double ey = std::max((double)camera->cy + 0.5, (double)camera->height - 0.5 - camera->cy) / camera->fy;
