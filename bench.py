@@ -390,6 +390,11 @@ def single_stream(args):
                                 "solves": "float64" if other == "bf16x3" else "float32"}
         # B copies of the workload batched through one server
         out["batched_copies"] = [batched_copies(T, w, frames, prm, B, args.batch_frames) for B in (16, 32)]
+        # the serving mix, shortened: 64 streams of six sizes, 45 frames each
+        # at 30 frames/s (Poisson), then saturation
+        lite = argparse.Namespace(**vars(args))
+        lite.streams, lite.frames, lite.sat_frames, lite.seq_frames = 64, 45, 10, 10
+        out["serving_mix"] = serve(lite, lite=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
@@ -408,7 +413,10 @@ def _pingpong(k, n):
     return q if q < n else 2 * n - 2 - q
 
 
-def serve(args):
+def serve(args, lite=False):
+    """The serving mix: configured load (Poisson arrivals), saturation, and
+    unless `lite` the admission run under a 1 GiB budget and the alone-vs-mix
+    check.  Prints the JSON line, or with `lite` returns it."""
     import torch
 
     import synth
@@ -504,6 +512,16 @@ def serve(args):
                  for s in chosen}
     T.track_server_destroy(sv)
     log(f"saturation: {n_sat} frames in {t_sat:.2f} s")
+    mix = {}
+    for st in streams:
+        name = seqs[st["ci"]][0].name
+        mix[name] = mix.get(name, 0) + 1
+    if lite:
+        return {"streams": len(streams), "mix": mix, "sequence_frames_per_size": args.seq_frames,
+                "configured_load": {"offered_fps": 30.0 * len(streams), "achieved_fps": done / t_load,
+                                    "p50_ms": float(np.percentile(lat_ms, 50)),
+                                    "p99_ms": float(np.percentile(lat_ms, 99)), "frames": done},
+                "saturation_fps": n_sat / t_sat, "saturation_frames": n_sat}
 
     # (iv) eight streams rerun alone must end bit-identical
     same = []
@@ -544,10 +562,6 @@ def serve(args):
     T.track_server_destroy(sv)
     log(f"admission: {n_adm} frames, max resident {max_res}")
 
-    mix = {}
-    for st in streams:
-        name = seqs[st["ci"]][0].name
-        mix[name] = mix.get(name, 0) + 1
     out = {
         "metric": "aggregate tracked frames/s + p99 latency (64 streams, 10k-200k-vert bodies, 320x240/640x480)",
         "value": n_sat / t_sat,
