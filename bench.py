@@ -39,10 +39,14 @@ def algorithmic_bytes(kernel, V, F, N_px, N_valid, K=4, temporal=False):
         "skin": V * (36 + 5 * K),
         # vertices, incident faces in; normals out
         "normals": 12 * F + 24 * V,
-        # vertices in; per-pixel counts, z range and records; sorted vertices
-        "bucket": 36 * V + 24 * N_px,
-        # depth in, association out, the buckets read once, per-vertex sums
-        "assoc": 20 * N_px + 44 * V + 28 * N_valid,
+        # (no launch of its own: the producing kernels count into the
+        # buckets, the association lays them out)
+        "bucket": 0,
+        # depth in, association out, cell records read and the next layout
+        # written (16 B per 16 pixels each), the bucketed vertices read once,
+        # per-pixel sums; in the same launch the normals (vertices and fans
+        # in, normals out)
+        "assoc": 10 * N_px + 16 * V + 28 * N_valid + 12 * F + 28 * V,
         # vertices, normals, offsets, template, weights, links, sums in
         "normal_eq": V * (52 + 5 * K),
         "solve": 0,
@@ -52,11 +56,12 @@ def algorithmic_bytes(kernel, V, F, N_px, N_valid, K=4, temporal=False):
 
 def frame_bytes(V, F, N_px, N_valid, n_iters, K=4, temporal=False, depth_upload=True):
     """Algorithmic bytes of one frame of (pose + offset) iterations: per
-    iteration the bucket index, association, normal equations, re-skin at
-    the new pose and the offset step (which skins and counts the next
-    surface), plus the frame-start skin and the depth image."""
+    iteration the association (with the normals and the bucket layout),
+    normal equations, re-skin at the new pose and the offset step (which
+    skins the next surface into the buckets), plus the frame-start skin and
+    the depth image."""
     b = lambda k: algorithmic_bytes(k, V, F, N_px, N_valid, K, temporal)  # noqa: E731
-    per_iter = b("bucket") + b("normals") + b("assoc") + b("normal_eq") + b("skin") + b("shape")
+    per_iter = b("assoc") + b("normal_eq") + b("skin") + b("shape")
     return n_iters * per_iter + b("skin") + (4 * N_px if depth_upload else 0)
 
 
@@ -65,7 +70,6 @@ REPEATABLE = ("skin", "assoc", "normal_eq", "solve")
 # sources whose change invalidates a kernel's committed counter reading
 KERNEL_SOURCES = {
     "assoc": ["association.hip", "common.h", "surface.h"],
-    "bucket": ["association.hip", "common.h", "surface.h"],
     "normal_eq": ["normal_eq.hip", "common.h"],
     "solve": ["solve.hip", "common.h", "fk.h"],
     "shape": ["solve.hip", "common.h", "surface.h"],

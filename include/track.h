@@ -209,8 +209,8 @@ int track_frame_xyz(track_ctx *ctx, const float *xyz, int32_t on_device);
  * overlap on one GPU race (issue them from one thread, or serialise them).
  * The kernels are launched directly, not from a graph.  TRACK_E_INVALID if
  * the frame's working buffers exceed 64 MiB (about 20 MiB for 50k vertices
- * with 640x480 depth, 52 bytes more per vertex: up to about 850k vertices at
- * that size) or kernel timing is on.  Working buffers read back through
+ * with 640x480 depth, 108 bytes more per vertex: up to about 440k vertices
+ * at that size) or kernel timing is on.  Working buffers read back through
  * track_dbg_get (matches, counts, Gram) are those of track_frame's last frame.
  */
 int track_frame_noalloc(track_ctx *ctx, const float *depth, int32_t depth_on_device);
@@ -380,7 +380,9 @@ enum {
 enum {
     TRACK_PASS_SKIN = 0,      /* FK at THETA, skin PHI -> VERTS, NORMALS                    */
     TRACK_PASS_NORMALS = 1,   /* NORMALS from VERTS                                        */
-    TRACK_PASS_ASSOCIATE = 2, /* buckets of VERTS; ASSOC, COUNT, DELTA from the set frame  */
+    TRACK_PASS_ASSOCIATE = 2, /* buckets of VERTS in the layout the last association left
+                                 (none after set-up); ASSOC, COUNT, DELTA from the set frame;
+                                 NORMALS of VERTS                                            */
     TRACK_PASS_NORMAL_EQ = 3, /* GRAM from THETA, PHI, VERTS, NORMALS, COUNT, DELTA        */
     TRACK_PASS_POSE_STEP = 4, /* damped solve of GRAM; THETA -= x; STEP                    */
     TRACK_PASS_SHAPE = 5      /* re-skin at THETA into VERTS_NEW and new normals, then one
@@ -396,7 +398,10 @@ int track_dbg_run(track_ctx *ctx, int32_t pass);
  * dispatch packets on the context's stream (the kernels' execution span);
  * while any timer is on, launches are issued directly, not from graphs.
  * track_kernel_time returns the number of timed launches and their summed
- * duration since the last reset.
+ * duration since the last reset.  The bucket index has no launch of its own
+ * inside frames (the kernels that produce a surface count it into the
+ * buckets, and the association launch lays them out and forms the normals),
+ * so the TRACK_K_BUCKET and TRACK_K_NORMALS timers count no launches.
  * ---------------------------------------------------------------------- */
 enum {
     TRACK_K_SKIN = 0,

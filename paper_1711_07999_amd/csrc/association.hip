@@ -1,16 +1,13 @@
 // Projective data association (Section 4.1).
 //
-// Vertices are projected into per-pixel buckets (a point-rasterised index
-// buffer kept as a counting sort) together with each bucket's z range (the
-// z-buffer).  Pixels are numbered tile by tile (8x8 tiles, row-major) and in
-// Morton order inside a tile, so the vertices of every 4x4-pixel quadrant
-// ("cell") are contiguous after the sort and each cell has one record
-// (offset, count, zmin, zmax).  Every valid pixel then finds the nearest
-// vertex closer than tau: cells are visited in rings around the pixel's tile
-// and skipped when a lower bound on the distance of anything inside them
-// (from the pixel distance to the cell, or from its z range) cannot beat the
-// best distance so far, so the result equals the exhaustive nearest-vertex
-// search.  The matched offsets are summed per vertex in 64-bit fixed point
+// Vertices are projected into pixel buckets (a point-rasterised index kept
+// per 4x4-pixel cell, see Buckets) together with each cell's and tile's z
+// range (the z-buffer).  Every valid pixel then finds the nearest vertex
+// closer than tau: cells are visited in rings around the pixel's cell and
+// skipped when a lower bound on the distance of anything inside them (from
+// the pixel distance to the cell, or from its z range) cannot beat the best
+// distance so far, so the result equals the exhaustive nearest-vertex search.
+// The matched offsets are summed per vertex in 64-bit fixed point
 // (deterministic).
 //
 // Float32 decisions follow one operation order, compiled without contraction:
@@ -27,23 +24,29 @@ namespace trk {
 
 __device__ __forceinline__ int wave_lane() { return threadIdx.x & 63; }
 
+constexpr uint32_t kInfBits = 0x7F800000u;   // +inf: the z minimum of an empty cell or tile
+
 // ---------------------------------------------------------------------------
-// clear the bucket counters, z ranges, tile sums and per-vertex accumulators
-// (on the frame path they are cleared by their last reader instead)
+// clear both parities' bucket records (counters and layout: every region
+// empty, so the first count sends its vertices to the overflow list), the
+// per-vertex accumulators and the solve's front image
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_clear(Batch B) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_CLEAR, blockIdx.x, local)];
     const Buckets& b = S.b;
     const Accum& a = S.a;
-    const int npad = S.npad, V = S.m.V;
+    const int V = S.m.V, ntiles = S.c.tiles_x * S.c.tiles_y, ncells = 4 * ntiles;
     const int i = local * blockDim.x + threadIdx.x;
-    if (i < npad) {
-        b.pcnt[i] = 0u;
-        b.pzmin[i] = 0x7F800000u;  // +inf
-        b.pzmax[i] = 0u;
+    if (i <= ncells) {
+        b.cells[0][i] = make_uint4(kInfBits, 0u, 0u, 0u);
+        b.cells[1][i] = make_uint4(kInfBits, 0u, 0u, 0u);
     }
-    if (i < (npad >> 6)) b.tsum[i] = 0u;
+    if (i < ntiles) {
+        b.tsum[0][i] = 0u;
+        b.tsum[1][i] = 0u;
+    }
+    if (i < 2) b.ovfn[i] = 0u;
     if (i < V) {
         a.cnt[i] = 0u;
         a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
@@ -51,13 +54,34 @@ __global__ void __launch_bounds__(256) k_clear(Batch B) {
     // the tree solve's front image: zero outside the entries the Gram
     // reduction writes
     if (S.tree.gfmap) {
-        const int stride = ((npad > V ? npad : V) + 255) / 256 * 256;
+        const int n = 2 * (ncells + 1) > V ? 2 * (ncells + 1) : V;
+        const int stride = (n + 255) / 256 * 256;
         for (int e = i; e < S.tree.elems; e += stride) S.tree.fimg[e] = 0.0;
     }
 }
 
 void launch_clear(const Launch& L) {
     launch_kernel(L, true, true, k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B);
+}
+
+// the counters of one parity, its layout kept
+__global__ void __launch_bounds__(256) k_clear_counts(Batch B, int bsel) {
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_CLEAR, blockIdx.x, local)];
+    const Buckets& b = S.b;
+    const int par = S.bpar ^ bsel;
+    const int ntiles = S.c.tiles_x * S.c.tiles_y, ncells = 4 * ntiles;
+    const int i = local * blockDim.x + threadIdx.x;
+    if (i <= ncells) {
+        uint4* c = &b.cells[par][i];
+        c->x = kInfBits; c->y = 0u; c->z = 0u;
+    }
+    if (i < ntiles) b.tsum[par][i] = 0u;
+    if (i == 0) b.ovfn[par] = 0u;
+}
+
+void launch_clear_counts(const Launch& L, int bsel) {
+    launch_kernel(L, true, true, k_clear_counts, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B, bsel);
 }
 
 __global__ void __launch_bounds__(256) k_clear_acc(Batch B) {
@@ -73,123 +97,141 @@ void launch_clear_acc(const Launch& L) {
     launch_kernel(L, true, true, k_clear_acc, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B);
 }
 
-// ---------------------------------------------------------------------------
-// bucket construction: count (fused into skinning, or this kernel for a
-// given surface) -> tile prefix -> per-pixel offsets -> scatter
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int which) {
+// count a given surface into the buckets (the producing kernels count their
+// own output instead)
+__global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int which, int bsel) {
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
     if (!selected(S, which)) return;
     const int i = local * blockDim.x + threadIdx.x;
-    if (i >= S.m.V) return;
-    count_vertex(S, i, S.verts[S.v_cur ^ vsel][i]);
+    const bool live = i < S.m.V;
+    count_vertex(S, bsel, i, S.verts[S.v_cur ^ vsel][live ? i : 0], live, false);
 }
 
-void launch_bucket_count(const Launch& L, int vsel, int which) {
-    launch_kernel(L, true, true, k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel, which);
+void launch_bucket_count(const Launch& L, int vsel, int which, int bsel) {
+    launch_kernel(L, true, true, k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel, which, bsel);
 }
 
-// exclusive prefix over tiles, one workgroup of 1024 threads; the tile sums
-// are zeroed for the next count
+// ---------------------------------------------------------------------------
+// Bucket layout for the next count, from the counts of parity `par`, with
+// room for the surface to move: tile t gets d + d/2 + 32 slots, d the largest
+// count among the 3x3 tiles around it (so a tile the surface moves into has
+// room), placed after the tiles before it; inside it, cell c gets its own
+// count n + n/2 + 8 plus a quarter of what the tile has beyond the sum of
+// those (the last cell the rest).  Written into the other parity with its
+// counters cleared.  A workgroup takes kLayoutTiles tiles (one per thread)
+// and sums the shares of all tiles before them itself, from the tile counts
+// staged in LDS (read from memory when they do not fit).
+// ---------------------------------------------------------------------------
+constexpr int kLayoutStage = 8192;   // tile counts staged in LDS (32 KB)
 
-// Per-pixel (offset, count, zmin, zmax), the same record per 4x4 cell (the 16
-// consecutive Morton positions of a tile quadrant) and the tile's z range;
-// one wave per tile.  The pixel counters are reset for the next count.
-__global__ void __launch_bounds__(256) k_pixel_offsets(Batch B) {
-    __shared__ uint32_t spart[4];
-    int local;
-    const Slot& S = B.slots[slot_of(B, KK_TILE4, blockIdx.x, local)];
+__device__ __forceinline__ uint32_t tile_share(uint32_t d) { return d + (d >> 1) + 32u; }
+
+__device__ __forceinline__ void layout_tiles(const Slot& S, int par, int lblk, uint32_t* stage, uint32_t* sred) {
     const Buckets& b = S.b;
-    const int ntiles = S.c.tiles_x * S.c.tiles_y;
-    const int wid = threadIdx.x >> 6, lane = wave_lane();
-    const int t0 = local * 4;
-    const int tile = t0 + wid;
-    const bool live = tile < ntiles;
-    const int p = (tile << 6) + lane;
-    const uint32_t* __restrict__ tsum = b.tsum;
-    // every load of the kernel is issued before the first wait, none of them
-    // under a branch: this tile's pixels, the counts of this workgroup's
-    // earlier tiles and of every earlier workgroup's tiles (which the
-    // workgroup sums itself; the scatter clears them)
-    const int pl = live ? p : 0;
-    const uint32_t cnt = b.pcnt[pl], zmn = b.pzmin[pl], zmx = b.pzmax[pl];
-    uint32_t own = 0u;
+    const int tx = S.c.tiles_x, ty = S.c.tiles_y, ntiles = tx * ty;
+    const uint32_t* __restrict__ tin = b.tsum[par];
+    const uint4* __restrict__ cin = b.cells[par];
+    uint4* __restrict__ cout = b.cells[par ^ 1];
+    uint32_t* __restrict__ tout = b.tsum[par ^ 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nthr = blockDim.x, nw = nthr / 64;
+    const int t0 = lblk * kLayoutTiles;
+    const bool staged = ntiles <= kLayoutStage;
+    // this thread's tile: its cells' counts, issued first
+    const int t = t0 + threadIdx.x;
+    const bool live = t < ntiles;
+    const int tl = live ? t : 0;
+    uint32_t c4[4];
 #pragma unroll
-    for (int w = 0; w < 3; ++w) {
-        const uint32_t c = tsum[t0 + (w < wid ? w : 0)];
-        own += w < wid ? c : 0u;
+    for (int q = 0; q < 4; ++q) c4[q] = cin[4 * tl + q].z;
+    if (staged) {
+        for (int u = threadIdx.x; u < ntiles; u += nthr * 10) {
+            uint32_t a[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) a[k] = tin[min(u + nthr * k, ntiles - 1)];
+#pragma unroll
+            for (int k = 0; k < 10; ++k)
+                if (u + nthr * k < ntiles) stage[u + nthr * k] = a[k];
+        }
+        __syncthreads();
     }
+    // largest count of column x over rows y-1..y+1 (0 outside the image);
+    // the largest count of the 3x3 tiles around (x, y) is that of columns
+    // x-1, x, x+1
+    auto column = [&](int x, int y) {
+        uint32_t d = 0u;
+        if (x >= 0 && x < tx)
+            for (int yy = max(y - 1, 0); yy <= min(y + 1, ty - 1); ++yy)
+                d = max(d, staged ? stage[yy * tx + x] : tin[yy * tx + x]);
+        return d;
+    };
+    // shares of the tiles before this workgroup's: a contiguous run per
+    // thread, walked along its rows with the three columns carried over
     uint32_t part = 0u;
-    for (int t = threadIdx.x; t < t0; t += 256 * 20) {   // one round up to 5120 tiles
-        uint32_t a[20];
-#pragma unroll
-        for (int k = 0; k < 20; ++k) a[k] = tsum[min(t + 256 * k, t0 - 1)];   // past t0: a repeat, not added
-#pragma unroll
-        for (int k = 0; k < 20; ++k) part += t + 256 * k < t0 ? a[k] : 0u;
+    {
+        const int chunk = (t0 + nthr - 1) / nthr;
+        int u = threadIdx.x * chunk;
+        const int ue = min(u + chunk, t0);
+        if (u < ue) {
+            int x = u % tx, y = u / tx;
+            uint32_t cl = column(x - 1, y), cm = column(x, y), cr = column(x + 1, y);
+            for (; u < ue; ++u) {
+                part += tile_share(max(cl, max(cm, cr)));
+                if (++x == tx) {
+                    x = 0;
+                    ++y;
+                    cl = 0u; cm = column(0, y); cr = column(1, y);
+                } else {
+                    cl = cm; cm = cr; cr = column(x + 1, y);
+                }
+            }
+        }
     }
     for (int o = 32; o > 0; o >>= 1) part += (uint32_t)__shfl_xor((int)part, o);
-    if (lane == 0) spart[wid] = part;
-    __syncthreads();
-    if (!live) return;
-    const uint32_t tile_off = spart[0] + spart[1] + spart[2] + spart[3] + own;
-    uint32_t incl = cnt;
+    // this thread's tile share, scanned over the wave
+    const int xl = tl % tx, yl = tl / tx;
+    const uint32_t R = live ? tile_share(max(column(xl - 1, yl), max(column(xl, yl), column(xl + 1, yl)))) : 0u;
+    uint32_t incl = R;
     for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(incl, o);
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, o);
         if (lane >= o) incl += y;
     }
-    const uint32_t off = tile_off + incl - cnt;
-    b.poff[p] = off;
-    b.pcnt[p] = 0u;
-    b.pzmin[p] = 0x7F800000u;
-    b.pzmax[p] = 0u;
-    uint32_t csum = cnt, cmn = zmn, cmx = zmx;
-    for (int o = 1; o < 16; o <<= 1) {
-        csum += __shfl_xor(csum, o);
-        cmn = min(cmn, (uint32_t)__shfl_xor((int)cmn, o));
-        cmx = max(cmx, (uint32_t)__shfl_xor((int)cmx, o));
+    if (lane == 63) { sred[wid] = part; sred[nw + wid] = incl; }
+    __syncthreads();
+    uint32_t base = 0u;
+    for (int w = 0; w < nw; ++w) base += sred[w] + (w < wid ? sred[nw + w] : 0u);
+    if (live) {
+        // R >= the cells' own shares: d >= the tile's count, and the cells'
+        // halves sum to at most the tile's half
+        uint32_t own[4], sum = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { own[q] = c4[q] + (c4[q] >> 1) + 8u; sum += own[q]; }
+        const uint32_t extra = (R - sum) >> 2;
+        // counts of one count phase sum to at most V, so the regions end by
+        // ncap; the clamp only keeps every region inside the buffer
+        const uint32_t ncap = (uint32_t)b.ncap;
+        uint32_t o = base + incl - R;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            cout[4 * t + q] = make_uint4(kInfBits, 0u, 0u, min(o, ncap));
+            o += own[q] + extra;
+        }
+        tout[t] = 0u;
+        if (t == ntiles - 1) cout[4 * ntiles] = make_uint4(kInfBits, 0u, 0u, min(base + incl, ncap));
     }
-    if ((lane & 15) == 0) b.cellrec[(tile << 2) + (lane >> 4)] = make_uint4(off, csum, cmn, cmx);
-    // tile z range (an empty pixel holds +inf / 0, neutral for min / max of z > 0)
-    for (int o = 16; o < 64; o <<= 1) {
-        cmn = min(cmn, (uint32_t)__shfl_xor((int)cmn, o));
-        cmx = max(cmx, (uint32_t)__shfl_xor((int)cmx, o));
-    }
-    if (lane == 0) b.tz[tile] = make_float2(__uint_as_float(cmn), cmx ? __uint_as_float(cmx) : -INFINITY);
+    if (lblk == 0 && threadIdx.x == 0) b.ovfn[par ^ 1] = 0u;
 }
 
-// vertices grouped by bucket (first half of the grid) and vertex normals of
-// the same surface (second half)
-__global__ void __launch_bounds__(256) k_scatter_normals(Batch B, int vsel) {
+__global__ void __launch_bounds__(kAssocThreads) k_layout(Batch B, int bsel) {
+    __shared__ uint32_t stage[kLayoutStage];
+    __shared__ uint32_t sred[2 * (kAssocThreads / 64)];
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_VERT2, blockIdx.x, local)];
-    const int half = (S.m.V + 255) / 256;
-    const float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
-    if (local < half) {
-        const Buckets& b = S.b;
-        const int i = local * blockDim.x + threadIdx.x;
-        // the tile counts were last read by the pixel records: zero them for
-        // the next count
-        for (int t = i; t < S.c.tiles_x * S.c.tiles_y; t += half * 256) b.tsum[t] = 0u;
-        if (i >= S.m.V) return;
-        const int pix = b.vpix[i];
-        const uint32_t slot = b.vslot[i];   // (stale when pix < 0: unused)
-        const float4 p = v[i];
-        if (pix < 0) return;
-        const uint32_t dst = b.poff[pix] + slot;
-        b.sorted[dst] = make_float4(p.x, p.y, p.z, __int_as_float(i));
-    } else {
-        const int i = (local - half) * blockDim.x + threadIdx.x;
-        const bool live = i < S.m.V;
-        float nx, ny, nz;
-        vertex_normal(S.m, v, i, live, nx, ny, nz);   // the whole wave
-        if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
-    }
+    const Slot& S = B.slots[slot_of(B, KK_LAYOUT, blockIdx.x, local)];
+    layout_tiles(S, S.bpar ^ bsel, local, stage, sred);
 }
 
-void launch_bucket(const Launch& L, int vsel) {
-    launch_kernel(L, true, false, k_pixel_offsets, dim3(L.grid[KK_TILE4]), dim3(256), 0, L.B);
-    launch_kernel(L, false, true, k_scatter_normals, dim3(L.grid[KK_VERT2]), dim3(256), 0, L.B, vsel);
+void launch_layout(const Launch& L, int bsel) {
+    launch_kernel(L, true, true, k_layout, dim3(L.grid[KK_LAYOUT]), dim3(kAssocThreads), 0, L.B, bsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -223,8 +265,10 @@ __device__ __forceinline__ bool z_pruned(float zmn, float zmx, float pz, float b
 // with the candidate of its slot and keeping the key (d2 bits << 32 | vertex
 // id), whose minimum is the nearest vertex with ties to the lower index; the
 // slots of a pixel are combined by shuffles.  The search walks square rings
-// of cells around the quadrant's own cell.
-constexpr int kAssocWaves = 8;
+// of cells around the quadrant's own cell.  The same launch also runs the
+// layout of the next count (its first workgroups, from the counts read here)
+// and the vertex normals of the surface (the workgroups after them).
+constexpr int kAssocWaves = kAssocThreads / 64;
 constexpr int kAssocPass = 256;   // candidates per pass (LDS per wave: 4 KB)
 
 __device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) {
@@ -236,13 +280,35 @@ __device__ __forceinline__ unsigned long long slot_min(unsigned long long k) {
     return min_u64(k, __shfl_xor(k, 32));
 }
 
-__global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vsel) {
+__global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vsel, int bsel) {
     __shared__ float4 scand[kAssocWaves][kAssocPass];
     __shared__ int4 scount[kAssocWaves];
     int local;
-    const Slot& S = B.slots[slot_of(B, KK_TILE, blockIdx.x, local)];
+    const Slot& S = B.slots[slot_of(B, KK_ASSOC, blockIdx.x, local)];
     const DevCam& c = S.c;
     const Buckets& b = S.b;
+    const int par = S.bpar ^ bsel;
+    {
+        const int nlay = layout_blocks(c.tiles_x * c.tiles_y), nnorm = assoc_normal_blocks(S.m.V);
+        if (local < nlay) {
+            static_assert(sizeof(scand) >= kLayoutStage * sizeof(uint32_t), "layout stage fits the candidate LDS");
+            layout_tiles(S, par, local, reinterpret_cast<uint32_t*>(&scand[0][0]), reinterpret_cast<uint32_t*>(scount));
+            return;
+        }
+        if (local < nlay + nnorm) {
+            const int i = (local - nlay) * kAssocThreads + threadIdx.x;
+            const bool live = i < S.m.V;
+            float nx, ny, nz;
+            vertex_normal_lean(S.m, S.verts[S.v_cur ^ vsel], i, live, nx, ny, nz);   // the whole wave
+            if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
+            return;
+        }
+        local -= nlay + nnorm;
+    }
+    const uint4* __restrict__ cells = b.cells[par];
+    // the overflow list: compared whole, once, by a wave that needs one of
+    // the cells whose region was full
+    const uint32_t novf = min(b.ovfn[par], (uint32_t)S.m.V);
     const Accum& a = S.a;
     const float tau = S.tau;
     const float* __restrict__ depth = S.depth;
@@ -314,8 +380,13 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
             bool cand = false;
             if (qw < nwin) {
                 const int wy = qw / nwx;
-                const float2 tz = b.tz[(wy0 + wy) * c.tiles_x + wx0 + (qw - wy * nwx)];
-                cand = tz.x <= tz.y && tz.x < pmax + tz_tol && tz.y > pmin - tz_tol;
+                // the tile's z range from its four cells' (an empty cell
+                // holds (+inf, 0): an empty tile is never a candidate)
+                const uint2* cz = reinterpret_cast<const uint2*>(cells + 4 * ((wy0 + wy) * c.tiles_x + wx0 + (qw - wy * nwx)));
+                const uint2 r0 = cz[0], r1 = cz[2], r2 = cz[4], r3 = cz[6];
+                const float zlo = __uint_as_float(min(min(r0.x, r1.x), min(r2.x, r3.x)));
+                const float zhi = __uint_as_float(max(max(r0.y, r1.y), max(r2.y, r3.y)));
+                cand = zlo <= zhi && zlo < pmax + tz_tol && zhi > pmin - tz_tol;
             }
             candidate_tiles = __any(cand);
         }
@@ -328,7 +399,9 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
         // (entries 0..8) first, then the rest -- and a batch takes every cell
         // some pixel still needs under the bound left by the batches before,
         // loading all of its candidates before comparing any.
-        auto run_batch = [&](unsigned long long cells, const uint4& rec, int rcx, int rcy) {
+        bool ovf_done = false;
+        auto run_batch = [&](unsigned long long cellmask, unsigned long long ovfcells, const uint4& rec, int rcx,
+                             int rcy) {
             // lane = cell: is it needed by one of the wave's 8 pixels (the
             // pixel-distance and z-range bounds cannot exclude a better vertex)?
             // A finished pixel counts with bound 0, which excludes everything.
@@ -346,8 +419,9 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
                 const float lb = ring_lb(c, pzp, max(mx, my));
                 need = need || (!(lb * lb >= bound) && !z_pruned(c_zmn, c_zmx, pzp, bound, bp < tau2_bits));
             }
-            const unsigned long long needed = __ballot(need) & cells;
-            uint32_t total = 0u;
+            const unsigned long long needed = __ballot(need) & cellmask;
+            const bool take_ovf = !ovf_done && (needed & ovfcells) != 0ull;
+            uint32_t total = take_ovf ? novf : 0u;
             for (unsigned long long m = needed; m; m &= m - 1ull)
                 total += (uint32_t)__builtin_amdgcn_readlane((int)rec.y, __builtin_ctzll(m));
             // the needed cells' candidates in cell order, up to kAssocPass per
@@ -358,20 +432,24 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
             for (uint32_t pass = 0; pass < total; pass += kAssocPass) {
                 const uint32_t pend = pass + (uint32_t)kAssocPass;
                 uint32_t pre = 0u;
-                for (unsigned long long m = needed; m; m &= m - 1ull) {
-                    const int k = __builtin_ctzll(m);
-                    const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)rec.x, k);
-                    const uint32_t cnt = (uint32_t)__builtin_amdgcn_readlane((int)rec.y, k);
+                // candidates [off, off + cnt) of `cellv` as the segment after `pre`
+                auto segment = [&](uint32_t off, uint32_t cnt) {
                     const uint32_t a0 = max(pre, pass), a1 = min(pre + cnt, pend);
                     for (uint32_t s0 = a0; s0 < a1; s0 += 64u) {
                         if ((uint32_t)lane < a1 - s0)
                             __builtin_amdgcn_global_load_lds(
-                                (const void*)(b.sorted + off + (s0 - pre) + lane),
+                                (const void*)(b.cellv + off + (s0 - pre) + lane),
                                 (__attribute__((address_space(3))) void*)&scand[wid][s0 - pass], 16, 0, 0);
                     }
                     pre += cnt;
+                };
+                for (unsigned long long m = needed; m; m &= m - 1ull) {
+                    const int k = __builtin_ctzll(m);
+                    segment((uint32_t)__builtin_amdgcn_readlane((int)rec.x, k),
+                            (uint32_t)__builtin_amdgcn_readlane((int)rec.y, k));
                     if (pre >= pend) break;   // the rest belongs to later passes
                 }
+                if (take_ovf && pre < pend) segment((uint32_t)b.ncap, novf);
                 __builtin_amdgcn_s_waitcnt(0);   // the copies have landed in LDS
                 __builtin_amdgcn_wave_barrier();
                 const int n = (int)min((uint32_t)kAssocPass, total - pass);
@@ -391,6 +469,7 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
                 }
                 __builtin_amdgcn_wave_barrier();
             }
+            if (take_ovf) ovf_done = true;
             best = slot_min(key);
         };
         const int last = (2 * Rc + 1) * (2 * Rc + 1);
@@ -400,7 +479,9 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
             while ((sq + 1) * (sq + 1) <= l2) ++sq;
             while (sq * sq > l2) --sq;
             const int rr = (sq + 1) >> 1;
+            // (first slot, vertices in the region, zmin bits, zmax bits)
             uint4 myrec = make_uint4(0u, 0u, 0u, 0u);
+            uint32_t mycnt = 0u;
             int mycx = 0, mycy = 0;
             if (l2 < last) {
                 const int kq = rr == 0 ? 0 : l2 - (2 * rr - 1) * (2 * rr - 1);
@@ -410,15 +491,22 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
                 else if (kq < 2 * side) { mycx = ccx - rr + (kq - side); mycy = ccy + rr; }
                 else if (kq < 3 * side - 2) { mycx = ccx - rr; mycy = ccy - rr + 1 + (kq - 2 * side); }
                 else { mycx = ccx + rr; mycy = ccy - rr + 1 + (kq - (3 * side - 2)); }
-                if (mycx >= 0 && mycy >= 0 && mycx < cells_x && mycy < cells_y)
-                    myrec = b.cellrec[(((mycy >> 1) * c.tiles_x + (mycx >> 1)) << 2) | ((mycy & 1) << 1) | (mycx & 1)];
+                if (mycx >= 0 && mycy >= 0 && mycx < cells_x && mycy < cells_y) {
+                    const int ci = (((mycy >> 1) * c.tiles_x + (mycx >> 1)) << 2) | ((mycy & 1) << 1) | (mycx & 1);
+                    const uint4 r = cells[ci];
+                    const uint32_t end = cells[ci + 1].w;
+                    const uint32_t cap = end > r.w ? end - r.w : 0u;
+                    mycnt = r.z;
+                    myrec = make_uint4(r.w, min(r.z, cap), r.x, r.y);
+                }
             }
-            const unsigned long long todo = __ballot(myrec.y != 0u);
+            const unsigned long long todo = __ballot(mycnt != 0u);
+            const unsigned long long ovfc = __ballot(mycnt > myrec.y);
             if (cur == 0) {
-                run_batch(todo & 0x1FFull, myrec, mycx, mycy);
-                run_batch(todo & ~0x1FFull, myrec, mycx, mycy);
+                run_batch(todo & 0x1FFull, ovfc, myrec, mycx, mycy);
+                run_batch(todo & ~0x1FFull, ovfc, myrec, mycx, mycy);
             } else {
-                run_batch(todo, myrec, mycx, mycy);
+                run_batch(todo, ovfc, myrec, mycx, mycy);
             }
             // the complete rings so far; every cell outside their square is
             // at least m_next pixels away
@@ -463,8 +551,8 @@ __global__ void __launch_bounds__(64 * kAssocWaves) k_associate(Batch B, int vse
     }
 }
 
-void launch_associate(const Launch& L, int vsel) {
-    launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_TILE]), dim3(64 * kAssocWaves), 0, L.B, vsel);
+void launch_associate(const Launch& L, int vsel, int bsel) {
+    launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_ASSOC]), dim3(kAssocThreads), 0, L.B, vsel, bsel);
 }
 
 }  // namespace trk

@@ -107,19 +107,23 @@ struct Accum {
     long long *sx, *sy, *sz; // sum of (p - v) in units of 2^-32 m
 };
 
-// Bucket (index/z-buffer) storage; pixels are numbered tile-major: 8x8
-// tiles in row-major order, 64 pixels per tile in Morton order.
+// Bucket (index/z-buffer) storage.  Pixels are numbered tile-major (8x8
+// tiles in row-major order, 64 pixels per tile in Morton order), so a 4x4
+// quadrant of a tile ("cell") is 16 consecutive pixels and pixel k lies in
+// cell k >> 4.  Every counted vertex goes straight into its cell's region of
+// `cellv`; the regions were laid out by the previous association from the
+// counts it read (with room for the surface to move, see layout_tiles), and
+// a vertex that finds its cell's region full goes to the overflow list after
+// the regions.  The counters are double-buffered: the association reads one
+// parity and writes the other's layout (counters cleared), which the next
+// count fills.
 struct Buckets {
-    uint32_t* pcnt;    // [Npad] vertices per pixel        } zero again once the
-    uint32_t* pzmin;   // [Npad] bits of the smallest z     } pixel records are
-    uint32_t* pzmax;   // [Npad] bits of the largest z      } built (+inf, 0, 0)
-    uint32_t* poff;    // [Npad] first slot of each pixel's vertices in `sorted`
-    uint32_t* tsum;    // [tiles] vertices per tile (zero again after the scatter)
-    float2* tz;        // [tiles] z range of the tile
-    int* vpix;         // [V] bucket of each vertex or -1
-    uint32_t* vslot;   // [V] rank inside its bucket
-    float4* sorted;    // [V] (x, y, z, vertex id bits) grouped by bucket
-    uint4* cellrec;    // [tiles*4] per 4x4 cell: (offset, count, zmin bits, zmax bits)
+    uint4* cells[2];   // [cells + 1] per parity: (zmin bits, zmax bits, vertices counted, first slot
+                       // of the cell's region); entry `cells` holds the end of the last region in .w
+    uint32_t* tsum[2]; // [tiles] per parity: vertices counted per tile
+    uint32_t* ovfn;    // [2] vertices in the overflow list, per parity
+    float4* cellv;     // [ncap + V] (x, y, z, vertex id bits): the cells' regions, then the overflow list
+    int ncap;          // slots of the regions (bucket_capacity bounds every layout)
     int4* bstat;       // [tiles] valid, matched, newly observed pixels per tile
     const int* torder; // [tiles] the order association takes tiles in: nearest the image centre
                        // first (where the subject and the longest searches usually are)
@@ -165,12 +169,13 @@ struct alignas(16) Slot {
     int32_t* assoc;
     DevStats* st;
     DevSummary* summary;
-    int PP, npad, negrid, flags;
+    int PP, negrid, flags;
     float tau, lambda_k, lphi, lnbr, lt, lw;
     int v_cur;                    // current vertex buffer when the launch starts
     int phi_cur, phi_prev;        // current and previous-frame offset buffers
     int iter;                     // iteration of the frame the launch starts at
     int blend;                    // 0 dual-quaternion blend, kBlendLinear: linear blend of the links' motions
+    int bpar;                     // bucket counters filled by the next count when the launch starts
 };
 
 // Offset buffer written by the step after `src` (never the previous frame's
@@ -191,10 +196,9 @@ __host__ __device__ __forceinline__ int phi_index(const Slot& S, int n) {
 enum KernelKind {
     KK_ONE = 0,     // one workgroup per slot (frame bookkeeping, FK, solve)
     KK_VERT,        // ceil(V / 256) workgroups
-    KK_VERT2,       // 2 ceil(V / 256): two vertex passes in one launch
-    KK_CLEAR,       // ceil(max(Npad, V) / 256)
-    KK_TILE4,       // ceil(tiles / 4): one wave per tile
-    KK_TILE,        // tiles: one workgroup per tile
+    KK_CLEAR,       // ceil(max(2 (cells + 1), V) / 256)
+    KK_LAYOUT,      // ceil(tiles / kLayoutTiles): bucket layout
+    KK_ASSOC,       // association: layout + normals + one workgroup per tile
     KK_NE,          // normal-equation workgroups
     KK_REDUCE,      // Gram reduction workgroups
     KK_VERT64,      // ceil(V / 64): one wave per 64 vertices
@@ -261,16 +265,27 @@ __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& l
 
 int ne_grid(int V);
 
+// association launch: layout workgroups, then normal workgroups, then tiles
+constexpr int kAssocThreads = 512;
+constexpr int kLayoutTiles = kAssocThreads;   // tiles per layout workgroup (one per thread)
+__host__ __device__ inline int layout_blocks(int ntiles) { return (ntiles + kLayoutTiles - 1) / kLayoutTiles; }
+__host__ __device__ inline int assoc_normal_blocks(int V) { return (V + kAssocThreads - 1) / kAssocThreads; }
+// Slots of the cells' regions.  A layout gives tile t d + d/2 + 32 slots, d
+// the largest count of the 3x3 tiles around it; the d sum to about 2 V on a
+// body (9 V at most), so 4 V + 32 per tile leaves room to spare.  Regions
+// past the end are cut to nothing (their vertices take the overflow list):
+// a layout never writes outside the buffer, whatever the counts.
+inline int bucket_capacity(int V, int ntiles) { return 4 * V + 32 * ntiles; }
+
 // workgroups of each kind for one slot (host side)
 inline int slot_blocks(const Slot& s, int kind) {
     const int V = s.m.V, ntiles = s.c.tiles_x * s.c.tiles_y;
     switch (kind) {
         case KK_ONE: return 1;
         case KK_VERT: return (V + 255) / 256;
-        case KK_VERT2: return 2 * ((V + 255) / 256);
-        case KK_CLEAR: return ((s.npad > V ? s.npad : V) + 255) / 256;
-        case KK_TILE4: return (ntiles + 3) / 4;
-        case KK_TILE: return ntiles;
+        case KK_CLEAR: { const int n = 2 * (4 * ntiles + 1); return ((n > V ? n : V) + 255) / 256; }
+        case KK_LAYOUT: return layout_blocks(ntiles);
+        case KK_ASSOC: return layout_blocks(ntiles) + assoc_normal_blocks(V) + ntiles;
         case KK_NE: return s.negrid;
         case KK_REDUCE: { int nb = s.PP >> 4; return nb * (nb + 1) / 2 * 8; }
         case KK_VERT64: return (V + 63) / 64;
@@ -292,16 +307,22 @@ void launch_stage(hipStream_t s, const Slot* src, Slot* dst, int n, const int* p
 void launch_frame_begin(const Launch& L);
 void launch_frame_end(const Launch& L, int first_pose, int last_pose);  // iterations of the frame, -1 = none
 void launch_fk(const Launch& L);
+// bsel: 0 = the bucket counters of parity Slot::bpar, 1 = the other.
 // skin into vsel for the slots selected by `which`; `count` of them also
-// enter the buckets; `clear_acc` slots have their accumulators zeroed
-void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc);  // count: a SlotSel
+// enter the buckets of bsel (count_only: the counts alone, for a layout);
+// `clear_acc` slots have their accumulators zeroed
+void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int bsel, int count_only,
+                 int clear_acc);  // count: a SlotSel
 void launch_normals(const Launch& L, int vsel);
-void launch_clear(const Launch& L);                 // buckets, tile sums, accumulators, front image
+void launch_clear(const Launch& L);                 // both parities' bucket records (no layout), accumulators,
+                                                    // front image
 void launch_clear_acc(const Launch& L);             // accumulators only
-void launch_bucket_count(const Launch& L, int vsel, int which);
-// pixel offsets with the tile prefix (+ clearing the counters), scatter (+ normals)
-void launch_bucket(const Launch& L, int vsel);
-void launch_associate(const Launch& L, int vsel);
+void launch_clear_counts(const Launch& L, int bsel);  // bsel's counters, its layout kept
+void launch_bucket_count(const Launch& L, int vsel, int which, int bsel);
+void launch_layout(const Launch& L, int bsel);      // bsel's counts -> the other parity's layout
+// association of the surface vsel counted into bsel; the same launch forms
+// the surface's normals and lays out the other parity from bsel's counts
+void launch_associate(const Launch& L, int vsel, int bsel);
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
 void launch_gram_reduce(const Launch& L);
 void launch_pose_solve(const Launch& L, int fp64, int iter);
@@ -310,7 +331,7 @@ bool prepare_pose_solve();   // once per process, before the first launch
 bool prepare_normal_eq();    // likewise
 // offset step from v_old / v_new (normals of v_new formed in place); the
 // slots selected by `next` also skin the new offsets into v_new ^ 1 and count
-// them into the buckets
-void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next);
+// them into the buckets of bsel
+void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next, int bsel);
 
 }  // namespace trk

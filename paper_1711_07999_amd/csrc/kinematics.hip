@@ -56,11 +56,12 @@ void launch_fk(const Launch& L) {
 // ---------------------------------------------------------------------------
 // Skinning (Eq. 3 and 5): v_i = T(sum_j w_ij H_{j,Delta}, v0_i + phi_i), one
 // vertex per lane, link offsets staged in LDS, coalesced SoA streams.  The
-// vertex can also be counted into the bucket index of the next association,
-// and the per-vertex accumulators of the last association cleared, so that
-// neither needs a launch of its own.
+// vertex can also be counted into the bucket index of the next association
+// (or only counted, to lay out the index), and the per-vertex accumulators
+// of the last association cleared, so that neither needs a launch of its own.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int which, int count, int clear_acc) {
+__global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int which, int count, int bsel, int count_only,
+                                              int clear_acc) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
     float x = m.rx[ii] + phi.x[ii], y = m.ry[ii] + phi.y[ii], z = m.rz[ii] + phi.z[ii];
     copy_to_lds(sdq, S.dq, 8 * m.L);
     __syncthreads();
-    if (i >= m.V) return;
+    const bool live = i < m.V;   // lanes past the end skin vertex 0 and store nothing
     float4* __restrict__ v = S.verts[S.v_cur ^ vsel];
     float ox, oy, oz;
     if (S.blend == kBlendLinear) {
@@ -85,17 +86,18 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
         dq_apply(H, x, y, z, ox, oy, oz);
     }
     const float4 p = make_float4(ox, oy, oz, 0.0f);
-    v[i] = p;
-    if (selected(S, count)) count_vertex(S, i, p);
-    if (clear_acc) {
+    if (live) v[i] = p;
+    if (selected(S, count)) count_vertex(S, bsel, i, p, live, count_only != 0);   // the whole wave
+    if (live && clear_acc) {
         S.a.cnt[i] = 0u;
         S.a.sx[i] = 0; S.a.sy[i] = 0; S.a.sz[i] = 0;
     }
 }
 
-void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
+void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int bsel, int count_only, int clear_acc) {
     // one wave per workgroup: the vertices spread over every compute unit
-    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT64]), dim3(64), 0, L.B, vsel, pn, which, count, clear_acc);
+    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT64]), dim3(64), 0, L.B, vsel, pn, which, count, bsel,
+                  count_only, clear_acc);
 }
 
 // Vertex normals (one lane per vertex; see vertex_normal)

@@ -578,7 +578,7 @@ __device__ __forceinline__ void solve3(const T M[9], const T g[3], T x[3]) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn, int next) {
+__global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn, int next, int bsel) {
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     }
     float nx, ny, nz;
     vertex_normal_fan(m, v_new, i, live && c > 0u, fan, nx, ny, nz);   // the whole wave
-    if (!live) return;
+    // lanes past the end go on with vertex 0's values (count 0) and store nothing
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
     const bool linear = S.blend == kBlendLinear;
@@ -651,8 +651,10 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         }
     }
     // this is the association's last reader: clear for the next one
-    a.cnt[i] = 0u;
-    a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
+    if (live) {
+        a.cnt[i] = 0u;
+        a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
+    }
     T alpha = (T)lphi + (T)lt;
     T g[3] = {u[0] * r + (T)lphi * px + (T)lt * (px - qx),
               u[1] * r + (T)lphi * py + (T)lt * (py - qy),
@@ -672,9 +674,11 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     T xs[3];
     solve3(M, g, xs);
     const float fx = (float)(px - xs[0]), fy = (float)(py - xs[1]), fz = (float)(pz - xs[2]);
-    phi_out.x[i] = fx;
-    phi_out.y[i] = fy;
-    phi_out.z[i] = fz;
+    if (live) {
+        phi_out.x[i] = fx;
+        phi_out.y[i] = fy;
+        phi_out.z[i] = fz;
+    }
     if (selected(S, next)) {
         // the next iteration's surface: skin the new offsets (same blend) into
         // the buffer not read here by other vertices, and count it
@@ -682,18 +686,18 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         if (linear) lbs_apply(sdq, wv, lk, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         else dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         const float4 q = make_float4(ox, oy, oz, 0.0f);
-        S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
-        count_vertex(S, i, q);
+        if (live) S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
+        count_vertex(S, bsel, i, q, live, false);   // the whole wave
     }
 }
 
-void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next) {
+void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int next, int bsel) {
     // one wave per workgroup: the vertices spread over every compute unit
     const dim3 g(L.grid[KK_VERT64]);
     if (fp64)
-        launch_kernel(L, true, true, k_shape<double>, g, dim3(64), 0, L.B, v_old, v_new, pn, next);
+        launch_kernel(L, true, true, k_shape<double>, g, dim3(64), 0, L.B, v_old, v_new, pn, next, bsel);
     else
-        launch_kernel(L, true, true, k_shape<float>, g, dim3(64), 0, L.B, v_old, v_new, pn, next);
+        launch_kernel(L, true, true, k_shape<float>, g, dim3(64), 0, L.B, v_old, v_new, pn, next, bsel);
 }
 
 }  // namespace trk

@@ -16,34 +16,125 @@ __device__ __forceinline__ int tile_pixel(const DevCam& c, int u, int v) {
 // Bucket of vertex i at p (float32 decisions in one fixed order, no
 // contraction):  floor((fx * x) / z + cx + 0.5), floor((fy * y) / z + cy + 0.5)
 // for z > kZNear inside the image, else none.  Counts the vertex into its
-// pixel (rank kept for the scatter), the pixel's z range and the tile's sum.
-__device__ __forceinline__ void count_vertex(const Slot& S, int i, float4 p) {
+// cell and tile of the counters bsel selects; unless count_only, also into
+// the cell's z range, and stores (x, y, z, i) in the cell's region, or in
+// the overflow list when the region is full.  Every lane of the wave calls
+// it together: the lanes that share a cell (or tile) are grouped and take
+// one atomic per counter (a cell's vertices come from many waves, so
+// per-lane atomics on it would queue behind each other).
+__device__ __forceinline__ void count_vertex(const Slot& S, int bsel, int i, float4 p, bool live, bool count_only) {
 #pragma clang fp contract(off)
     const DevCam& c = S.c;
     const Buckets& b = S.b;
+    const int par = S.bpar ^ bsel;
+    uint4* __restrict__ cells = b.cells[par];
+    const int lane = threadIdx.x & 63;
     int pix = -1;
-    if (p.z > kZNear) {
+    if (live && p.z > kZNear) {
         const float fu = floorf((c.fx * p.x) / p.z + c.cx + 0.5f);
         const float fv = floorf((c.fy * p.y) / p.z + c.cy + 0.5f);
         if (fu >= 0.0f && fu < (float)c.W && fv >= 0.0f && fv < (float)c.H) pix = tile_pixel(c, (int)fu, (int)fv);
     }
-    b.vpix[i] = pix;
-    if (pix >= 0) {
-        b.vslot[i] = atomicAdd(&b.pcnt[pix], 1u);
+    const int cell = pix >= 0 ? (pix >> 4) : -1;
+    if (count_only) {
+        for (unsigned long long todo = __ballot(cell >= 0); todo;) {
+            const int lead = __builtin_ctzll(todo);
+            const int c0 = __builtin_amdgcn_readlane(cell, lead);
+            const unsigned long long grp = __ballot(cell == c0);
+            if (lane == lead) atomicAdd(&cells[c0].z, (uint32_t)__popcll(grp));
+            todo &= ~grp;
+        }
+    } else {
+        // the region's bounds do not wait for the slot
+        const uint32_t off = cell >= 0 ? cells[cell].w : 0u, end = cell >= 0 ? cells[cell + 1].w : 0u;
         const uint32_t zb = __float_as_uint(p.z);  // z > 0: integer order is float order
-        atomicMin(&b.pzmin[pix], zb);
-        atomicMax(&b.pzmax[pix], zb);
+        // per cell: the group's first lane adds the group's count (the slot
+        // base returns into that lane) and the group's z range; a lane's
+        // slot is its leader's base plus its rank in the group
+        uint32_t base = 0u;
+        int leader = lane, rank = 0;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        for (unsigned long long todo = __ballot(cell >= 0); todo;) {
+            const int lead = __builtin_ctzll(todo);
+            const int c0 = __builtin_amdgcn_readlane(cell, lead);
+            const unsigned long long grp = __ballot(cell == c0);
+            // the group's z range, one lane at a time on the scalar unit
+            // (a group is a few lanes)
+            uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+            for (unsigned long long m = grp; m; m &= m - 1ull) {
+                const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)zb, __builtin_ctzll(m));
+                mn = min(mn, z);
+                mx = max(mx, z);
+            }
+            if (lane == lead) {
+                base = atomicAdd(&cells[c0].z, (uint32_t)__popcll(grp));
+                atomicMin(&cells[c0].x, mn);
+                atomicMax(&cells[c0].y, mx);
+            }
+            if (cell == c0) { leader = lead; rank = __popcll(grp & below); }
+            todo &= ~grp;
+        }
+        const uint32_t slot = (uint32_t)__shfl((int)base, leader) + (uint32_t)rank;
+        if (cell >= 0) {
+            const float4 rec = make_float4(p.x, p.y, p.z, __int_as_float(i));
+            if (slot < (end > off ? end - off : 0u)) {
+                b.cellv[off + slot] = rec;
+            } else {
+                // at most V entries between two clears of the counters
+                const uint32_t o = atomicAdd(&b.ovfn[par], 1u);
+                if (o < (uint32_t)S.m.V) b.cellv[(uint32_t)b.ncap + o] = rec;
+            }
+        }
     }
-    // tile sums: neighbouring vertices share tiles, so the lanes of a wave
-    // are grouped by tile and one lane per tile adds the group's count
+    // tile counts, grouped the same way
+    uint32_t* __restrict__ tsum = b.tsum[par];
     const int tile = pix >= 0 ? (pix >> 6) : -1;
-    unsigned long long todo = __ballot(tile >= 0);
-    while (todo) {
-        const int t0 = __builtin_amdgcn_readlane(tile, __builtin_ctzll(todo));
+    for (unsigned long long todo = __ballot(tile >= 0); todo;) {
+        const int lead = __builtin_ctzll(todo);
+        const int t0 = __builtin_amdgcn_readlane(tile, lead);
         const unsigned long long grp = __ballot(tile == t0);
-        if (tile == t0 && (threadIdx.x & 63) == __builtin_ctzll(grp)) atomicAdd(&b.tsum[t0], (uint32_t)__popcll(grp));
+        if (lane == lead) atomicAdd(&tsum[t0], (uint32_t)__popcll(grp));
         todo &= ~grp;
     }
+}
+
+// The faces past the inline table (vertices of more than kFanInline faces,
+// summed by the whole wave: lane l takes faces l, l + 64, ... of the rest; a
+// fixed tree adds the lanes' sums), added to (sx, sy, sz), then normalised.
+__device__ __forceinline__ void fan_rest_and_normalise(const DevModel& m, const float4* __restrict__ v, int ii,
+                                                       bool live, uint32_t e0, uint32_t e1, float sx, float sy,
+                                                       float sz, float& nx, float& ny, float& nz) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x & 63;
+    for (unsigned long long h = __ballot(live && e1 - e0 > (uint32_t)kFanInline); h; h &= h - 1ull) {
+        const int k = __builtin_ctzll(h);
+        const int hv = __builtin_amdgcn_readlane(ii, k);
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)e0, k) + kFanInline;
+        const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)e1, k);
+        const float4 ph = v[hv];
+        float tx = 0.0f, ty = 0.0f, tz = 0.0f;
+        for (uint32_t e = a + (uint32_t)lane; e < z; e += 64u) {
+            const int2 f = m.fan[e];
+            const float4 b = v[f.x], c = v[f.y];
+            const float ax = b.x - ph.x, ay = b.y - ph.y, az = b.z - ph.z;
+            const float bx = c.x - ph.x, by = c.y - ph.y, bz = c.z - ph.z;
+            tx += ay * bz - az * by;
+            ty += az * bx - ax * bz;
+            tz += ax * by - ay * bx;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            tx += __shfl_down(tx, o);
+            ty += __shfl_down(ty, o);
+            tz += __shfl_down(tz, o);
+        }
+        const float ex = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tx), 0));
+        const float ey = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ty), 0));
+        const float ez = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tz), 0));
+        if (lane == k) { sx += ex; sy += ey; sz += ez; }
+    }
+    const float l = sqrtf(sx * sx + sy * sy + sz * sz);
+    const float inv = l > 0.0f ? 1.0f / l : 0.0f;
+    nx = sx * inv; ny = sy * inv; nz = sz * inv;
 }
 
 // A vertex's own position and its inline fan (the loads that wait on
@@ -95,36 +186,43 @@ __device__ __forceinline__ void vertex_normal_fan(const DevModel& m, const float
         sy += az * bx - ax * bz;
         sz += ax * by - ay * bx;
     }
-    const int lane = threadIdx.x & 63;
-    for (unsigned long long h = __ballot(live && e1 - e0 > (uint32_t)kFanInline); h; h &= h - 1ull) {
-        const int k = __builtin_ctzll(h);
-        const int hv = __builtin_amdgcn_readlane(ii, k);
-        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)e0, k) + kFanInline;
-        const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)e1, k);
-        const float4 ph = v[hv];
-        float tx = 0.0f, ty = 0.0f, tz = 0.0f;
-        for (uint32_t e = a + (uint32_t)lane; e < z; e += 64u) {
-            const int2 f = m.fan[e];
-            const float4 b = v[f.x], c = v[f.y];
-            const float ax = b.x - ph.x, ay = b.y - ph.y, az = b.z - ph.z;
-            const float bx = c.x - ph.x, by = c.y - ph.y, bz = c.z - ph.z;
-            tx += ay * bz - az * by;
-            ty += az * bx - ax * bz;
-            tz += ax * by - ay * bx;
+    fan_rest_and_normalise(m, v, ii, live, e0, e1, sx, sy, sz, nx, ny, nz);
+}
+
+// The same normal with fewer registers live: the inline fan's vertices are
+// gathered two faces a round (for a kernel that must stay within 64
+// registers).
+__device__ __forceinline__ void vertex_normal_lean(const DevModel& m, const float4* __restrict__ v, int i, bool live,
+                                                   float& nx, float& ny, float& nz) {
+#pragma clang fp contract(off)
+    const int ii = live ? i : 0;
+    const float4 p = v[ii];
+    const uint32_t e0 = live ? m.fan_off[i] : 0u, e1 = live ? m.fan_off[i + 1] : 0u;
+    int2 bcs[kFanInline];
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) bcs[k] = live ? m.fan8[(size_t)k * m.V + i] : make_int2(0, 0);
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int k0 = 0; k0 < kFanInline; k0 += 2) {
+        // no gather of a later round is moved above this one (registers)
+        __builtin_amdgcn_sched_barrier(0);
+        float4 vb[2], vc[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int2 bc = bcs[k0 + k];
+            vb[k] = v[bc.x];
+            vc[k] = v[bc.y];
         }
-        for (int o = 32; o > 0; o >>= 1) {
-            tx += __shfl_down(tx, o);
-            ty += __shfl_down(ty, o);
-            tz += __shfl_down(tz, o);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float ax = vb[k].x - p.x, ay = vb[k].y - p.y, az = vb[k].z - p.z;
+            const float bx = vc[k].x - p.x, by = vc[k].y - p.y, bz = vc[k].z - p.z;
+            sx += ay * bz - az * by;
+            sy += az * bx - ax * bz;
+            sz += ax * by - ay * bx;
         }
-        const float ex = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tx), 0));
-        const float ey = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ty), 0));
-        const float ez = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tz), 0));
-        if (lane == k) { sx += ex; sy += ey; sz += ez; }
     }
-    const float l = sqrtf(sx * sx + sy * sy + sz * sz);
-    const float inv = l > 0.0f ? 1.0f / l : 0.0f;
-    nx = sx * inv; ny = sy * inv; nz = sz * inv;
+    fan_rest_and_normalise(m, v, ii, live, e0, e1, sx, sy, sz, nx, ny, nz);
 }
 
 __device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* __restrict__ v, int i, bool live,

@@ -261,7 +261,7 @@ struct Schedule {
 // the host's record of which vertex and offset buffers are current.
 // ---------------------------------------------------------------------------
 struct Stream {
-    int P = 0, L = 0, V = 0, F = 0, K = 0, PP = 0, W = 0, H = 0, npad = 0, ntiles = 0, negrid = 0;
+    int P = 0, L = 0, V = 0, F = 0, K = 0, PP = 0, W = 0, H = 0, ntiles = 0, negrid = 0;
     int blend = TRACK_BLEND_DQ;
     JointTable hjt{};
     JointTable* djt = nullptr;
@@ -275,9 +275,10 @@ struct Stream {
     Slot slot{};                   // device pointers and constants of this stream
     float *depth_buf = nullptr, *xyz_buf = nullptr;
     int v_cur = 0, phi_cur = 0, phi_prev = 0;
+    int bpar = 0;                  // bucket counters the next count fills (the other parity holds the last ones)
     bool surface_valid = false, refresh_pose = true;
     bool dirty = true;             // buckets / accumulators not known to be clear
-    bool buckets_ready = false;    // the buckets hold a cleared or filled index
+    bool buckets_ready = false;    // the other bucket parity holds the last association's counts
     int input_mode = 0;            // per-pass interface: 0 depth, 1 xyz
 };
 
@@ -614,18 +615,15 @@ void stream_layout(Stream* c) {
     S.m.fan = carve<int2>(c, 3 * (size_t)c->F);
     S.m.fan8 = carve<int2>(c, (size_t)kFanInline * V);
     Buckets& b = S.b;
-    b.pcnt = carve<uint32_t>(c, c->npad);
-    b.pzmin = carve<uint32_t>(c, c->npad);
-    b.pzmax = carve<uint32_t>(c, c->npad);
-    b.poff = carve<uint32_t>(c, c->npad);
-    b.tsum = carve<uint32_t>(c, c->ntiles);
-    b.tz = carve<float2>(c, c->ntiles);
+    for (int q = 0; q < 2; ++q) {
+        b.cells[q] = carve<uint4>(c, 4 * (size_t)c->ntiles + 1);
+        b.tsum[q] = carve<uint32_t>(c, c->ntiles);
+    }
+    b.ovfn = carve<uint32_t>(c, 2);
+    b.ncap = bucket_capacity(c->V, c->ntiles);
+    b.cellv = carve<float4>(c, (size_t)b.ncap + V);
     b.torder = carve<int>(c, c->ntiles);
-    b.vpix = carve<int>(c, V);
-    b.vslot = carve<uint32_t>(c, V);
-    b.sorted = carve<float4>(c, V);
     b.bstat = carve<int4>(c, c->ntiles);
-    b.cellrec = carve<uint4>(c, 4 * (size_t)c->ntiles);
     S.a.cnt = carve<uint32_t>(c, V);
     S.a.sx = carve<long long>(c, V);
     S.a.sy = carve<long long>(c, V);
@@ -641,7 +639,6 @@ size_t stream_bytes(const track_model* m, const track_camera* cam) {
     s.PP = ((s.P + 1) + 15) / 16 * 16;
     s.W = cam->width; s.H = cam->height;
     s.ntiles = ((s.W + 7) / 8) * ((s.H + 7) / 8);
-    s.npad = s.ntiles * 64;
     s.negrid = ne_grid(s.V);
     stream_layout(&s);
     return s.arena_used;
@@ -663,17 +660,14 @@ size_t frame_scratch_layout(const Stream* c, char* base, Slot& S, float** depth_
     S.partials = static_cast<float*>(take((size_t)c->negrid * c->PP * c->PP, sizeof(float)));
     S.tree.fimg = static_cast<double*>(take((size_t)std::max(2, c->hplan.elems), sizeof(double)));
     Buckets& b = S.b;
-    b.pcnt = static_cast<uint32_t*>(take(c->npad, 4));
-    b.pzmin = static_cast<uint32_t*>(take(c->npad, 4));
-    b.pzmax = static_cast<uint32_t*>(take(c->npad, 4));
-    b.poff = static_cast<uint32_t*>(take(c->npad, 4));
-    b.tsum = static_cast<uint32_t*>(take(c->ntiles, 4));
-    b.tz = static_cast<float2*>(take(c->ntiles, sizeof(float2)));
-    b.vpix = static_cast<int*>(take(V, 4));
-    b.vslot = static_cast<uint32_t*>(take(V, 4));
-    b.sorted = static_cast<float4*>(take(V, sizeof(float4)));
+    for (int q = 0; q < 2; ++q) {
+        b.cells[q] = static_cast<uint4*>(take(4 * (size_t)c->ntiles + 1, sizeof(uint4)));
+        b.tsum[q] = static_cast<uint32_t*>(take(c->ntiles, sizeof(uint32_t)));
+    }
+    b.ovfn = static_cast<uint32_t*>(take(2, 4));
+    b.ncap = bucket_capacity(c->V, c->ntiles);
+    b.cellv = static_cast<float4*>(take((size_t)b.ncap + V, sizeof(float4)));
     b.bstat = static_cast<int4*>(take(c->ntiles, sizeof(int4)));
-    b.cellrec = static_cast<uint4*>(take(4 * (size_t)c->ntiles, sizeof(uint4)));
     S.a.cnt = static_cast<uint32_t*>(take(V, 4));
     S.a.sx = static_cast<long long*>(take(V, 8));
     S.a.sy = static_cast<long long*>(take(V, 8));
@@ -755,7 +749,6 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
     c->W = camera->width; c->H = camera->height;
     const int tx = (c->W + 7) / 8, ty = (c->H + 7) / 8;
     c->ntiles = tx * ty;
-    c->npad = c->ntiles * 64;
     c->negrid = ne_grid(c->V);
     build_joint_table(c, model);
     stream_layout(c);  // size only
@@ -767,7 +760,6 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
     Slot& S = c->slot;
     S.jt = c->djt;
     S.PP = c->PP;
-    S.npad = c->npad;
     S.negrid = c->negrid;
     const size_t V = c->V;
     // ---- host-side tables, uploaded once ----
@@ -826,7 +818,13 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
               (!S.tree.gfmap || up(S.tree.gfmap, c->hgfmap.data(), sizeof(int) * c->hgfmap.size())) &&
               (c->hblob.empty() || up(c->hplan.blob, c->hblob.data(), sizeof(uint32_t) * c->hblob.size())) &&
               (!S.tree.gfmap || hipMemset(S.tree.fimg, 0, sizeof(double) * c->hplan.elems) == hipSuccess) &&
-              hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess;
+              hipMemset(S.st, 0, sizeof(DevStats)) == hipSuccess &&
+              // every bucket region empty: a count before the first layout goes to the overflow list
+              hipMemset(S.b.cells[0], 0, sizeof(uint4) * (4 * (size_t)c->ntiles + 1)) == hipSuccess &&
+              hipMemset(S.b.cells[1], 0, sizeof(uint4) * (4 * (size_t)c->ntiles + 1)) == hipSuccess &&
+              hipMemset(S.b.tsum[0], 0, sizeof(uint32_t) * c->ntiles) == hipSuccess &&
+              hipMemset(S.b.tsum[1], 0, sizeof(uint32_t) * c->ntiles) == hipSuccess &&
+              hipMemset(S.b.ovfn, 0, 2 * sizeof(uint32_t)) == hipSuccess;
     if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
     S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F; S.blend = c->blend;
     const float fmax = std::max(camera->fx, camera->fy);
@@ -1046,6 +1044,7 @@ Launch stage_table(Runner& R, int off, const TableEntry* e, int n) {
         S.v_cur = e[i].s->v_cur;
         S.phi_cur = e[i].s->phi_cur;
         S.phi_prev = e[i].s->phi_prev;
+        S.bpar = e[i].s->bpar;
         S.flags = e[i].flags;
         S.iter = e[i].iter;
         S.depth = e[i].depth;
@@ -1088,22 +1087,16 @@ void issue_stage(const Launch& L) {
 // ---------------------------------------------------------------------------
 struct SurfaceState {
     int vsel = 0;          // vertex buffer relative to the launch's start
+    int bsel = 0;          // bucket counters of the next count, relative to the launch's start
     int pn = 0;            // offset steps taken since the launch's start
     bool counted = false;  // vsel holds the current surface, counted into the buckets
     bool valid = false;    // vsel holds the current surface
 };
 
-void enqueue_associate(Runner& R, const Launch& L, int vsel) {
-    {
-        const Launch T = timed(R, TRACK_K_BUCKET, L);
-        launch_bucket(T, vsel);
-        timed_done(R, TRACK_K_BUCKET, T);
-    }
-    {
-        const Launch T = timed(R, TRACK_K_ASSOC, L);
-        launch_associate(T, vsel);
-        timed_done(R, TRACK_K_ASSOC, T);
-    }
+void enqueue_associate(Runner& R, const Launch& L, int vsel, int bsel) {
+    const Launch T = timed(R, TRACK_K_ASSOC, L);
+    launch_associate(T, vsel, bsel);
+    timed_done(R, TRACK_K_ASSOC, T);
 }
 
 void enqueue_normal_eq(Runner& R, const Launch& L, int gram_mode, int vsel, int pn) {
@@ -1121,10 +1114,21 @@ void enqueue_pose_step(Runner& R, const Launch& L, int fp64, int iter) {
     timed_done(R, TRACK_K_SOLVE, T);
 }
 
-void enqueue_skin(Runner& R, const Launch& L, int vsel, int pn, int which, int count, int clear_acc) {
+void enqueue_skin(Runner& R, const Launch& L, int vsel, int pn, int which, int count, int bsel, int clear_acc) {
     const Launch T = timed(R, TRACK_K_SKIN, L);
-    launch_skin(T, vsel, pn, which, count, clear_acc);
+    launch_skin(T, vsel, pn, which, count, bsel, 0, clear_acc);
     timed_done(R, TRACK_K_SKIN, T);
+}
+
+// Lay out the bucket index of the next count from the surface at the current
+// state (forward kinematics first if `fk`): the surface counted alone into
+// the other parity (cleared before), its counts laid out into bpar.  Any
+// layout gives the same association; this one only keeps the overflow list
+// short for the first frame.
+void prime_buckets(const Launch& L, bool fk) {
+    if (fk) launch_fk(L);
+    launch_skin(L, 0, 0, SEL_ALL, SEL_ALL, 1, 1, 0);
+    launch_layout(L, 1);
 }
 
 // One iteration; `iter` is added to each slot's own iteration index.
@@ -1139,10 +1143,12 @@ void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool s
                int first, int next, bool issue) {
     const bool more = next != SEL_NONE;
     if (!st.counted) {
-        if (issue) enqueue_skin(R, L, st.vsel, st.pn, first, first, 0);
+        if (issue) enqueue_skin(R, L, st.vsel, st.pn, first, first, st.bsel, 0);
         st.counted = st.valid = true;
     }
-    if (issue) enqueue_associate(R, L, st.vsel);
+    // the association lays out the other parity, which the next count fills
+    if (issue) enqueue_associate(R, L, st.vsel, st.bsel);
+    st.bsel ^= 1;
     if (pose && issue) {
         enqueue_normal_eq(R, L, sc.gram_mode, st.vsel, st.pn);
         enqueue_pose_step(R, L, sc.pose_fp64, iter);
@@ -1153,11 +1159,11 @@ void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool s
         int vn = st.vsel;
         if (pose) {
             vn = st.vsel ^ 1;
-            if (issue) enqueue_skin(R, L, vn, st.pn, SEL_ALL, SEL_NONE, 0);
+            if (issue) enqueue_skin(R, L, vn, st.pn, SEL_ALL, SEL_NONE, st.bsel, 0);
         }
         if (issue) {
             const Launch T = timed(R, TRACK_K_SHAPE, L);
-            launch_shape(T, sc.shape_fp64, st.vsel, vn, st.pn, next);
+            launch_shape(T, sc.shape_fp64, st.vsel, vn, st.pn, next, st.bsel);
             timed_done(R, TRACK_K_SHAPE, T);
         }
         st.pn += 1;
@@ -1165,13 +1171,13 @@ void iteration(Runner& R, const Launch& L, const Schedule& sc, bool pose, bool s
         st.counted = st.valid = more;
     } else if (pose) {
         st.vsel ^= 1;
-        if (issue) enqueue_skin(R, L, st.vsel, st.pn, SEL_ALL, next, 1);
+        if (issue) enqueue_skin(R, L, st.vsel, st.pn, SEL_ALL, next, st.bsel, 1);
         st.counted = more;
         st.valid = true;
     } else {
         if (issue) {
             launch_clear_acc(L);
-            launch_bucket_count(L, st.vsel, next);
+            launch_bucket_count(L, st.vsel, next, st.bsel);
         }
         st.counted = more;
     }
@@ -1264,6 +1270,8 @@ const char* lost_reason(int why) {
 
 // host record after a frame of stream s: advance or roll back the buffers
 void finish_frame(Stream* s, const SurfaceState& st, int status) {
+    s->bpar ^= st.bsel;   // every launch of the frame ran, whatever its status
+    s->buckets_ready = true;
     if (status == TRACK_OK) {
         s->v_cur ^= st.vsel;
         int q = s->phi_cur;
@@ -1321,7 +1329,7 @@ int refresh_surface(track_ctx* c) {
     if (c->st.surface_valid) return TRACK_OK;
     Launch L = stage_one(c, 0, nullptr, nullptr);
     if (c->st.refresh_pose) launch_fk(L);
-    enqueue_skin(c->run, L, 0, 0, SEL_ALL, SEL_NONE, 0);
+    enqueue_skin(c->run, L, 0, 0, SEL_ALL, SEL_NONE, 0, 0);
     launch_normals(L, 0);
     c->st.surface_valid = true;
     c->st.refresh_pose = false;
@@ -1333,11 +1341,12 @@ int run_frame(track_ctx* c, const float* depth, const float* xyz) {
     Runner& R = c->run;
     Stream& s = c->st;
     const int flags = kSlotBeginFrame | kSlotEndFrame | (s.refresh_pose ? kSlotRefreshPose : 0);
-    if (s.dirty) {  // buckets and accumulators zero before a frame
-        launch_clear(stage_one(c, 0, nullptr, nullptr));
+    if (s.dirty) {  // buckets and accumulators zero, bucket layout from the current surface
+        const Launch Lc = stage_one(c, 0, nullptr, nullptr);
+        launch_clear(Lc);
+        prime_buckets(Lc, s.refresh_pose);
         HIP_TRY(hipStreamSynchronize(R.s));  // before the table window is rewritten
         s.dirty = false;
-        s.buckets_ready = true;
     }
     TableEntry e{&s, flags, 0, depth, xyz};
     Launch L = stage_table(R, 0, &e, 1);
@@ -1387,7 +1396,11 @@ int run_frame_noalloc(track_ctx* c, char* base, const float* depth, int32_t on_d
         HIP_TRY(hipMemcpyAsync(stage, depth, sizeof(float) * s.W * s.H, hipMemcpyHostToDevice, R.s));
         d = stage;
     }
-    launch_clear(stage_one(c, 0, nullptr, nullptr));
+    {
+        const Launch Lc = stage_one(c, 0, nullptr, nullptr);
+        launch_clear(Lc);
+        prime_buckets(Lc, s.refresh_pose);
+    }
     HIP_TRY(hipStreamSynchronize(R.s));  // before the table window is rewritten
     const int flags = kSlotBeginFrame | kSlotEndFrame | (s.refresh_pose ? kSlotRefreshPose : 0);
     TableEntry e{&s, flags, 0, d, nullptr};
@@ -1401,7 +1414,12 @@ int run_frame_noalloc(track_ctx* c, char* base, const float* depth, int32_t on_d
     (void)hipEventElapsedTime(&ms, R.f0, R.f1);
     const DevSummary sum = R.hsum[0];
     c->last = to_stats(sum, ms);
+    // the context's own bucket records were not used: keep their parity
+    const int bpar = s.bpar;
+    const bool ready = s.buckets_ready;
     finish_frame(&s, st, sum.status);
+    s.bpar = bpar;
+    s.buckets_ready = ready;
     if (sum.status != TRACK_OK) return fail(sum.status, lost_reason(sum.reason));
     return TRACK_OK;
 }
@@ -1517,14 +1535,15 @@ int server_admit(track_server* sv) {
         sv->used += (int64_t)ss->bytes;
         ss->model.release();
         sv->waiting.pop_front();
-        // buckets and accumulators start clear
+        // buckets and accumulators start clear, the bucket layout from the
+        // stream's first surface
         TableEntry e{d, 0, 0, nullptr, nullptr};
         const Launch Lc = stage_table(sv->run, sv->run.cap - 1, &e, 1);
         issue_stage(Lc);
         launch_clear(Lc);
+        prime_buckets(Lc, true);
         HIP_TRY(hipStreamSynchronize(sv->run.s));
         d->dirty = false;
-        d->buckets_ready = true;
     }
     return TRACK_OK;
 }
@@ -1637,6 +1656,10 @@ int track_reset(track_ctx* c, const double* theta, const float* phi) {
     c->st.phi_cur = c->st.phi_prev = 0;
     c->st.surface_valid = false;
     c->st.refresh_pose = true;
+    // the bucket layout follows the surface it was counted from: lay it out
+    // again from the new one before the next frame (a far jump would send
+    // most vertices to the overflow list)
+    c->st.dirty = true;
     return refresh_surface(c);
 }
 
@@ -1708,15 +1731,17 @@ int track_kernel_bench(track_ctx* c, int32_t k, const float* depth, int32_t reps
     Runner& R = c->run;
     HIP_TRY(hipStreamSynchronize(R.s));
     Launch L = stage_one(c, 0, depth, nullptr);
+    // the last association read the counters of the other parity, which
+    // hold the last count (bpar was laid out by it)
     if (k == TRACK_K_NORMAL_EQ) {  // one association, as inside a frame
         launch_clear_acc(L);
-        launch_associate(L, 0);
+        launch_associate(L, 0, 1);
     }
     HIP_TRY(hipEventRecord(R.f0, R.s));
     for (int r = 0; r < reps; ++r) {
         switch (k) {
-            case TRACK_K_SKIN: launch_skin(L, 0, 0, SEL_ALL, SEL_NONE, 0); break;
-            case TRACK_K_ASSOC: launch_associate(L, 0); break;
+            case TRACK_K_SKIN: launch_skin(L, 0, 0, SEL_ALL, SEL_NONE, 0, 0, 0); break;
+            case TRACK_K_ASSOC: launch_associate(L, 0, 1); break;
             case TRACK_K_NORMAL_EQ: launch_normal_eq(L, c->sched.gram_mode, 0, 0); break;
             default: launch_pose_solve(L, c->sched.pose_fp64, 0); break;
         }
@@ -1880,7 +1905,7 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
         case TRACK_PASS_SKIN: {
             Launch L = stage_one(c, 0, depth, xyz);
             launch_fk(L);
-            enqueue_skin(R, L, 0, 0, SEL_ALL, SEL_NONE, 0);
+            enqueue_skin(R, L, 0, 0, SEL_ALL, SEL_NONE, 0, 0);
             launch_normals(L, 0);
             s.surface_valid = true;
             s.refresh_pose = false;
@@ -1890,10 +1915,15 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
             launch_normals(stage_one(c, 0, depth, xyz), 0);
             break;
         case TRACK_PASS_ASSOCIATE: {
+            // count VERTS in the layout the last association (or priming)
+            // left -- none after set-up: every vertex then takes the overflow
+            // list -- and associate; the result does not depend on the layout
             Launch L = stage_one(c, 0, depth, xyz);
-            launch_clear(L);
-            launch_bucket_count(L, 0, SEL_ALL);
-            enqueue_associate(R, L, 0);
+            launch_clear_acc(L);
+            launch_clear_counts(L, 0);
+            launch_bucket_count(L, 0, SEL_ALL, 0);
+            enqueue_associate(R, L, 0, 0);
+            s.bpar ^= 1;
             s.buckets_ready = true;
             break;
         }
@@ -1913,10 +1943,10 @@ int track_dbg_run(track_ctx* c, int32_t pass) {
         case TRACK_PASS_SHAPE: {
             Launch L = stage_one(c, 0, depth, xyz);
             launch_fk(L);
-            enqueue_skin(R, L, 1, 0, SEL_ALL, SEL_NONE, 0);
+            enqueue_skin(R, L, 1, 0, SEL_ALL, SEL_NONE, 0, 0);
             {
                 const Launch T = timed(R, TRACK_K_SHAPE, L);
-                launch_shape(T, c->sched.shape_fp64, 0, 1, 0, SEL_NONE);
+                launch_shape(T, c->sched.shape_fp64, 0, 1, 0, SEL_NONE, 0);
                 timed_done(R, TRACK_K_SHAPE, T);
             }
             s.v_cur ^= 1;
@@ -2063,6 +2093,7 @@ int track_server_step(track_server* sv, int32_t* n_completed) {
             Stream* d = ss->dev;
             const SurfaceState& it = ss->iter == sc.n_iters - 1 ? last : more;
             d->v_cur ^= it.vsel;
+            d->bpar ^= it.bsel;
             if (it.pn) d->phi_cur = phi_next(d->phi_cur, d->phi_prev);
         }
         off += n;

@@ -101,17 +101,67 @@ def test_skin_and_normals(T, tiny, ragged, human, highres, case):
         trk.close()
 
 
+def _bucket_cells(cam, v):
+    """Cell (4x4 pixels, tile-major: 4 per 8x8 tile) of each float32 vertex
+    by the library's bucket rule, -1 outside the image."""
+    f32 = np.float32
+    W, H = cam["width"], cam["height"]
+    x, y, z = v[:, 0], v[:, 1], v[:, 2]
+    with np.errstate(all="ignore"):
+        u = np.floor((f32(cam["fx"]) * x) / z + f32(cam["cx"]) + f32(0.5))
+        w = np.floor((f32(cam["fy"]) * y) / z + f32(cam["cy"]) + f32(0.5))
+    ok = (z > f32(1e-3)) & (u >= 0) & (u < W) & (w >= 0) & (w < H)
+    u = np.where(ok, u, 0).astype(np.int64)
+    w = np.where(ok, w, 0).astype(np.int64)
+    tile = (w // 8) * ((W + 7) // 8) + u // 8
+    return np.where(ok, 4 * tile + 2 * ((w // 4) & 1) + ((u // 4) & 1), -1)
+
+
+def _overflow(cam, v_layout, v_count):
+    """Vertices of v_count that find their cell's region full when the
+    regions were laid out from the counts of v_layout: tile t gets
+    d + d/2 + 32 slots (d the largest count of the 3x3 tiles around it),
+    each cell its count n + n/2 + 8 plus a quarter of the tile's remainder,
+    the last cell the rest."""
+    W, H = cam["width"], cam["height"]
+    tx, ty = (W + 7) // 8, (H + 7) // 8
+    ntiles = tx * ty
+    ca = _bucket_cells(cam, v_layout)
+    cnt = np.bincount(ca[ca >= 0], minlength=4 * ntiles).reshape(ntiles, 4)
+    pad = np.pad(cnt.sum(1).reshape(ty, tx), 1)
+    d = np.max([pad[1 + dy:1 + dy + ty, 1 + dx:1 + dx + tx] for dy in (-1, 0, 1) for dx in (-1, 0, 1)], 0).reshape(-1)
+    R = d + d // 2 + 32
+    own = cnt + cnt // 2 + 8
+    cap = own + ((R - own.sum(1)) // 4)[:, None]
+    cap[:, 3] = R - cap[:, :3].sum(1)
+    cb = _bucket_cells(cam, v_count)
+    got = np.bincount(cb[cb >= 0], minlength=4 * ntiles).reshape(ntiles, 4)
+    return int(np.maximum(got - cap, 0).sum())
+
+
 @pytest.mark.parametrize("case", ["tiny", "ragged", "human", "highres"])
 @pytest.mark.parametrize("source", ["depth", "xyz"])
 def test_association_is_bit_exact(T, tiny, ragged, human, highres, case, source):
     """Same float32 vertices and frame: identical nearest-vertex index per
     pixel and identical counts; mean offsets within 1e-8 m (fixed-point sums
-    quantised at 2^-32 m, float32 output)."""
+    quantised at 2^-32 m, float32 output).  Three associations in a row: the
+    first finds no bucket layout (every vertex in the overflow list), the
+    second the layout of the same surface (no overflow), the third the same
+    layout for the surface moved by five pixels (cells that gained vertices
+    overflow) -- the layout must not change the result."""
     _say(f"[assoc] {case} {source}")
     m, cam, prm, th, depth = _cases(tiny, ragged, human, highres)[case]
     v_or, _ = oracle.skin(m, th)
     v32 = v_or.astype(np.float32)
+    # about five pixels across, three down
+    px = float(np.median(v32[:, 2])) / cam["fx"]
+    moved = (v32 + np.float32([5 * px, 3 * px, 0.0])).astype(np.float32)
     H, W = cam["height"], cam["width"]
+    V = m["rest_xyz"].shape[0]
+    assert _overflow(cam, v32, v32) == 0
+    n_moved = _overflow(cam, v32, moved)
+    _say(f"  {n_moved} vertices overflow on the moved surface")
+    assert n_moved > 0
     trk = T.Tracker(m, cam, prm, th)
     try:
         if source == "xyz":
@@ -129,17 +179,23 @@ def test_association_is_bit_exact(T, tiny, ragged, human, highres, case, source)
             d[::9, ::4] = np.nan
             T.track_dbg_set(trk.ctx, T.TRACK_BUF_DEPTH, d)
             kw = dict(depth=d)
-        T.track_dbg_set(trk.ctx, T.TRACK_BUF_VERTS, v32)
-        assert T.track_dbg_run(trk.ctx, T.TRACK_PASS_ASSOCIATE) == 0
-        a = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (H * W,), np.int32)
-        a_or = oracle.associate(cam, prm["tau"], v32, **kw)
-        assert (a_or >= 0).sum() > 100
-        np.testing.assert_array_equal(a, a_or)
-        cnt = T.track_dbg_get(trk.ctx, T.TRACK_BUF_COUNT, (m["rest_xyz"].shape[0],), np.int32)
-        delta = T.track_dbg_get(trk.ctx, T.TRACK_BUF_DELTA, (m["rest_xyz"].shape[0], 3), np.float32)
-        c_or, d_or = oracle.average(cam, a_or, v32.astype(np.float64), **kw)
-        np.testing.assert_array_equal(cnt, c_or)
-        assert np.abs(delta - d_or).max() <= 1e-8
+        for what, vs in (("no layout", v32), ("own layout", v32), ("moved surface", moved)):
+            _say(f"  {what}")
+            T.track_dbg_set(trk.ctx, T.TRACK_BUF_VERTS, vs)
+            assert T.track_dbg_run(trk.ctx, T.TRACK_PASS_ASSOCIATE) == 0
+            a = T.track_dbg_get(trk.ctx, T.TRACK_BUF_ASSOC, (H * W,), np.int32)
+            a_or = oracle.associate(cam, prm["tau"], vs, **kw)
+            assert (a_or >= 0).sum() > 100
+            np.testing.assert_array_equal(a, a_or, err_msg=what)
+            cnt = T.track_dbg_get(trk.ctx, T.TRACK_BUF_COUNT, (V,), np.int32)
+            delta = T.track_dbg_get(trk.ctx, T.TRACK_BUF_DELTA, (V, 3), np.float32)
+            c_or, d_or = oracle.average(cam, a_or, vs.astype(np.float64), **kw)
+            np.testing.assert_array_equal(cnt, c_or, err_msg=what)
+            assert np.abs(delta - d_or).max() <= 1e-8, what
+            # the same launch formed the surface's normals
+            nrm = T.track_dbg_get(trk.ctx, T.TRACK_BUF_NORMALS, (V, 3), np.float32)
+            n_or = oracle.normals(m, vs.astype(np.float64))
+            assert np.abs(nrm - n_or).max() <= 1e-5, what
     finally:
         trk.close()
 
