@@ -116,9 +116,10 @@ def _cpu_model():
     return "unknown"
 
 
-def _oracle_rate(w, threads, budget_s, max_frames):
-    """Frames/s of the float64 oracle on the first frames of the sequence
-    (at least two), until the time budget is spent."""
+def _oracle_rate(w, threads, budget_s, max_frames, fp32=False):
+    """Frames/s of the oracle (float64, or its float32 instantiation) on the
+    first frames of the sequence (at least two), until the time budget is
+    spent."""
     import oracle
 
     used = oracle.set_threads(threads)
@@ -129,7 +130,7 @@ def _oracle_rate(w, threads, budget_s, max_frames):
     t0 = time.perf_counter()
     n = 0
     while n < max_frames and (n < 2 or time.perf_counter() - t0 < budget_s):
-        oracle.track_frame(m, w.body.camera, w.params, th, phi, prev, depth=w.frames[n % len(w.frames)])
+        oracle.track_frame(m, w.body.camera, w.params, th, phi, prev, depth=w.frames[n % len(w.frames)], fp32=fp32)
         n += 1
     dt = time.perf_counter() - t0
     return used, n, dt
@@ -138,16 +139,20 @@ def _oracle_rate(w, threads, budget_s, max_frames):
 def cpu_baseline(w, budget_s=12.0, max_frames=30):
     """The oracle (float64 C++, OpenMP over the pixel and vertex loops) on
     the same frames: all of the host's cores available to this process,
-    then one core."""
+    then one core; and its float32 instantiation on all cores."""
     cores = len(os.sched_getaffinity(0))
     used, n, dt = _oracle_rate(w, cores, budget_s, max_frames)
     used1, n1, dt1 = _oracle_rate(w, 1, budget_s, max_frames)
+    used32, n32, dt32 = _oracle_rate(w, cores, budget_s / 2, max_frames, fp32=True)
     return {"value": n / dt, "unit": "frames/s", "cores": used, "kind": "oracle",
             "sample": f"first {n} frames of the same 30-frame sequence, float64 oracle, "
                       f"{used} OpenMP threads, {dt:.1f} s",
             "nproc": os.cpu_count(), "affinity_cores": cores, "cpu_model": _cpu_model(),
             "one_core": {"value": n1 / dt1, "unit": "frames/s", "cores": used1,
-                         "sample": f"first {n1} frames, 1 thread, {dt1:.1f} s"}}
+                         "sample": f"first {n1} frames, 1 thread, {dt1:.1f} s"},
+            "fp32": {"value": n32 / dt32, "unit": "frames/s", "cores": used32,
+                     "sample": f"first {n32} frames, float32 instantiation of the oracle, "
+                               f"{used32} OpenMP threads, {dt32:.1f} s"}}
 
 
 def _gram_params(base, gram):

@@ -7,7 +7,8 @@ this package imports nothing from it.
 Each function mirrors one step of the paper's method (see oracle.hpp for the
 section and equation each follows); all floating point is float64 except the
 association decisions, which are taken in float32 with the operation order
-stated in oracle.hpp.
+stated in oracle.hpp.  track_frame(..., fp32=True) runs a float32
+instantiation of the same source, for the CPU timing baseline only.
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ def build(force: bool = True) -> str:
         subprocess.check_call([
             "g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
             "-fopenmp", "-fPIC", "-shared", os.path.join(_HERE, "capi.cpp"),
-            "-o", tmp])
+            os.path.join(_HERE, "capi32.cpp"), "-o", tmp])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -73,7 +74,7 @@ def lib():
         for name in ("orc_fk", "orc_skin", "orc_normals", "orc_skin_dual", "orc_transform",
                      "orc_associate", "orc_average", "orc_pose_system",
                      "orc_prior_weights", "orc_lm_solve", "orc_shape_step", "orc_shape_step_literal",
-                     "orc_track_frame", "orc_set_threads"):
+                     "orc_track_frame", "orc32_track_frame", "orc_set_threads"):
             getattr(_lib, name).restype = ctypes.c_int
     return _lib
 
@@ -275,12 +276,16 @@ class FrameResult(dict):
     pass
 
 
-def track_frame(model, cam, params, theta, phi, phi_prev, depth=None, xyz=None, assoc=None):
+def track_frame(model, cam, params, theta, phi, phi_prev, depth=None, xyz=None, assoc=None, fp32=False):
     """Run one frame; theta/phi/phi_prev are updated in place (float64).
 
     assoc (test hook): int32 [n_iters, H*W] matches used instead of each
     iteration's own association (another implementation's choice at pixels
     whose candidates tie within rounding).
+
+    fp32: run the float32 instantiation of the same source instead (a timing
+    baseline at the GPU path's precision; its energies and step norm are not
+    reported: NaN, and assoc_first stays -1).
 
     Returns dict(status, n_valid_px, n_assoc_px, n_obs_verts, energy_first,
     energy_last, step_norm_last, energies [n_iters], assoc_first [H*W])."""
@@ -307,8 +312,15 @@ def track_frame(model, cam, params, theta, phi, phi_prev, depth=None, xyz=None, 
     if assoc is not None:
         ai = _c(assoc, np.int32).reshape(-1)
         assert ai.shape[0] == n_it * af.shape[0], "assoc must be [n_iters, H*W]"
-    rc = lib().orc_track_frame(ctypes.byref(m.c), ctypes.byref(c), ctypes.byref(pr), _p(theta),
-                               _p(phi), _p(phi_prev), _p(d), _p(x), _p(si), _p(sd), _p(en), _p(af), _p(ai))
+    if fp32:
+        assert assoc is None, "the float32 instantiation has no association hook"
+        rc = lib().orc32_track_frame(ctypes.byref(m.c), ctypes.byref(c), ctypes.byref(pr), _p(theta),
+                                     _p(phi), _p(phi_prev), _p(d), _p(x), _p(si))
+        sd[:] = np.nan
+        en[:] = np.nan
+    else:
+        rc = lib().orc_track_frame(ctypes.byref(m.c), ctypes.byref(c), ctypes.byref(pr), _p(theta),
+                                   _p(phi), _p(phi_prev), _p(d), _p(x), _p(si), _p(sd), _p(en), _p(af), _p(ai))
     return FrameResult(status=int(rc), n_valid_px=int(si[1]), n_assoc_px=int(si[2]),
                        n_obs_verts=int(si[3]), energy_first=float(sd[0]),
                        energy_last=float(sd[1]), step_norm_last=float(sd[2]),

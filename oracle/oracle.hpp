@@ -9,7 +9,8 @@
 // Every function is a slow, direct transcription of the paper's definitions:
 // loops over joints, vertices and pixels in index order, no blocking, no
 // fusion.  The scalar type S is double for the reference runs and a forward
-// dual number for the derivative pins.  Where the paper is silent or garbled
+// dual number for the derivative pins (`real`, the scalar of the rest, is
+// double too; only the CPU timing baseline builds a float instantiation).  Where the paper is silent or garbled
 // the reading used is stated at the function (the same readings are listed
 // in the design notes of the repository).
 #pragma once
@@ -20,7 +21,17 @@
 #include <vector>
 #include <algorithm>
 
-namespace orc {
+#ifndef ORC_REAL
+#define ORC_REAL double   // the scalar of the reference runs
+#define ORC_NS orc
+#endif
+
+namespace ORC_NS {
+
+// Scalar of the oracle's arithmetic: double for every reference run and pin;
+// a second instantiation in float (namespace orc32) serves only as a timing
+// baseline at the GPU path's precision.
+using real = ORC_REAL;
 
 // ---------------------------------------------------------------------------
 // forward dual number (value + one directional derivative), for pins only
@@ -39,7 +50,7 @@ inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
 inline Dual sin(Dual a) { return {std::sin(a.v), a.d * std::cos(a.v)}; }
 inline Dual cos(Dual a) { return {std::cos(a.v), -a.d * std::sin(a.v)}; }
 inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return {s, a.d / (2.0 * s)}; }
-inline double val(double a) { return a; }
+template <class T> inline T val(T a) { return a; }
 inline double val(Dual a) { return a.v; }
 using std::sin; using std::cos; using std::sqrt;
 
@@ -76,27 +87,27 @@ template <class S> DQ<S> dq_add(const DQ<S>& a, const DQ<S>& b) { return {qadd(a
 template <class S> DQ<S> dq_scale(const DQ<S>& a, S s) { return {qscale(a.r, s), qscale(a.d, s)}; }
 
 // Eq. (1): hinge, rotation by theta about unit axis z.
-template <class S> DQ<S> dq_hinge(S th, const double z[3]) {
+template <class S> DQ<S> dq_hinge(S th, const real z[3]) {
     S c = cos(th * S(0.5)), s = sin(th * S(0.5));
     return {{c, s * S(z[0]), s * S(z[1]), s * S(z[2])}, {S(0), S(0), S(0), S(0)}};
 }
 // Eq. (2): prismatic, translation by theta along unit axis z.
-template <class S> DQ<S> dq_prismatic(S th, const double z[3]) {
+template <class S> DQ<S> dq_prismatic(S th, const real z[3]) {
     S h = th * S(0.5);
     return {{S(1), S(0), S(0), S(0)}, {S(0), h * S(z[0]), h * S(z[1]), h * S(z[2])}};
 }
 // Derivatives of Eq. (1) and (2) with respect to theta (Section 4.2).
-template <class S> DQ<S> dq_hinge_dtheta(S th, const double z[3]) {
+template <class S> DQ<S> dq_hinge_dtheta(S th, const real z[3]) {
     S c = cos(th * S(0.5)) * S(0.5), s = sin(th * S(0.5)) * S(0.5);
     return {{-s, c * S(z[0]), c * S(z[1]), c * S(z[2])}, {S(0), S(0), S(0), S(0)}};
 }
-template <class S> DQ<S> dq_prismatic_dtheta(const double z[3]) {
-    return {{S(0), S(0), S(0), S(0)}, {S(0), S(0.5 * z[0]), S(0.5 * z[1]), S(0.5 * z[2])}};
+template <class S> DQ<S> dq_prismatic_dtheta(const real z[3]) {
+    return {{S(0), S(0), S(0), S(0)}, {S(0), S(real(0.5) * z[0]), S(real(0.5) * z[1]), S(real(0.5) * z[2])}};
 }
 // Rigid transform x -> R(q) x + t as a dual quaternion: (q, 1/2 t q).
-template <class S> DQ<S> dq_from_rt(const double q[4], const double t[3]) {
+template <class S> DQ<S> dq_from_rt(const real q[4], const real t[3]) {
     Quat<S> r{S(q[0]), S(q[1]), S(q[2]), S(q[3])};
-    Quat<S> tq{S(0), S(0.5 * t[0]), S(0.5 * t[1]), S(0.5 * t[2])};
+    Quat<S> tq{S(0), S(real(0.5) * t[0]), S(real(0.5) * t[1]), S(real(0.5) * t[2])};
     return {r, qmul(tq, r)};
 }
 
@@ -164,7 +175,7 @@ struct Model {
     int P = 0, L = 0, V = 0, F = 0, K = 0;
     int blend = BLEND_DQ;   // how a vertex's links are combined (see skin)
     std::vector<int> parent, type, link_joint, faces, skin_link, nbr;
-    std::vector<double> axis, offq, offt, rest, skin_w;
+    std::vector<real> axis, offq, offt, rest, skin_w;
     // derived
     std::vector<std::vector<char>> anc;  // anc[l][k]: joint k on the chain of link l
 };
@@ -175,7 +186,7 @@ struct Params {
     float tau = 0.05f;
     int n_iters = 1;
     std::vector<uint8_t> do_pose, do_shape, active;
-    double lambda_k = 0.01, lambda_s = 0.0, lambda_phi = 0.01, lambda_nbr = 1.0,
+    real lambda_k = 0.01, lambda_s = 0.0, lambda_phi = 0.01, lambda_nbr = 1.0,
            lambda_t = 0.0, lambda_w = 0.1;
 };
 
@@ -219,14 +230,14 @@ template <class S> std::vector<DQ<S>> bind_pose(const Model& m) {
 
 // Sign of each influence relative to the largest-weight influence (ties: the
 // lower link index), so the blend stays on one hemisphere of the quaternion
-// double cover.  The paper does not state this; it is Kavan et al.'s rule for
+// real cover.  The paper does not state this; it is Kavan et al.'s rule for
 // dual-quaternion blending.
 template <class S> void blend_signs(const Model& m, const std::vector<DQ<S>>& D, int i, S sgn[4]) {
     int piv = -1;
-    double wbest = -1.0;
+    real wbest = -1.0;
     for (int k = 0; k < m.K; ++k) {
         int l = m.skin_link[i * m.K + k];
-        double w = m.skin_w[i * m.K + k];
+        real w = m.skin_w[i * m.K + k];
         if (l < 0) continue;
         if (w > wbest || (w == wbest && l < m.skin_link[i * m.K + piv])) { wbest = w; piv = k; }
     }
@@ -235,7 +246,7 @@ template <class S> void blend_signs(const Model& m, const std::vector<DQ<S>>& D,
         sgn[k] = S(1);
         if (l < 0 || piv < 0) continue;
         S d = qdot(D[l].r, D[m.skin_link[i * m.K + piv]].r);
-        if (val(d) < 0.0) sgn[k] = S(-1);
+        if (val(d) < real(0)) sgn[k] = S(-1);
     }
 }
 
@@ -278,13 +289,13 @@ template <class S> void skin(const Model& m, const std::vector<DQ<S>>& D, const 
 
 // d v_i / d x_i: the rotation of the blend (dual quaternions), or the
 // weighted sum of the links' rotations (linear variant).
-inline void point_jacobian(const Model& m, const std::vector<DQ<double>>& D, int i, double R[9]) {
+inline void point_jacobian(const Model& m, const std::vector<DQ<real>>& D, int i, real R[9]) {
     if (m.blend == BLEND_LINEAR) {
         std::fill(R, R + 9, 0.0);
         for (int k = 0; k < m.K; ++k) {
             int l = m.skin_link[i * m.K + k];
             if (l < 0) continue;
-            double Rl[9];
+            real Rl[9];
             quat_rotation(D[l].r, Rl);
             for (int q = 0; q < 9; ++q) R[q] += m.skin_w[i * m.K + k] * Rl[q];
         }
@@ -297,18 +308,18 @@ inline void point_jacobian(const Model& m, const std::vector<DQ<double>>& D, int
 // the vertex normal without defining it): sum over incident faces (a,b,c), in
 // face order, of (v_b - v_a) x (v_c - v_a) -- each face weighted by twice its
 // area -- normalised; zero if the sum is zero.
-inline void vertex_normals(const Model& m, const double* v, double* n) {
+inline void vertex_normals(const Model& m, const real* v, real* n) {
     std::fill(n, n + 3 * m.V, 0.0);
     for (int f = 0; f < m.F; ++f) {
         int a = m.faces[3 * f], b = m.faces[3 * f + 1], c = m.faces[3 * f + 2];
-        double e1[3], e2[3];
+        real e1[3], e2[3];
         for (int d = 0; d < 3; ++d) { e1[d] = v[3 * b + d] - v[3 * a + d]; e2[d] = v[3 * c + d] - v[3 * a + d]; }
-        double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+        real cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
         for (int d = 0; d < 3; ++d) { n[3 * a + d] += cr[d]; n[3 * b + d] += cr[d]; n[3 * c + d] += cr[d]; }
     }
     for (int i = 0; i < m.V; ++i) {
-        double l = std::sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
-        for (int d = 0; d < 3; ++d) n[3 * i + d] = l > 0.0 ? n[3 * i + d] / l : 0.0;
+        real l = std::sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
+        for (int d = 0; d < 3; ++d) n[3 * i + d] = l > real(0) ? n[3 * i + d] / l : real(0);
     }
 }
 
@@ -377,10 +388,10 @@ inline void associate_brute(const Camera& c, float tau, const float* v, int V, c
 inline void associate_grid(const Camera& c, float tau, const float* v, int V, const float* depth,
                            const float* xyz, int32_t* a) {
     const float t2 = tau * tau;
-    double cell = (double)tau * 1.001;
+    real cell = (real)tau * real(1.001);
     struct Item { int64_t key; int i; };
     std::vector<Item> items;
-    auto cellof = [&](double x) { return (int64_t)std::floor(x / cell); };
+    auto cellof = [&](real x) { return (int64_t)std::floor(x / cell); };
     auto keyof = [](int64_t x, int64_t y, int64_t z) {
         return ((x + (1 << 20)) << 42) | ((y + (1 << 20)) << 21) | (z + (1 << 20));
     };
@@ -420,7 +431,7 @@ inline void associate_grid(const Camera& c, float tau, const float* v, int V, co
 // Section 4.1 (averaging): c_i = number of points whose closest vertex is i,
 // delta_i = (1/c_i) sum_k (p_k - v_i), summed in ascending pixel order.
 inline void average_offsets(const Camera& c, const float* depth, const float* xyz, const int32_t* a,
-                            const double* v, int V, int32_t* cnt, double* delta) {
+                            const real* v, int V, int32_t* cnt, real* delta) {
     std::fill(cnt, cnt + V, 0);
     std::fill(delta, delta + 3 * V, 0.0);
     for (int k = 0; k < c.W * c.H; ++k) {
@@ -429,11 +440,11 @@ inline void average_offsets(const Camera& c, const float* depth, const float* xy
         float p[3];
         point_of_pixel(c, depth, xyz, k, p);
         cnt[i] += 1;
-        for (int d = 0; d < 3; ++d) delta[3 * i + d] += (double)p[d] - v[3 * i + d];
+        for (int d = 0; d < 3; ++d) delta[3 * i + d] += (real)p[d] - v[3 * i + d];
     }
     for (int i = 0; i < V; ++i)
         if (cnt[i] > 0)
-            for (int d = 0; d < 3; ++d) delta[3 * i + d] /= (double)cnt[i];
+            for (int d = 0; d < 3; ++d) delta[3 * i + d] /= (real)cnt[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -444,32 +455,32 @@ inline void average_offsets(const Camera& c, const float* depth, const float* xy
 // with H_{k,l} = H_{0,k}^{-1} H_{0,l}.  (The printed block ends in H_{j,Delta};
 // the trailing factor must be the inverse bind pose for the product to be the
 // derivative of H_{0,l} (H^0_{0,l})^{-1}.)
-inline DQ<double> delta_derivative(const Model& m, const std::vector<DQ<double>>& H,
-                                   const std::vector<DQ<double>>& H0, const double* theta, int k, int l) {
+inline DQ<real> delta_derivative(const Model& m, const std::vector<DQ<real>>& H,
+                                   const std::vector<DQ<real>>& H0, const real* theta, int k, int l) {
     int jl = m.link_joint[l];
-    DQ<double> base = m.parent[k] < 0 ? dq_identity<double>() : H[m.parent[k]];
-    DQ<double> off = dq_from_rt<double>(&m.offq[4 * k], &m.offt[3 * k]);
-    DQ<double> dHk = m.type[k] == HINGE ? dq_hinge_dtheta<double>(theta[k], &m.axis[3 * k])
-                                        : dq_prismatic_dtheta<double>(&m.axis[3 * k]);
-    DQ<double> Hkl = dq_mul(dq_inv_unit(H[k]), H[jl]);
+    DQ<real> base = m.parent[k] < 0 ? dq_identity<real>() : H[m.parent[k]];
+    DQ<real> off = dq_from_rt<real>(&m.offq[4 * k], &m.offt[3 * k]);
+    DQ<real> dHk = m.type[k] == HINGE ? dq_hinge_dtheta<real>(theta[k], &m.axis[3 * k])
+                                        : dq_prismatic_dtheta<real>(&m.axis[3 * k]);
+    DQ<real> Hkl = dq_mul(dq_inv_unit(H[k]), H[jl]);
     return dq_mul(dq_mul(dq_mul(dq_mul(base, off), dHk), Hkl), dq_inv_unit(H0[jl]));
 }
 
 struct PoseSystem {
-    std::vector<double> J;   // [V*P], zero rows for vertices outside O
-    std::vector<double> r;   // [V]
+    std::vector<real> J;   // [V*P], zero rows for vertices outside O
+    std::vector<real> r;   // [V]
     std::vector<char> obs;   // [V] membership of O
-    std::vector<double> A;   // [P*P] J^T J (+ prior)
-    std::vector<double> b;   // [P]   J^T r (+ prior)
-    double rr = 0.0;         // r^T r
+    std::vector<real> A;   // [P*P] J^T J (+ prior)
+    std::vector<real> b;   // [P]   J^T r (+ prior)
+    real rr = 0.0;         // r^T r
 };
 
 // Default-pose prior weights S_kk: the number of vertices with a non-zero
 // weight on a link whose chain contains joint k, divided by |V|; zero for the
 // joints carrying the root link (a prior pulling the body toward the camera
 // origin has no meaning).
-inline std::vector<double> prior_weights(const Model& m) {
-    std::vector<double> Sk(m.P, 0.0);
+inline std::vector<real> prior_weights(const Model& m) {
+    std::vector<real> Sk(m.P, 0.0);
     for (int k = 0; k < m.P; ++k) {
         if (m.anc[0][k]) continue;
         int cnt = 0;
@@ -477,11 +488,11 @@ inline std::vector<double> prior_weights(const Model& m) {
             bool hit = false;
             for (int q = 0; q < m.K; ++q) {
                 int l = m.skin_link[i * m.K + q];
-                if (l >= 0 && m.skin_w[i * m.K + q] > 0.0 && m.anc[l][k]) hit = true;
+                if (l >= 0 && m.skin_w[i * m.K + q] > real(0) && m.anc[l][k]) hit = true;
             }
             cnt += hit ? 1 : 0;
         }
-        Sk[k] = (double)cnt / (double)m.V;
+        Sk[k] = (real)cnt / (real)m.V;
     }
     return Sk;
 }
@@ -489,43 +500,43 @@ inline std::vector<double> prior_weights(const Model& m) {
 // Eq. (6)-(8) with the prior: r_i = n_i^T delta_i for i in O = {c_i >= 1,
 // |n_i| > 0}; J_i = -n_i^T dv_i/dTheta through dv/dH_Sigma, dH_Sigma/dH_Delta
 // (the weight times the identity, with the blend sign) and dH_Delta/dTheta.
-inline PoseSystem pose_system(const Model& m, const double* theta, const double* phi, const double* n,
-                              const double* delta, const int32_t* cnt, double lambda_s) {
+inline PoseSystem pose_system(const Model& m, const real* theta, const real* phi, const real* n,
+                              const real* delta, const int32_t* cnt, real lambda_s) {
     PoseSystem ps;
     ps.J.assign((size_t)m.V * m.P, 0.0);
     ps.r.assign(m.V, 0.0);
     ps.obs.assign(m.V, 0);
     ps.A.assign((size_t)m.P * m.P, 0.0);
     ps.b.assign(m.P, 0.0);
-    auto H = forward_kinematics<double>(m, theta);
-    auto H0 = bind_pose<double>(m);
+    auto H = forward_kinematics<real>(m, theta);
+    auto H0 = bind_pose<real>(m);
     auto D = link_deltas(m, H, H0);
     // dH_Delta/dtheta blocks per (link, joint)
-    std::vector<DQ<double>> dD((size_t)m.L * m.P);
+    std::vector<DQ<real>> dD((size_t)m.L * m.P);
     for (int l = 0; l < m.L; ++l)
         for (int k = 0; k < m.P; ++k)
             if (m.anc[l][k]) dD[(size_t)l * m.P + k] = delta_derivative(m, H, H0, theta, k, l);
     for (int i = 0; i < m.V; ++i) {
-        double nl = n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2];
-        if (cnt[i] < 1 || nl == 0.0) continue;
+        real nl = n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2];
+        if (cnt[i] < 1 || nl == real(0)) continue;
         ps.obs[i] = 1;
         ps.r[i] = n[3 * i] * delta[3 * i] + n[3 * i + 1] * delta[3 * i + 1] + n[3 * i + 2] * delta[3 * i + 2];
-        double x[3] = {m.rest[3 * i] + phi[3 * i], m.rest[3 * i + 1] + phi[3 * i + 1], m.rest[3 * i + 2] + phi[3 * i + 2]};
+        real x[3] = {m.rest[3 * i] + phi[3 * i], m.rest[3 * i + 1] + phi[3 * i + 1], m.rest[3 * i + 2] + phi[3 * i + 2]};
         if (m.blend == BLEND_LINEAR) {
             // each influence through its own rigid transform: dv = sum_m w_m dT/dH(H_m, x) dH_m
-            double Jm[4][3][8];
+            real Jm[4][3][8];
             for (int q = 0; q < m.K; ++q) {
                 int l = m.skin_link[i * m.K + q];
                 if (l >= 0) dq_transform_jacobian(D[l], x, Jm[q]);
             }
             for (int k = 0; k < m.P; ++k) {
-                double dv[3] = {0, 0, 0};
+                real dv[3] = {0, 0, 0};
                 for (int q = 0; q < m.K; ++q) {
                     int l = m.skin_link[i * m.K + q];
                     if (l < 0 || !m.anc[l][k]) continue;
-                    const DQ<double>& g = dD[(size_t)l * m.P + k];
-                    const double comp[8] = {g.r.w, g.r.x, g.r.y, g.r.z, g.d.w, g.d.x, g.d.y, g.d.z};
-                    const double w = m.skin_w[i * m.K + q];
+                    const DQ<real>& g = dD[(size_t)l * m.P + k];
+                    const real comp[8] = {g.r.w, g.r.x, g.r.y, g.r.z, g.d.w, g.d.x, g.d.y, g.d.z};
+                    const real w = m.skin_w[i * m.K + q];
                     for (int d = 0; d < 3; ++d)
                         for (int c = 0; c < 8; ++c) dv[d] += w * Jm[q][d][c] * comp[c];
                 }
@@ -533,22 +544,22 @@ inline PoseSystem pose_system(const Model& m, const double* theta, const double*
             }
             continue;
         }
-        DQ<double> Hs = blend(m, D, i);
-        double Jt[3][8];
+        DQ<real> Hs = blend(m, D, i);
+        real Jt[3][8];
         dq_transform_jacobian(Hs, x, Jt);
-        double sgn[4];
+        real sgn[4];
         blend_signs(m, D, i, sgn);
         for (int k = 0; k < m.P; ++k) {
-            double dH[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            real dH[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int q = 0; q < m.K; ++q) {
                 int l = m.skin_link[i * m.K + q];
                 if (l < 0 || !m.anc[l][k]) continue;
-                const DQ<double>& g = dD[(size_t)l * m.P + k];
-                double w = m.skin_w[i * m.K + q] * sgn[q];
-                const double comp[8] = {g.r.w, g.r.x, g.r.y, g.r.z, g.d.w, g.d.x, g.d.y, g.d.z};
+                const DQ<real>& g = dD[(size_t)l * m.P + k];
+                real w = m.skin_w[i * m.K + q] * sgn[q];
+                const real comp[8] = {g.r.w, g.r.x, g.r.y, g.r.z, g.d.w, g.d.x, g.d.y, g.d.z};
                 for (int c = 0; c < 8; ++c) dH[c] += w * comp[c];
             }
-            double dv[3] = {0, 0, 0};
+            real dv[3] = {0, 0, 0};
             for (int d = 0; d < 3; ++d)
                 for (int c = 0; c < 8; ++c) dv[d] += Jt[d][c] * dH[c];
             ps.J[(size_t)i * m.P + k] = -(n[3 * i] * dv[0] + n[3 * i + 1] * dv[1] + n[3 * i + 2] * dv[2]);
@@ -557,7 +568,7 @@ inline PoseSystem pose_system(const Model& m, const double* theta, const double*
     // Eq. (7), (8): sums over the observed vertices in index order.
     for (int i = 0; i < m.V; ++i) {
         if (!ps.obs[i]) continue;
-        const double* Ji = &ps.J[(size_t)i * m.P];
+        const real* Ji = &ps.J[(size_t)i * m.P];
         for (int k = 0; k < m.P; ++k) {
             ps.b[k] += Ji[k] * ps.r[i];
             for (int q = 0; q < m.P; ++q) ps.A[(size_t)k * m.P + q] += Ji[k] * Ji[q];
@@ -565,10 +576,10 @@ inline PoseSystem pose_system(const Model& m, const double* theta, const double*
         ps.rr += ps.r[i] * ps.r[i];
     }
     // default pose prior: A += (lambda_s S)^2, b += (lambda_s S)^2 Theta
-    if (lambda_s != 0.0) {
+    if (lambda_s != real(0)) {
         auto Sk = prior_weights(m);
         for (int k = 0; k < m.P; ++k) {
-            double w = (lambda_s * Sk[k]) * (lambda_s * Sk[k]);
+            real w = (lambda_s * Sk[k]) * (lambda_s * Sk[k]);
             ps.A[(size_t)k * m.P + k] += w;
             ps.b[k] += w * theta[k];
         }
@@ -579,36 +590,36 @@ inline PoseSystem pose_system(const Model& m, const double* theta, const double*
 // Damped least squares (Marquardt): (A + lambda_k diag(A)) x = b by Cholesky.
 // Parameters with A_kk == 0 exactly (nothing observed moves them) or masked
 // inactive are frozen: x_k = 0.  Returns 0, or -4 if the factorisation fails.
-inline int lm_solve(int P, const double* A, const double* b, double lambda_k, const uint8_t* active, double* x) {
+inline int lm_solve(int P, const real* A, const real* b, real lambda_k, const uint8_t* active, real* x) {
     std::vector<char> frozen(P, 0);
-    for (int k = 0; k < P; ++k) frozen[k] = (A[(size_t)k * P + k] == 0.0) || (active && !active[k]);
-    std::vector<double> M((size_t)P * P, 0.0), y(P, 0.0);
+    for (int k = 0; k < P; ++k) frozen[k] = (A[(size_t)k * P + k] == real(0)) || (active && !active[k]);
+    std::vector<real> M((size_t)P * P, 0.0), y(P, 0.0);
     for (int k = 0; k < P; ++k) {
         for (int q = 0; q < P; ++q)
-            M[(size_t)k * P + q] = (frozen[k] || frozen[q]) ? 0.0 : A[(size_t)k * P + q];
-        M[(size_t)k * P + k] = frozen[k] ? 1.0 : A[(size_t)k * P + k] * (1.0 + lambda_k);
-        y[k] = frozen[k] ? 0.0 : b[k];
+            M[(size_t)k * P + q] = (frozen[k] || frozen[q]) ? real(0) : A[(size_t)k * P + q];
+        M[(size_t)k * P + k] = frozen[k] ? real(1) : A[(size_t)k * P + k] * (real(1) + lambda_k);
+        y[k] = frozen[k] ? real(0) : b[k];
     }
     // Cholesky M = L L^T (lower triangle stored in place)
     for (int j = 0; j < P; ++j) {
-        double s = M[(size_t)j * P + j];
+        real s = M[(size_t)j * P + j];
         for (int q = 0; q < j; ++q) s -= M[(size_t)j * P + q] * M[(size_t)j * P + q];
-        if (!(s > 0.0)) return -4;
-        double d = std::sqrt(s);
+        if (!(s > real(0))) return -4;
+        real d = std::sqrt(s);
         M[(size_t)j * P + j] = d;
         for (int i = j + 1; i < P; ++i) {
-            double t = M[(size_t)i * P + j];
+            real t = M[(size_t)i * P + j];
             for (int q = 0; q < j; ++q) t -= M[(size_t)i * P + q] * M[(size_t)j * P + q];
             M[(size_t)i * P + j] = t / d;
         }
     }
     for (int i = 0; i < P; ++i) {
-        double t = y[i];
+        real t = y[i];
         for (int q = 0; q < i; ++q) t -= M[(size_t)i * P + q] * x[q];
         x[i] = t / M[(size_t)i * P + i];
     }
     for (int i = P - 1; i >= 0; --i) {
-        double t = x[i];
+        real t = x[i];
         for (int q = i + 1; q < P; ++q) t -= M[(size_t)q * P + i] * x[q];
         x[i] = t / M[(size_t)i * P + i];
     }
@@ -627,39 +638,39 @@ inline int lm_solve(int P, const double* A, const double* b, double lambda_k, co
 // approximation), and all vertices update together.  dr_i/dphi_i = -R_i^T n_i
 // with R_i the rotation of H_{i,Sigma}; unobserved vertices have no data term.
 struct ShapeArgs {
-    const double *theta, *phi, *phi_prev, *n, *delta;
+    const real *theta, *phi, *phi_prev, *n, *delta;
     const int32_t* cnt;
-    double lambda_phi, lambda_nbr, lambda_t, lambda_w;
+    real lambda_phi, lambda_nbr, lambda_t, lambda_w;
 };
 
 // Solve the 3x3 system M x = g by Cramer's rule.
-inline bool solve3(const double M[9], const double g[3], double x[3]) {
-    double c00 = M[4] * M[8] - M[5] * M[7], c01 = M[5] * M[6] - M[3] * M[8], c02 = M[3] * M[7] - M[4] * M[6];
-    double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
-    if (!(std::fabs(det) > 0.0)) return false;
-    double inv[9] = {c00, M[2] * M[7] - M[1] * M[8], M[1] * M[5] - M[2] * M[4],
+inline bool solve3(const real M[9], const real g[3], real x[3]) {
+    real c00 = M[4] * M[8] - M[5] * M[7], c01 = M[5] * M[6] - M[3] * M[8], c02 = M[3] * M[7] - M[4] * M[6];
+    real det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    if (!(std::fabs(det) > real(0))) return false;
+    real inv[9] = {c00, M[2] * M[7] - M[1] * M[8], M[1] * M[5] - M[2] * M[4],
                      c01, M[0] * M[8] - M[2] * M[6], M[2] * M[3] - M[0] * M[5],
                      c02, M[1] * M[6] - M[0] * M[7], M[0] * M[4] - M[1] * M[3]};
     for (int r = 0; r < 3; ++r) x[r] = (inv[3 * r] * g[0] + inv[3 * r + 1] * g[1] + inv[3 * r + 2] * g[2]) / det;
     return true;
 }
 
-inline void shape_step(const Model& m, const ShapeArgs& s, double* phi_out) {
-    auto H = forward_kinematics<double>(m, s.theta);
-    auto H0 = bind_pose<double>(m);
+inline void shape_step(const Model& m, const ShapeArgs& s, real* phi_out) {
+    auto H = forward_kinematics<real>(m, s.theta);
+    auto H0 = bind_pose<real>(m);
     auto D = link_deltas(m, H, H0);
     for (int i = 0; i < m.V; ++i) {
-        const double* ni = &s.n[3 * i];
-        double nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
-        double u[3] = {0, 0, 0}, r = 0.0;
-        if (s.cnt[i] >= 1 && nl > 0.0) {
-            double R[9];
+        const real* ni = &s.n[3 * i];
+        real nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
+        real u[3] = {0, 0, 0}, r = 0.0;
+        if (s.cnt[i] >= 1 && nl > real(0)) {
+            real R[9];
             point_jacobian(m, D, i, R);
             for (int c = 0; c < 3; ++c) u[c] = -(R[c] * ni[0] + R[3 + c] * ni[1] + R[6 + c] * ni[2]);
             r = ni[0] * s.delta[3 * i] + ni[1] * s.delta[3 * i + 1] + ni[2] * s.delta[3 * i + 2];
         }
-        const double* ph = &s.phi[3 * i];
-        double g[3], alpha = s.lambda_phi + s.lambda_t;
+        const real* ph = &s.phi[3 * i];
+        real g[3], alpha = s.lambda_phi + s.lambda_t;
         for (int c = 0; c < 3; ++c) g[c] = u[c] * r + s.lambda_phi * ph[c] + s.lambda_t * (ph[c] - s.phi_prev[3 * i + c]);
         for (int q = 0; q < 4; ++q) {
             int j = m.nbr[4 * i + q];
@@ -667,11 +678,11 @@ inline void shape_step(const Model& m, const ShapeArgs& s, double* phi_out) {
             alpha += s.lambda_nbr;
             for (int c = 0; c < 3; ++c) g[c] += s.lambda_nbr * (ph[c] - s.phi[3 * j + c]);
         }
-        double M[9];
+        real M[9];
         for (int a = 0; a < 3; ++a)
-            for (int b = 0; b < 3; ++b) M[3 * a + b] = u[a] * u[b] + (a == b ? alpha : 0.0);
-        for (int a = 0; a < 3; ++a) M[4 * a] *= (1.0 + s.lambda_w);
-        double x[3] = {0, 0, 0};
+            for (int b = 0; b < 3; ++b) M[3 * a + b] = u[a] * u[b] + (a == b ? alpha : real(0));
+        for (int a = 0; a < 3; ++a) M[4 * a] *= (real(1) + s.lambda_w);
+        real x[3] = {0, 0, 0};
         if (!solve3(M, g, x)) x[0] = x[1] = x[2] = 0.0;
         for (int c = 0; c < 3; ++c) phi_out[3 * i + c] = ph[c] - x[c];
     }
@@ -686,41 +697,41 @@ inline void shape_step(const Model& m, const ShapeArgs& s, double* phi_out) {
 // solution x_k = r^_i / ((m + lam_w) j_k) (m = non-zero entries of j) grows
 // without bound as any entry of j goes to zero.  A singular system (some
 // j_k exactly zero) takes no step, as in the reading's solver.
-inline void shape_step_literal(const Model& m, const ShapeArgs& s, double* phi_out) {
-    auto H = forward_kinematics<double>(m, s.theta);
-    auto H0 = bind_pose<double>(m);
+inline void shape_step_literal(const Model& m, const ShapeArgs& s, real* phi_out) {
+    auto H = forward_kinematics<real>(m, s.theta);
+    auto H0 = bind_pose<real>(m);
     auto D = link_deltas(m, H, H0);
     for (int i = 0; i < m.V; ++i) {
-        const double* ni = &s.n[3 * i];
-        const double* ph = &s.phi[3 * i];
-        double nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
-        double j[3] = {0, 0, 0}, r = 0.0;
-        if (s.cnt[i] >= 1 && nl > 0.0) {
-            double R[9];
+        const real* ni = &s.n[3 * i];
+        const real* ph = &s.phi[3 * i];
+        real nl = ni[0] * ni[0] + ni[1] * ni[1] + ni[2] * ni[2];
+        real j[3] = {0, 0, 0}, r = 0.0;
+        if (s.cnt[i] >= 1 && nl > real(0)) {
+            real R[9];
             point_jacobian(m, D, i, R);
             for (int c = 0; c < 3; ++c) j[c] = -(R[c] * ni[0] + R[3 + c] * ni[1] + R[6 + c] * ni[2]);
             r = ni[0] * s.delta[3 * i] + ni[1] * s.delta[3 * i + 1] + ni[2] * s.delta[3 * i + 2];
         }
-        double rh = r + s.lambda_phi * (ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2]);
-        for (int c = 0; c < 3; ++c) j[c] += 2.0 * s.lambda_phi * ph[c];
+        real rh = r + s.lambda_phi * (ph[0] * ph[0] + ph[1] * ph[1] + ph[2] * ph[2]);
+        for (int c = 0; c < 3; ++c) j[c] += real(2) * s.lambda_phi * ph[c];
         for (int q = 0; q < 4; ++q) {
             int k = m.nbr[4 * i + q];
             if (k < 0) continue;
-            double d2 = 0.0;
+            real d2 = 0.0;
             for (int c = 0; c < 3; ++c) {
-                double d = ph[c] - s.phi[3 * k + c];
+                real d = ph[c] - s.phi[3 * k + c];
                 d2 += d * d;
-                j[c] += 2.0 * s.lambda_nbr * d;
+                j[c] += real(2) * s.lambda_nbr * d;
             }
             rh += s.lambda_nbr * d2;
         }
-        double M[9], g[3];
+        real M[9], g[3];
         for (int a = 0; a < 3; ++a) {
             for (int b = 0; b < 3; ++b) M[3 * a + b] = j[a] * j[b];
-            M[4 * a] *= (1.0 + s.lambda_w);
+            M[4 * a] *= (real(1) + s.lambda_w);
             g[a] = j[a] * rh;
         }
-        double x[3] = {0, 0, 0};
+        real x[3] = {0, 0, 0};
         if (!solve3(M, g, x)) x[0] = x[1] = x[2] = 0.0;
         for (int c = 0; c < 3; ++c) phi_out[3 * i + c] = ph[c] - x[c];
     }
@@ -732,17 +743,17 @@ inline void shape_step_literal(const Model& m, const ShapeArgs& s, double* phi_o
 // ---------------------------------------------------------------------------
 struct FrameStats {
     int32_t status, n_valid_px, n_assoc_px, n_obs_verts;
-    double energy_first, energy_last, step_norm_last;
+    real energy_first, energy_last, step_norm_last;
 };
 
-struct SkinState { std::vector<double> v, n; };
+struct SkinState { std::vector<real> v, n; };
 
-inline SkinState skin_state(const Model& m, const double* theta, const double* phi) {
+inline SkinState skin_state(const Model& m, const real* theta, const real* phi) {
     SkinState s;
     s.v.resize(3 * m.V);
     s.n.resize(3 * m.V);
-    auto H = forward_kinematics<double>(m, theta);
-    auto H0 = bind_pose<double>(m);
+    auto H = forward_kinematics<real>(m, theta);
+    auto H0 = bind_pose<real>(m);
     auto D = link_deltas(m, H, H0);
     skin(m, D, phi, s.v.data());
     vertex_normals(m, s.v.data(), s.n.data());
@@ -752,12 +763,12 @@ inline SkinState skin_state(const Model& m, const double* theta, const double* p
 // assoc_in (test hook, may be null): [n_iters * W * H] matches to use in
 // place of each iteration's own association, e.g. another implementation's
 // choice at pixels whose nearest vertices tie within rounding.
-inline int track_frame(const Model& m, const Camera& cam, const Params& prm, double* theta, double* phi,
-                       double* phi_prev, const float* depth, const float* xyz, FrameStats* st,
-                       double* energies, int32_t* assoc_out, const int32_t* assoc_in = nullptr) {
+inline int track_frame(const Model& m, const Camera& cam, const Params& prm, real* theta, real* phi,
+                       real* phi_prev, const float* depth, const float* xyz, FrameStats* st,
+                       real* energies, int32_t* assoc_out, const int32_t* assoc_in = nullptr) {
     const int NP = cam.W * cam.H;
     std::vector<int32_t> a(NP), cnt(m.V);
-    std::vector<double> delta(3 * m.V);
+    std::vector<real> delta(3 * m.V);
     std::vector<float> vf(3 * m.V);
     int n_valid = 0;
     for (int k = 0; k < NP; ++k) { float p[3]; n_valid += point_of_pixel(cam, depth, xyz, k, p) ? 1 : 0; }
@@ -780,11 +791,11 @@ inline int track_frame(const Model& m, const Camera& cam, const Params& prm, dou
             if (first) { s.energy_first = ps.rr; first = false; }
             s.energy_last = ps.rr;
             if (energies) energies[t] = ps.rr;
-            std::vector<double> x(m.P, 0.0);
+            std::vector<real> x(m.P, 0.0);
             int rc = lm_solve(m.P, ps.A.data(), ps.b.data(), prm.lambda_k,
                               prm.active.empty() ? nullptr : prm.active.data(), x.data());
             if (rc != 0) { s.status = rc; if (st) *st = s; return rc; }
-            double nrm = 0.0;
+            real nrm = 0.0;
             for (int k = 0; k < m.P; ++k) { theta[k] -= x[k]; nrm += x[k] * x[k]; }
             s.step_norm_last = std::sqrt(nrm);
             SkinState s2 = skin_state(m, theta, phi);
@@ -794,7 +805,7 @@ inline int track_frame(const Model& m, const Camera& cam, const Params& prm, dou
             ss = std::move(s2);
         }
         if (prm.do_shape[t]) {
-            std::vector<double> out(3 * m.V);
+            std::vector<real> out(3 * m.V);
             ShapeArgs sa{theta, phi, phi_prev, ss.n.data(), delta.data(), cnt.data(),
                          prm.lambda_phi, prm.lambda_nbr, prm.lambda_t, prm.lambda_w};
             shape_step(m, sa, out.data());
@@ -806,4 +817,4 @@ inline int track_frame(const Model& m, const Camera& cam, const Params& prm, dou
     return 0;
 }
 
-}  // namespace orc
+}  // namespace ORC_NS

@@ -974,3 +974,25 @@ def test_linear_and_dq_blends_agree_on_rigid_vertices(small_body, rng):
     b, _ = oracle.skin(dict(m, blend=1), th)
     np.testing.assert_allclose(a, b, atol=1e-13)
 
+
+
+def test_float32_instantiation_tracks_like_float64(tiny):
+    """The float32 build of the same source (a CPU timing baseline at the
+    GPU path's precision) follows the float64 frame on the tiny arm: same
+    matches and status, joint angles within 1e-4 rad, offsets within 1e-6 m
+    (float32 rounding through ten iterations)."""
+    m, cam, prm = tiny.body.model, tiny.body.camera, tiny.params
+    V = m["rest_xyz"].shape[0]
+    out = []
+    for fp32 in (False, True):
+        th = tiny.theta0.copy()
+        phi, prev = np.zeros((V, 3)), np.zeros((V, 3))
+        r = oracle.track_frame(m, cam, prm, th, phi, prev, depth=tiny.frames[0], fp32=fp32)
+        out.append((r, th, phi))
+    (r64, th64, phi64), (r32, th32, phi32) = out
+    assert r64["status"] == 0 and r32["status"] == 0
+    assert r32["n_valid_px"] == r64["n_valid_px"]
+    assert abs(r32["n_assoc_px"] - r64["n_assoc_px"]) <= 2
+    assert np.abs(th32 - th64).max() < 1e-4
+    assert np.abs(phi32 - phi64).max() < 1e-6
+    assert not np.array_equal(th32, th64)   # it did run in another precision
