@@ -303,7 +303,10 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
             if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
             return;
         }
-        local -= nlay + nnorm;
+        // workgroups rounding the extras up to a multiple of kXcds: none
+        const int nextra = assoc_extra_blocks(c.tiles_x * c.tiles_y, S.m.V);
+        if (local < nextra) return;
+        local -= nextra;
     }
     const uint4* __restrict__ cells = b.cells[par];
     // the overflow list: compared whole, once, by a wave that needs one of
@@ -317,6 +320,7 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
     int32_t* __restrict__ assoc = S.assoc;
     const int lane = wave_lane(), wid = threadIdx.x >> 6;
     const int tile = b.torder[local];
+    if (tile < 0) return;   // an XCD with fewer tiles than the others
     const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
     const int q = lane & 7, slot = lane >> 3, quad = wid >> 1, rows = 2 * (wid & 1);
     const int ccx = 2 * tx + (quad & 1), ccy = 2 * ty + (quad >> 1);   // the quadrant's cell

@@ -125,8 +125,10 @@ struct Buckets {
     float4* cellv;     // [ncap + V] (x, y, z, vertex id bits): the cells' regions, then the overflow list
     int ncap;          // slots of the regions (bucket_capacity bounds every layout)
     int4* bstat;       // [tiles] valid, matched, newly observed pixels per tile
-    const int* torder; // [tiles] the order association takes tiles in: nearest the image centre
-                       // first (where the subject and the longest searches usually are)
+    const int* torder; // [ntorder] the tile each association workgroup takes, -1 none (see
+                       // tile_order in track.hip: entry k runs on XCD k % 8, each XCD's tiles
+                       // nearest the image centre first)
+    int ntorder;       // a multiple of 8
 };
 
 // Summary of one frame, written by the frame-end kernel.
@@ -265,11 +267,18 @@ __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& l
 
 int ne_grid(int V);
 
-// association launch: layout workgroups, then normal workgroups, then tiles
+// association launch: layout workgroups, then normal workgroups, then (from
+// a multiple of 8, so that entry k of the tile order runs on XCD k % 8) the
+// tiles' workgroups
 constexpr int kAssocThreads = 512;
+constexpr int kXcds = 8;             // workgroups are dealt to the chip's XCDs in turn
 constexpr int kLayoutTiles = kAssocThreads;   // tiles per layout workgroup (one per thread)
 __host__ __device__ inline int layout_blocks(int ntiles) { return (ntiles + kLayoutTiles - 1) / kLayoutTiles; }
 __host__ __device__ inline int assoc_normal_blocks(int V) { return (V + kAssocThreads - 1) / kAssocThreads; }
+// the layout and normal workgroups, rounded up to a multiple of kXcds
+__host__ __device__ inline int assoc_extra_blocks(int ntiles, int V) {
+    return (layout_blocks(ntiles) + assoc_normal_blocks(V) + kXcds - 1) / kXcds * kXcds;
+}
 // Slots of the cells' regions.  A layout gives tile t d + d/2 + 32 slots, d
 // the largest count of the 3x3 tiles around it; the d sum to about 2 V on a
 // body (9 V at most), so 4 V + 32 per tile leaves room to spare.  Regions
@@ -285,7 +294,7 @@ inline int slot_blocks(const Slot& s, int kind) {
         case KK_VERT: return (V + 255) / 256;
         case KK_CLEAR: { const int n = 2 * (4 * ntiles + 1); return ((n > V ? n : V) + 255) / 256; }
         case KK_LAYOUT: return layout_blocks(ntiles);
-        case KK_ASSOC: return layout_blocks(ntiles) + assoc_normal_blocks(V) + ntiles;
+        case KK_ASSOC: return assoc_extra_blocks(ntiles, V) + s.b.ntorder;
         case KK_NE: return s.negrid;
         case KK_REDUCE: { int nb = s.PP >> 4; return nb * (nb + 1) / 2 * 8; }
         case KK_VERT64: return (V + 63) / 64;

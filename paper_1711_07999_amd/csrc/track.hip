@@ -572,6 +572,37 @@ int stream_set_params(Stream* c, const track_params* p) {
     return TRACK_OK;
 }
 
+// The association's tile order.  Workgroups are dealt to the XCDs in turn
+// (workgroup b runs on XCD b % 8), so entry k of the order runs on XCD k % 8.
+// Each XCD takes whole blocks of 4x4 tiles (block (bx, by) on XCD
+// (bx + 3 by) % 8: neighbouring blocks on different XCDs, the subject spread
+// over all of them), so that a tile's neighbours -- whose cells its search
+// reads -- mostly share its XCD's L2; within an XCD, tiles nearest the
+// principal point first (where the subject and the longest searches usually
+// are; ties: index).  Lists of unequal length leave -1 entries.
+std::vector<int> tile_order(int tx, int ty, double cx, double cy) {
+    std::vector<std::vector<int>> lists(kXcds);
+    for (int t = 0; t < tx * ty; ++t) {
+        const int bx = (t % tx) / 4, by = (t / tx) / 4;
+        lists[(bx + 3 * by) % kXcds].push_back(t);
+    }
+    size_t len = 0;
+    for (auto& l : lists) {
+        std::stable_sort(l.begin(), l.end(), [&](int a, int b) {
+            auto d = [&](int u) {
+                const double dx = (u % tx) * 8 + 3.5 - cx, dy = (u / tx) * 8 + 3.5 - cy;
+                return dx * dx + dy * dy;
+            };
+            return d(a) < d(b);
+        });
+        len = std::max(len, l.size());
+    }
+    std::vector<int> order(kXcds * len, -1);
+    for (int x = 0; x < kXcds; ++x)
+        for (size_t k = 0; k < lists[x].size(); ++k) order[kXcds * k + x] = lists[x][k];
+    return order;
+}
+
 // Lay out the stream's device memory.  Without an arena only the size is
 // accumulated (admission control uses it).
 void stream_layout(Stream* c) {
@@ -622,7 +653,8 @@ void stream_layout(Stream* c) {
     b.ovfn = carve<uint32_t>(c, 2);
     b.ncap = bucket_capacity(c->V, c->ntiles);
     b.cellv = carve<float4>(c, (size_t)b.ncap + V);
-    b.torder = carve<int>(c, c->ntiles);
+    b.ntorder = (int)tile_order((c->W + 7) / 8, (c->H + 7) / 8, 0.0, 0.0).size();
+    b.torder = carve<int>(c, b.ntorder);
     b.bstat = carve<int4>(c, c->ntiles);
     S.a.cnt = carve<uint32_t>(c, V);
     S.a.sx = carve<long long>(c, V);
@@ -834,16 +866,11 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
     S.c = DevCam{c->W, c->H, tx, ty, camera->fx, camera->fy, camera->cx, camera->cy,
                  (float)((1.0 - 1e-4) / (fmax * rmax))};
     {
-        // tiles by distance of their centre from the principal point (ties: index)
-        std::vector<int> order(c->ntiles);
-        std::vector<double> dist(c->ntiles);
-        for (int t = 0; t < c->ntiles; ++t) {
-            order[t] = t;
-            const double dx = (t % tx) * 8 + 3.5 - camera->cx, dy = (t / tx) * 8 + 3.5 - camera->cy;
-            dist[t] = dx * dx + dy * dy;
+        const std::vector<int> order = tile_order(tx, ty, camera->cx, camera->cy);
+        if ((int)order.size() != S.b.ntorder || !up(S.b.torder, order.data(), sizeof(int) * order.size())) {
+            stream_free(c);
+            return fail(TRACK_E_DEVICE, "upload failed");
         }
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b2) { return dist[a] < dist[b2]; });
-        if (!up(S.b.torder, order.data(), sizeof(int) * order.size())) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
     }
     int rc;
     if ((rc = stream_set_params(c, params))) { stream_free(c); return rc; }
