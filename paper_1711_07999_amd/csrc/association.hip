@@ -47,6 +47,7 @@ __global__ void __launch_bounds__(256) k_clear(Batch B) {
         b.tsum[1][i] = 0u;
     }
     if (i < 2) b.ovfn[i] = 0u;
+    if (i < 2 * kXcds) b.scnt[i] = 0u;
     if (i < V) {
         a.cnt[i] = 0u;
         a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
@@ -78,6 +79,7 @@ __global__ void __launch_bounds__(256) k_clear_counts(Batch B, int bsel) {
     }
     if (i < ntiles) b.tsum[par][i] = 0u;
     if (i == 0) b.ovfn[par] = 0u;
+    if (i < kXcds) b.scnt[par * kXcds + i] = 0u;
 }
 
 void launch_clear_counts(const Launch& L, int bsel) {
@@ -222,6 +224,13 @@ __device__ __forceinline__ void layout_tiles(const Slot& S, int par, int lblk, u
     if (lblk == 0 && threadIdx.x == 0) b.ovfn[par ^ 1] = 0u;
 }
 
+// the screen counters the next association uses (the association launch
+// clears them: its screen has finished with them, this launch's own are
+// the other parity's)
+__device__ __forceinline__ void clear_screen_counters(const Buckets& b, int spar) {
+    if (threadIdx.x < kXcds) b.scnt[spar * kXcds + threadIdx.x] = 0u;
+}
+
 __global__ void __launch_bounds__(kAssocThreads) k_layout(Batch B, int bsel) {
     __shared__ uint32_t stage[kLayoutStage];
     __shared__ uint32_t sred[2 * (kAssocThreads / 64)];
@@ -280,93 +289,49 @@ __device__ __forceinline__ unsigned long long slot_min(unsigned long long k) {
     return min_u64(k, __shfl_xor(k, 32));
 }
 
-__global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vsel, int bsel) {
-    __shared__ float4 scand[kAssocWaves][kAssocPass];
-    __shared__ int4 scount[kAssocWaves];
-    int local;
-    const Slot& S = B.slots[slot_of(B, KK_ASSOC, blockIdx.x, local)];
-    const DevCam& c = S.c;
-    const Buckets& b = S.b;
-    const int par = S.bpar ^ bsel;
-    {
-        const int nlay = layout_blocks(c.tiles_x * c.tiles_y), nnorm = assoc_normal_blocks(S.m.V);
-        if (local < nlay) {
-            static_assert(sizeof(scand) >= kLayoutStage * sizeof(uint32_t), "layout stage fits the candidate LDS");
-            layout_tiles(S, par, local, reinterpret_cast<uint32_t*>(&scand[0][0]), reinterpret_cast<uint32_t*>(scount));
-            return;
-        }
-        if (local < nlay + nnorm) {
-            const int i = (local - nlay) * kAssocThreads + threadIdx.x;
-            const bool live = i < S.m.V;
-            float nx, ny, nz;
-            vertex_normal_lean(S.m, S.verts[S.v_cur ^ vsel], i, live, nx, ny, nz);   // the whole wave
-            if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
-            return;
-        }
-        // workgroups rounding the extras up to a multiple of kXcds: none
-        const int nextra = assoc_extra_blocks(c.tiles_x * c.tiles_y, S.m.V);
-        if (local < nextra) return;
-        local -= nextra;
+// The pixel's point (x, y, z) from the depth image (back-projected) or the
+// organised cloud; false if the pixel has no measurement.
+__device__ __forceinline__ bool pixel_point(const DevCam& c, const float* __restrict__ depth,
+                                            const float* __restrict__ xyz, int u, int v, float& px, float& py,
+                                            float& pz) {
+#pragma clang fp contract(off)
+    px = py = pz = 0.0f;
+    if (u >= c.W || v >= c.H) return false;
+    const int k = v * c.W + u;
+    if (xyz) {
+        px = xyz[3 * k]; py = xyz[3 * k + 1]; pz = xyz[3 * k + 2];
+        return isfinite(px) && isfinite(py) && isfinite(pz) && pz > 0.0f;
     }
-    const uint4* __restrict__ cells = b.cells[par];
-    // the overflow list: compared whole, once, by a wave that needs one of
-    // the cells whose region was full
-    const uint32_t novf = min(b.ovfn[par], (uint32_t)S.m.V);
-    const Accum& a = S.a;
-    const float tau = S.tau;
-    const float* __restrict__ depth = S.depth;
-    const float* __restrict__ xyz = S.xyz;
-    const float4* __restrict__ verts = S.verts[S.v_cur ^ vsel];
-    int32_t* __restrict__ assoc = S.assoc;
-    const int lane = wave_lane(), wid = threadIdx.x >> 6;
-    const int tile = b.torder[local];
-    if (tile < 0) return;   // an XCD with fewer tiles than the others
-    const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
-    const int q = lane & 7, slot = lane >> 3, quad = wid >> 1, rows = 2 * (wid & 1);
-    const int ccx = 2 * tx + (quad & 1), ccy = 2 * ty + (quad >> 1);   // the quadrant's cell
-    const int u = ccx * 4 + (q & 3), v = ccy * 4 + rows + (q >> 2);
-    const bool inimg = u < c.W && v < c.H;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    bool valid = false;
-    if (inimg) {
-        int k = v * c.W + u;
-        if (xyz) {
-            px = xyz[3 * k]; py = xyz[3 * k + 1]; pz = xyz[3 * k + 2];
-            valid = isfinite(px) && isfinite(py) && isfinite(pz) && pz > 0.0f;
-        } else {
-            float d = depth[k];
-            valid = d > 0.0f && isfinite(d);
-            if (valid) {
-                px = (((float)u - c.cx) * d) / c.fx;
-                py = (((float)v - c.cy) * d) / c.fy;
-                pz = d;
-            }
-        }
-    }
-    const float tau2 = tau * tau;
-    const uint32_t tau2_bits = __float_as_uint(tau2);
-    // key of the best candidate so far (this slot's, and the pixel's as of
-    // the last finished ring); an unmatched valid pixel holds (tau^2, 0),
-    // which no candidate at distance >= tau can undercut
-    unsigned long long key = valid ? ((unsigned long long)tau2_bits << 32) : ~0ull;
-    unsigned long long best = key;
-    // pixel rings that can hold a vertex closer than tau (over-estimate is
-    // harmless), capped by the image; the wave's widest need sets the cells
+    const float d = depth[k];
+    if (!(d > 0.0f && isfinite(d))) return false;
+    px = (((float)u - c.cx) * d) / c.fx;
+    py = (((float)v - c.cy) * d) / c.fy;
+    pz = d;
+    return true;
+}
+
+// Pixel rings that can hold a vertex closer than tau to the wave's points
+// (over-estimate is harmless), capped by the image: the widest need of the
+// wave's lanes.
+__device__ __forceinline__ int window_rings(const DevCam& c, float tau, bool valid, float pz) {
     int rmax = 0;
     if (valid) {
         const int cap = max(c.W, c.H);
         float mf = 0.501f + (tau / pz + 1e-6f) / c.lb_c1;
         rmax = mf >= (float)cap ? cap : (int)mf + 1;
     }
-    int rw = rmax;
-    for (int o = 32; o > 0; o >>= 1) rw = max(rw, __shfl_xor(rw, o));
-    // rings 0..Rc of cells cover every pixel within 4 Rc of the quadrant
-    const int Rc = (rw + 3) / 4 + 1;
-    bool done = !valid;
-    const int cells_x = 2 * c.tiles_x, cells_y = 2 * c.tiles_y;
-    // cheap rejection of background: if no tile of the wave's window has a z
-    // range within tau of the z range of the wave's points, nothing can be
-    // found.  One tile of the window per lane, all loads in flight at once.
+    for (int o = 32; o > 0; o >>= 1) rmax = max(rmax, __shfl_xor(rmax, o));
+    return rmax;
+}
+
+// Cheap rejection of background: false if no tile of the window (rw pixel
+// rings around tile (tx, ty), in whole tiles) has a z range within tau of
+// the z range of the wave's points, so nothing can be found.  One tile of
+// the window per lane, all loads in flight at once.  A wave with more
+// points or a wider window tests a superset.
+__device__ __forceinline__ bool window_has_candidates(const DevCam& c, const uint4* __restrict__ cells, float tau,
+                                                      int tx, int ty, int rw, bool valid, float pz) {
+    const int lane = threadIdx.x & 63;
     bool candidate_tiles = false;
     if (__any(valid)) {
         float pmin = valid ? pz : INFINITY, pmax = valid ? pz : -INFINITY;
@@ -395,6 +360,48 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
             candidate_tiles = __any(cand);
         }
     }
+    return candidate_tiles;
+}
+
+// The search of one part of a tile -- two pixel rows of one of its 4x4
+// quadrants (part = 2 quadrant + row pair) -- by one wave with an LDS buffer
+// of kAssocPass candidates: the pixels' matches, the per-vertex sums, and
+// the part's counts of (valid, matched, newly observed) pixels.
+__device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, int tile, int part, float4* cand) {
+    const DevCam& c = S.c;
+    const Buckets& b = S.b;
+    const uint4* __restrict__ cells = b.cells[par];
+    // the overflow list: compared whole, once, by a wave that needs one of
+    // the cells whose region was full
+    const uint32_t novf = min(b.ovfn[par], (uint32_t)S.m.V);
+    const Accum& a = S.a;
+    const float tau = S.tau;
+    const float4* __restrict__ verts = S.verts[S.v_cur ^ vsel];
+    int32_t* __restrict__ assoc = S.assoc;
+    const int lane = wave_lane();
+    const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
+    const int q = lane & 7, slot = lane >> 3, quad = part >> 1, rows = 2 * (part & 1);
+    const int ccx = 2 * tx + (quad & 1), ccy = 2 * ty + (quad >> 1);   // the quadrant's cell
+    const int u = ccx * 4 + (q & 3), v = ccy * 4 + rows + (q >> 2);
+    const bool inimg = u < c.W && v < c.H;
+    float px, py, pz;
+    const bool valid = pixel_point(c, S.depth, S.xyz, u, v, px, py, pz);
+    const float tau2 = tau * tau;
+    const uint32_t tau2_bits = __float_as_uint(tau2);
+    // key of the best candidate so far (this slot's, and the pixel's as of
+    // the last finished ring); an unmatched valid pixel holds (tau^2, 0),
+    // which no candidate at distance >= tau can undercut
+    unsigned long long key = valid ? ((unsigned long long)tau2_bits << 32) : ~0ull;
+    unsigned long long best = key;
+    // pixel rings that can hold a vertex closer than tau (over-estimate is
+    // harmless), capped by the image; the wave's widest need sets the cells
+    const int rw = window_rings(c, tau, valid, pz);
+    // rings 0..Rc of cells cover every pixel within 4 Rc of the quadrant
+    const int Rc = (rw + 3) / 4 + 1;
+    bool done = !valid;
+    const int cells_x = 2 * c.tiles_x, cells_y = 2 * c.tiles_y;
+    // cheap rejection of background (see window_has_candidates)
+    const bool candidate_tiles = window_has_candidates(c, cells, tau, tx, ty, rw, valid, pz);
     if (candidate_tiles) {
         // The cells of the (2 Rc + 1)^2 square around the quadrant's cell, in
         // ring order (ring R >= 1, the perimeter of the (2R+1)^2 square,
@@ -443,7 +450,7 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
                         if ((uint32_t)lane < a1 - s0)
                             __builtin_amdgcn_global_load_lds(
                                 (const void*)(b.cellv + off + (s0 - pre) + lane),
-                                (__attribute__((address_space(3))) void*)&scand[wid][s0 - pass], 16, 0, 0);
+                                (__attribute__((address_space(3))) void*)&cand[s0 - pass], 16, 0, 0);
                     }
                     pre += cnt;
                 };
@@ -461,7 +468,7 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
                 for (int i0 = 0; i0 < n; i0 += 32) {
                     float4 sv[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) sv[j] = scand[wid][min(i0 + 8 * j + slot, kAssocPass - 1)];
+                    for (int j = 0; j < 4; ++j) sv[j] = cand[min(i0 + 8 * j + slot, kAssocPass - 1)];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const float dx = sv[j].x - px, dy = sv[j].y - py, dz = sv[j].z - pz;
@@ -543,10 +550,98 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
         first = old == 0u;
     }
     if (mine && inimg) assoc[v * c.W + u] = bestv;
+    const unsigned long long vb = __ballot(mine && valid), ab = __ballot(bestv >= 0), fb = __ballot(first);
+    return make_int3(__popcll(vb), __popcll(ab), __popcll(fb));
+}
+
+// Tiles where nothing can match are finished by the screen (one wave per
+// tile); the others are queued for the search workgroups of the XCD the
+// screen ran on, or, when that queue is full, searched by the screen wave
+// itself, part by part.
+__global__ void __launch_bounds__(64) k_assoc_screen(Batch B, int vsel, int bsel, int sflip) {
+    __shared__ float4 scand1[kAssocPass];
+    int local;
+    const Slot& S = B.slots[slot_of(B, KK_SCREEN, blockIdx.x, local)];
+    const DevCam& c = S.c;
+    const Buckets& b = S.b;
+    const int par = S.bpar ^ bsel, spar = par ^ sflip;
+    const int tile = b.torder[local];
+    if (tile < 0) return;   // an XCD with fewer tiles than the others
+    const int lane = threadIdx.x;
+    const int tx = tile % c.tiles_x, ty = tile / c.tiles_x;
+    const int u = 8 * tx + (lane & 7), v = 8 * ty + (lane >> 3);
+    float px, py, pz;
+    const bool valid = pixel_point(c, S.depth, S.xyz, u, v, px, py, pz);
+    // the tile's 64 points together: their z range and rings bound those of
+    // every wave that would search a part of the tile
+    const int rw = window_rings(c, S.tau, valid, pz);
+    if (!window_has_candidates(c, b.cells[par], S.tau, tx, ty, rw, valid, pz)) {
+        if (u < c.W && v < c.H) S.assoc[v * c.W + u] = -1;
+        const int nv = __popcll(__ballot(valid));
+        if (lane == 0) b.bstat[tile] = make_int4(nv, 0, 0, 0);
+        return;
+    }
+    const int x = local % kXcds;   // this workgroup's XCD
+    uint32_t at = 0u;
+    if (lane == 0) at = atomicAdd(&b.scnt[spar * kXcds + x], 1u);
+    at = (uint32_t)__builtin_amdgcn_readfirstlane((int)at);
+    if (at < (uint32_t)b.capx) {
+        if (lane == 0) b.tlist[x * b.capx + at] = tile;
+        return;
+    }
+    int4 t = make_int4(0, 0, 0, 0);
+    for (int part = 0; part < kAssocWaves; ++part) {
+        const int3 r = search_part(S, par, vsel, tile, part, scand1);
+        t.x += r.x; t.y += r.y; t.z += r.z;
+    }
+    if (lane == 0) b.bstat[tile] = t;
+}
+
+__global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vsel, int bsel, int sflip, int queued) {
+    __shared__ float4 scand[kAssocWaves][kAssocPass];
+    __shared__ int4 scount[kAssocWaves];
+    int local;
+    const Slot& S = B.slots[slot_of(B, queued ? KK_ASSOCQ : KK_ASSOC, blockIdx.x, local)];
+    const DevCam& c = S.c;
+    const Buckets& b = S.b;
+    const int par = S.bpar ^ bsel;
+    {
+        const int nlay = layout_blocks(c.tiles_x * c.tiles_y), nnorm = assoc_normal_blocks(S.m.V);
+        if (local < nlay) {
+            static_assert(sizeof(scand) >= kLayoutStage * sizeof(uint32_t), "layout stage fits the candidate LDS");
+            if (local == 0) clear_screen_counters(b, par ^ sflip ^ 1);
+            layout_tiles(S, par, local, reinterpret_cast<uint32_t*>(&scand[0][0]), reinterpret_cast<uint32_t*>(scount));
+            return;
+        }
+        if (local < nlay + nnorm) {
+            const int i = (local - nlay) * kAssocThreads + threadIdx.x;
+            const bool live = i < S.m.V;
+            float nx, ny, nz;
+            vertex_normal_lean(S.m, S.verts[S.v_cur ^ vsel], i, live, nx, ny, nz);   // the whole wave
+            if (live) { S.normals.x[i] = nx; S.normals.y[i] = ny; S.normals.z[i] = nz; }
+            return;
+        }
+        // workgroups rounding the extras up to a multiple of kXcds: none
+        const int nextra = assoc_extra_blocks(c.tiles_x * c.tiles_y, S.m.V);
+        if (local < nextra) return;
+        local -= nextra;
+    }
+    int tile;
+    if (queued) {
+        // workgroup k (on XCD k % 8) takes entry k / 8 of that XCD's queue
+        const int x = local % kXcds, at = local / kXcds;
+        const uint32_t nq = min(b.scnt[(par ^ sflip) * kXcds + x], (uint32_t)b.capx);
+        if ((uint32_t)at >= nq) return;
+        tile = b.tlist[x * b.capx + at];
+    } else {
+        tile = b.torder[local];
+        if (tile < 0) return;   // an XCD with fewer tiles than the others
+    }
+    const int wid = threadIdx.x >> 6;
+    const int3 r = search_part(S, par, vsel, tile, wid, scand[wid]);
     // per-workgroup counts go to this workgroup's own slot (no shared counter:
     // device-wide atomics on one address serialise across the chip)
-    const unsigned long long vb = __ballot(mine && valid), ab = __ballot(bestv >= 0), fb = __ballot(first);
-    if (lane == 0) scount[wid] = make_int4(__popcll(vb), __popcll(ab), __popcll(fb), 0);
+    if ((threadIdx.x & 63) == 0) scount[wid] = make_int4(r.x, r.y, r.z, 0);
     __syncthreads();
     if (threadIdx.x == 0) {
         int4 t = scount[0];
@@ -555,8 +650,19 @@ __global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vse
     }
 }
 
-void launch_associate(const Launch& L, int vsel, int bsel) {
-    launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_ASSOC]), dim3(kAssocThreads), 0, L.B, vsel, bsel);
+void launch_associate(const Launch& L, int vsel, int bsel, int sflip) {
+    // A single stream is bound by its longest searches, which start at once
+    // with every tile's workgroup in flight; a batch is bound by the total
+    // work, most of it the background tiles' workgroups, which the screen
+    // finishes with a wave each.
+    if (L.B.n == 1) {
+        launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_ASSOC]), dim3(kAssocThreads), 0, L.B, vsel, bsel,
+                      sflip, 0);
+        return;
+    }
+    launch_kernel(L, true, false, k_assoc_screen, dim3(L.grid[KK_SCREEN]), dim3(64), 0, L.B, vsel, bsel, sflip);
+    launch_kernel(L, false, true, k_associate, dim3(L.grid[KK_ASSOCQ]), dim3(kAssocThreads), 0, L.B, vsel, bsel,
+                  sflip, 1);
 }
 
 }  // namespace trk

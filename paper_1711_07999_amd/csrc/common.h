@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <cstdint>
+#include <algorithm>
 
 namespace trk {
 
@@ -129,6 +130,9 @@ struct Buckets {
                        // tile_order in track.hip: entry k runs on XCD k % 8, each XCD's tiles
                        // nearest the image centre first)
     int ntorder;       // a multiple of 8
+    uint32_t* scnt;    // [2][kXcds] per parity: tiles the screen queued for each XCD's search workgroups
+    int* tlist;        // [kXcds][capx] the queued tiles
+    int capx;          // queue length per XCD (a tile beyond it is searched by its screen wave)
 };
 
 // Summary of one frame, written by the frame-end kernel.
@@ -200,7 +204,9 @@ enum KernelKind {
     KK_VERT,        // ceil(V / 256) workgroups
     KK_CLEAR,       // ceil(max(2 (cells + 1), V) / 256)
     KK_LAYOUT,      // ceil(tiles / kLayoutTiles): bucket layout
-    KK_ASSOC,       // association: layout + normals + one workgroup per tile
+    KK_SCREEN,      // one wave per entry of the tile order: the association's screen
+    KK_ASSOC,       // association: layout + normals + one search workgroup per entry of the tile order
+    KK_ASSOCQ,      // association after a screen: layout + normals + the queued tiles' search workgroups
     KK_NE,          // normal-equation workgroups
     KK_REDUCE,      // Gram reduction workgroups
     KK_VERT64,      // ceil(V / 64): one wave per 64 vertices
@@ -267,9 +273,12 @@ __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& l
 
 int ne_grid(int V);
 
-// association launch: layout workgroups, then normal workgroups, then (from
-// a multiple of 8, so that entry k of the tile order runs on XCD k % 8) the
-// tiles' workgroups
+// Association launch: layout workgroups, normal workgroups, then (from a
+// multiple of 8, so that workgroup k runs on XCD k % 8) the tiles' search
+// workgroups -- one per entry of the tile order (entry k on XCD k % 8), or,
+// for a batch of streams, behind a screen launch (one wave per entry of the
+// tile order) that finishes the tiles where nothing can match and queues
+// the others per XCD, one search workgroup per queue entry
 constexpr int kAssocThreads = 512;
 constexpr int kXcds = 8;             // workgroups are dealt to the chip's XCDs in turn
 constexpr int kLayoutTiles = kAssocThreads;   // tiles per layout workgroup (one per thread)
@@ -279,6 +288,10 @@ __host__ __device__ inline int assoc_normal_blocks(int V) { return (V + kAssocTh
 __host__ __device__ inline int assoc_extra_blocks(int ntiles, int V) {
     return (layout_blocks(ntiles) + assoc_normal_blocks(V) + kXcds - 1) / kXcds * kXcds;
 }
+// Queue length per XCD: a quarter of the tiles over the XCDs (a body in the
+// image leaves most tiles to the screen).
+inline int screen_queue(int ntiles) { return std::max(16, (ntiles + 4 * kXcds - 1) / (4 * kXcds)); }
+
 // Slots of the cells' regions.  A layout gives tile t d + d/2 + 32 slots, d
 // the largest count of the 3x3 tiles around it; the d sum to about 2 V on a
 // body (9 V at most), so 4 V + 32 per tile leaves room to spare.  Regions
@@ -294,7 +307,9 @@ inline int slot_blocks(const Slot& s, int kind) {
         case KK_VERT: return (V + 255) / 256;
         case KK_CLEAR: { const int n = 2 * (4 * ntiles + 1); return ((n > V ? n : V) + 255) / 256; }
         case KK_LAYOUT: return layout_blocks(ntiles);
+        case KK_SCREEN: return s.b.ntorder;
         case KK_ASSOC: return assoc_extra_blocks(ntiles, V) + s.b.ntorder;
+        case KK_ASSOCQ: return assoc_extra_blocks(ntiles, V) + kXcds * s.b.capx;
         case KK_NE: return s.negrid;
         case KK_REDUCE: { int nb = s.PP >> 4; return nb * (nb + 1) / 2 * 8; }
         case KK_VERT64: return (V + 63) / 64;
@@ -331,7 +346,9 @@ void launch_bucket_count(const Launch& L, int vsel, int which, int bsel);
 void launch_layout(const Launch& L, int bsel);      // bsel's counts -> the other parity's layout
 // association of the surface vsel counted into bsel; the same launch forms
 // the surface's normals and lays out the other parity from bsel's counts
-void launch_associate(const Launch& L, int vsel, int bsel);
+// sflip: 1 takes the screen queues of the other parity (repeated launches on
+// one parity of the buckets alternate them)
+void launch_associate(const Launch& L, int vsel, int bsel, int sflip = 0);
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn);
 void launch_gram_reduce(const Launch& L);
 void launch_pose_solve(const Launch& L, int fp64, int iter);

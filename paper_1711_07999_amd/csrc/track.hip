@@ -651,10 +651,13 @@ void stream_layout(Stream* c) {
         b.tsum[q] = carve<uint32_t>(c, c->ntiles);
     }
     b.ovfn = carve<uint32_t>(c, 2);
+    b.scnt = carve<uint32_t>(c, 2 * kXcds);
+    b.tlist = carve<int>(c, kXcds * (size_t)screen_queue(c->ntiles));
     b.ncap = bucket_capacity(c->V, c->ntiles);
     b.cellv = carve<float4>(c, (size_t)b.ncap + V);
     b.ntorder = (int)tile_order((c->W + 7) / 8, (c->H + 7) / 8, 0.0, 0.0).size();
     b.torder = carve<int>(c, b.ntorder);
+    b.capx = screen_queue(c->ntiles);
     b.bstat = carve<int4>(c, c->ntiles);
     S.a.cnt = carve<uint32_t>(c, V);
     S.a.sx = carve<long long>(c, V);
@@ -697,6 +700,8 @@ size_t frame_scratch_layout(const Stream* c, char* base, Slot& S, float** depth_
         b.tsum[q] = static_cast<uint32_t*>(take(c->ntiles, sizeof(uint32_t)));
     }
     b.ovfn = static_cast<uint32_t*>(take(2, 4));
+    b.scnt = static_cast<uint32_t*>(take(2 * kXcds, 4));
+    b.tlist = static_cast<int*>(take(kXcds * (size_t)b.capx, 4));
     b.ncap = bucket_capacity(c->V, c->ntiles);
     b.cellv = static_cast<float4*>(take((size_t)b.ncap + V, sizeof(float4)));
     b.bstat = static_cast<int4*>(take(c->ntiles, sizeof(int4)));
@@ -856,7 +861,8 @@ int stream_create(Stream* c, const track_model* model, const track_camera* camer
               hipMemset(S.b.cells[1], 0, sizeof(uint4) * (4 * (size_t)c->ntiles + 1)) == hipSuccess &&
               hipMemset(S.b.tsum[0], 0, sizeof(uint32_t) * c->ntiles) == hipSuccess &&
               hipMemset(S.b.tsum[1], 0, sizeof(uint32_t) * c->ntiles) == hipSuccess &&
-              hipMemset(S.b.ovfn, 0, 2 * sizeof(uint32_t)) == hipSuccess;
+              hipMemset(S.b.ovfn, 0, 2 * sizeof(uint32_t)) == hipSuccess &&
+              hipMemset(S.b.scnt, 0, 2 * kXcds * sizeof(uint32_t)) == hipSuccess;
     if (!ok) { stream_free(c); return fail(TRACK_E_DEVICE, "upload failed"); }
     S.m.P = c->P; S.m.L = c->L; S.m.V = c->V; S.m.F = c->F; S.blend = c->blend;
     const float fmax = std::max(camera->fx, camera->fy);
@@ -1760,15 +1766,17 @@ int track_kernel_bench(track_ctx* c, int32_t k, const float* depth, int32_t reps
     Launch L = stage_one(c, 0, depth, nullptr);
     // the last association read the counters of the other parity, which
     // hold the last count (bpar was laid out by it)
+    // (the screen queues of the last association's parity are still full:
+    // the repeats start on the other and alternate)
     if (k == TRACK_K_NORMAL_EQ) {  // one association, as inside a frame
         launch_clear_acc(L);
-        launch_associate(L, 0, 1);
+        launch_associate(L, 0, 1, 1);
     }
     HIP_TRY(hipEventRecord(R.f0, R.s));
     for (int r = 0; r < reps; ++r) {
         switch (k) {
             case TRACK_K_SKIN: launch_skin(L, 0, 0, SEL_ALL, SEL_NONE, 0, 0, 0); break;
-            case TRACK_K_ASSOC: launch_associate(L, 0, 1); break;
+            case TRACK_K_ASSOC: launch_associate(L, 0, 1, (r & 1) ^ 1); break;
             case TRACK_K_NORMAL_EQ: launch_normal_eq(L, c->sched.gram_mode, 0, 0); break;
             default: launch_pose_solve(L, c->sched.pose_fp64, 0); break;
         }

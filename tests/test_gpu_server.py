@@ -295,3 +295,29 @@ def test_served_stream_matches_the_oracle_iteration_by_iteration(T, streams):
         T.track_server_destroy(sv)
     _say(f"  worst: joint {worst[0]:.1e} rad, root {worst[1]:.1e} m, vertex {worst[2]:.1e} m")
     assert not fails, fails
+
+
+def test_screened_association_with_full_queues_equals_alone(T, tiny):
+    """A batch of streams associates behind a screen that queues each XCD's
+    candidate tiles; a tile beyond its queue is searched by its screen wave.
+    A close-up body (158 of 300 tiles on the subject, the queues hold 128)
+    overflows the queues; served beside another stream it must end
+    bit-identical to a single-stream context, which searches every tile
+    directly."""
+    _say("[server] close-up body: full screen queues vs the direct search")
+    cam = dict(width=160, height=120, fx=400.0, fy=400.0, cx=79.5, cy=59.5)
+    body = synth.make_body(3000, cam, 2.6)
+    P = len(body.model["joint_parent"])
+    rng = np.random.default_rng(77)
+    th = np.where(body.angular, rng.uniform(-0.05, 0.05, P), rng.uniform(-0.01, 0.01, P))
+    close = (body.model, cam, th + np.where(body.angular, 0.02, 0.005), _frames(body, th, 2, 78), 0)
+    Pt = len(tiny.body.model["joint_parent"])
+    tht = np.where(tiny.body.angular, rng.uniform(-0.05, 0.05, Pt), rng.uniform(-0.01, 0.01, Pt))
+    other = (tiny.body.model, tiny.body.camera, tht + np.where(tiny.body.angular, 0.02, 0.005),
+             _frames(tiny.body, tht, 2, 79), 0)
+    pair = [close, other]
+    mix = _run_server(T, pair, [0, 1])[0]
+    for k in range(2):
+        th_a, phi_a = _run_alone(T, pair[k])
+        th_m, phi_m = mix[k]
+        assert np.array_equal(th_m, th_a) and np.array_equal(phi_m, phi_a), k
