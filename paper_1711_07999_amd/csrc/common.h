@@ -91,6 +91,11 @@ struct DevCam {
     float lb_c1;   // lower bound of the 3-D distance per pixel ring, per metre of depth
 };
 
+// DevStats::status set by a kernel: -4 the pose system is not positive
+// definite; kStatusBucketOverflow a count found the overflow list full
+// (counters not cleared: an internal error).
+constexpr int kStatusBucketOverflow = -16;
+
 // Per-iteration bookkeeping written by the kernels and read back per frame.
 struct DevStats {
     int n_valid_px, n_assoc_px, n_obs_verts, status;
@@ -139,7 +144,8 @@ struct Buckets {
 struct DevSummary {
     int status, n_valid_px, n_assoc_px, n_obs_verts;
     float energy_first, energy_last, step_norm_last;
-    int reason;   // 0 ok, 1 not positive definite, 2 no valid pixel, 3 nothing matched, 4/5 diverged
+    int reason;   // 0 ok, 1 not positive definite, 2 no valid pixel, 3 nothing matched, 4/5 diverged,
+                  // 6 bucket index overflow
 };
 
 // ---------------------------------------------------------------------------

@@ -163,6 +163,7 @@ __global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int 
         out.step_norm_last = last_pose >= 0 ? st->step_norm[last_pose] : 0.0f;
         int status = 0, why = 0;
         if (st->status == -4) { status = -4; why = 1; }
+        else if (st->status == kStatusBucketOverflow) { status = -5; why = 6; }
         else if (nv == 0) { status = -5; why = 2; }
         else if (na == 0) { status = -5; why = 3; }
         else if (s_bad) { status = -5; why = 4; }

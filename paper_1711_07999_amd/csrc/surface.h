@@ -80,9 +80,12 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int bsel, int i, flo
             if (slot < (end > off ? end - off : 0u)) {
                 b.cellv[off + slot] = rec;
             } else {
-                // at most V entries between two clears of the counters
+                // at most V entries between two clears of the counters; more
+                // would mean a count into counters nobody cleared: the frame
+                // is failed rather than a vertex dropped
                 const uint32_t o = atomicAdd(&b.ovfn[par], 1u);
                 if (o < (uint32_t)S.m.V) b.cellv[(uint32_t)b.ncap + o] = rec;
+                else S.st->status = kStatusBucketOverflow;
             }
         }
     }

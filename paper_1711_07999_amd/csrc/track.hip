@@ -1297,6 +1297,7 @@ const char* lost_reason(int why) {
         case 3: return "no pixel matched the surface";
         case 4: return "pose diverged";
         case 5: return "energy diverged";
+        case 6: return "bucket index overflow (internal error)";
     }
     return "frame rejected";
 }
