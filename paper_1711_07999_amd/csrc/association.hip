@@ -279,6 +279,7 @@ __device__ __forceinline__ bool z_pruned(float zmn, float zmx, float pz, float b
 // and the vertex normals of the surface (the workgroups after them).
 constexpr int kAssocWaves = kAssocThreads / 64;
 constexpr int kAssocPass = 256;   // candidates per pass (LDS per wave: 4 KB)
+static_assert(kAssocPass % 32 == 0, "a pass is whole trips of eight slots x four steps");
 
 __device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) {
     return a < b ? a : b;
@@ -390,8 +391,9 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
     const uint32_t tau2_bits = __float_as_uint(tau2);
     // key of the best candidate so far (this slot's, and the pixel's as of
     // the last finished ring); an unmatched valid pixel holds (tau^2, 0),
-    // which no candidate at distance >= tau can undercut
-    unsigned long long key = valid ? ((unsigned long long)tau2_bits << 32) : ~0ull;
+    // which no candidate at distance >= tau can undercut, an invalid one 0,
+    // which nothing undercuts
+    unsigned long long key = valid ? ((unsigned long long)tau2_bits << 32) : 0ull;
     unsigned long long best = key;
     // pixel rings that can hold a vertex closer than tau (over-estimate is
     // harmless), capped by the image; the wave's widest need sets the cells
@@ -461,21 +463,26 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
                     if (pre >= pend) break;   // the rest belongs to later passes
                 }
                 if (take_ovf && pre < pend) segment((uint32_t)b.ncap, novf);
+                const int n = (int)min((uint32_t)kAssocPass, total - pass);
+                // the pass's last trip filled up with entries at x = +inf: for a
+                // finite pixel their d2 is +inf or NaN, whose bits no key of a
+                // valid pixel (at most tau^2, 0) or of an invalid one (0) exceeds
+                const int ntrip = (n + 31) & ~31;
+                if (lane < ntrip - n) cand[n + lane].x = __builtin_inff();
                 __builtin_amdgcn_s_waitcnt(0);   // the copies have landed in LDS
                 __builtin_amdgcn_wave_barrier();
-                const int n = (int)min((uint32_t)kAssocPass, total - pass);
                 // eight slots x four steps per trip, the LDS reads issued together
-                for (int i0 = 0; i0 < n; i0 += 32) {
+                for (int i0 = 0; i0 < ntrip; i0 += 32) {
                     float4 sv[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) sv[j] = cand[min(i0 + 8 * j + slot, kAssocPass - 1)];
+                    for (int j = 0; j < 4; ++j) sv[j] = cand[i0 + 8 * j + slot];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const float dx = sv[j].x - px, dy = sv[j].y - py, dz = sv[j].z - pz;
                         const float d2 = (dx * dx + dy * dy) + dz * dz;
                         const unsigned long long kk =
                             ((unsigned long long)__float_as_uint(d2) << 32) | (uint32_t)__float_as_int(sv[j].w);
-                        if (valid && i0 + 8 * j + slot < n && kk < key) key = kk;
+                        key = kk < key ? kk : key;
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
