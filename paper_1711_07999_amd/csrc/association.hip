@@ -375,6 +375,12 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
     // the overflow list: compared whole, once, by a wave that needs one of
     // the cells whose region was full
     const uint32_t novf = min(b.ovfn[par], (uint32_t)S.m.V);
+    // held in scalar registers: read through the slot inside the copy loops,
+    // they would be reloaded after every copy into LDS (which the compiler
+    // takes as a store that may alias them), each reload waiting for every
+    // copy still in flight
+    const float4* __restrict__ cellv = wave_uniform(b.cellv);
+    const uint32_t ovf_at = wave_uniform((uint32_t)b.ncap);
     const Accum& a = S.a;
     const float tau = S.tau;
     const float4* __restrict__ verts = S.verts[S.v_cur ^ vsel];
@@ -451,7 +457,7 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
                     for (uint32_t s0 = a0; s0 < a1; s0 += 64u) {
                         if ((uint32_t)lane < a1 - s0)
                             __builtin_amdgcn_global_load_lds(
-                                (const void*)(b.cellv + off + (s0 - pre) + lane),
+                                (const void*)(cellv + (off + (s0 - pre) + (uint32_t)lane)),
                                 (__attribute__((address_space(3))) void*)&cand[s0 - pass], 16, 0, 0);
                     }
                     pre += cnt;
@@ -462,7 +468,7 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
                             (uint32_t)__builtin_amdgcn_readlane((int)rec.y, k));
                     if (pre >= pend) break;   // the rest belongs to later passes
                 }
-                if (take_ovf && pre < pend) segment((uint32_t)b.ncap, novf);
+                if (take_ovf && pre < pend) segment(ovf_at, novf);
                 const int n = (int)min((uint32_t)kAssocPass, total - pass);
                 // the pass's last trip filled up with entries at x = +inf: for a
                 // finite pixel their d2 is +inf or NaN, whose bits no key of a

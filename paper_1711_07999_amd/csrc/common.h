@@ -266,6 +266,20 @@ __device__ __forceinline__ void copy_to_lds(float* dst, const float* __restrict_
 }
 
 // slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
+// A value the whole wave holds alike (a field of its workgroup's slot), put
+// in scalar registers: the compiler reads the slot table with vector loads,
+// since kernels store through pointers it cannot tell apart from it.
+template <class T>
+__device__ __forceinline__ T* wave_uniform(T* p) {
+    const unsigned long long a = (unsigned long long)p;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)a);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(a >> 32));
+    return (T*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
 __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& local) {
     const int* p = B.pre + kind * (B.n + 1);
     int lo = 0, hi = B.n - 1;
