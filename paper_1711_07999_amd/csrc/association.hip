@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int whi
     if (!selected(S, which)) return;
     const int i = local * blockDim.x + threadIdx.x;
     const bool live = i < S.m.V;
-    count_vertex(S, bsel, i, S.verts[S.v_cur ^ vsel][live ? i : 0], live, false);
+    count_vertex(count_refs(S, bsel), i, S.verts[S.v_cur ^ vsel][live ? i : 0], live, false);
 }
 
 void launch_bucket_count(const Launch& L, int vsel, int which, int bsel) {

@@ -266,6 +266,13 @@ __device__ __forceinline__ void copy_to_lds(float* dst, const float* __restrict_
 }
 
 // slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
+// Keeps a loaded value where it stands: the compiler would otherwise move a
+// load into the branch that alone uses it, to be waited for there on its
+// own instead of together with the loads issued before it.  Emits nothing.
+__device__ __forceinline__ void pin_load(int& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_load(uint32_t& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_load(int2& x) { pin_load(x.x); pin_load(x.y); }
+
 // A value the whole wave holds alike (a field of its workgroup's slot), put
 // in scalar registers: the compiler reads the slot table with vector loads,
 // since kernels store through pointers it cannot tell apart from it.
@@ -278,6 +285,10 @@ __device__ __forceinline__ T* wave_uniform(T* p) {
 }
 __device__ __forceinline__ uint32_t wave_uniform(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
 __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& local) {

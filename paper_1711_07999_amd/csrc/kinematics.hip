@@ -67,6 +67,8 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
     const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
     if (!selected(S, which)) return;
     const DevModel& m = S.m;
+    const bool counted = selected(S, count);
+    const CountRefs cr = count_refs(S, bsel);
     const int i = local * blockDim.x + threadIdx.x;
     const int ii = i < m.V ? i : 0;   // the vertex's own loads go out before the table copy
     const Vec3Buf phi = S.phi[phi_index(S, pn)];
@@ -87,7 +89,7 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
     }
     const float4 p = make_float4(ox, oy, oz, 0.0f);
     if (live) v[i] = p;
-    if (selected(S, count)) count_vertex(S, bsel, i, p, live, count_only != 0);   // the whole wave
+    if (counted) count_vertex(cr, i, p, live, count_only != 0);   // the whole wave
     if (live && clear_acc) {
         S.a.cnt[i] = 0u;
         S.a.sx[i] = 0; S.a.sy[i] = 0; S.a.sz[i] = 0;

@@ -466,15 +466,25 @@ __global__ void __launch_bounds__(32 * kRedGroups) k_gram_reduce(Batch B) {
     block_of(blk, nb, I, J);
     const int i = I * 16 + (el >> 4), j = J * 16 + (el & 15);
     // the tree-form pose solve takes this element (damped, frozen) in its front image
-    const int fe = (S.tree.gfmap && grp == 0 && i <= j) ? S.tree.gfmap[i * PP + j] : -1;
+    // (its reads unconditional at clamped indices, issued with the partials'
+    // below: a read under a condition is waited for inside it)
+    const int* __restrict__ gfm = S.tree.gfmap;
     const int P = S.m.P;
+    int fe = -1;
     double prior_i = 0.0, theta_i = 0.0;
     int act_i = 0, act_j = 0;
-    if (fe >= 0) {
-        prior_i = S.jt->prior[i];
-        act_i = S.jt->active[i];
-        act_j = j < P ? S.jt->active[j] : 1;
-        theta_i = S.theta[i];
+    if (gfm) {   // the same for the whole workgroup
+        const int ic = min(i, P - 1), jc = min(j, P - 1);
+        const int f0 = gfm[i * PP + j];
+        const double pr = S.jt->prior[ic], th = S.theta[ic];
+        const int ai = S.jt->active[ic], aj = S.jt->active[jc];
+        fe = (grp == 0 && i <= j) ? f0 : -1;
+        if (fe >= 0) {
+            prior_i = pr;
+            act_i = ai;
+            act_j = j < P ? aj : 1;
+            theta_i = th;
+        }
     }
     const size_t stride = (size_t)PP * PP;
     const int per = (nparts + kRedGroups - 1) / kRedGroups;

@@ -417,23 +417,21 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
     // pose and whether it is frozen
     const int elems = tr.elems;   // even: rows are multiples of 8 wide
     const double2* __restrict__ img = reinterpret_cast<const double2*>(tr.fimg);
+    // (unconditional loads at clamped indices, the unused ones dropped after:
+    // a load under a condition is waited for inside it, one after another)
     constexpr int kPre = 8;
     double2 iv[kPre];
 #pragma unroll
-    for (int k = 0; k < kPre; ++k) {
-        const int e = tid + kSolveThreads * k;
-        iv[k] = 2 * e < elems ? img[e] : make_double2(0.0, 0.0);
-    }
+    for (int k = 0; k < kPre; ++k) iv[k] = img[min(tid + kSolveThreads * k, elems / 2 - 1)];
     const uint4* __restrict__ bsrc = reinterpret_cast<const uint4*>(tr.blob);
     const int nw4 = (tr.nwords + 3) / 4;
-    uint4 bw = tid < nw4 ? bsrc[tid] : make_uint4(0u, 0u, 0u, 0u);
-    double thk = 0.0;
-    int fz = 1;
-    if (tid < P) {
-        thk = theta[tid];
-        fz = (gram[tid * PP + tid] + jt->prior[tid] == 0.0) || !jt->active[tid];
-    }
-    const double energy = tid == 0 ? gram[P * PP + P] : 0.0;
+    const uint4 bw = bsrc[min(tid, nw4 - 1)];
+    const int tp = min(tid, P - 1);
+    const double th0 = theta[tp], gdiag = gram[tp * PP + tp], prior = jt->prior[tp];
+    const int act = jt->active[tp];
+    const double energy = gram[P * PP + P];
+    const double thk = tid < P ? th0 : 0.0;
+    const int fz = tid < P ? (int)((gdiag + prior == 0.0) | !act) : 1;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
         const int e = tid + kSolveThreads * k;
@@ -591,6 +589,8 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     const Vec3Buf phi_prev = S.phi[S.phi_prev];
     const Vec3Buf phi_out = S.phi[phi_next(src, S.phi_prev)];
     const float lphi = S.lphi, lnbr = S.lnbr, lt = S.lt, lw = S.lw;
+    const bool counted = selected(S, next);
+    const CountRefs cr = count_refs(S, bsel);
     copy_to_lds(sdq, S.dq, 8 * m.L);
     __syncthreads();
     const int i = local * blockDim.x + threadIdx.x;
@@ -598,7 +598,8 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     const int ii = live ? i : 0;   // lanes past the end read vertex 0 and store nothing
     // every per-vertex load that does not wait on another goes out first, so
     // their latencies overlap the normal's gathers below
-    const uint32_t c = live ? a.cnt[i] : 0u;
+    const uint32_t c0 = a.cnt[ii];
+    const uint32_t c = live ? c0 : 0u;
     const T px = phi.x[ii], py = phi.y[ii], pz = phi.z[ii];
     const T qx = phi_prev.x[ii], qy = phi_prev.y[ii], qz = phi_prev.z[ii];
     const int4 nb = m.nbr[ii];
@@ -679,7 +680,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         phi_out.y[i] = fy;
         phi_out.z[i] = fz;
     }
-    if (selected(S, next)) {
+    if (counted) {
         // the next iteration's surface: skin the new offsets (same blend) into
         // the buffer not read here by other vertices, and count it
         float ox, oy, oz;
@@ -687,7 +688,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         else dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         const float4 q = make_float4(ox, oy, oz, 0.0f);
         if (live) S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
-        count_vertex(S, bsel, i, q, live, false);   // the whole wave
+        count_vertex(cr, i, q, live, false);   // the whole wave
     }
 }
 

@@ -8,9 +8,43 @@ namespace trk {
 
 // pixel (u, v) -> its bucket: 8x8 tiles in row-major order, Morton order
 // inside a tile (so every 4x4 quadrant of a tile is 16 consecutive buckets)
-__device__ __forceinline__ int tile_pixel(const DevCam& c, int u, int v) {
+__device__ __forceinline__ int tile_pixel(int tiles_x, int u, int v) {
     const int m = (u & 1) | ((v & 1) << 1) | ((u & 2) << 1) | ((v & 2) << 2) | ((u & 4) << 2) | ((v & 4) << 3);
-    return (((v >> 3) * c.tiles_x + (u >> 3)) << 6) + m;
+    return (((v >> 3) * tiles_x + (u >> 3)) << 6) + m;
+}
+
+// What a count reads of its slot, read before the kernel's first global
+// store and held in scalar registers: read after a store, each field would
+// be reloaded and waited for on its own.
+struct CountRefs {
+    uint4* cells;       // the counters bsel selects
+    uint32_t* tsum;
+    uint32_t* ovfn;
+    float4* cellv;
+    int* status;
+    float fx, fy, cx, cy;
+    int W, H, tiles_x;
+    uint32_t ncap, V;
+};
+
+__device__ __forceinline__ CountRefs count_refs(const Slot& S, int bsel) {
+    const int par = S.bpar ^ bsel;
+    CountRefs r;
+    r.cells = wave_uniform(S.b.cells[par]);
+    r.tsum = wave_uniform(S.b.tsum[par]);
+    r.ovfn = wave_uniform(S.b.ovfn + par);
+    r.cellv = wave_uniform(S.b.cellv);
+    r.status = wave_uniform(&S.st->status);
+    r.fx = wave_uniform(S.c.fx);
+    r.fy = wave_uniform(S.c.fy);
+    r.cx = wave_uniform(S.c.cx);
+    r.cy = wave_uniform(S.c.cy);
+    r.W = wave_uniform(S.c.W);
+    r.H = wave_uniform(S.c.H);
+    r.tiles_x = wave_uniform(S.c.tiles_x);
+    r.ncap = wave_uniform((uint32_t)S.b.ncap);
+    r.V = wave_uniform((uint32_t)S.m.V);
+    return r;
 }
 
 // Bucket of vertex i at p (float32 decisions in one fixed order, no
@@ -22,18 +56,15 @@ __device__ __forceinline__ int tile_pixel(const DevCam& c, int u, int v) {
 // it together: the lanes that share a cell (or tile) are grouped and take
 // one atomic per counter (a cell's vertices come from many waves, so
 // per-lane atomics on it would queue behind each other).
-__device__ __forceinline__ void count_vertex(const Slot& S, int bsel, int i, float4 p, bool live, bool count_only) {
+__device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p, bool live, bool count_only) {
 #pragma clang fp contract(off)
-    const DevCam& c = S.c;
-    const Buckets& b = S.b;
-    const int par = S.bpar ^ bsel;
-    uint4* __restrict__ cells = b.cells[par];
+    uint4* __restrict__ cells = R.cells;
     const int lane = threadIdx.x & 63;
     int pix = -1;
     if (live && p.z > kZNear) {
-        const float fu = floorf((c.fx * p.x) / p.z + c.cx + 0.5f);
-        const float fv = floorf((c.fy * p.y) / p.z + c.cy + 0.5f);
-        if (fu >= 0.0f && fu < (float)c.W && fv >= 0.0f && fv < (float)c.H) pix = tile_pixel(c, (int)fu, (int)fv);
+        const float fu = floorf((R.fx * p.x) / p.z + R.cx + 0.5f);
+        const float fv = floorf((R.fy * p.y) / p.z + R.cy + 0.5f);
+        if (fu >= 0.0f && fu < (float)R.W && fv >= 0.0f && fv < (float)R.H) pix = tile_pixel(R.tiles_x, (int)fu, (int)fv);
     }
     const int cell = pix >= 0 ? (pix >> 4) : -1;
     if (count_only) {
@@ -45,8 +76,11 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int bsel, int i, flo
             todo &= ~grp;
         }
     } else {
-        // the region's bounds do not wait for the slot
-        const uint32_t off = cell >= 0 ? cells[cell].w : 0u, end = cell >= 0 ? cells[cell + 1].w : 0u;
+        // the region's bounds do not wait for the slot (unconditional loads:
+        // a lane with no cell reads cell 0's and drops them)
+        const int cc = cell >= 0 ? cell : 0;
+        const uint32_t off0 = cells[cc].w, end0 = cells[cc + 1].w;
+        const uint32_t off = cell >= 0 ? off0 : 0u, end = cell >= 0 ? end0 : 0u;
         const uint32_t zb = __float_as_uint(p.z);  // z > 0: integer order is float order
         // per cell: the group's first lane adds the group's count (the slot
         // base returns into that lane) and the group's z range; a lane's
@@ -78,19 +112,19 @@ __device__ __forceinline__ void count_vertex(const Slot& S, int bsel, int i, flo
         if (cell >= 0) {
             const float4 rec = make_float4(p.x, p.y, p.z, __int_as_float(i));
             if (slot < (end > off ? end - off : 0u)) {
-                b.cellv[off + slot] = rec;
+                R.cellv[off + slot] = rec;
             } else {
                 // at most V entries between two clears of the counters; more
                 // would mean a count into counters nobody cleared: the frame
                 // is failed rather than a vertex dropped
-                const uint32_t o = atomicAdd(&b.ovfn[par], 1u);
-                if (o < (uint32_t)S.m.V) b.cellv[(uint32_t)b.ncap + o] = rec;
-                else S.st->status = kStatusBucketOverflow;
+                const uint32_t o = atomicAdd(R.ovfn, 1u);
+                if (o < R.V) R.cellv[R.ncap + o] = rec;
+                else *R.status = kStatusBucketOverflow;
             }
         }
     }
     // tile counts, grouped the same way
-    uint32_t* __restrict__ tsum = b.tsum[par];
+    uint32_t* __restrict__ tsum = R.tsum;
     const int tile = pix >= 0 ? (pix >> 6) : -1;
     for (unsigned long long todo = __ballot(tile >= 0); todo;) {
         const int lead = __builtin_ctzll(todo);
@@ -150,11 +184,22 @@ struct FanIn {
 
 __device__ __forceinline__ void vertex_fan_load(const DevModel& m, const float4* __restrict__ v, int i, bool live,
                                                 FanIn& f) {
-    f.p = v[live ? i : 0];
-    f.e0 = live ? m.fan_off[i] : 0u;
-    f.e1 = live ? m.fan_off[i + 1] : 0u;
+    // every load unconditional (lanes past the end read vertex 0's entries),
+    // so that none waits under a branch for the one before it
+    const int ii = live ? i : 0;
+    f.p = v[ii];
+    uint32_t e0 = m.fan_off[ii], e1 = m.fan_off[ii + 1];
+    int2 bc[kFanInline];
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) f.bc[k] = live ? m.fan8[(size_t)k * m.V + i] : make_int2(0, 0);
+    for (int k = 0; k < kFanInline; ++k) bc[k] = m.fan8[(size_t)k * m.V + ii];
+    pin_load(e0);
+    pin_load(e1);
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) pin_load(bc[k]);
+    f.e0 = live ? e0 : 0u;
+    f.e1 = live ? e1 : 0u;
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) f.bc[k] = live ? bc[k] : make_int2(0, 0);
 }
 
 // Sum over the incident faces (b, c) of (v_b - v_i) x (v_c - v_i),
@@ -200,10 +245,20 @@ __device__ __forceinline__ void vertex_normal_lean(const DevModel& m, const floa
 #pragma clang fp contract(off)
     const int ii = live ? i : 0;
     const float4 p = v[ii];
-    const uint32_t e0 = live ? m.fan_off[i] : 0u, e1 = live ? m.fan_off[i + 1] : 0u;
+    // unconditional loads (vertex 0's entries past the end): none waits
+    // under a branch for the one before it
+    uint32_t f0 = m.fan_off[ii], f1 = m.fan_off[ii + 1];
     int2 bcs[kFanInline];
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) bcs[k] = live ? m.fan8[(size_t)k * m.V + i] : make_int2(0, 0);
+    for (int k = 0; k < kFanInline; ++k) bcs[k] = m.fan8[(size_t)k * m.V + ii];
+    pin_load(f0);
+    pin_load(f1);
+#pragma unroll
+    for (int k = 0; k < kFanInline; ++k) {
+        pin_load(bcs[k]);
+        bcs[k] = live ? bcs[k] : make_int2(0, 0);
+    }
+    const uint32_t e0 = live ? f0 : 0u, e1 = live ? f1 : 0u;
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
     for (int k0 = 0; k0 < kFanInline; k0 += 2) {
