@@ -273,6 +273,36 @@ __device__ __forceinline__ void pin_load(int& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void pin_load(uint32_t& x) { asm volatile("" : "+v"(x)); }
 __device__ __forceinline__ void pin_load(int2& x) { pin_load(x.x); pin_load(x.y); }
 
+// A read of global memory as such: through a generic pointer the compiler
+// emits a flat load, which also counts as an LDS access, so that any later
+// wait for LDS waits for it too.
+template <class T>
+__device__ __forceinline__ T ldg(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+__device__ __forceinline__ float4 ldg(const float4* p) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    const v4f t = *(const __attribute__((address_space(1))) v4f*)p;
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+// x, y, z of a float4 (w = 0): an unused fourth register of a load in
+// flight would be taken for other values, which must then wait for the load
+__device__ __forceinline__ float4 ldg_xyz(const float4* p) {
+    typedef float v3f __attribute__((ext_vector_type(3)));
+    const v3f t = *(const __attribute__((address_space(1))) v3f*)p;
+    return make_float4(t.x, t.y, t.z, 0.0f);
+}
+__device__ __forceinline__ int4 ldg(const int4* p) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i t = *(const __attribute__((address_space(1))) v4i*)p;
+    return make_int4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ int2 ldg(const int2* p) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const v2i t = *(const __attribute__((address_space(1))) v2i*)p;
+    return make_int2(t.x, t.y);
+}
+
 // A value the whole wave holds alike (a field of its workgroup's slot), put
 // in scalar registers: the compiler reads the slot table with vector loads,
 // since kernels store through pointers it cannot tell apart from it.

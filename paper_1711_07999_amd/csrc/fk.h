@@ -104,21 +104,20 @@ struct FkJoint { double off[8], z[3]; int type, parent; };
 struct FkLink { double binv[8]; int joint; };
 
 __device__ __forceinline__ void fk_prefetch(const JointTable* __restrict__ jt, int P, int L, FkJoint& fj, FkLink& fl) {
+    // every thread reads (at clamped indices; the others' values go unused),
+    // so that no read waits under a branch, and as global reads, so that the
+    // LDS work in between does not wait for them
     const int t = threadIdx.x;
-    if (t < P) {
+    const int tj = min(t, P - 1), tl = min(max(t - kLinkThread, 0), L - 1);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) fj.off[c] = jt->off[t][c];
+    for (int c = 0; c < 8; ++c) fj.off[c] = ldg(&jt->off[tj][c]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) fj.z[c] = jt->axis[t][c];
-        fj.type = jt->type[t];
-        fj.parent = jt->parent[t];
-    }
-    const int l = t - kLinkThread;
-    if (l >= 0 && l < L) {
+    for (int c = 0; c < 3; ++c) fj.z[c] = ldg(&jt->axis[tj][c]);
+    fj.type = ldg(&jt->type[tj]);
+    fj.parent = ldg(&jt->parent[tj]);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) fl.binv[c] = jt->binv[l][c];
-        fl.joint = jt->link_joint[l];
-    }
+    for (int c = 0; c < 8; ++c) fl.binv[c] = ldg(&jt->binv[tl][c]);
+    fl.joint = ldg(&jt->link_joint[tl]);
 }
 
 __device__ __forceinline__ void fk_block_pre(int P, int L, int rounds, const double* __restrict__ sth,

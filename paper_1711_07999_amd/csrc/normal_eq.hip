@@ -55,13 +55,21 @@ struct VertexIn {
 
 __device__ __forceinline__ void vertex_load(const DevModel& m, int i, const float4* v, const Vec3Buf& n,
                                             const Vec3Buf& phi, const Accum& a, VertexIn& in) {
-    in.w = m.w[i];
-    in.links = m.links[i];
-    in.v = v[i];
-    in.nx = n.x[i]; in.ny = n.y[i]; in.nz = n.z[i];
-    in.x0 = m.rx[i] + phi.x[i]; in.x1 = m.ry[i] + phi.y[i]; in.x2 = m.rz[i] + phi.z[i];
-    in.cnt = a.cnt[i];
-    in.sx = (long long)a.sx[i]; in.sy = (long long)a.sy[i]; in.sz = (long long)a.sz[i];
+    // global reads: as flat reads they would also count as LDS and scalar
+    // accesses, and the first wait for one of those would wait for them
+    in.w = ldg(m.w + i);
+    in.links = ldg(m.links + i);
+    in.v = ldg(v + i);
+    in.nx = ldg(n.x + i); in.ny = ldg(n.y + i); in.nz = ldg(n.z + i);
+    in.cnt = ldg(a.cnt + i);
+    in.sx = (long long)ldg(a.sx + i); in.sy = (long long)ldg(a.sy + i); in.sz = (long long)ldg(a.sz + i);
+    const float rx = ldg(m.rx + i), ry = ldg(m.ry + i), rz = ldg(m.rz + i);
+    const float px = ldg(phi.x + i), py = ldg(phi.y + i), pz = ldg(phi.z + i);
+    // every read issued before the first use of one
+    __builtin_amdgcn_sched_barrier(0);
+    in.x0 = rx + px;
+    in.x1 = ry + py;
+    in.x2 = rz + pz;
 }
 
 // per-vertex 6-vectors of the Jacobian (one per influence) and the residual
@@ -202,9 +210,21 @@ __global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int
     const int nchunks = (m.V + kNeRows - 1) / kNeRows;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int P = m.P;
-    for (int q = tid; q < 8 * m.L; q += kNeThreads) sdq[q] = dq[q];
-    for (int q = tid; q < 6 * P; q += kNeThreads) sxi[q] = xi[8 * (q / 6) + (q % 6)];
-    for (int q = tid; q < 4 * m.L; q += kNeThreads) sanc[q] = anc[q];
+    {
+        // the three tables' first rounds read together (clamped indices; the
+        // values past a table's end are not stored), the rest after
+        const int n1 = 8 * m.L, n2 = 6 * P, n3 = 4 * m.L;
+        const int q2 = min(tid, n2 - 1);
+        const float t1 = ldg(dq + min(tid, n1 - 1));
+        const float t2 = ldg(xi + 8 * (q2 / 6) + (q2 % 6));
+        const uint32_t t3 = ldg(anc + min(tid, n3 - 1));
+        if (tid < n1) sdq[tid] = t1;
+        if (tid < n2) sxi[tid] = t2;
+        if (tid < n3) sanc[tid] = t3;
+        for (int q = tid + kNeThreads; q < n1; q += kNeThreads) sdq[q] = dq[q];
+        for (int q = tid + kNeThreads; q < n2; q += kNeThreads) sxi[q] = xi[8 * (q / 6) + (q % 6)];
+        for (int q = tid + kNeThreads; q < n3; q += kNeThreads) sanc[q] = anc[q];
+    }
 
     const int nb = PP >> 4;
     const int nbt = nb * (nb + 1) / 2;

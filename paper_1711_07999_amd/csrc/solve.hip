@@ -430,6 +430,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
     const double th0 = theta[tp], gdiag = gram[tp * PP + tp], prior = jt->prior[tp];
     const int act = jt->active[tp];
     const double energy = gram[P * PP + P];
+    const int rounds = jt->rounds;
     const double thk = tid < P ? th0 : 0.0;
     const int fz = tid < P ? (int)((gdiag + prior == 0.0) | !act) : 1;
 #pragma unroll
@@ -515,7 +516,7 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
         st->step_norm[S.iter + iter] = fail ? 0.0f : (float)sqrt(norm2);
         if (fail) st->status = -4;
     }
-    fk_block_pre(P, NL, jt->rounds, sth, fj, fl, S.dq, S.xi, fk_ws);
+    fk_block_pre(P, NL, rounds, sth, fj, fl, S.dq, S.xi, fk_ws);
 }
 
 // let the BIG instances take the largest system (P = 127, float64: about
@@ -591,38 +592,52 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     const float lphi = S.lphi, lnbr = S.lnbr, lt = S.lt, lw = S.lw;
     const bool counted = selected(S, next);
     const CountRefs cr = count_refs(S, bsel);
-    copy_to_lds(sdq, S.dq, 8 * m.L);
-    __syncthreads();
+    // the slot fields used after the first loads, read here (into scalar
+    // registers) rather than each where it is used, behind its own wait
+    const bool linear = wave_uniform(S.blend) == kBlendLinear;
+    uint32_t* const acnt = wave_uniform(a.cnt);
+    long long* const asx = wave_uniform(a.sx);
+    long long* const asy = wave_uniform(a.sy);
+    long long* const asz = wave_uniform(a.sz);
+    float* const pox = wave_uniform(phi_out.x);
+    float* const poy = wave_uniform(phi_out.y);
+    float* const poz = wave_uniform(phi_out.z);
+    float4* const vnext = wave_uniform(S.verts[S.v_cur ^ vn_sel ^ 1]);
     const int i = local * blockDim.x + threadIdx.x;
     const bool live = i < m.V;
     const int ii = live ? i : 0;   // lanes past the end read vertex 0 and store nothing
-    // every per-vertex load that does not wait on another goes out first, so
-    // their latencies overlap the normal's gathers below
-    const uint32_t c0 = a.cnt[ii];
-    const uint32_t c = live ? c0 : 0u;
-    const T px = phi.x[ii], py = phi.y[ii], pz = phi.z[ii];
-    const T qx = phi_prev.x[ii], qy = phi_prev.y[ii], qz = phi_prev.z[ii];
-    const int4 nb = m.nbr[ii];
-    const float4 vo = v_old[ii], vn = v_new[ii];
-    const long long ax = a.sx[ii], ay = a.sy[ii], az = a.sz[ii];
-    const float4 wv = m.w[ii];
-    const uint32_t lk = m.links[ii];
-    const float rx = m.rx[ii], ry = m.ry[ii], rz = m.rz[ii];
+    // every per-vertex load that does not wait on another goes out first,
+    // ahead of the link table's copy (global reads: the barrier does not wait
+    // for them), so their latencies overlap the copy's and each other's
+    const uint32_t c0 = ldg(a.cnt + ii);
+    const float px0 = ldg(phi.x + ii), py0 = ldg(phi.y + ii), pz0 = ldg(phi.z + ii);
+    const float qx0 = ldg(phi_prev.x + ii), qy0 = ldg(phi_prev.y + ii), qz0 = ldg(phi_prev.z + ii);
+    const int4 nb = ldg(m.nbr + ii);
+    const float4 vo = ldg_xyz(v_old + ii), vn = ldg_xyz(v_new + ii);
+    const long long ax = ldg(a.sx + ii), ay = ldg(a.sy + ii), az = ldg(a.sz + ii);
+    const float4 wv = ldg(m.w + ii);
+    const uint32_t lk = ldg(m.links + ii);
+    const float rx = ldg(m.rx + ii), ry = ldg(m.ry + ii), rz = ldg(m.rz + ii);
     FanIn fan;
     vertex_fan_load(m, v_new, i, live, fan);   // not waiting for the count
+    copy_to_lds(sdq, S.dq, 8 * m.L);
+    __syncthreads();
+    vertex_fan_settle(fan, live);
+    const uint32_t c = live ? c0 : 0u;
+    const T px = px0, py = py0, pz = pz0;
+    const T qx = qx0, qy = qy0, qz = qz0;
     const int nbs[4] = {nb.x, nb.y, nb.z, nb.w};
     T nphi[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = nbs[q] < 0 ? ii : nbs[q];
-        nphi[q][0] = (T)phi.x[j]; nphi[q][1] = (T)phi.y[j]; nphi[q][2] = (T)phi.z[j];
+        nphi[q][0] = (T)ldg(phi.x + j); nphi[q][1] = (T)ldg(phi.y + j); nphi[q][2] = (T)ldg(phi.z + j);
     }
     float nx, ny, nz;
     vertex_normal_fan(m, v_new, i, live && c > 0u, fan, nx, ny, nz);   // the whole wave
     // lanes past the end go on with vertex 0's values (count 0) and store nothing
     T u[3] = {T(0), T(0), T(0)};
     T r = T(0);
-    const bool linear = S.blend == kBlendLinear;
     float H[8];
     if (!linear) dq_blend(sdq, wv, lk, H);
     if (c > 0u) {
@@ -653,8 +668,8 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     }
     // this is the association's last reader: clear for the next one
     if (live) {
-        a.cnt[i] = 0u;
-        a.sx[i] = 0; a.sy[i] = 0; a.sz[i] = 0;
+        acnt[i] = 0u;
+        asx[i] = 0; asy[i] = 0; asz[i] = 0;
     }
     T alpha = (T)lphi + (T)lt;
     T g[3] = {u[0] * r + (T)lphi * px + (T)lt * (px - qx),
@@ -676,9 +691,9 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     solve3(M, g, xs);
     const float fx = (float)(px - xs[0]), fy = (float)(py - xs[1]), fz = (float)(pz - xs[2]);
     if (live) {
-        phi_out.x[i] = fx;
-        phi_out.y[i] = fy;
-        phi_out.z[i] = fz;
+        pox[i] = fx;
+        poy[i] = fy;
+        poz[i] = fz;
     }
     if (counted) {
         // the next iteration's surface: skin the new offsets (same blend) into
@@ -687,7 +702,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         if (linear) lbs_apply(sdq, wv, lk, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         else dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         const float4 q = make_float4(ox, oy, oz, 0.0f);
-        if (live) S.verts[S.v_cur ^ vn_sel ^ 1][i] = q;
+        if (live) vnext[i] = q;
         count_vertex(cr, i, q, live, false);   // the whole wave
     }
 }

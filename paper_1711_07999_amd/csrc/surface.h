@@ -185,21 +185,27 @@ struct FanIn {
 __device__ __forceinline__ void vertex_fan_load(const DevModel& m, const float4* __restrict__ v, int i, bool live,
                                                 FanIn& f) {
     // every load unconditional (lanes past the end read vertex 0's entries),
-    // so that none waits under a branch for the one before it
+    // so that none waits under a branch for the one before it, and global,
+    // so that a wait for LDS does not wait for them
     const int ii = live ? i : 0;
-    f.p = v[ii];
-    uint32_t e0 = m.fan_off[ii], e1 = m.fan_off[ii + 1];
-    int2 bc[kFanInline];
+    f.p = ldg_xyz(v + ii);
+    f.e0 = ldg(m.fan_off + ii);
+    f.e1 = ldg(m.fan_off + ii + 1);
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) bc[k] = m.fan8[(size_t)k * m.V + ii];
-    pin_load(e0);
-    pin_load(e1);
+    for (int k = 0; k < kFanInline; ++k) f.bc[k] = ldg(m.fan8 + (size_t)k * m.V + ii);
+}
+
+// The loads of vertex_fan_load held where this stands (waited for here, not
+// moved under the branches that use them) and dropped for lanes not live.
+__device__ __forceinline__ void vertex_fan_settle(FanIn& f, bool live) {
+    pin_load(f.e0);
+    pin_load(f.e1);
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) pin_load(bc[k]);
-    f.e0 = live ? e0 : 0u;
-    f.e1 = live ? e1 : 0u;
+    for (int k = 0; k < kFanInline; ++k) pin_load(f.bc[k]);
+    f.e0 = live ? f.e0 : 0u;
+    f.e1 = live ? f.e1 : 0u;
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) f.bc[k] = live ? bc[k] : make_int2(0, 0);
+    for (int k = 0; k < kFanInline; ++k) f.bc[k] = live ? f.bc[k] : make_int2(0, 0);
 }
 
 // Sum over the incident faces (b, c) of (v_b - v_i) x (v_c - v_i),
@@ -210,7 +216,8 @@ __device__ __forceinline__ void vertex_fan_load(const DevModel& m, const float4*
 // vertex of more faces, the rest summed by the whole wave (lane l takes
 // faces l, l + 64, ... of the rest; a fixed tree adds the lanes' sums).
 // Every lane of the wave must call it together.  This form takes the loads
-// made by vertex_fan_load (with a `live` at least as wide as this one);
+// made by vertex_fan_load and vertex_fan_settle (with a `live` at least as
+// wide as this one);
 // lanes with live == false gather nothing of their own (their result is not
 // meaningful) but take part in the shared work.
 __device__ __forceinline__ void vertex_normal_fan(const DevModel& m, const float4* __restrict__ v, int i, bool live,
@@ -224,7 +231,7 @@ __device__ __forceinline__ void vertex_normal_fan(const DevModel& m, const float
     for (int k = 0; k < kFanInline; ++k) bc[k] = live ? f.bc[k] : make_int2(0, 0);
     float4 vb[kFanInline], vc[kFanInline];
 #pragma unroll
-    for (int k = 0; k < kFanInline; ++k) { vb[k] = v[bc[k].x]; vc[k] = v[bc[k].y]; }
+    for (int k = 0; k < kFanInline; ++k) { vb[k] = ldg_xyz(v + bc[k].x); vc[k] = ldg_xyz(v + bc[k].y); }
     float sx = 0.0f, sy = 0.0f, sz = 0.0f;
 #pragma unroll
     for (int k = 0; k < kFanInline; ++k) {
@@ -287,6 +294,7 @@ __device__ __forceinline__ void vertex_normal(const DevModel& m, const float4* _
                                               float& nx, float& ny, float& nz) {
     FanIn f;
     vertex_fan_load(m, v, i, live, f);
+    vertex_fan_settle(f, live);
     vertex_normal_fan(m, v, i, live, f, nx, ny, nz);
 }
 
