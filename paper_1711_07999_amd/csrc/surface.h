@@ -68,13 +68,15 @@ __device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p
     }
     const int cell = pix >= 0 ? (pix >> 4) : -1;
     if (count_only) {
+        uint32_t gsize = 0u;
         for (unsigned long long todo = __ballot(cell >= 0); todo;) {
             const int lead = __builtin_ctzll(todo);
             const int c0 = __builtin_amdgcn_readlane(cell, lead);
             const unsigned long long grp = __ballot(cell == c0);
-            if (lane == lead) atomicAdd(&cells[c0].z, (uint32_t)__popcll(grp));
+            if (lane == lead) gsize = (uint32_t)__popcll(grp);
             todo &= ~grp;
         }
+        if (gsize != 0u) atomicAdd(&cells[cell].z, gsize);
     } else {
         // the region's bounds do not wait for the slot (unconditional loads:
         // a lane with no cell reads cell 0's and drops them)
@@ -82,31 +84,34 @@ __device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p
         const uint32_t off0 = cells[cc].w, end0 = cells[cc + 1].w;
         const uint32_t off = cell >= 0 ? off0 : 0u, end = cell >= 0 ? end0 : 0u;
         const uint32_t zb = __float_as_uint(p.z);  // z > 0: integer order is float order
-        // per cell: the group's first lane adds the group's count (the slot
-        // base returns into that lane) and the group's z range; a lane's
-        // slot is its leader's base plus its rank in the group
-        uint32_t base = 0u;
+        // per cell: the group's first lane gets the group's size and z range
+        // (the z range one lane at a time on the scalar unit: a group is a
+        // few lanes); then every group's first lane adds them at once (the
+        // slot base returns into that lane: one round trip for the wave,
+        // not one per group).  A lane's slot is its leader's base plus its
+        // rank in the group.
+        uint32_t gsize = 0u, gmn = 0xFFFFFFFFu, gmx = 0u;
         int leader = lane, rank = 0;
         const unsigned long long below = (1ull << lane) - 1ull;
         for (unsigned long long todo = __ballot(cell >= 0); todo;) {
             const int lead = __builtin_ctzll(todo);
             const int c0 = __builtin_amdgcn_readlane(cell, lead);
             const unsigned long long grp = __ballot(cell == c0);
-            // the group's z range, one lane at a time on the scalar unit
-            // (a group is a few lanes)
             uint32_t mn = 0xFFFFFFFFu, mx = 0u;
             for (unsigned long long m = grp; m; m &= m - 1ull) {
                 const uint32_t z = (uint32_t)__builtin_amdgcn_readlane((int)zb, __builtin_ctzll(m));
                 mn = min(mn, z);
                 mx = max(mx, z);
             }
-            if (lane == lead) {
-                base = atomicAdd(&cells[c0].z, (uint32_t)__popcll(grp));
-                atomicMin(&cells[c0].x, mn);
-                atomicMax(&cells[c0].y, mx);
-            }
+            if (lane == lead) { gsize = (uint32_t)__popcll(grp); gmn = mn; gmx = mx; }
             if (cell == c0) { leader = lead; rank = __popcll(grp & below); }
             todo &= ~grp;
+        }
+        uint32_t base = 0u;
+        if (gsize != 0u) {
+            base = atomicAdd(&cells[cell].z, gsize);
+            atomicMin(&cells[cell].x, gmn);
+            atomicMax(&cells[cell].y, gmx);
         }
         const uint32_t slot = (uint32_t)__shfl((int)base, leader) + (uint32_t)rank;
         if (cell >= 0) {
@@ -126,13 +131,15 @@ __device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p
     // tile counts, grouped the same way
     uint32_t* __restrict__ tsum = R.tsum;
     const int tile = pix >= 0 ? (pix >> 6) : -1;
+    uint32_t tsize = 0u;
     for (unsigned long long todo = __ballot(tile >= 0); todo;) {
         const int lead = __builtin_ctzll(todo);
         const int t0 = __builtin_amdgcn_readlane(tile, lead);
         const unsigned long long grp = __ballot(tile == t0);
-        if (lane == lead) atomicAdd(&tsum[t0], (uint32_t)__popcll(grp));
+        if (lane == lead) tsize = (uint32_t)__popcll(grp);
         todo &= ~grp;
     }
+    if (tsize != 0u) atomicAdd(&tsum[tile], tsize);
 }
 
 // The faces past the inline table (vertices of more than kFanInline faces,
