@@ -285,6 +285,19 @@ __device__ __forceinline__ float4 ldg(const float4* p) {
     const v4f t = *(const __attribute__((address_space(1))) v4f*)p;
     return make_float4(t.x, t.y, t.z, t.w);
 }
+// A store to global memory as such: a flat store also counts as an LDS
+// access, so that the next wait for LDS (a shuffle, a barrier) waits for it.
+template <class T>
+__device__ __forceinline__ void stg(T* p, T v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+__device__ __forceinline__ void stg(float4* p, float4 v) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f t;
+    t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+    *(__attribute__((address_space(1))) v4f*)p = t;
+}
+
 // x, y, z of a float4 (w = 0): an unused fourth register of a load in
 // flight would be taken for other values, which must then wait for the load
 __device__ __forceinline__ float4 ldg_xyz(const float4* p) {

@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
         dq_apply(H, x, y, z, ox, oy, oz);
     }
     const float4 p = make_float4(ox, oy, oz, 0.0f);
-    if (live) v[i] = p;
+    if (live) stg(v + i, p);
     if (counted) count_vertex(cr, i, p, live, count_only != 0);   // the whole wave
     if (live && clear_acc) {
         S.a.cnt[i] = 0u;

@@ -501,8 +501,8 @@ __global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int 
         const double th = thk - x;
         sth[tid] = th;
         if (!fail) {
-            S.step[tid] = x;
-            theta[tid] = th;
+            stg(S.step + tid, x);
+            stg(theta + tid, th);
         }
     }
     double part = x * x;
@@ -668,8 +668,8 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     }
     // this is the association's last reader: clear for the next one
     if (live) {
-        acnt[i] = 0u;
-        asx[i] = 0; asy[i] = 0; asz[i] = 0;
+        stg(acnt + i, 0u);
+        stg(asx + i, 0ll); stg(asy + i, 0ll); stg(asz + i, 0ll);
     }
     T alpha = (T)lphi + (T)lt;
     T g[3] = {u[0] * r + (T)lphi * px + (T)lt * (px - qx),
@@ -691,9 +691,9 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
     solve3(M, g, xs);
     const float fx = (float)(px - xs[0]), fy = (float)(py - xs[1]), fz = (float)(pz - xs[2]);
     if (live) {
-        pox[i] = fx;
-        poy[i] = fy;
-        poz[i] = fz;
+        stg(pox + i, fx);
+        stg(poy + i, fy);
+        stg(poz + i, fz);
     }
     if (counted) {
         // the next iteration's surface: skin the new offsets (same blend) into
@@ -702,7 +702,7 @@ __global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, 
         if (linear) lbs_apply(sdq, wv, lk, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         else dq_apply(H, rx + fx, ry + fy, rz + fz, ox, oy, oz);
         const float4 q = make_float4(ox, oy, oz, 0.0f);
-        if (live) vnext[i] = q;
+        if (live) stg(vnext + i, q);
         count_vertex(cr, i, q, live, false);   // the whole wave
     }
 }
