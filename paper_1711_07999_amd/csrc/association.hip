@@ -300,10 +300,10 @@ __device__ __forceinline__ bool pixel_point(const DevCam& c, const float* __rest
     if (u >= c.W || v >= c.H) return false;
     const int k = v * c.W + u;
     if (xyz) {
-        px = xyz[3 * k]; py = xyz[3 * k + 1]; pz = xyz[3 * k + 2];
+        px = ldg(xyz + 3 * k); py = ldg(xyz + 3 * k + 1); pz = ldg(xyz + 3 * k + 2);
         return isfinite(px) && isfinite(py) && isfinite(pz) && pz > 0.0f;
     }
-    const float d = depth[k];
+    const float d = ldg(depth + k);
     if (!(d > 0.0f && isfinite(d))) return false;
     px = (((float)u - c.cx) * d) / c.fx;
     py = (((float)v - c.cy) * d) / c.fy;
@@ -353,7 +353,7 @@ __device__ __forceinline__ bool window_has_candidates(const DevCam& c, const uin
                 // the tile's z range from its four cells' (an empty cell
                 // holds (+inf, 0): an empty tile is never a candidate)
                 const uint2* cz = reinterpret_cast<const uint2*>(cells + 4 * ((wy0 + wy) * c.tiles_x + wx0 + (qw - wy * nwx)));
-                const uint2 r0 = cz[0], r1 = cz[2], r2 = cz[4], r3 = cz[6];
+                const uint2 r0 = ldg(cz), r1 = ldg(cz + 2), r2 = ldg(cz + 4), r3 = ldg(cz + 6);
                 const float zlo = __uint_as_float(min(min(r0.x, r1.x), min(r2.x, r3.x)));
                 const float zhi = __uint_as_float(max(max(r0.y, r1.y), max(r2.y, r3.y)));
                 cand = zlo <= zhi && zlo < pmax + tz_tol && zhi > pmin - tz_tol;
@@ -517,8 +517,8 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
                 else { mycx = ccx + rr; mycy = ccy - rr + 1 + (kq - (3 * side - 2)); }
                 if (mycx >= 0 && mycy >= 0 && mycx < cells_x && mycy < cells_y) {
                     const int ci = (((mycy >> 1) * c.tiles_x + (mycx >> 1)) << 2) | ((mycy & 1) << 1) | (mycx & 1);
-                    const uint4 r = cells[ci];
-                    const uint32_t end = cells[ci + 1].w;
+                    const uint4 r = ldg(cells + ci);
+                    const uint32_t end = ldg(&cells[ci + 1].w);
                     const uint32_t cap = end > r.w ? end - r.w : 0u;
                     mycnt = r.z;
                     myrec = make_uint4(r.w, min(r.z, cap), r.x, r.y);
@@ -554,15 +554,15 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
     const bool mine = slot == 0;
     if (mine && valid && (uint32_t)(key >> 32) < tau2_bits) {
         bestv = (int)(uint32_t)key;
-        const float4 sv = verts[bestv];
+        const float4 sv = ldg_xyz(verts + bestv);
         const float dx = sv.x - px, dy = sv.y - py, dz = sv.z - pz;
-        uint32_t old = atomicAdd(&a.cnt[bestv], 1u);
-        atomicAdd((unsigned long long*)&a.sx[bestv], (unsigned long long)(long long)rintf(-dx * 4294967296.0f));
-        atomicAdd((unsigned long long*)&a.sy[bestv], (unsigned long long)(long long)rintf(-dy * 4294967296.0f));
-        atomicAdd((unsigned long long*)&a.sz[bestv], (unsigned long long)(long long)rintf(-dz * 4294967296.0f));
+        uint32_t old = atomic_add_g(a.cnt + bestv, 1u);
+        atomic_add_g((unsigned long long*)&a.sx[bestv], (unsigned long long)(long long)rintf(-dx * 4294967296.0f));
+        atomic_add_g((unsigned long long*)&a.sy[bestv], (unsigned long long)(long long)rintf(-dy * 4294967296.0f));
+        atomic_add_g((unsigned long long*)&a.sz[bestv], (unsigned long long)(long long)rintf(-dz * 4294967296.0f));
         first = old == 0u;
     }
-    if (mine && inimg) assoc[v * c.W + u] = bestv;
+    if (mine && inimg) stg(assoc + v * c.W + u, bestv);
     const unsigned long long vb = __ballot(mine && valid), ab = __ballot(bestv >= 0), fb = __ballot(first);
     return make_int3(__popcll(vb), __popcll(ab), __popcll(fb));
 }
@@ -571,7 +571,9 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
 // tile); the others are queued for the search workgroups of the XCD the
 // screen ran on, or, when that queue is full, searched by the screen wave
 // itself, part by part.
-__global__ void __launch_bounds__(64) k_assoc_screen(Batch B, int vsel, int bsel, int sflip) {
+// (held to eight waves per SIMD: its own work is a few loads and a test; the
+// registers of the rare search of a tile beyond its queue spill instead)
+__global__ void __launch_bounds__(64, 8) k_assoc_screen(Batch B, int vsel, int bsel, int sflip) {
     __shared__ float4 scand1[kAssocPass];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_SCREEN, blockIdx.x, local)];

@@ -298,6 +298,34 @@ __device__ __forceinline__ void stg(float4* p, float4 v) {
     *(__attribute__((address_space(1))) v4f*)p = t;
 }
 
+__device__ __forceinline__ uint4 ldg(const uint4* p) {
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const v4u t = *(const __attribute__((address_space(1))) v4u*)p;
+    return make_uint4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ uint2 ldg(const uint2* p) {
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    const v2u t = *(const __attribute__((address_space(1))) v2u*)p;
+    return make_uint2(t.x, t.y);
+}
+// Relaxed device-scope atomics on global memory as such (see ldg).
+__device__ __forceinline__ uint32_t atomic_add_g(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_add((__attribute__((address_space(1))) uint32_t*)p, v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_add_g(unsigned long long* p, unsigned long long v) {
+    return __hip_atomic_fetch_add((__attribute__((address_space(1))) unsigned long long*)p, v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_min_g(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_min((__attribute__((address_space(1))) uint32_t*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_max_g(uint32_t* p, uint32_t v) {
+    __hip_atomic_fetch_max((__attribute__((address_space(1))) uint32_t*)p, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // x, y, z of a float4 (w = 0): an unused fourth register of a load in
 // flight would be taken for other values, which must then wait for the load
 __device__ __forceinline__ float4 ldg_xyz(const float4* p) {

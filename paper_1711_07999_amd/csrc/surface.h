@@ -76,12 +76,12 @@ __device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p
             if (lane == lead) gsize = (uint32_t)__popcll(grp);
             todo &= ~grp;
         }
-        if (gsize != 0u) atomicAdd(&cells[cell].z, gsize);
+        if (gsize != 0u) atomic_add_g(&cells[cell].z, gsize);
     } else {
         // the region's bounds do not wait for the slot (unconditional loads:
         // a lane with no cell reads cell 0's and drops them)
         const int cc = cell >= 0 ? cell : 0;
-        const uint32_t off0 = cells[cc].w, end0 = cells[cc + 1].w;
+        const uint32_t off0 = ldg(&cells[cc].w), end0 = ldg(&cells[cc + 1].w);
         const uint32_t off = cell >= 0 ? off0 : 0u, end = cell >= 0 ? end0 : 0u;
         const uint32_t zb = __float_as_uint(p.z);  // z > 0: integer order is float order
         // per cell: the group's first lane gets the group's size and z range
@@ -109,21 +109,21 @@ __device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p
         }
         uint32_t base = 0u;
         if (gsize != 0u) {
-            base = atomicAdd(&cells[cell].z, gsize);
-            atomicMin(&cells[cell].x, gmn);
-            atomicMax(&cells[cell].y, gmx);
+            base = atomic_add_g(&cells[cell].z, gsize);
+            atomic_min_g(&cells[cell].x, gmn);
+            atomic_max_g(&cells[cell].y, gmx);
         }
         const uint32_t slot = (uint32_t)__shfl((int)base, leader) + (uint32_t)rank;
         if (cell >= 0) {
             const float4 rec = make_float4(p.x, p.y, p.z, __int_as_float(i));
             if (slot < (end > off ? end - off : 0u)) {
-                R.cellv[off + slot] = rec;
+                stg(R.cellv + off + slot, rec);
             } else {
                 // at most V entries between two clears of the counters; more
                 // would mean a count into counters nobody cleared: the frame
                 // is failed rather than a vertex dropped
-                const uint32_t o = atomicAdd(R.ovfn, 1u);
-                if (o < R.V) R.cellv[R.ncap + o] = rec;
+                const uint32_t o = atomic_add_g(R.ovfn, 1u);
+                if (o < R.V) stg(R.cellv + R.ncap + o, rec);
                 else *R.status = kStatusBucketOverflow;
             }
         }
@@ -139,7 +139,7 @@ __device__ __forceinline__ void count_vertex(const CountRefs& R, int i, float4 p
         if (lane == lead) tsize = (uint32_t)__popcll(grp);
         todo &= ~grp;
     }
-    if (tsize != 0u) atomicAdd(&tsum[tile], tsize);
+    if (tsize != 0u) atomic_add_g(tsum + tile, tsize);
 }
 
 // The faces past the inline table (vertices of more than kFanInline faces,
