@@ -31,7 +31,8 @@ constexpr uint32_t kInfBits = 0x7F800000u;   // +inf: the z minimum of an empty 
 // empty, so the first count sends its vertices to the overflow list), the
 // per-vertex accumulators and the solve's front image
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_clear(Batch B) {
+__global__ void __launch_bounds__(256) k_clear(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_CLEAR, blockIdx.x, local)];
     const Buckets& b = S.b;
@@ -62,11 +63,12 @@ __global__ void __launch_bounds__(256) k_clear(Batch B) {
 }
 
 void launch_clear(const Launch& L) {
-    launch_kernel(L, true, true, k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B);
+    launch_kernel(L, true, true, k_clear, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B.slots, L.B.pre, L.B.n);
 }
 
 // the counters of one parity, its layout kept
-__global__ void __launch_bounds__(256) k_clear_counts(Batch B, int bsel) {
+__global__ void __launch_bounds__(256) k_clear_counts(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int bsel) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_CLEAR, blockIdx.x, local)];
     const Buckets& b = S.b;
@@ -83,10 +85,11 @@ __global__ void __launch_bounds__(256) k_clear_counts(Batch B, int bsel) {
 }
 
 void launch_clear_counts(const Launch& L, int bsel) {
-    launch_kernel(L, true, true, k_clear_counts, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B, bsel);
+    launch_kernel(L, true, true, k_clear_counts, dim3(L.grid[KK_CLEAR]), dim3(256), 0, L.B.slots, L.B.pre, L.B.n, bsel);
 }
 
-__global__ void __launch_bounds__(256) k_clear_acc(Batch B) {
+__global__ void __launch_bounds__(256) k_clear_acc(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
     const int i = local * blockDim.x + threadIdx.x;
@@ -96,12 +99,13 @@ __global__ void __launch_bounds__(256) k_clear_acc(Batch B) {
 }
 
 void launch_clear_acc(const Launch& L) {
-    launch_kernel(L, true, true, k_clear_acc, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B);
+    launch_kernel(L, true, true, k_clear_acc, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B.slots, L.B.pre, L.B.n);
 }
 
 // count a given surface into the buckets (the producing kernels count their
 // own output instead)
-__global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int which, int bsel) {
+__global__ void __launch_bounds__(256) k_bucket_count(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vsel, int which, int bsel) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
     if (!selected(S, which)) return;
@@ -111,7 +115,7 @@ __global__ void __launch_bounds__(256) k_bucket_count(Batch B, int vsel, int whi
 }
 
 void launch_bucket_count(const Launch& L, int vsel, int which, int bsel) {
-    launch_kernel(L, true, true, k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel, which, bsel);
+    launch_kernel(L, true, true, k_bucket_count, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B.slots, L.B.pre, L.B.n, vsel, which, bsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,7 +235,8 @@ __device__ __forceinline__ void clear_screen_counters(const Buckets& b, int spar
     if (threadIdx.x < kXcds) b.scnt[spar * kXcds + threadIdx.x] = 0u;
 }
 
-__global__ void __launch_bounds__(kAssocThreads) k_layout(Batch B, int bsel) {
+__global__ void __launch_bounds__(kAssocThreads) k_layout(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int bsel) {
+    const Batch B{bs, bp, bn};
     __shared__ uint32_t stage[kLayoutStage];
     __shared__ uint32_t sred[2 * (kAssocThreads / 64)];
     int local;
@@ -240,7 +245,7 @@ __global__ void __launch_bounds__(kAssocThreads) k_layout(Batch B, int bsel) {
 }
 
 void launch_layout(const Launch& L, int bsel) {
-    launch_kernel(L, true, true, k_layout, dim3(L.grid[KK_LAYOUT]), dim3(kAssocThreads), 0, L.B, bsel);
+    launch_kernel(L, true, true, k_layout, dim3(L.grid[KK_LAYOUT]), dim3(kAssocThreads), 0, L.B.slots, L.B.pre, L.B.n, bsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -573,7 +578,8 @@ __device__ __forceinline__ int3 search_part(const Slot& S, int par, int vsel, in
 // itself, part by part.
 // (held to eight waves per SIMD: its own work is a few loads and a test; the
 // registers of the rare search of a tile beyond its queue spill instead)
-__global__ void __launch_bounds__(64, 8) k_assoc_screen(Batch B, int vsel, int bsel, int sflip) {
+__global__ void __launch_bounds__(64, 8) k_assoc_screen(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vsel, int bsel, int sflip) {
+    const Batch B{bs, bp, bn};
     __shared__ float4 scand1[kAssocPass];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_SCREEN, blockIdx.x, local)];
@@ -612,7 +618,8 @@ __global__ void __launch_bounds__(64, 8) k_assoc_screen(Batch B, int vsel, int b
     if (lane == 0) b.bstat[tile] = t;
 }
 
-__global__ void __launch_bounds__(kAssocThreads, 8) k_associate(Batch B, int vsel, int bsel, int sflip, int queued) {
+__global__ void __launch_bounds__(kAssocThreads, 8) k_associate(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vsel, int bsel, int sflip, int queued) {
+    const Batch B{bs, bp, bn};
     __shared__ float4 scand[kAssocWaves][kAssocPass];
     __shared__ int4 scount[kAssocWaves];
     int local;
@@ -671,12 +678,12 @@ void launch_associate(const Launch& L, int vsel, int bsel, int sflip) {
     // work, most of it the background tiles' workgroups, which the screen
     // finishes with a wave each.
     if (L.B.n == 1) {
-        launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_ASSOC]), dim3(kAssocThreads), 0, L.B, vsel, bsel,
+        launch_kernel(L, true, true, k_associate, dim3(L.grid[KK_ASSOC]), dim3(kAssocThreads), 0, L.B.slots, L.B.pre, L.B.n, vsel, bsel,
                       sflip, 0);
         return;
     }
-    launch_kernel(L, true, false, k_assoc_screen, dim3(L.grid[KK_SCREEN]), dim3(64), 0, L.B, vsel, bsel, sflip);
-    launch_kernel(L, false, true, k_associate, dim3(L.grid[KK_ASSOCQ]), dim3(kAssocThreads), 0, L.B, vsel, bsel,
+    launch_kernel(L, true, false, k_assoc_screen, dim3(L.grid[KK_SCREEN]), dim3(64), 0, L.B.slots, L.B.pre, L.B.n, vsel, bsel, sflip);
+    launch_kernel(L, false, true, k_associate, dim3(L.grid[KK_ASSOCQ]), dim3(kAssocThreads), 0, L.B.slots, L.B.pre, L.B.n, vsel, bsel,
                   sflip, 1);
 }
 

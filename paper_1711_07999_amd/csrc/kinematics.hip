@@ -27,7 +27,8 @@ void launch_stage(hipStream_t s, const Slot* src, Slot* dst, int n, const int* p
 // frame start: keep the pose for a rollback, clear the status flag and (when
 // the slot asks for it) redo forward kinematics at the current pose
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(128) k_frame_begin(Batch B) {
+__global__ void __launch_bounds__(128) k_frame_begin(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     if (!(S.flags & kSlotBeginFrame)) return;
@@ -39,10 +40,11 @@ __global__ void __launch_bounds__(128) k_frame_begin(Batch B) {
 }
 
 void launch_frame_begin(const Launch& L) {
-    launch_kernel(L, true, true, k_frame_begin, dim3(L.grid[KK_ONE]), dim3(128), 0, L.B);
+    launch_kernel(L, true, true, k_frame_begin, dim3(L.grid[KK_ONE]), dim3(128), 0, L.B.slots, L.B.pre, L.B.n);
 }
 
-__global__ void __launch_bounds__(128) k_fk(Batch B) {
+__global__ void __launch_bounds__(128) k_fk(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_ONE, blockIdx.x, local)];
     __shared__ FkScratch ws;
@@ -50,7 +52,7 @@ __global__ void __launch_bounds__(128) k_fk(Batch B) {
 }
 
 void launch_fk(const Launch& L) {
-    launch_kernel(L, true, true, k_fk, dim3(L.grid[KK_ONE]), dim3(128), 0, L.B);
+    launch_kernel(L, true, true, k_fk, dim3(L.grid[KK_ONE]), dim3(128), 0, L.B.slots, L.B.pre, L.B.n);
 }
 
 // ---------------------------------------------------------------------------
@@ -60,8 +62,9 @@ void launch_fk(const Launch& L) {
 // (or only counted, to lay out the index), and the per-vertex accumulators
 // of the last association cleared, so that neither needs a launch of its own.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int which, int count, int bsel, int count_only,
+__global__ void __launch_bounds__(256) k_skin(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vsel, int pn, int which, int count, int bsel, int count_only,
                                               int clear_acc) {
+    const Batch B{bs, bp, bn};
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
@@ -98,12 +101,13 @@ __global__ void __launch_bounds__(256) k_skin(Batch B, int vsel, int pn, int whi
 
 void launch_skin(const Launch& L, int vsel, int pn, int which, int count, int bsel, int count_only, int clear_acc) {
     // one wave per workgroup: the vertices spread over every compute unit
-    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT64]), dim3(64), 0, L.B, vsel, pn, which, count, bsel,
+    launch_kernel(L, true, true, k_skin, dim3(L.grid[KK_VERT64]), dim3(64), 0, L.B.slots, L.B.pre, L.B.n, vsel, pn, which, count, bsel,
                   count_only, clear_acc);
 }
 
 // Vertex normals (one lane per vertex; see vertex_normal)
-__global__ void __launch_bounds__(256) k_normals(Batch B, int vsel) {
+__global__ void __launch_bounds__(256) k_normals(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vsel) {
+    const Batch B{bs, bp, bn};
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT, blockIdx.x, local)];
     const int i = local * blockDim.x + threadIdx.x;
@@ -114,7 +118,7 @@ __global__ void __launch_bounds__(256) k_normals(Batch B, int vsel) {
 }
 
 void launch_normals(const Launch& L, int vsel) {
-    launch_kernel(L, true, true, k_normals, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B, vsel);
+    launch_kernel(L, true, true, k_normals, dim3(L.grid[KK_VERT]), dim3(256), 0, L.B.slots, L.B.pre, L.B.n, vsel);
 }
 
 // ---------------------------------------------------------------------------
@@ -124,7 +128,8 @@ void launch_normals(const Launch& L, int vsel) {
 // keeps the frame-start offset buffer untouched).  The per-tile counts of the
 // last association are summed into the slot's summary.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int last_pose) {
+__global__ void __launch_bounds__(256) k_frame_end(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int first_pose, int last_pose) {
+    const Batch B{bs, bp, bn};
     __shared__ int s_sum[3][4];
     __shared__ int s_bad;
     int local;
@@ -180,7 +185,7 @@ __global__ void __launch_bounds__(256) k_frame_end(Batch B, int first_pose, int 
 }
 
 void launch_frame_end(const Launch& L, int first_pose, int last_pose) {
-    launch_kernel(L, true, true, k_frame_end, dim3(L.grid[KK_ONE]), dim3(256), 0, L.B, first_pose, last_pose);
+    launch_kernel(L, true, true, k_frame_end, dim3(L.grid[KK_ONE]), dim3(256), 0, L.B.slots, L.B.pre, L.B.n, first_pose, last_pose);
 }
 
 }  // namespace trk

@@ -172,7 +172,8 @@ __host__ __device__ inline size_t ne_lds_bytes(int ppmax, int lmax) {
 // BIG: an instance allowed more than 64 KB of LDS (hi/mid/lo planes, or
 // P > 79); smaller sizes use the other instance, which launches faster
 template <int MODE, bool BIG>
-__global__ void __launch_bounds__(kNeThreads) k_normal_eq(Batch B, int vsel, int pn, int ppmax, int lmax) {
+__global__ void __launch_bounds__(kNeThreads) k_normal_eq(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vsel, int pn, int ppmax, int lmax) {
+    const Batch B{bs, bp, bn};
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     unsigned char* q0 = smem;
     // [col][row] tile: float32 (mode 0) or two / three bfloat16 planes
@@ -453,9 +454,9 @@ void launch_normal_eq_t(const Launch& L, int vsel, int pn) {
     const int pp = L.ne_pp, lm = L.ne_l;
     const size_t bytes = ne_lds_bytes<MODE>(pp, lm);
     if (bytes <= kSmallLds)
-        launch_kernel(L, true, true, k_normal_eq<MODE, false>, g, dim3(kNeThreads), bytes, L.B, vsel, pn, pp, lm);
+        launch_kernel(L, true, true, k_normal_eq<MODE, false>, g, dim3(kNeThreads), bytes, L.B.slots, L.B.pre, L.B.n, vsel, pn, pp, lm);
     else
-        launch_kernel(L, true, true, k_normal_eq<MODE, true>, g, dim3(kNeThreads), bytes, L.B, vsel, pn, pp, lm);
+        launch_kernel(L, true, true, k_normal_eq<MODE, true>, g, dim3(kNeThreads), bytes, L.B.slots, L.B.pre, L.B.n, vsel, pn, pp, lm);
 }
 
 void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
@@ -471,7 +472,8 @@ void launch_normal_eq(const Launch& L, int gram_mode, int vsel, int pn) {
 // groups summed by as many threads (a few rounds of eight loads each), and
 // the group sums are added in group order.
 constexpr int kRedGroups = 16;
-__global__ void __launch_bounds__(32 * kRedGroups) k_gram_reduce(Batch B) {
+__global__ void __launch_bounds__(32 * kRedGroups) k_gram_reduce(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn) {
+    const Batch B{bs, bp, bn};
     __shared__ double part[kRedGroups][32];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_REDUCE, blockIdx.x, local)];
@@ -541,7 +543,7 @@ __global__ void __launch_bounds__(32 * kRedGroups) k_gram_reduce(Batch B) {
 }
 
 void launch_gram_reduce(const Launch& L) {
-    launch_kernel(L, true, true, k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(32 * kRedGroups), 0, L.B);
+    launch_kernel(L, true, true, k_gram_reduce, dim3(L.grid[KK_REDUCE]), dim3(32 * kRedGroups), 0, L.B.slots, L.B.pre, L.B.n);
 }
 
 }  // namespace trk

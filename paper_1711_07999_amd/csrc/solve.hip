@@ -77,7 +77,8 @@ constexpr size_t kSmallLds = 64 * 1024;
 // kernel allowed that much is launched more slowly, so sizes below use the
 // other instance
 template <class T, bool BIG>
-__global__ void __launch_bounds__(256) k_pose_solve(Batch B, int iter, int nmax) {
+__global__ void __launch_bounds__(256) k_pose_solve(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int iter, int nmax) {
+    const Batch B{bs, bp, bn};
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int ld = nmax + 4;   // row stride shared by the batch
     size_t mat = sizeof(T) * (size_t)(nmax + 1) * ld;
@@ -389,7 +390,8 @@ __device__ __forceinline__ void tree_back(const T* Fr, T* wb, int np, int f, int
 }
 
 template <class T>
-__global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(Batch B, int iter, int elems_max, int words_max) {
+__global__ void __launch_bounds__(kSolveThreads) k_pose_solve_tree(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int iter, int elems_max, int words_max) {
+    const Batch B{bs, bp, bn};
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const size_t mat = tree_front_bytes<T>(elems_max);
     T* Fs = reinterpret_cast<T*>(smem);
@@ -535,16 +537,16 @@ template <class T>
 void launch_pose_solve_t(const Launch& L, int iter) {
     if (L.solve_elems > 0) {
         const size_t bytes = tree_lds_bytes<T>(L.solve_elems, L.solve_words);
-        launch_kernel(L, true, true, k_pose_solve_tree<T>, dim3(L.grid[KK_ONE]), dim3(kSolveThreads), bytes, L.B,
+        launch_kernel(L, true, true, k_pose_solve_tree<T>, dim3(L.grid[KK_ONE]), dim3(kSolveThreads), bytes, L.B.slots, L.B.pre, L.B.n,
                       iter, L.solve_elems, L.solve_words);
         return;
     }
     const int n = L.solve_n;
     const size_t bytes = solve_lds_bytes<T>(n);
     if (bytes <= kSmallLds)
-        launch_kernel(L, true, true, k_pose_solve<T, false>, dim3(L.grid[KK_ONE]), dim3(256), bytes, L.B, iter, n);
+        launch_kernel(L, true, true, k_pose_solve<T, false>, dim3(L.grid[KK_ONE]), dim3(256), bytes, L.B.slots, L.B.pre, L.B.n, iter, n);
     else
-        launch_kernel(L, true, true, k_pose_solve<T, true>, dim3(L.grid[KK_ONE]), dim3(256), bytes, L.B, iter, n);
+        launch_kernel(L, true, true, k_pose_solve<T, true>, dim3(L.grid[KK_ONE]), dim3(256), bytes, L.B.slots, L.B.pre, L.B.n, iter, n);
 }
 
 void launch_pose_solve(const Launch& L, int fp64, int iter) {
@@ -577,7 +579,8 @@ __device__ __forceinline__ void solve3(const T M[9], const T g[3], T x[3]) {
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_shape(Batch B, int vo_sel, int vn_sel, int pn, int next, int bsel) {
+__global__ void __launch_bounds__(256) k_shape(const Slot* __restrict__ bs, const int* __restrict__ bp, int bn, int vo_sel, int vn_sel, int pn, int next, int bsel) {
+    const Batch B{bs, bp, bn};
     __shared__ float sdq[8 * (kMaxLinks + 1)];
     int local;
     const Slot& S = B.slots[slot_of(B, KK_VERT64, blockIdx.x, local)];
@@ -711,9 +714,9 @@ void launch_shape(const Launch& L, int fp64, int v_old, int v_new, int pn, int n
     // one wave per workgroup: the vertices spread over every compute unit
     const dim3 g(L.grid[KK_VERT64]);
     if (fp64)
-        launch_kernel(L, true, true, k_shape<double>, g, dim3(64), 0, L.B, v_old, v_new, pn, next, bsel);
+        launch_kernel(L, true, true, k_shape<double>, g, dim3(64), 0, L.B.slots, L.B.pre, L.B.n, v_old, v_new, pn, next, bsel);
     else
-        launch_kernel(L, true, true, k_shape<float>, g, dim3(64), 0, L.B, v_old, v_new, pn, next, bsel);
+        launch_kernel(L, true, true, k_shape<float>, g, dim3(64), 0, L.B.slots, L.B.pre, L.B.n, v_old, v_new, pn, next, bsel);
 }
 
 }  // namespace trk
