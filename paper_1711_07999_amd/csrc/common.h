@@ -265,17 +265,10 @@ __device__ __forceinline__ void copy_to_lds(float* dst, const float* __restrict_
     }
 }
 
-// slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
-// Keeps a loaded value where it stands: the compiler would otherwise move a
-// load into the branch that alone uses it, to be waited for there on its
-// own instead of together with the loads issued before it.  Emits nothing.
-__device__ __forceinline__ void pin_load(int& x) { asm volatile("" : "+v"(x)); }
-__device__ __forceinline__ void pin_load(uint32_t& x) { asm volatile("" : "+v"(x)); }
-__device__ __forceinline__ void pin_load(int2& x) { pin_load(x.x); pin_load(x.y); }
-
-// A read of global memory as such: through a generic pointer the compiler
-// emits a flat load, which also counts as an LDS access, so that any later
-// wait for LDS waits for it too.
+// Global memory read, written and updated as such.  Through a generic
+// pointer the compiler emits flat instructions, which also count as LDS
+// accesses: the next wait for LDS (a shuffle, an LDS read, a barrier) or for
+// a scalar load then waits for every one of them still in flight.
 template <class T>
 __device__ __forceinline__ T ldg(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;
@@ -285,19 +278,16 @@ __device__ __forceinline__ float4 ldg(const float4* p) {
     const v4f t = *(const __attribute__((address_space(1))) v4f*)p;
     return make_float4(t.x, t.y, t.z, t.w);
 }
-// A store to global memory as such: a flat store also counts as an LDS
-// access, so that the next wait for LDS (a shuffle, a barrier) waits for it.
-template <class T>
-__device__ __forceinline__ void stg(T* p, T v) {
-    *(__attribute__((address_space(1))) T*)p = v;
+__device__ __forceinline__ int4 ldg(const int4* p) {
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i t = *(const __attribute__((address_space(1))) v4i*)p;
+    return make_int4(t.x, t.y, t.z, t.w);
 }
-__device__ __forceinline__ void stg(float4* p, float4 v) {
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    v4f t;
-    t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
-    *(__attribute__((address_space(1))) v4f*)p = t;
+__device__ __forceinline__ int2 ldg(const int2* p) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const v2i t = *(const __attribute__((address_space(1))) v2i*)p;
+    return make_int2(t.x, t.y);
 }
-
 __device__ __forceinline__ uint4 ldg(const uint4* p) {
     typedef unsigned v4u __attribute__((ext_vector_type(4)));
     const v4u t = *(const __attribute__((address_space(1))) v4u*)p;
@@ -308,7 +298,24 @@ __device__ __forceinline__ uint2 ldg(const uint2* p) {
     const v2u t = *(const __attribute__((address_space(1))) v2u*)p;
     return make_uint2(t.x, t.y);
 }
-// Relaxed device-scope atomics on global memory as such (see ldg).
+// x, y, z of a float4 (w = 0): an unused fourth register of a load in
+// flight would be taken for other values, which must then wait for the load
+__device__ __forceinline__ float4 ldg_xyz(const float4* p) {
+    typedef float v3f __attribute__((ext_vector_type(3)));
+    const v3f t = *(const __attribute__((address_space(1))) v3f*)p;
+    return make_float4(t.x, t.y, t.z, 0.0f);
+}
+template <class T>
+__device__ __forceinline__ void stg(T* p, T v) {
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+__device__ __forceinline__ void stg(float4* p, float4 v) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f t;
+    t.x = v.x; t.y = v.y; t.z = v.z; t.w = v.w;
+    *(__attribute__((address_space(1))) v4f*)p = t;
+}
+// relaxed device-scope atomics
 __device__ __forceinline__ uint32_t atomic_add_g(uint32_t* p, uint32_t v) {
     return __hip_atomic_fetch_add((__attribute__((address_space(1))) uint32_t*)p, v, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
@@ -326,27 +333,17 @@ __device__ __forceinline__ void atomic_max_g(uint32_t* p, uint32_t v) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// x, y, z of a float4 (w = 0): an unused fourth register of a load in
-// flight would be taken for other values, which must then wait for the load
-__device__ __forceinline__ float4 ldg_xyz(const float4* p) {
-    typedef float v3f __attribute__((ext_vector_type(3)));
-    const v3f t = *(const __attribute__((address_space(1))) v3f*)p;
-    return make_float4(t.x, t.y, t.z, 0.0f);
-}
-__device__ __forceinline__ int4 ldg(const int4* p) {
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    const v4i t = *(const __attribute__((address_space(1))) v4i*)p;
-    return make_int4(t.x, t.y, t.z, t.w);
-}
-__device__ __forceinline__ int2 ldg(const int2* p) {
-    typedef int v2i __attribute__((ext_vector_type(2)));
-    const v2i t = *(const __attribute__((address_space(1))) v2i*)p;
-    return make_int2(t.x, t.y);
-}
+// Keeps a loaded value where it stands: the compiler would otherwise move a
+// load into the branch that alone uses it, to be waited for there on its
+// own instead of together with the loads issued before it.  Emits nothing.
+__device__ __forceinline__ void pin_load(int& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_load(uint32_t& x) { asm volatile("" : "+v"(x)); }
+__device__ __forceinline__ void pin_load(int2& x) { pin_load(x.x); pin_load(x.y); }
 
-// A value the whole wave holds alike (a field of its workgroup's slot), put
-// in scalar registers: the compiler reads the slot table with vector loads,
-// since kernels store through pointers it cannot tell apart from it.
+// A value the whole wave holds alike (a field of its workgroup's slot), in
+// scalar registers: where the compiler cannot tell that it is uniform (a
+// value carried through a loop that also copies into LDS) it would keep a
+// copy per lane in vector registers.
 template <class T>
 __device__ __forceinline__ T* wave_uniform(T* p) {
     const unsigned long long a = (unsigned long long)p;
@@ -362,6 +359,7 @@ __device__ __forceinline__ float wave_uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// slot of workgroup `blk` of kernel kind `kind`, and its index in that slot
 __device__ __forceinline__ int slot_of(const Batch& B, int kind, int blk, int& local) {
     const int* p = B.pre + kind * (B.n + 1);
     int lo = 0, hi = B.n - 1;
