@@ -273,6 +273,28 @@ def batched_only(args):
           flush=True)
 
 
+def highres(T, stream, args):
+    """The high-resolution configuration on its own: 200,000 vertices,
+    512x424, 60 frames, offsets under Laplacian and temporal regularisation,
+    float64 pose solve; frames/s and per-frame latency of whole frames."""
+    import torch
+
+    import synth
+
+    w = synth.workload_highres()
+    m, cam = w.body.model, w.body.camera
+    frames = [torch.from_numpy(f).to(torch.device("cuda:0")) for f in w.frames]
+    trk = T.Tracker(m, cam, w.params, w.theta0, stream=stream.cuda_stream)
+    el, lat = _timed_frames(T, trk, frames, w.theta0, max(args.warmup, 1), args.steps)
+    trk.close()
+    return {"workload": w.name, "value": args.steps / el, "unit": "frames/s",
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "vertices": int(m["rest_xyz"].shape[0]), "triangles": int(m["faces"].shape[0]),
+            "depth": f"{cam['width']}x{cam['height']}", "gn_iters_per_frame": int(w.params["n_iters"]),
+            "sequence_frames": len(frames), "lambda_t": float(w.params["lambda_t"]),
+            "pose_solve": "float64" if w.params.get("pose_solve_fp64") else "float32"}
+
+
 def single_stream(args):
     import torch
 
@@ -397,6 +419,8 @@ def single_stream(args):
                                 "p50_ms": float(np.percentile(lat2, 50)), "p99_ms": float(np.percentile(lat2, 99)),
                                 "speedup_vs_main": (args.steps / el2) / fps,
                                 "solves": "float64" if other == "bf16x3" else "float32"}
+        # the high-resolution configuration
+        out["highres"] = highres(T, stream, args)
         # B copies of the workload batched through one server
         out["batched_copies"] = [batched_copies(T, w, frames, prm, B, args.batch_frames) for B in (16, 32)]
         # the serving mix, shortened: 64 streams of six sizes, 45 frames each
