@@ -352,7 +352,7 @@ def single_stream(args):
     trk.close()
 
     # The roofline takes the back-to-back figure: a pair of events around a
-    # single launch adds the events' own dispatch to the span (about 6 us
+    # single launch adds the events' own dispatch to the span (several us
     # against the profiler's trace of the same launches), while 200 launches
     # between one pair agree with the trace to within 1 %.  The in-frame
     # event figure stands beside it as an upper bound of the in-frame time.
