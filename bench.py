@@ -349,6 +349,17 @@ def single_stream(args):
     # inputs and launch configuration), one pair of HIP events around them
     last = frames[(args.inframe_frames - 1) % nseq]
     avg_rep = T.track_kernel_bench(trk.ctx, dom_id, last, args.kernel_reps)
+    # and from cold caches: before each launch a 512 MiB write evicts the
+    # L2s and the 256 MB last-level cache; each launch is timed alone between
+    # its own pair of events (so it includes their dispatch, as the in-frame
+    # figure does), the same single-launch timing without the eviction beside
+    flush = torch.empty(1 << 29, dtype=torch.uint8, device=dev)
+    cold, warm1 = [], []
+    for _ in range(20):
+        flush.zero_()
+        cold.append(T.track_kernel_bench(trk.ctx, dom_id, last, 1))
+        warm1.append(T.track_kernel_bench(trk.ctx, dom_id, last, 1))
+    del flush
     trk.close()
 
     # The roofline takes the back-to-back figure: a pair of events around a
@@ -366,6 +377,13 @@ def single_stream(args):
                                           "frac": inf["frac"],
                                           "timing": "each in-frame launch between its own pair of HIP events "
                                                     "(includes the events' dispatch)"}})
+    cold_ms = float(np.mean(cold))
+    cr = _roof(kind, dom, cold_ms, V, F, N_px, N_valid, P, V_obs, prm["gram_mode"], temporal)
+    roof["cold_upper_bound"] = {"avg_launch_ms": cold_ms, "launches": len(cold), "achieved": cr["achieved"],
+                                "frac": cr["frac"], "single_launch_warm_ms": float(np.mean(warm1)),
+                                "timing": "each launch alone between its own pair of HIP events after a 512 MiB "
+                                          "write that evicts the caches (includes the events' dispatch); "
+                                          "single_launch_warm_ms: the same without the eviction"}
 
     # every pass inside frames (from the timed warm-up): microseconds per
     # launch and its algorithmic bytes (flops for the Gram) against peak
