@@ -295,6 +295,18 @@ def highres(T, stream, args):
             "pose_solve": "float64" if w.params.get("pose_solve_fp64") else "float32"}
 
 
+def highres_only(args):
+    import torch
+
+    from paper_1711_07999_amd import track as T
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    stream = torch.cuda.current_stream(torch.device("cuda:0"))
+    out = highres(T, stream, args)
+    print(json.dumps({"metric": "tracked frames/s + p99 frame latency (high-resolution configuration)", **out}),
+          flush=True)
+
+
 def single_stream(args):
     import torch
 
@@ -736,6 +748,8 @@ def main():
     ap.add_argument("--serve", action="store_true", help="serving mix instead of the single-stream step")
     ap.add_argument("--modes", action="store_true",
                     help="tracking modes and schedules against the synthetic ground truth")
+    ap.add_argument("--highres", action="store_true",
+                    help="only the high-resolution configuration (200,000 vertices, 512x424)")
     ap.add_argument("--batched", type=int, default=0,
                     help="only B copies of the workload batched through one server")
     ap.add_argument("--streams", type=int, default=64)
@@ -760,6 +774,8 @@ def main():
         modes(args)
     elif args.batched:
         batched_only(args)
+    elif args.highres:
+        highres_only(args)
     else:
         single_stream(args)
 
